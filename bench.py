@@ -1,0 +1,193 @@
+#!/usr/bin/env python3
+"""Benchmark of the lattice-Boltzmann + momentum-exchange step on one MI355X.
+
+Default workload: the 2000x800 D2Q9 channel with an oscillating cylinder
+(R=40, y(t) = 400 + 20 sin(2 pi t/4000), interpolated bounce-back,
+lattice-frame moving-body force and torque every step), FP32 storage with
+FP64 force accumulation. A step is the whole hot path: boundary rule and
+momentum exchange at the body, fused stream-collide with the domain faces,
+covered/uncovered nodes with refill, and the link rebuild for the next pose.
+
+Prints ONE JSON line (rank 0). `value` = million lattice-node updates per
+second over the timed steps (every node of the box counts). `roofline` is
+the stream-collide kernel: algorithmic bytes (2 Q s per active node) over its
+average duration from HIP events around each launch in the timed region,
+against 8 TB/s. `cpu_baseline` is the FP64 CPU oracle on a bounded sample of
+the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "MLUPS incl. ME force/torque; batched solves/s + p99 latency vs plain"
+
+
+def workload(name):
+    import lbm_workloads as W
+    if name == "channel_oscillating_f32":
+        return W.channel_oscillating_f32(scale=1)
+    if name == "duct_sphere_f32":
+        return W.duct_sphere(scale=1, storage="f32")
+    if name == "duct_sphere_f16":
+        return W.duct_sphere(scale=1, storage="f16")
+    if name == "channel_cylinder_f64":
+        return W.channel_cylinder_f64()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def active_nodes(w):
+    """nodes the stream-collide kernel updates (all but the wall layers)"""
+    n = [w["nx"], w["ny"], w["nz"] if w["lattice"] == "D3Q19" else 1]
+    faces = w["faces"]
+    dims = 2 if w["lattice"] == "D2Q9" else 3
+    tot = 1
+    for a in range(3):
+        k = n[a]
+        if a < dims:
+            k -= (faces[2 * a] == 1) + (faces[2 * a + 1] == 1)
+        tot *= k
+    return tot
+
+
+def bytes_per_node(w):
+    q = 9 if w["lattice"] == "D2Q9" else 19
+    s = {"f64": 8, "f32": 4, "f16": 2}[w["storage"]]
+    return 2 * q * s
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "lattice.hpp", "geom.hpp"):
+        with open(os.path.join(ROOT, "paper_1407_4524_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(name):
+    """HBM bytes per stream-collide launch from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"stream_collide_{name}_traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except OSError:
+        return None
+    if rec.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def run_gpu(name, steps, warmup):
+    import torch
+    from paper_1407_4524_amd import Domain
+    w = workload(name)
+    dom = Domain.from_spec(w)
+    dom.step(warmup)
+    dom.synchronize()
+    dom.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dom.step(steps)
+    dom.synchronize()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kms, launches = dom.timing_read()
+    ft = dom.force_torque(0, dom.t - 1, 1)[0]
+    cells = w["nx"] * w["ny"] * (w["nz"] if w["lattice"] == "D3Q19" else 1)
+    sec = t1 - t0
+    avg_s = kms / launches / 1e3
+    algo = active_nodes(w) * bytes_per_node(w)
+    achieved = algo / avg_s / 1e9
+    out = dict(
+        w=w, cells=cells, seconds=sec, ms_per_step=sec / steps * 1e3, mlups=cells * steps / sec / 1e6,
+        kernel_avg_us=avg_s * 1e6, roofline=dict(
+            bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+            frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(name),
+            algorithmic_bytes_per_launch=algo),
+        last_force_torque=[float(x) for x in ft])
+    dom.close()
+    return out
+
+
+def cpu_baseline(name, budget_s):
+    """The FP64 oracle (untuned, OpenMP on its bulk loops) on the first steps
+    of the same workload, until about budget_s seconds of CPU time."""
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import oracle
+    from oracle_helpers import make_oracle
+    w = workload(name)
+    o = make_oracle(w)
+    o.step(1)
+    t0 = time.perf_counter()
+    n = 0
+    while time.perf_counter() - t0 < budget_s:
+        o.step(1)
+        n += 1
+    sec = time.perf_counter() - t0
+    cells = w["nx"] * w["ny"] * (w["nz"] if w["lattice"] == "D3Q19" else 1)
+    o.close()
+    return dict(value=round(cells * n / sec / 1e6, 3), unit="MLUPS", cores=oracle.nthreads(), kind="oracle",
+                sample=f"{w['name']}: steps 2..{n + 1} ({n} steps, {sec:.1f} s), FP64 oracle")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=500)
+    ap.add_argument("--workload", default="channel_oscillating_f32")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(a domain larger than one GPU would be split into x-slabs with a one-layer halo "
+              "exchange; that is described, not built).", file=sys.stderr)
+        sys.exit(2)
+    rank = int(os.environ.get("RANK", "0"))
+
+    main_run = run_gpu(args.workload, args.steps, args.warmup)
+    w = main_run["w"]
+    line = {
+        "metric": METRIC,
+        "value": round(main_run["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_run["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f64": "f64", "f32": "f32", "f16": "f16"}[w["storage"]],
+        "data": "synthetic",
+        "config": {"workload": w["name"], "lattice": w["lattice"], "nx": w["nx"], "ny": w["ny"],
+                   "nz": w["nz"], "tau": w["tau"], "storage": w["storage"],
+                   "force_accumulation": "f64", "bodies": len(w["bodies"]),
+                   "me": w["bodies"][0]["me"] if w["bodies"] else None, "parallelism": "single-gpu"},
+        "roofline": main_run["roofline"],
+        "kernel_avg_us": round(main_run["kernel_avg_us"], 3),
+    }
+    if not args.no_secondary and args.workload == "channel_oscillating_f32":
+        sec = {}
+        for name in ("duct_sphere_f32", "duct_sphere_f16"):
+            r = run_gpu(name, 500, 50)
+            sec[r["w"]["name"]] = dict(value=round(r["mlups"], 1), unit="MLUPS",
+                                       ms_per_step=round(r["ms_per_step"], 5), roofline=r["roofline"])
+        line["secondary"] = sec
+    if not args.no_cpu_baseline and rank == 0:
+        line["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)
+    if rank == 0:
+        print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

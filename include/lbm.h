@@ -1,0 +1,213 @@
+/*
+ * lbm.h -- C ABI of the MI355X lattice-Boltzmann library with
+ * momentum-exchange force and torque.
+ *
+ * The operation: the time step of the lattice-Boltzmann equation (BGK
+ * collision then streaming, Sec. II, Eqs. LBE, collision, streaming) for a
+ * flow around submerged bodies whose motion is prescribed (Sec. III: Omega(t)
+ * is a given function of t, strictly inside the simulated region), with the
+ * interpolated boundary rule of Sec. II.A (Filippova-Haenel with the
+ * Mei-Luo-Shyy choices; halfway bounce-back as the special case Delta = 1/2)
+ * and the flow force and torque on each body by momentum exchange, every
+ * step, in the three forms the paper derives:
+ *   static     Eqs. flow_force_2 / flow_torque_2,
+ *   lattice    Eqs. ForceInMovement / TorqueInMovement (static sums plus the
+ *              covered/uncovered-node terms, sets taken forward in time),
+ *   comoving   Eqs. ForceInMovementMovingFrame / TorqueInMovementMovingFrame
+ *              (node terms dropped).
+ *
+ * Units and signs: lattice units (dx = dt = 1). F is the force ON the body BY
+ * the flow; T is the torque about the body centre X_c(t). In 2D only Fx, Fy
+ * and Tz are non-zero.
+ *
+ * Lattices (numbering is part of this interface):
+ *   D2Q9:  0 (0,0); 1 (1,0); 2 (0,1); 3 (-1,0); 4 (0,-1); 5 (1,1); 6 (-1,1);
+ *          7 (-1,-1); 8 (1,-1). Weights 4/9, 1/9 (1..4), 1/36 (5..8).
+ *   D3Q19: 0 rest; 1..6 = +x,-x,+y,-y,+z,-z; 7..18 = (1,1,0),(-1,-1,0),
+ *          (1,-1,0),(-1,1,0),(1,0,1),(-1,0,-1),(1,0,-1),(-1,0,1),(0,1,1),
+ *          (0,-1,-1),(0,1,-1),(0,-1,1). Weights 1/3, 1/18, 1/36.
+ *
+ * Geometry (part of this interface, so that the solid/fluid decision is
+ * reproducible bit for bit): node (x,y,z) sits at the integer point
+ * (x,y,z). With d = p - X(t), xi = ct*dx + st*dy, eta = ct*dy - st*dx
+ * (ct = cos theta, st = sin theta), a node is solid iff phi <= 0 with
+ *   CIRCLE (sphere in 3D):  phi = (dx*dx + dy*dy [+ dz*dz]) - R*R
+ *   ELLIPSE (ellipsoid):    phi = xi*xi*ia2 + eta*eta*ib2 [+ dz*dz*ic2] - 1,
+ *                           ia2 = 1/(a*a), ib2 = 1/(b*b), ic2 = 1/(c*c)
+ *   OUTER_CIRCLE:           phi = R*R - (dx*dx + dy*dy [+ dz*dz])   (solid outside R)
+ * every expression evaluated left to right in IEEE double without fused
+ * multiply-add. Poses at integer step t (evaluated on the host, libm
+ * sin/cos, same rules):
+ *   STATIC     X = c0, theta = theta0
+ *   CONST_VEL  X = c0 + vel*(double)t, V = vel
+ *   ROTATE     theta = theta0 + omega*(double)t, Omega = omega (about z)
+ *   OSCILLATE  ph = (2*pi)*(double)t/period; X = c0 + amp*sin(ph);
+ *              V = amp*((2*pi)/period)*cos(ph)
+ *   TABLE      rows of 8 doubles X[3], theta, V[3], Omega_z per step (the last
+ *              row holds after the table ends)
+ * The wall velocity at a point x is V + Omega e_z x (x - X).
+ *
+ * Faces: -x,+x,-y,+y,-z,+z each PERIODIC (in pairs), WALL (the boundary
+ * layer of nodes is solid; halfway bounce-back puts the no-slip plane half
+ * way into it), INLET (-x only: velocity bounce-back at x = -1/2 with the
+ * inlet profile), OUTLET (+x only: zero gradient, the incoming populations of
+ * the last column copied from the column's own outgoing ones shifted along
+ * the link) or OUTLET_VELOCITY (+x only: velocity bounce-back at
+ * x = nx - 1/2). A parabolic profile is 4 u (p - 1/2)(n - 3/2 - p)/(n-2)^2
+ * along every WALL axis transverse to x.
+ *
+ * Ownership and threading: a domain owns its device arrays unless the caller
+ * passes device_buffer, which then must outlive the domain. The caller owns
+ * every host pointer; the library copies what it keeps. The stream is
+ * borrowed. One thread per domain at a time. lbm_step only enqueues work and
+ * never synchronises; errors raised on the device surface at the next call
+ * that reads results (lbm_force_torque, lbm_records, lbm_get_*).
+ * No exception crosses this interface; every call returns lbm_status and
+ * lbm_last_error() gives a thread-local message.
+ */
+#ifndef LBM_H
+#define LBM_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_E_INVAL = -1,    /* malformed descriptor or argument */
+  LBM_E_NOMEM = -2,    /* device allocation failed or caller buffer too small */
+  LBM_E_HIP = -3,      /* HIP runtime error */
+  LBM_E_RANGE = -4,    /* body not strictly inside the domain, or record out of the ring */
+  LBM_E_UNSTABLE = -5, /* non-finite force/torque or field (checked when results are read) */
+  LBM_E_STATE = -6     /* call not valid in the current state (e.g. body id in use) */
+} lbm_status;
+
+enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1 };
+enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16_SHIFTED = 2 };
+enum { LBM_EQ_BGK = 0, LBM_EQ_HELUO = 1 };
+enum { LBM_FACE_PERIODIC = 0, LBM_FACE_WALL = 1, LBM_FACE_INLET = 2, LBM_FACE_OUTLET = 3,
+       LBM_FACE_OUTLET_VELOCITY = 4 };
+enum { LBM_PROFILE_UNIFORM = 0, LBM_PROFILE_PARABOLIC = 1 };
+enum { LBM_SHAPE_CIRCLE = 0, LBM_SHAPE_ELLIPSE = 1, LBM_SHAPE_OUTER_CIRCLE = 2 };
+enum { LBM_BC_HALFWAY = 0, LBM_BC_MLS = 1 };
+enum { LBM_ME_STATIC = 0, LBM_ME_LATTICE = 1, LBM_ME_COMOVING = 2 };
+enum { LBM_MOTION_STATIC = 0, LBM_MOTION_CONST_VEL = 1, LBM_MOTION_ROTATE = 2,
+       LBM_MOTION_OSCILLATE = 3, LBM_MOTION_TABLE = 4 };
+
+#define LBM_MAX_BODIES 4
+/* one per-step record of a body: 20 doubles */
+#define LBM_REC_LEN 20
+#define LBM_REC_F_STATIC 0 /* Fx,Fy,Fz of Eq. flow_force_2 */
+#define LBM_REC_T_STATIC 3 /* Tx,Ty,Tz of Eq. flow_torque_2 */
+#define LBM_REC_F_NODES 6  /* covered minus uncovered node momentum (Eq. ForceInMovement) */
+#define LBM_REC_T_NODES 9  /* the same for the torque (Eq. TorqueInMovement) */
+#define LBM_REC_F_COMOVING 12
+#define LBM_REC_T_COMOVING 15
+#define LBM_REC_N_COVERED 18
+#define LBM_REC_N_UNCOVERED 19
+
+typedef struct lbm_domain_s* lbm_domain;
+
+typedef struct {
+  int32_t lattice;          /* LBM_D2Q9 | LBM_D3Q19 */
+  int32_t nx, ny, nz;       /* nodes per axis (nz ignored for D2Q9); each >= 3 */
+  double tau;               /* BGK relaxation time, > 1/2 */
+  double rho0;              /* reference density (rest equilibrium w_i rho0) */
+  int32_t storage;          /* LBM_F64 | LBM_F32 | LBM_F16_SHIFTED; populations are stored
+                               as deviations f_i - w_i rho0 in this type */
+  int32_t eq_model;         /* LBM_EQ_BGK (standard) | LBM_EQ_HELUO (quasi-incompressible) */
+  int32_t face[6];          /* -x,+x,-y,+y,-z,+z, LBM_FACE_* */
+  int32_t inlet_profile;    /* LBM_PROFILE_* */
+  double inlet_u;           /* uniform speed or peak of the parabola */
+  const double* init_rho;   /* host, optional: nx*ny*nz densities, x fastest; NULL = rho0 */
+  const double* init_u;     /* host, optional: 3 per node (ux,uy,uz); NULL = 0 */
+  void* stream;             /* hipStream_t (borrowed); NULL = the default stream */
+  void* device_buffer;      /* optional caller-owned device memory; NULL = library allocates */
+  size_t device_buffer_bytes;
+  int64_t record_capacity;  /* steps kept in each body's record ring; 0 = 65536 */
+} lbm_domain_desc;
+
+typedef struct {
+  int32_t shape;            /* LBM_SHAPE_* */
+  double axes[3];           /* radius, or semi-axes a, b (, c) */
+  int32_t bc;               /* LBM_BC_HALFWAY | LBM_BC_MLS */
+  int32_t me_mode;          /* which form lbm_force_torque returns */
+  int32_t motion;           /* LBM_MOTION_* */
+  double c0[3], theta0;
+  double vel[3];
+  double omega;
+  double amp[3], period;
+  const double* pose_table; /* TABLE: host rows of 8 doubles, copied */
+  int64_t pose_count;
+} lbm_body_desc;
+
+/* Device bytes a domain with this descriptor needs (for admission by HBM
+   footprint and for sizing device_buffer). Bodies add a small per-body amount
+   reported by lbm_body_footprint_bytes. */
+lbm_status lbm_footprint_bytes(const lbm_domain_desc* desc, size_t* bytes);
+
+/* Creates the domain and initialises every node to the equilibrium at
+   (init_rho, init_u) (Eq. Fillipova_equilibrium's truncated Maxwellian), step
+   counter 0. Enqueued on desc->stream. */
+lbm_status lbm_create_domain(const lbm_domain_desc* desc, lbm_domain* out);
+
+/* Waits for the domain's stream and frees what the library allocated. */
+lbm_status lbm_destroy_domain(lbm_domain dom);
+
+/* Places body `body_id` (0..LBM_MAX_BODIES-1) at its pose of the current
+   step: marks its nodes solid and builds its boundary-link list, the gained
+   sets G_i of Sec. III.B (x_F fluid with x_F - c_i inside the body), with
+   Delta per link (Sec. II.A). Its bounding box plus two nodes must stay
+   inside the non-wall interior at every step that lbm_step reaches
+   (LBM_E_RANGE otherwise), except for a static OUTER_CIRCLE. Synchronises
+   the stream once. */
+lbm_status lbm_set_body(lbm_domain dom, int32_t body_id, const lbm_body_desc* body);
+
+/* Advances nsteps time steps. Enqueue only. */
+lbm_status lbm_step(lbm_domain dom, int64_t nsteps);
+
+/* Blocks until the domain's queued work is done and reports device errors. */
+lbm_status lbm_synchronize(lbm_domain dom);
+
+/* Current step counter (number of steps taken). */
+int64_t lbm_time(lbm_domain dom);
+
+/* Force and torque on body `body_id` in its me_mode, for steps
+   first_step..first_step+count-1: ft[6*k..6*k+5] = Fx,Fy,Fz,Tx,Ty,Tz.
+   Synchronises. LBM_E_RANGE if a step is not in the record ring. */
+lbm_status lbm_force_torque(lbm_domain dom, int32_t body_id, int64_t first_step, int64_t count,
+                            double* ft);
+
+/* Full per-step records (LBM_REC_LEN doubles each, layout LBM_REC_*). */
+lbm_status lbm_records(lbm_domain dom, int32_t body_id, int64_t first_step, int64_t count,
+                       double* rec);
+
+/* Boundary links of a body at the current step, canonical order (node index
+   x + nx*(y + ny*z) ascending, then direction ascending). Writes at most cap
+   entries and the total count to *n. Synchronises. */
+lbm_status lbm_get_links(lbm_domain dom, int32_t body_id, int64_t cap, int64_t* node,
+                         int32_t* dir, double* delta, int64_t* n);
+
+/* Density and velocity of every node at the current step (host arrays of
+   nx*ny*nz and 3*nx*ny*nz doubles); solid nodes get NaN. Synchronises. */
+lbm_status lbm_get_fields(lbm_domain dom, double* rho, double* u);
+
+/* Node types at the current step: 0 fluid, 1 wall layer, 2+b body b. */
+lbm_status lbm_get_types(lbm_domain dom, int32_t* type);
+
+/* Kernel timing, for measurement: while enabled, HIP events recorded on the
+   domain's stream around every launch of the stream-collide kernel time it;
+   lbm_timing_read waits for the stream and returns the summed duration in
+   milliseconds and the number of launches since the last enable. */
+lbm_status lbm_timing_enable(lbm_domain dom, int32_t enable);
+lbm_status lbm_timing_read(lbm_domain dom, double* total_ms, int64_t* launches);
+
+/* Thread-local description of the last error. */
+const char* lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,113 @@
+// Domain layout, body poses and the shape function of the GPU path.
+//
+// Everything here is shared by the host layer and the kernels. The shape
+// function and the link root are evaluated with FP contraction off, in the
+// left-to-right order that include/lbm.h fixes, so the solid/fluid decision
+// and Delta are reproducible bit for bit wherever they are computed.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+enum { FACE_PERIODIC = 0, FACE_WALL = 1, FACE_INLET = 2, FACE_OUTLET = 3, FACE_OUTLET_VELOCITY = 4 };
+enum { SRC_NONE = 0, SRC_WALL = 1, SRC_INLET = 2, SRC_OUTLET = 3, SRC_OUTVEL = 4 };
+enum { SHAPE_CIRCLE = 0, SHAPE_ELLIPSE = 1, SHAPE_OUTER_CIRCLE = 2 };
+enum { MASK_FLUID = 0, MASK_WALL = 1, MASK_BODY0 = 2 };
+
+// Padded structure-of-arrays layout. Node (x,y,z), with each coordinate in
+// [-1, n] (one halo layer), lives at element base + x + y*sy + z*sz of every
+// population array; population i starts at i*S. Interior node x = 0 sits on a
+// 128-byte boundary.
+struct Geom {
+  int nx, ny, nz, D;
+  int64_t sy, sz, S, base;
+  int face[6];
+  // active (non-wall) index ranges, inclusive
+  int lo[3], hi[3];
+  __host__ __device__ int64_t idx(int x, int y, int z) const { return base + x + y * sy + z * sz; }
+};
+
+// Physical parameters of the update.
+struct Phys {
+  double tau, omega, rho0;
+  int eq;  // 0 standard, 1 quasi-incompressible
+  int inlet_profile;
+  double inlet_u;
+};
+
+// Pose of a body at one step: 16 doubles on the device.
+struct Pose {
+  double X[3];
+  double ct, st;
+  double V[3];
+  double Om;
+  double theta;
+  double lo[3], hi[3];  // region (inclusive node box) that holds the body and its links
+};
+
+struct BodyShape {
+  int shape, D;
+  double R;              // radius (circle/sphere, outer circle)
+  double ia2, ib2, ic2;  // 1/(a*a), 1/(b*b), 1/(c*c)
+};
+
+__host__ __device__ inline double shape_phi(const BodyShape& b, const Pose& p, double x, double y, double z) {
+#pragma clang fp contract(off)
+  double dx = x - p.X[0], dy = y - p.X[1], dz = z - p.X[2];
+  if (b.shape == SHAPE_CIRCLE || b.shape == SHAPE_OUTER_CIRCLE) {
+    double r2 = (b.D == 3) ? dx * dx + dy * dy + dz * dz : dx * dx + dy * dy;
+    return b.shape == SHAPE_CIRCLE ? r2 - b.R * b.R : b.R * b.R - r2;
+  }
+  double xi = p.ct * dx + p.st * dy;
+  double eta = p.ct * dy - p.st * dx;
+  if (b.D == 3) return xi * xi * b.ia2 + eta * eta * b.ib2 + dz * dz * b.ic2 - 1.0;
+  return xi * xi * b.ia2 + eta * eta * b.ib2 - 1.0;
+}
+
+// Fractional wall distance of the link from fluid node xF toward xF - c:
+// the root in (0,1] of phi(xF - s c) = A s^2 + 2 B s + C, C = phi(xF) > 0,
+// as C / (-B + sqrt(B^2 - A C)).
+__host__ __device__ inline double link_delta(const BodyShape& b, const Pose& p, double x, double y, double z,
+                                             int cxi, int cyi, int czi) {
+#pragma clang fp contract(off)
+  double dx = x - p.X[0], dy = y - p.X[1], dz = z - p.X[2];
+  double cx = cxi, cy = cyi, cz = czi;
+  double A, B;
+  double C = shape_phi(b, p, x, y, z);
+  if (b.shape == SHAPE_CIRCLE) {
+    A = (b.D == 3) ? cx * cx + cy * cy + cz * cz : cx * cx + cy * cy;
+    B = -((b.D == 3) ? dx * cx + dy * cy + dz * cz : dx * cx + dy * cy);
+  } else if (b.shape == SHAPE_OUTER_CIRCLE) {
+    A = -((b.D == 3) ? cx * cx + cy * cy + cz * cz : cx * cx + cy * cy);
+    B = (b.D == 3) ? dx * cx + dy * cy + dz * cz : dx * cx + dy * cy;
+  } else {
+    double xi = p.ct * dx + p.st * dy;
+    double eta = p.ct * dy - p.st * dx;
+    double xic = p.ct * cx + p.st * cy;
+    double etac = p.ct * cy - p.st * cx;
+    if (b.D == 3) {
+      A = xic * xic * b.ia2 + etac * etac * b.ib2 + cz * cz * b.ic2;
+      B = -(xi * xic * b.ia2 + eta * etac * b.ib2 + dz * cz * b.ic2);
+    } else {
+      A = xic * xic * b.ia2 + etac * etac * b.ib2;
+      B = -(xi * xic * b.ia2 + eta * etac * b.ib2);
+    }
+  }
+  double disc = B * B - A * C;
+  if (disc < 0.0) disc = 0.0;
+  double s = C / (-B + sqrt(disc));
+  return s > 1.0 ? 1.0 : s;
+}
+
+// One boundary link: fluid node (x,y,z) at padded index `cell`, direction
+// `dir` pointing out of the body, fractional distance delta.
+struct Link {
+  int32_t cell;
+  int16_t x, y, z;
+  int16_t dir;
+  double delta;
+};
+static_assert(sizeof(Link) == 24, "link record layout");
+
+}  // namespace lbm

@@ -1,0 +1,708 @@
+// HIP kernels of the lattice-Boltzmann step with momentum-exchange force and
+// torque, for gfx950 (MI355X).
+//
+// Per time step t the host enqueues, on one stream:
+//   k_links         (static bodies, or a moving body's first step) -- the
+//                   interpolated boundary rule of Sec. II.A writes the value
+//                   leaving the body into the solid node's slot of the source
+//                   buffer and sums the momentum exchange of Eqs. flow_force_2,
+//                   flow_torque_2 and the comoving-frame forms;
+//   k_stream_collide the fused pull streaming + BGK collision (Eqs. LBE,
+//                   collision, streaming) over every non-wall node, which
+//                   also writes the domain-face ghost values for step t+1;
+//   k_body_advance  (moving bodies) covered/uncovered nodes between pose t
+//                   and t+1, their momentum (Eqs. ForceInMovement,
+//                   TorqueInMovement), refill, the link list of pose t+1 and
+//                   the boundary rule + momentum exchange of step t+1.
+// Populations are stored as deviations h_i = f_i - w_i rho0 in
+// structure-of-arrays layout; momentum exchange accumulates in FP64.
+#include "kernels.hpp"
+
+#include <algorithm>
+#include <type_traits>
+
+namespace lbm {
+
+// ---------------------------------------------------------------------------
+// domain faces
+
+// Kind of a (possibly halo) source node of a pull, for the face rules:
+// periodic axes wrap first, wall layers take precedence, then the inlet
+// (beyond -x) and the outlets (beyond +x).
+__device__ inline int source_type(const Geom& g, int sx, int sy, int sz) {
+  if (g.face[0] == FACE_PERIODIC) sx = sx < 0 ? sx + g.nx : (sx >= g.nx ? sx - g.nx : sx);
+  if (g.face[2] == FACE_PERIODIC) sy = sy < 0 ? sy + g.ny : (sy >= g.ny ? sy - g.ny : sy);
+  if (g.D == 3 && g.face[4] == FACE_PERIODIC) sz = sz < 0 ? sz + g.nz : (sz >= g.nz ? sz - g.nz : sz);
+  if ((g.face[0] == FACE_WALL && sx <= 0) || (g.face[1] == FACE_WALL && sx >= g.nx - 1)) return SRC_WALL;
+  if ((g.face[2] == FACE_WALL && sy <= 0) || (g.face[3] == FACE_WALL && sy >= g.ny - 1)) return SRC_WALL;
+  if (g.D == 3 && ((g.face[4] == FACE_WALL && sz <= 0) || (g.face[5] == FACE_WALL && sz >= g.nz - 1)))
+    return SRC_WALL;
+  if (sx < 0) return SRC_INLET;
+  if (sx >= g.nx) return g.face[1] == FACE_OUTLET_VELOCITY ? SRC_OUTVEL : SRC_OUTLET;
+  return SRC_NONE;
+}
+
+// inlet speed at the wall point (x = -1/2 or nx - 1/2) with transverse
+// coordinates yB, zB: uniform, or 4 u (p-1/2)(n-3/2-p)/(n-2)^2 per wall axis
+__device__ inline double inlet_speed(const Geom& g, const Phys& ph, double yB, double zB) {
+  double u = ph.inlet_u;
+  if (ph.inlet_profile == 1) {
+    if (g.face[2] == FACE_WALL) {
+      double H = g.ny - 2.0;
+      u *= 4.0 * (yB - 0.5) * (g.ny - 1.5 - yB) / (H * H);
+    }
+    if (g.D == 3 && g.face[4] == FACE_WALL) {
+      double H = g.nz - 2.0;
+      u *= 4.0 * (zB - 0.5) * (g.nz - 1.5 - zB) / (H * H);
+    }
+  }
+  return u;
+}
+
+// Ghost values of the domain faces for the next step, written by the node
+// that owns them, from its post-collision deviations hout:
+//  * bounce rules (resting wall, inlet / velocity outlet at the half-way
+//    plane): the slot of source x - c_i gets hout[opp i] + 6 w_i rho_w c_i.u;
+//  * copy rules (periodic images, zero-gradient outlet): the halo slot that a
+//    wrapped (or outlet-shifted) destination pulls from gets hout[i].
+template <class L, class S>
+__device__ void write_faces(typename S::T* __restrict__ B, const Geom& g, const Phys& ph, int x, int y, int z,
+                            int64_t c, const typename S::C* hout, typename S::C rho_w) {
+  using C = typename S::C;
+#pragma unroll
+  for (int i = 1; i < L::Q; ++i) {
+    const int cx = L::cx(i), cy = L::cy(i), cz = L::cz(i);
+    const int64_t off = cx + cy * g.sy + cz * g.sz;
+    const int st = source_type(g, x - cx, y - cy, z - cz);
+    if (st == SRC_WALL) {
+      S::store(B + i * g.S + c - off, hout[L::opp(i)]);
+    } else if (st == SRC_INLET || st == SRC_OUTVEL) {
+      double u = inlet_speed(g, ph, y - 0.5 * cy, z - 0.5 * cz);
+      C add = (C)(6.0 * L::w(i)) * rho_w * (C)(cx * u);
+      S::store(B + i * g.S + c - off, hout[L::opp(i)] + add);
+    }
+    int ex = x + cx, ey = y + cy, ez = z + cz;
+    bool sh = false;
+    if (g.face[1] == FACE_OUTLET && cx == -1 && x == g.nx - 1) {
+      ex += 1;
+      sh = true;
+    }
+    if (g.face[0] == FACE_PERIODIC && (ex < 0 || ex >= g.nx)) {
+      ex = ex < 0 ? ex + g.nx : ex - g.nx;
+      sh = true;
+    }
+    if (g.face[2] == FACE_PERIODIC && (ey < 0 || ey >= g.ny)) {
+      ey = ey < 0 ? ey + g.ny : ey - g.ny;
+      sh = true;
+    }
+    if (L::D == 3 && g.face[4] == FACE_PERIODIC && (ez < 0 || ez >= g.nz)) {
+      ez = ez < 0 ? ez + g.nz : ez - g.nz;
+      sh = true;
+    }
+    bool active = ex >= g.lo[0] && ex <= g.hi[0] && ey >= g.lo[1] && ey <= g.hi[1] &&
+                  (L::D == 2 || (ez >= g.lo[2] && ez <= g.hi[2]));
+    if (sh && active) S::store(B + i * g.S + g.idx(ex - cx, ey - cy, ez - cz), hout[i]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// fused pull stream + collide
+
+template <class L, class S, int EQ>
+__device__ __forceinline__ void collide(typename S::C* h, typename S::C rho0, typename S::C omega,
+                                        typename S::C& rho_out) {
+  using C = typename S::C;
+  C drho = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) {
+    drho += h[i];
+    if (L::cx(i)) jx += L::cx(i) > 0 ? h[i] : -h[i];
+    if (L::cy(i)) jy += L::cy(i) > 0 ? h[i] : -h[i];
+    if (L::D == 3 && L::cz(i)) jz += L::cz(i) > 0 ? h[i] : -h[i];
+  }
+  const C rho = rho0 + drho;
+  const C rhoU = EQ ? rho0 : rho;
+  const C inv = (C)1 / rhoU;
+  const C ux = jx * inv, uy = jy * inv, uz = jz * inv;
+  const C usq = (C)1.5 * (ux * ux + uy * uy + uz * uz);
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) {
+    C cu = 0;
+    if (L::cx(i)) cu += L::cx(i) > 0 ? ux : -ux;
+    if (L::cy(i)) cu += L::cy(i) > 0 ? uy : -uy;
+    if (L::D == 3 && L::cz(i)) cu += L::cz(i) > 0 ? uz : -uz;
+    const C heq = (C)L::w(i) * (drho + rhoU * ((C)3 * cu + (C)4.5 * cu * cu - usq));
+    h[i] = h[i] + omega * (heq - h[i]);
+  }
+  rho_out = rho;
+}
+
+constexpr int BULK_BLOCK = 256;
+
+template <class L, class S, int EQ>
+__global__ __launch_bounds__(BULK_BLOCK) void k_stream_collide(const typename S::T* __restrict__ A,
+                                                               typename S::T* __restrict__ B, Geom g, Phys ph,
+                                                               int nbx, int nrows, int nblocks) {
+  using C = typename S::C;
+  // XCD-aware mapping: hardware block k runs on XCD k % 8; give every XCD a
+  // contiguous run of logical blocks so that the cache lines shared by
+  // neighbouring blocks stay in one L2.
+  const int hw = blockIdx.x;
+  const int q = nblocks >> 3, r = nblocks & 7;
+  const int xcd = hw & 7, k = hw >> 3;
+  const int blk = xcd * q + (xcd < r ? xcd : r) + k;
+  const int bx = blk % nbx;
+  const int row = blk / nbx;
+  const int y = g.lo[1] + row % nrows;
+  const int z = g.lo[2] + row / nrows;
+  const int x = g.lo[0] + bx * BULK_BLOCK + threadIdx.x;
+  if (x > g.hi[0]) return;
+  const int64_t c = g.idx(x, y, z);
+  C h[L::Q];
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i)
+    h[i] = S::load(A + i * g.S + c - (L::cx(i) + L::cy(i) * g.sy + L::cz(i) * g.sz));
+  C rho;
+  collide<L, S, EQ>(h, (C)ph.rho0, (C)ph.omega, rho);
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) S::store(B + i * g.S + c, h[i]);
+  const bool near = x <= g.lo[0] || x >= g.hi[0] || y <= g.lo[1] || y >= g.hi[1] ||
+                    (L::D == 3 && (z <= g.lo[2] || z >= g.hi[2]));
+  if (near) write_faces<L, S>(B, g, ph, x, y, z, c, h, EQ ? (C)ph.rho0 : rho);
+}
+
+// initial state: equilibrium deviations at (rho, u) per node, the face ghosts
+// of step 0 and the fluid mask
+template <class L, class S, int EQ>
+__global__ __launch_bounds__(BULK_BLOCK) void k_init(typename S::T* __restrict__ A, uint8_t* __restrict__ mask,
+                                                     Geom g, Phys ph, const double* __restrict__ rho_in,
+                                                     const double* __restrict__ u_in) {
+  using C = typename S::C;
+  const int x = g.lo[0] + blockIdx.x * BULK_BLOCK + threadIdx.x;
+  const int y = g.lo[1] + blockIdx.y;
+  const int z = g.lo[2] + blockIdx.z;
+  if (x > g.hi[0]) return;
+  const int64_t c = g.idx(x, y, z);
+  const int64_t node = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
+  double rho = rho_in ? rho_in[node] : ph.rho0;
+  double ux = 0, uy = 0, uz = 0;
+  if (u_in) {
+    ux = u_in[3 * node];
+    uy = u_in[3 * node + 1];
+    uz = L::D == 3 ? u_in[3 * node + 2] : 0.0;
+  }
+  const double drho = rho - ph.rho0;
+  const double rhoU = EQ ? ph.rho0 : rho;
+  const double usq = 1.5 * (ux * ux + uy * uy + uz * uz);
+  C h[L::Q];
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) {
+    double cu = L::cx(i) * ux + L::cy(i) * uy + L::cz(i) * uz;
+    double heq = L::w(i) * (drho + rhoU * (3.0 * cu + 4.5 * cu * cu - usq));
+    S::store_plain(A + i * g.S + c, heq);
+    h[i] = S::load(A + i * g.S + c);
+  }
+  mask[c] = MASK_FLUID;
+  const bool near = x <= g.lo[0] || x >= g.hi[0] || y <= g.lo[1] || y >= g.hi[1] ||
+                    (L::D == 3 && (z <= g.lo[2] || z >= g.hi[2]));
+  if (near) write_faces<L, S>(A, g, ph, x, y, z, c, h, EQ ? (C)ph.rho0 : (C)rho);
+}
+
+// ---------------------------------------------------------------------------
+// boundary links of a body
+
+template <class L>
+struct Dir {
+  int i, cx, cy, cz, oi;
+  double w;
+};
+
+template <class L>
+__device__ inline Dir<L> dir_of(int i) {
+  Dir<L> d{0, 0, 0, 0, 0, 0.0};
+#pragma unroll
+  for (int q = 1; q < L::Q; ++q)
+    if (q == i) d = Dir<L>{q, L::cx(q), L::cy(q), L::cz(q), L::opp(q), L::w(q)};
+  return d;
+}
+
+template <class L, class S>
+__device__ inline void moments_at(const typename S::T* A, const Geom& g, int64_t c, double rho0, int eq,
+                                  double h[L::Q], double& drho, double u[3]) {
+  double jx = 0, jy = 0, jz = 0;
+  drho = 0;
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) {
+    h[q] = (double)S::load(A + q * g.S + c);
+    drho += h[q];
+    jx += L::cx(q) * h[q];
+    jy += L::cy(q) * h[q];
+    jz += L::cz(q) * h[q];
+  }
+  const double rhoU = eq ? rho0 : rho0 + drho;
+  u[0] = jx / rhoU;
+  u[1] = jy / rhoU;
+  u[2] = jz / rhoU;
+}
+
+// The interpolated boundary rule (Eq. Fillipova_interpolation with the
+// Mei-Luo-Shyy u_bf and chi; halfway bounce-back when bc == 0) for one link,
+// in deviation form, written to the solid node's slot; then the link's
+// momentum exchange in FP64:
+//   static   m = -c_i (f_i(x_F - c_i) + f_ibar(x_F))            (Eq. flow_force_2)
+//   comoving m = -(c_i - v) f_i(x_F - c_i) + (c_ibar - v) f_ibar(x_F)
+// with v the wall velocity at the link's wall point, and torques r x m about
+// the body centre. The moving-wall term is +6 w_i rho c_i.u_B with c_i the
+// outgoing direction (the sign that drives the fluid with the wall).
+// acc: [0..2] F static, [3..5] T static, [6..8] F comoving, [9..11] T comoving.
+template <class L, class S, int EQ>
+__device__ void link_rule(typename S::T* A, const Link& lk, const Pose& P, int bc, const uint8_t* mask,
+                          const Geom& g, const Phys& ph, double acc[12]) {
+  const Dir<L> d = dir_of<L>(lk.dir);
+  const int64_t c = lk.cell;
+  const int64_t off = d.cx + d.cy * g.sy + d.cz * g.sz;
+  double h[L::Q], drho, uF[3];
+  moments_at<L, S>(A, g, c, ph.rho0, EQ, h, drho, uF);
+  double hin = 0;
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q)
+    if (q == d.oi) hin = h[q];
+  const double rho = ph.rho0 + drho;
+  const double rhoU = EQ ? ph.rho0 : rho;
+  const double xF = lk.x, yF = lk.y, zF = lk.z;
+  const double dl = lk.delta;
+  const double xB = xF - dl * d.cx, yB = yF - dl * d.cy;
+  double uB[3] = {P.V[0] - P.Om * (yB - P.X[1]), P.V[1] + P.Om * (xB - P.X[0]), L::D == 3 ? P.V[2] : 0.0};
+  const double wall = 6.0 * d.w * rhoU * (d.cx * uB[0] + d.cy * uB[1] + d.cz * uB[2]);
+  double hbc;
+  if (bc == 0) {
+    hbc = hin + wall;
+  } else {
+    double ubf[3], chi;
+    if (dl >= 0.5) {
+      const double f = 3.0 / (2.0 * dl);
+      for (int a = 0; a < 3; ++a) ubf[a] = uF[a] + f * (uB[a] - uF[a]);
+      chi = (2.0 * dl - 1.0) / (ph.tau + 0.5);
+    } else {
+      if (mask[c + off] == MASK_FLUID) {
+        double hg[L::Q], dg;
+        moments_at<L, S>(A, g, c + off, ph.rho0, EQ, hg, dg, ubf);
+      } else {
+        for (int a = 0; a < 3; ++a) ubf[a] = uF[a];
+      }
+      chi = (2.0 * dl - 1.0) / (ph.tau - 2.0);
+    }
+    const double cb_ubf = -(d.cx * ubf[0] + d.cy * ubf[1] + d.cz * ubf[2]);
+    const double cb_uF = -(d.cx * uF[0] + d.cy * uF[1] + d.cz * uF[2]);
+    const double uu = uF[0] * uF[0] + uF[1] * uF[1] + uF[2] * uF[2];
+    const double gdev = d.w * (drho + rhoU * (3.0 * cb_ubf + 4.5 * cb_uF * cb_uF - 1.5 * uu));
+    hbc = (1.0 - chi) * hin + chi * gdev + wall;
+  }
+  typename S::T* slot = A + d.i * g.S + c - off;
+  S::store_plain(slot, hbc);
+  const double wr = d.w * ph.rho0;
+  const double fbc = S::round_trip(hbc) + wr;
+  const double fin = hin + wr;
+  const double r[3] = {xF - P.X[0], yF - P.X[1], zF - P.X[2]};
+  const double s = fbc + fin;
+  const double m[3] = {-d.cx * s, -d.cy * s, -d.cz * s};
+  const double mc[3] = {-(d.cx - uB[0]) * fbc + (-d.cx - uB[0]) * fin,
+                        -(d.cy - uB[1]) * fbc + (-d.cy - uB[1]) * fin,
+                        -(d.cz - uB[2]) * fbc + (-d.cz - uB[2]) * fin};
+  acc[0] += m[0];
+  acc[1] += m[1];
+  acc[2] += m[2];
+  acc[3] += r[1] * m[2] - r[2] * m[1];
+  acc[4] += r[2] * m[0] - r[0] * m[2];
+  acc[5] += r[0] * m[1] - r[1] * m[0];
+  acc[6] += mc[0];
+  acc[7] += mc[1];
+  acc[8] += mc[2];
+  acc[9] += r[1] * mc[2] - r[2] * mc[1];
+  acc[10] += r[2] * mc[0] - r[0] * mc[2];
+  acc[11] += r[0] * mc[1] - r[1] * mc[0];
+}
+
+// Deterministic block sum of N doubles per thread: xor-shuffle tree inside
+// each 64-wide wavefront, then a fixed-order sum over wavefronts.
+template <int N, int NT>
+__device__ void block_sum(double v[N], double* out /* shared or global, N */, double* sm /* shared N*NT/64 */) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    double x = v[k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    if (lane == 0) sm[wave * N + k] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < N) {
+    double s = 0;
+    for (int w = 0; w < NT / 64; ++w) s += sm[w * N + threadIdx.x];
+    out[threadIdx.x] = s;
+  }
+  __syncthreads();
+}
+
+constexpr int LINK_BLOCK = 256;
+
+// Boundary rule + momentum exchange over a body's link list at step t. The
+// last block to finish sums the per-block partials in block order and writes
+// the step's record (static and comoving sums; node terms zero).
+template <class L, class S, int EQ>
+__global__ __launch_bounds__(LINK_BLOCK) void k_links(typename S::T* A, const Link* __restrict__ links, int n_host,
+                                                      const int* __restrict__ n_dev, const double* __restrict__ pose,
+                                                      int bc, const uint8_t* __restrict__ mask, Geom g, Phys ph,
+                                                      double* partials, unsigned* counter, double* rec) {
+  __shared__ double sm[12 * LINK_BLOCK / 64];
+  __shared__ double part[12];
+  __shared__ int last;
+  const int n = n_dev ? *n_dev : n_host;
+  const Pose P = *reinterpret_cast<const Pose*>(pose);
+  double acc[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int k = blockIdx.x * LINK_BLOCK + threadIdx.x; k < n; k += gridDim.x * LINK_BLOCK)
+    link_rule<L, S, EQ>(A, links[k], P, bc, mask, g, ph, acc);
+  block_sum<12, LINK_BLOCK>(acc, part, sm);
+  if (threadIdx.x < 12) partials[blockIdx.x * 12 + threadIdx.x] = part[threadIdx.x];
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = (atomicAdd(counter, 1u) == gridDim.x - 1);
+  __syncthreads();
+  if (last) {
+    __threadfence();
+    if (threadIdx.x < 12) {
+      double s = 0;
+      for (unsigned b = 0; b < gridDim.x; ++b) s += __builtin_nontemporal_load(partials + b * 12 + threadIdx.x);
+      const int k = threadIdx.x;
+      rec[k < 6 ? k : k + 6] = s;  // static -> 0..5, comoving -> 12..17
+    } else if (threadIdx.x < 18) {
+      rec[threadIdx.x - 6] = 0.0;  // node terms 6..11
+    } else if (threadIdx.x < 20) {
+      rec[threadIdx.x] = 0.0;      // counts 18, 19
+    }
+    if (threadIdx.x == 0) *counter = 0u;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// body placement and advance (one workgroup per body)
+
+constexpr int ADV_BLOCK = 1024;
+
+struct Region {
+  int lo[3], n[3];
+  int64_t total;
+  __device__ void at(int64_t k, int& x, int& y, int& z) const {
+    x = lo[0] + (int)(k % n[0]);
+    int64_t r = k / n[0];
+    y = lo[1] + (int)(r % n[1]);
+    z = lo[2] + (int)(r / n[1]);
+  }
+  __device__ bool contains(int x, int y, int z) const {
+    return x >= lo[0] && x < lo[0] + n[0] && y >= lo[1] && y < lo[1] + n[1] && z >= lo[2] && z < lo[2] + n[2];
+  }
+};
+
+__device__ inline int block_exclusive_scan(int v, int* sm /* ADV_BLOCK/64 + 1 */) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) sm[wave] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int s = 0;
+    for (int w = 0; w < ADV_BLOCK / 64; ++w) {
+      int t = sm[w];
+      sm[w] = s;
+      s += t;
+    }
+    sm[ADV_BLOCK / 64] = s;
+  }
+  __syncthreads();
+  return sm[wave] + x - v;
+}
+
+// mode 0: place the body at pose p0 (mark its nodes, build its links).
+// mode 1: advance from pose p0 (step t) to p1 (step t+1) after the bulk
+// update of step t wrote the state of t+1 into B: covered nodes A+ (fluid at
+// t, solid at t+1) give up their momentum, uncovered nodes A- are refilled
+// with the equilibrium at the mean density and velocity of their neighbours
+// that are fluid at t and t+1 (rho0 and the wall velocity if there are none);
+// rec_t receives sum_{A+} c f - sum_{A-} c f (and r x ..., r about X_c(t))
+// and the two counts; then the links of pose t+1 are built and the boundary
+// rule and momentum exchange of step t+1 run, into rec_t1.
+template <class L, class S, int EQ>
+__global__ __launch_bounds__(ADV_BLOCK) void k_body_advance(typename S::T* B, uint8_t* mask, uint8_t* mask_next,
+                                                            Link* links, int* n_links, int cap, const double* pose,
+                                                            BodyShape bs, int bc, int body, int mode, Geom g,
+                                                            Phys ph, double* rec_t, double* rec_t1, int* err) {
+  using T = typename S::T;
+  __shared__ double sm[20 * ADV_BLOCK / 64];
+  __shared__ double red[20];
+  __shared__ int scan_sm[ADV_BLOCK / 64 + 1];
+  const Pose P0 = reinterpret_cast<const Pose*>(pose)[0];
+  const Pose P1 = reinterpret_cast<const Pose*>(pose)[mode];
+  const uint8_t self = (uint8_t)(MASK_BODY0 + body);
+  Region R;
+  for (int a = 0; a < 3; ++a) {
+    int lo = (int)(P0.lo[a] < P1.lo[a] ? P0.lo[a] : P1.lo[a]);
+    int hi = (int)(P0.hi[a] > P1.hi[a] ? P0.hi[a] : P1.hi[a]);
+    R.lo[a] = lo;
+    R.n[a] = hi - lo + 1;
+  }
+  R.total = (int64_t)R.n[0] * R.n[1] * R.n[2];
+  const bool outer = bs.shape == SHAPE_OUTER_CIRCLE;
+  // imp: [0..2] F nodes, [3..5] T nodes, [6] n+, [7] n-
+  double imp[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+
+  // phase A: status at the new pose; momentum of covered nodes
+  for (int64_t k = threadIdx.x; k < R.total; k += ADV_BLOCK) {
+    int x, y, z;
+    R.at(k, x, y, z);
+    const int64_t c = g.idx(x, y, z);
+    const uint8_t old = mask[c];
+    const bool solid = shape_phi(bs, P1, (double)x, (double)y, (double)z) <= 0.0;
+    uint8_t nw = old;
+    if (old == MASK_FLUID || old == self) {
+      nw = solid ? self : MASK_FLUID;
+    } else if (solid && !outer) {
+      atomicOr(err, 2);
+    }
+    mask_next[c] = nw;
+    if (mode == 1 && old == MASK_FLUID && nw == self) {
+      double m[3] = {0, 0, 0};
+#pragma unroll
+      for (int q = 1; q < L::Q; ++q) {
+        const double v = (double)S::load(B + q * g.S + c);
+        m[0] += L::cx(q) * v;
+        m[1] += L::cy(q) * v;
+        m[2] += L::cz(q) * v;
+      }
+      const double r[3] = {x - P0.X[0], y - P0.X[1], z - P0.X[2]};
+      imp[0] += m[0];
+      imp[1] += m[1];
+      imp[2] += m[2];
+      imp[3] += r[1] * m[2] - r[2] * m[1];
+      imp[4] += r[2] * m[0] - r[0] * m[2];
+      imp[5] += r[0] * m[1] - r[1] * m[0];
+      imp[6] += 1.0;
+    }
+  }
+  __syncthreads();
+
+  // phase B: refill uncovered nodes; count links of the new pose (contiguous
+  // chunks per thread so that the list comes out in node order)
+  const int64_t chunk = (R.total + ADV_BLOCK - 1) / ADV_BLOCK;
+  const int64_t k0 = threadIdx.x * chunk;
+  const int64_t k1 = (k0 + chunk < R.total) ? k0 + chunk : R.total;
+  int my_links = 0;
+  for (int64_t k = k0; k < k1; ++k) {
+    int x, y, z;
+    R.at(k, x, y, z);
+    const int64_t c = g.idx(x, y, z);
+    const uint8_t nw = mask_next[c];
+    if (nw != MASK_FLUID) continue;
+    if (mode == 1 && mask[c] == self) {
+      double rs = 0, us[3] = {0, 0, 0};
+      int cnt = 0;
+#pragma unroll
+      for (int q = 1; q < L::Q; ++q) {
+        const int xn = x + L::cx(q), yn = y + L::cy(q), zn = z + L::cz(q);
+        const int64_t cn = g.idx(xn, yn, zn);
+        const uint8_t nn = R.contains(xn, yn, zn) ? mask_next[cn] : mask[cn];
+        if (mask[cn] != MASK_FLUID || nn != MASK_FLUID) continue;
+        double hn[L::Q], dn, un[3];
+        moments_at<L, S>(B, g, cn, ph.rho0, EQ, hn, dn, un);
+        rs += ph.rho0 + dn;
+        us[0] += un[0];
+        us[1] += un[1];
+        us[2] += un[2];
+        cnt++;
+      }
+      double rb, ub[3];
+      if (cnt > 0) {
+        rb = rs / cnt;
+        for (int a = 0; a < 3; ++a) ub[a] = us[a] / cnt;
+      } else {
+        rb = ph.rho0;
+        ub[0] = P1.V[0] - P1.Om * (y - P1.X[1]);
+        ub[1] = P1.V[1] + P1.Om * (x - P1.X[0]);
+        ub[2] = P1.V[2];
+      }
+      if (L::D == 2) ub[2] = 0.0;
+      const double drb = rb - ph.rho0;
+      const double rhoU = EQ ? ph.rho0 : rb;
+      const double usq = 1.5 * (ub[0] * ub[0] + ub[1] * ub[1] + ub[2] * ub[2]);
+      double m[3] = {0, 0, 0};
+#pragma unroll
+      for (int q = 0; q < L::Q; ++q) {
+        const double cu = L::cx(q) * ub[0] + L::cy(q) * ub[1] + L::cz(q) * ub[2];
+        const double heq = L::w(q) * (drb + rhoU * (3.0 * cu + 4.5 * cu * cu - usq));
+        S::store_plain(B + q * g.S + c, heq);
+        const double v = S::round_trip(heq);
+        m[0] += L::cx(q) * v;
+        m[1] += L::cy(q) * v;
+        m[2] += L::cz(q) * v;
+      }
+      const double r[3] = {x - P0.X[0], y - P0.X[1], z - P0.X[2]};
+      imp[0] -= m[0];
+      imp[1] -= m[1];
+      imp[2] -= m[2];
+      imp[3] -= r[1] * m[2] - r[2] * m[1];
+      imp[4] -= r[2] * m[0] - r[0] * m[2];
+      imp[5] -= r[0] * m[1] - r[1] * m[0];
+      imp[7] += 1.0;
+    }
+#pragma unroll
+    for (int q = 1; q < L::Q; ++q) {
+      const int xs = x - L::cx(q), ys = y - L::cy(q), zs = z - L::cz(q);
+      const int64_t cs = g.idx(xs, ys, zs);
+      const uint8_t ns = R.contains(xs, ys, zs) ? mask_next[cs] : mask[cs];
+      if (ns == self) my_links++;
+    }
+  }
+  int base = block_exclusive_scan(my_links, scan_sm);
+  const int total = scan_sm[ADV_BLOCK / 64];
+  for (int64_t k = k0; k < k1; ++k) {
+    int x, y, z;
+    R.at(k, x, y, z);
+    const int64_t c = g.idx(x, y, z);
+    if (mask_next[c] != MASK_FLUID) continue;
+#pragma unroll
+    for (int q = 1; q < L::Q; ++q) {
+      const int xs = x - L::cx(q), ys = y - L::cy(q), zs = z - L::cz(q);
+      const int64_t cs = g.idx(xs, ys, zs);
+      const uint8_t ns = R.contains(xs, ys, zs) ? mask_next[cs] : mask[cs];
+      if (ns != self) continue;
+      if (base < cap) {
+        Link lk;
+        lk.cell = (int32_t)c;
+        lk.x = (int16_t)x;
+        lk.y = (int16_t)y;
+        lk.z = (int16_t)z;
+        lk.dir = (int16_t)q;
+        lk.delta = bc ? link_delta(bs, P1, (double)x, (double)y, (double)z, L::cx(q), L::cy(q), L::cz(q)) : 0.5;
+        links[base] = lk;
+      }
+      base++;
+    }
+  }
+  __syncthreads();
+  // commit the new status
+  for (int64_t k = threadIdx.x; k < R.total; k += ADV_BLOCK) {
+    int x, y, z;
+    R.at(k, x, y, z);
+    const int64_t c = g.idx(x, y, z);
+    mask[c] = mask_next[c];
+  }
+  if (threadIdx.x == 0) {
+    *n_links = total < cap ? total : cap;
+    if (total > cap) atomicOr(err, 1);
+  }
+  __syncthreads();
+  if (mode == 0) return;
+
+  // phase C: boundary rule + momentum exchange of step t+1
+  const int nl = total < cap ? total : cap;
+  double acc[20];
+  for (int k = 0; k < 20; ++k) acc[k] = 0.0;
+  for (int k = threadIdx.x; k < nl; k += ADV_BLOCK) link_rule<L, S, EQ>(B, links[k], P1, bc, mask, g, ph, acc);
+  for (int k = 0; k < 8; ++k) acc[12 + k] = imp[k];
+  block_sum<20, ADV_BLOCK>(acc, red, sm);
+  if (threadIdx.x < 20) {
+    const int k = threadIdx.x;
+    const double v = red[k];
+    if (k < 6) rec_t1[k] = v;
+    else if (k < 12) rec_t1[k + 6] = v;
+    else if (k < 18) rec_t[k - 6] = v;   // node terms 6..11 of step t
+    else rec_t[k] = v;                   // counts 18, 19 of step t
+    if (k < 6) rec_t1[6 + k] = 0.0;
+    if (k < 2) rec_t1[18 + k] = 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+
+template <class F>
+static void with_types(int lat, int st, int eq, F&& f) {
+  auto by_eq = [&](auto Lt, auto St) {
+    if (eq) f(Lt, St, std::integral_constant<int, 1>{});
+    else f(Lt, St, std::integral_constant<int, 0>{});
+  };
+  auto by_st = [&](auto Lt) {
+    if (st == 0) by_eq(Lt, StoreF64{});
+    else if (st == 1) by_eq(Lt, StoreF32{});
+    else by_eq(Lt, StoreF16{});
+  };
+  if (lat == 0) by_st(D2Q9{});
+  else by_st(D3Q19{});
+}
+
+BulkShape bulk_shape(const Geom& g) {
+  BulkShape b;
+  b.nbx = (g.hi[0] - g.lo[0] + 1 + BULK_BLOCK - 1) / BULK_BLOCK;
+  b.nrows = g.hi[1] - g.lo[1] + 1;
+  b.nplanes = g.hi[2] - g.lo[2] + 1;
+  b.nblocks = b.nbx * b.nrows * b.nplanes;
+  return b;
+}
+
+hipError_t launch_stream_collide(int lat, int st, int eq, const void* A, void* B, const Geom& g, const Phys& ph,
+                                 hipStream_t s) {
+  BulkShape b = bulk_shape(g);
+  with_types(lat, st, eq, [&](auto Lt, auto St, auto E) {
+    using L = decltype(Lt);
+    using S = decltype(St);
+    constexpr int EQ = decltype(E)::value;
+    hipLaunchKernelGGL((k_stream_collide<L, S, EQ>), dim3(b.nblocks), dim3(BULK_BLOCK), 0, s,
+                       (const typename S::T*)A, (typename S::T*)B, g, ph, b.nbx, b.nrows, b.nblocks);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_init(int lat, int st, int eq, void* A, uint8_t* mask, const Geom& g, const Phys& ph,
+                       const double* rho, const double* u, hipStream_t s) {
+  BulkShape b = bulk_shape(g);
+  with_types(lat, st, eq, [&](auto Lt, auto St, auto E) {
+    using L = decltype(Lt);
+    using S = decltype(St);
+    constexpr int EQ = decltype(E)::value;
+    hipLaunchKernelGGL((k_init<L, S, EQ>), dim3(b.nbx, b.nrows, b.nplanes), dim3(BULK_BLOCK), 0, s,
+                       (typename S::T*)A, mask, g, ph, rho, u);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_links(int lat, int st, int eq, void* A, const Link* links, int n_host, const int* n_dev,
+                        int grid, const double* pose, int bc, const uint8_t* mask, const Geom& g, const Phys& ph,
+                        double* partials, unsigned* counter, double* rec, hipStream_t s) {
+  with_types(lat, st, eq, [&](auto Lt, auto St, auto E) {
+    using L = decltype(Lt);
+    using S = decltype(St);
+    constexpr int EQ = decltype(E)::value;
+    hipLaunchKernelGGL((k_links<L, S, EQ>), dim3(grid), dim3(LINK_BLOCK), 0, s, (typename S::T*)A, links, n_host,
+                       n_dev, pose, bc, mask, g, ph, partials, counter, rec);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_body_advance(int lat, int st, int eq, void* B, uint8_t* mask, uint8_t* mask_next, Link* links,
+                               int* n_links, int cap, const double* pose, const BodyShape& bs, int bc, int body,
+                               int mode, const Geom& g, const Phys& ph, double* rec_t, double* rec_t1, int* err,
+                               hipStream_t s) {
+  with_types(lat, st, eq, [&](auto Lt, auto St, auto E) {
+    using L = decltype(Lt);
+    using S = decltype(St);
+    constexpr int EQ = decltype(E)::value;
+    hipLaunchKernelGGL((k_body_advance<L, S, EQ>), dim3(1), dim3(ADV_BLOCK), 0, s, (typename S::T*)B, mask,
+                       mask_next, links, n_links, cap, pose, bs, bc, body, mode, g, ph, rec_t, rec_t1, err);
+  });
+  return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -1,0 +1,84 @@
+// Lattice and storage traits of the GPU path.
+//
+// D2Q9 and D3Q19 velocity sets with the numbering fixed by include/lbm.h.
+// The tables are constexpr functions so that, inside fully unrolled loops,
+// every c_i, w_i and opposite index folds to an immediate.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+struct D2Q9 {
+  static constexpr int D = 2;
+  static constexpr int Q = 9;
+  __host__ __device__ static constexpr int cx(int i) {
+    constexpr int t[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    return t[i];
+  }
+  __host__ __device__ static constexpr int cy(int i) {
+    constexpr int t[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    return t[i];
+  }
+  __host__ __device__ static constexpr int cz(int) { return 0; }
+  __host__ __device__ static constexpr int opp(int i) {
+    constexpr int t[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+    return t[i];
+  }
+  __host__ __device__ static constexpr double w(int i) {
+    return i == 0 ? 4.0 / 9.0 : (i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0);
+  }
+};
+
+struct D3Q19 {
+  static constexpr int D = 3;
+  static constexpr int Q = 19;
+  __host__ __device__ static constexpr int cx(int i) {
+    constexpr int t[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+    return t[i];
+  }
+  __host__ __device__ static constexpr int cy(int i) {
+    constexpr int t[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+    return t[i];
+  }
+  __host__ __device__ static constexpr int cz(int i) {
+    constexpr int t[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+    return t[i];
+  }
+  __host__ __device__ static constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+  __host__ __device__ static constexpr double w(int i) {
+    return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
+  }
+};
+
+// Storage of a population deviation h_i = f_i - w_i rho0 and the type the
+// bulk collision computes in.
+struct StoreF64 {
+  using T = double;
+  using C = double;
+  __device__ static C load(const T* p) { return *p; }
+  __device__ static void store(T* p, C v) { __builtin_nontemporal_store(v, p); }
+  __device__ static void store_plain(T* p, double v) { *p = v; }
+  __device__ static double round_trip(double v) { return v; }
+};
+
+struct StoreF32 {
+  using T = float;
+  using C = float;
+  __device__ static C load(const T* p) { return *p; }
+  __device__ static void store(T* p, C v) { __builtin_nontemporal_store(v, p); }
+  __device__ static void store_plain(T* p, double v) { *p = (float)v; }
+  __device__ static double round_trip(double v) { return (double)(float)v; }
+};
+
+// binary16 deviations, round-to-nearest-even on store, FP32 arithmetic
+struct StoreF16 {
+  using T = _Float16;
+  using C = float;
+  __device__ static C load(const T* p) { return (float)*p; }
+  __device__ static void store(T* p, C v) { *p = (_Float16)v; }
+  __device__ static void store_plain(T* p, double v) { *p = (_Float16)(float)v; }
+  __device__ static double round_trip(double v) { return (double)(float)(_Float16)(float)v; }
+};
+
+}  // namespace lbm

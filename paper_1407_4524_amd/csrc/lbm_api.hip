@@ -1,0 +1,687 @@
+// Host side of the C ABI declared in include/lbm.h: descriptor validation,
+// device layout and allocation, host-computed body poses, the per-step launch
+// sequence and the result queries.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "lbm.h"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+lbm_status fail(lbm_status code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess) return fail(LBM_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr double PI = 3.14159265358979323846;
+constexpr int POSE_LEN = 16;  // doubles per Pose record
+constexpr int LINK_GRID_MAX = 64;
+constexpr int64_t POSE_WINDOW = 8192;
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Body {
+  bool active = false;
+  lbm_body_desc desc{};
+  BodyShape shape{};
+  bool mask_moves = false;  // the solid set changes with the pose
+  std::vector<double> table;
+  Link* links = nullptr;
+  int* n_links = nullptr;
+  int cap = 0;
+  int n_host = 0;
+  double* pose_dev = nullptr;
+  double* pose_pinned = nullptr;
+  int64_t pose_base = 0, pose_cap = 0, pose_valid = 0;
+  bool bc_ready = false;
+};
+
+}  // namespace
+
+struct lbm_domain_s {
+  lbm_domain_desc desc{};
+  int lat = 0, st = 0, eq = 0, Q = 9, D = 2;
+  size_t elem = 8;
+  Geom g{};
+  Phys ph{};
+  hipStream_t stream = nullptr;
+  bool owns_pool = false;
+  char* pool = nullptr;
+  size_t pool_bytes = 0;
+  void* A = nullptr;
+  void* B = nullptr;
+  uint8_t* mask = nullptr;
+  uint8_t* mask_next = nullptr;
+  double* rec = nullptr;
+  int64_t rec_cap = 0;
+  int* err = nullptr;
+  double* partials = nullptr;  // [LBM_MAX_BODIES][LINK_GRID_MAX][12]
+  unsigned* counters = nullptr;
+  int64_t t = 0;
+  Body body[LBM_MAX_BODIES];
+  // kernel timing ring
+  bool timing = false;
+  hipEvent_t ev[2][64] = {};
+  int64_t timed = 0, folded = 0;
+  double timed_ms = 0.0;
+};
+
+namespace {
+
+struct Layout {
+  Geom g;
+  size_t pop_bytes, mask_bytes, rec_bytes, err_bytes, part_bytes, cnt_bytes, total;
+  int64_t rec_cap;
+};
+
+lbm_status check_desc(const lbm_domain_desc* d) {
+  if (!d) return fail(LBM_E_INVAL, "null descriptor");
+  if (d->lattice != LBM_D2Q9 && d->lattice != LBM_D3Q19) return fail(LBM_E_INVAL, "unknown lattice");
+  const int D = d->lattice == LBM_D2Q9 ? 2 : 3;
+  if (d->nx < 3 || d->ny < 3 || (D == 3 && d->nz < 3)) return fail(LBM_E_INVAL, "each axis needs >= 3 nodes");
+  if ((int64_t)d->nx > 32000 || d->ny > 32000 || (D == 3 && d->nz > 32000))
+    return fail(LBM_E_INVAL, "axis longer than 32000 nodes");
+  if (!(d->tau > 0.5)) return fail(LBM_E_INVAL, "tau must exceed 1/2");
+  if (!(d->rho0 > 0)) return fail(LBM_E_INVAL, "rho0 must be positive");
+  if (d->storage < LBM_F64 || d->storage > LBM_F16_SHIFTED) return fail(LBM_E_INVAL, "unknown storage");
+  if (d->eq_model != LBM_EQ_BGK && d->eq_model != LBM_EQ_HELUO) return fail(LBM_E_INVAL, "unknown eq_model");
+  for (int a = 0; a < D; ++a) {
+    int lo = d->face[2 * a], hi = d->face[2 * a + 1];
+    if (lo < 0 || lo > 4 || hi < 0 || hi > 4) return fail(LBM_E_INVAL, "unknown face type");
+    if ((lo == LBM_FACE_PERIODIC) != (hi == LBM_FACE_PERIODIC)) return fail(LBM_E_INVAL, "periodic faces come in pairs");
+    if (lo == LBM_FACE_OUTLET || lo == LBM_FACE_OUTLET_VELOCITY || hi == LBM_FACE_INLET)
+      return fail(LBM_E_INVAL, "inlet only on -x, outlets only on +x");
+    if (a > 0 && (lo == LBM_FACE_INLET || hi == LBM_FACE_OUTLET || hi == LBM_FACE_OUTLET_VELOCITY))
+      return fail(LBM_E_INVAL, "inlet/outlet faces only along x");
+  }
+  if (d->inlet_profile != LBM_PROFILE_UNIFORM && d->inlet_profile != LBM_PROFILE_PARABOLIC)
+    return fail(LBM_E_INVAL, "unknown inlet profile");
+  if (d->record_capacity < 0) return fail(LBM_E_INVAL, "negative record capacity");
+  return LBM_OK;
+}
+
+Layout make_layout(const lbm_domain_desc* d) {
+  Layout L{};
+  Geom& g = L.g;
+  const int D = d->lattice == LBM_D2Q9 ? 2 : 3;
+  const int Q = D == 2 ? 9 : 19;
+  const size_t elem = d->storage == LBM_F64 ? 8 : (d->storage == LBM_F32 ? 4 : 2);
+  g.nx = d->nx;
+  g.ny = d->ny;
+  g.nz = D == 3 ? d->nz : 1;
+  g.D = D;
+  for (int k = 0; k < 6; ++k) g.face[k] = d->face[k];
+  if (D == 2) g.face[4] = g.face[5] = LBM_FACE_PERIODIC;
+  const int64_t xoff = 128 / (int64_t)elem;  // node x = 0 on a 128-byte boundary
+  const int64_t px = (int64_t)align_up((size_t)(xoff + g.nx + 1), (size_t)xoff);
+  const int64_t rows = g.ny + 2;
+  const int64_t planes = D == 3 ? g.nz + 2 : 1;
+  g.sy = px;
+  g.sz = px * rows;
+  g.S = (int64_t)align_up((size_t)(g.sz * planes), 64);
+  g.base = xoff + g.sy + (D == 3 ? g.sz : 0);
+  int n[3] = {g.nx, g.ny, g.nz};
+  for (int a = 0; a < 3; ++a) {
+    if (a >= D) {
+      g.lo[a] = g.hi[a] = 0;
+      continue;
+    }
+    g.lo[a] = g.face[2 * a] == LBM_FACE_WALL ? 1 : 0;
+    g.hi[a] = g.face[2 * a + 1] == LBM_FACE_WALL ? n[a] - 2 : n[a] - 1;
+  }
+  L.rec_cap = d->record_capacity ? d->record_capacity : 65536;
+  L.pop_bytes = align_up((size_t)Q * g.S * elem, 256);
+  L.mask_bytes = align_up((size_t)g.S, 256);
+  L.rec_bytes = align_up((size_t)L.rec_cap * LBM_MAX_BODIES * LBM_REC_LEN * sizeof(double), 256);
+  L.err_bytes = 256;
+  L.part_bytes = align_up((size_t)LBM_MAX_BODIES * LINK_GRID_MAX * 12 * sizeof(double), 256);
+  L.cnt_bytes = 256;
+  L.total = 2 * L.pop_bytes + 2 * L.mask_bytes + L.rec_bytes + L.err_bytes + L.part_bytes + L.cnt_bytes;
+  return L;
+}
+
+// Pose of a body at integer step t, by the rules of include/lbm.h.
+Pose body_pose(const Body& b, const Geom& g, int64_t t) {
+#pragma clang fp contract(off)
+  Pose p{};
+  const lbm_body_desc& d = b.desc;
+  for (int a = 0; a < 3; ++a) p.X[a] = d.c0[a];
+  p.theta = d.theta0;
+  switch (d.motion) {
+    case LBM_MOTION_CONST_VEL:
+      for (int a = 0; a < 3; ++a) {
+        p.X[a] = d.c0[a] + d.vel[a] * (double)t;
+        p.V[a] = d.vel[a];
+      }
+      break;
+    case LBM_MOTION_ROTATE:
+      p.theta = d.theta0 + d.omega * (double)t;
+      p.Om = d.omega;
+      break;
+    case LBM_MOTION_OSCILLATE: {
+      double ph = (2.0 * PI) * (double)t / d.period;
+      double s = sin(ph), c = cos(ph);
+      for (int a = 0; a < 3; ++a) {
+        p.X[a] = d.c0[a] + d.amp[a] * s;
+        p.V[a] = d.amp[a] * ((2.0 * PI) / d.period) * c;
+      }
+      break;
+    }
+    case LBM_MOTION_TABLE: {
+      int64_t n = (int64_t)b.table.size() / 8;
+      int64_t k = t < n ? t : n - 1;
+      const double* r = b.table.data() + 8 * k;
+      for (int a = 0; a < 3; ++a) p.X[a] = r[a];
+      p.theta = r[3];
+      for (int a = 0; a < 3; ++a) p.V[a] = r[4 + a];
+      p.Om = r[7];
+      break;
+    }
+    default:
+      break;
+  }
+  if (g.D == 2) {
+    p.X[2] = 0.0;
+    p.V[2] = 0.0;
+  }
+  p.ct = cos(p.theta);
+  p.st = sin(p.theta);
+  // node box holding the body plus two layers (links and their neighbours)
+  if (d.shape == LBM_SHAPE_OUTER_CIRCLE) {
+    for (int a = 0; a < 3; ++a) {
+      p.lo[a] = g.lo[a];
+      p.hi[a] = g.hi[a];
+    }
+  } else {
+    double h[3];
+    if (d.shape == LBM_SHAPE_CIRCLE) {
+      h[0] = h[1] = h[2] = d.axes[0];
+    } else {
+      double a = d.axes[0], bb = d.axes[1];
+      h[0] = sqrt(a * a * p.ct * p.ct + bb * bb * p.st * p.st);
+      h[1] = sqrt(a * a * p.st * p.st + bb * bb * p.ct * p.ct);
+      h[2] = d.axes[2];
+    }
+    for (int a = 0; a < 3; ++a) {
+      if (a >= g.D) {
+        p.lo[a] = p.hi[a] = 0;
+        continue;
+      }
+      p.lo[a] = floor(p.X[a] - h[a]) - 2.0;
+      p.hi[a] = ceil(p.X[a] + h[a]) + 2.0;
+    }
+  }
+  return p;
+}
+
+bool pose_inside(const Pose& p, const Geom& g) {
+  for (int a = 0; a < g.D; ++a)
+    if (p.lo[a] < g.lo[a] || p.hi[a] > g.hi[a]) return false;
+  return true;
+}
+
+double* rec_slot(lbm_domain d, int64_t t, int b) {
+  return d->rec + ((t % d->rec_cap) * LBM_MAX_BODIES + b) * LBM_REC_LEN;
+}
+
+// make sure the device pose table of body b covers steps [t0, t1]
+lbm_status ensure_poses(lbm_domain d, Body& b, int64_t t0, int64_t t1) {
+  if (t0 >= b.pose_base && t1 < b.pose_base + b.pose_valid) return LBM_OK;
+  int64_t need = t1 - t0 + 1;
+  int64_t cap = std::max<int64_t>(need, POSE_WINDOW);
+  std::vector<Pose> poses((size_t)cap);
+  for (int64_t k = 0; k < cap; ++k) {
+    poses[k] = body_pose(b, d->g, t0 + k);
+    if (b.desc.shape != LBM_SHAPE_OUTER_CIRCLE && !pose_inside(poses[k], d->g)) {
+      if (k < need)
+        return fail(LBM_E_RANGE, "body leaves the interior (bounding box plus two nodes) at step " +
+                                     std::to_string(t0 + k));
+      cap = k;  // window ends before the body would leave
+      break;
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(d->stream));  // the staging buffer may still be in flight
+  if (cap > b.pose_cap) {
+    if (b.pose_dev) HIP_TRY(hipFree(b.pose_dev));
+    if (b.pose_pinned) HIP_TRY(hipHostFree(b.pose_pinned));
+    b.pose_dev = nullptr;
+    b.pose_pinned = nullptr;
+    HIP_TRY(hipMalloc(&b.pose_dev, cap * POSE_LEN * sizeof(double)));
+    HIP_TRY(hipHostMalloc(&b.pose_pinned, cap * POSE_LEN * sizeof(double), hipHostMallocDefault));
+    b.pose_cap = cap;
+  }
+  memcpy(b.pose_pinned, poses.data(), cap * sizeof(Pose));
+  HIP_TRY(hipMemcpyAsync(b.pose_dev, b.pose_pinned, cap * sizeof(Pose), hipMemcpyHostToDevice, d->stream));
+  b.pose_base = t0;
+  b.pose_valid = cap;
+  return LBM_OK;
+}
+
+const double* pose_at(const Body& b, int64_t t) { return b.pose_dev + (t - b.pose_base) * POSE_LEN; }
+
+lbm_status check_device_errors(lbm_domain d) {
+  int e[4] = {0, 0, 0, 0};
+  HIP_TRY(hipMemcpy(e, d->err, sizeof(e), hipMemcpyDeviceToHost));
+  if (e[0] & 1) return fail(LBM_E_NOMEM, "boundary-link list overflowed its capacity");
+  if (e[0] & 2) return fail(LBM_E_RANGE, "a body overlaps a wall layer or another body");
+  return LBM_OK;
+}
+
+// rest state everywhere (deviation 0), every node non-fluid until k_init
+// marks the active ones, then the equilibrium of the initial fields
+lbm_status init_state(lbm_domain d, const Layout& L, const lbm_domain_desc* desc) {
+  HIP_TRY(hipMemsetAsync(d->A, 0, 2 * L.pop_bytes, d->stream));
+  HIP_TRY(hipMemsetAsync(d->mask, MASK_WALL, 2 * L.mask_bytes, d->stream));
+  HIP_TRY(hipMemsetAsync(d->rec, 0, L.rec_bytes + L.err_bytes + L.part_bytes + L.cnt_bytes, d->stream));
+  const int64_t N = (int64_t)d->g.nx * d->g.ny * d->g.nz;
+  double* rho_dev = nullptr;
+  double* u_dev = nullptr;
+  hipError_t e = hipSuccess;
+  if (desc->init_rho && e == hipSuccess) {
+    e = hipMalloc(&rho_dev, N * sizeof(double));
+    if (e == hipSuccess) e = hipMemcpy(rho_dev, desc->init_rho, N * sizeof(double), hipMemcpyHostToDevice);
+  }
+  if (desc->init_u && e == hipSuccess) {
+    e = hipMalloc(&u_dev, 3 * N * sizeof(double));
+    if (e == hipSuccess) e = hipMemcpy(u_dev, desc->init_u, 3 * N * sizeof(double), hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess) e = launch_init(d->lat, d->st, d->eq, d->A, d->mask, d->g, d->ph, rho_dev, u_dev, d->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(d->stream);
+  if (rho_dev) (void)hipFree(rho_dev);
+  if (u_dev) (void)hipFree(u_dev);
+  if (e != hipSuccess) return fail(LBM_E_HIP, std::string("initial state: ") + hipGetErrorString(e));
+  return LBM_OK;
+}
+
+// fold the oldest event pairs of the timing ring into the running total
+lbm_status fold_timing(lbm_domain d, int64_t keep) {
+  while (d->folded < d->timed - keep) {
+    const int k = (int)(d->folded % 64);
+    HIP_TRY(hipEventSynchronize(d->ev[1][k]));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, d->ev[0][k], d->ev[1][k]));
+    d->timed_ms += ms;
+    d->folded++;
+  }
+  return LBM_OK;
+}
+
+lbm_status launch_bulk_timed(lbm_domain d) {
+  if (!d->timing) {
+    HIP_TRY(launch_stream_collide(d->lat, d->st, d->eq, d->A, d->B, d->g, d->ph, d->stream));
+    return LBM_OK;
+  }
+  lbm_status s = fold_timing(d, 63);
+  if (s != LBM_OK) return s;
+  const int k = (int)(d->timed % 64);
+  HIP_TRY(hipEventRecord(d->ev[0][k], d->stream));
+  HIP_TRY(launch_stream_collide(d->lat, d->st, d->eq, d->A, d->B, d->g, d->ph, d->stream));
+  HIP_TRY(hipEventRecord(d->ev[1][k], d->stream));
+  d->timed++;
+  return LBM_OK;
+}
+
+static_assert(sizeof(Pose) == POSE_LEN * sizeof(double), "pose record layout");
+
+}  // namespace
+
+extern "C" {
+
+const char* lbm_last_error(void) { return g_last_error.c_str(); }
+
+lbm_status lbm_footprint_bytes(const lbm_domain_desc* desc, size_t* bytes) {
+  lbm_status s = check_desc(desc);
+  if (s != LBM_OK) return s;
+  if (!bytes) return fail(LBM_E_INVAL, "null output");
+  *bytes = make_layout(desc).total;
+  return LBM_OK;
+}
+
+lbm_status lbm_create_domain(const lbm_domain_desc* desc, lbm_domain* out) {
+  lbm_status s = check_desc(desc);
+  if (s != LBM_OK) return s;
+  if (!out) return fail(LBM_E_INVAL, "null output");
+  Layout L = make_layout(desc);
+  lbm_domain d = new lbm_domain_s();
+  d->desc = *desc;
+  d->desc.init_rho = nullptr;
+  d->desc.init_u = nullptr;
+  d->lat = desc->lattice;
+  d->st = desc->storage;
+  d->eq = desc->eq_model;
+  d->D = L.g.D;
+  d->Q = d->D == 2 ? 9 : 19;
+  d->elem = desc->storage == LBM_F64 ? 8 : (desc->storage == LBM_F32 ? 4 : 2);
+  d->g = L.g;
+  d->ph.tau = desc->tau;
+  d->ph.omega = 1.0 / desc->tau;
+  d->ph.rho0 = desc->rho0;
+  d->ph.eq = desc->eq_model;
+  d->ph.inlet_profile = desc->inlet_profile;
+  d->ph.inlet_u = desc->inlet_u;
+  d->stream = (hipStream_t)desc->stream;
+  d->rec_cap = L.rec_cap;
+  if (desc->device_buffer) {
+    if (desc->device_buffer_bytes < L.total) {
+      delete d;
+      return fail(LBM_E_NOMEM, "device_buffer smaller than lbm_footprint_bytes");
+    }
+    d->pool = (char*)desc->device_buffer;
+    d->owns_pool = false;
+  } else {
+    if (hipMalloc(&d->pool, L.total) != hipSuccess) {
+      delete d;
+      return fail(LBM_E_NOMEM, "hipMalloc of " + std::to_string(L.total) + " bytes failed");
+    }
+    d->owns_pool = true;
+  }
+  d->pool_bytes = L.total;
+  char* p = d->pool;
+  d->A = p;
+  p += L.pop_bytes;
+  d->B = p;
+  p += L.pop_bytes;
+  d->mask = (uint8_t*)p;
+  p += L.mask_bytes;
+  d->mask_next = (uint8_t*)p;
+  p += L.mask_bytes;
+  d->rec = (double*)p;
+  p += L.rec_bytes;
+  d->err = (int*)p;
+  p += L.err_bytes;
+  d->partials = (double*)p;
+  p += L.part_bytes;
+  d->counters = (unsigned*)p;
+  p += L.cnt_bytes;
+  s = init_state(d, L, desc);
+  if (s != LBM_OK) {
+    std::string msg = g_last_error;
+    lbm_destroy_domain(d);
+    return fail(s, msg);
+  }
+  *out = d;
+  return LBM_OK;
+}
+
+lbm_status lbm_destroy_domain(lbm_domain d) {
+  if (!d) return fail(LBM_E_INVAL, "null domain");
+  hipError_t e = hipStreamSynchronize(d->stream);
+  for (auto& b : d->body) {
+    if (b.links) (void)hipFree(b.links);
+    if (b.n_links) (void)hipFree(b.n_links);
+    if (b.pose_dev) (void)hipFree(b.pose_dev);
+    if (b.pose_pinned) (void)hipHostFree(b.pose_pinned);
+  }
+  if (d->owns_pool) (void)hipFree(d->pool);
+  for (int k = 0; k < 64; ++k)
+    for (int j = 0; j < 2; ++j)
+      if (d->ev[j][k]) (void)hipEventDestroy(d->ev[j][k]);
+  delete d;
+  if (e != hipSuccess) return fail(LBM_E_HIP, hipGetErrorString(e));
+  return LBM_OK;
+}
+
+lbm_status lbm_set_body(lbm_domain d, int32_t id, const lbm_body_desc* bd) {
+  if (!d || !bd) return fail(LBM_E_INVAL, "null argument");
+  if (id < 0 || id >= LBM_MAX_BODIES) return fail(LBM_E_INVAL, "body id out of range");
+  Body& b = d->body[id];
+  if (b.active) return fail(LBM_E_STATE, "body id already in use");
+  if (bd->shape < 0 || bd->shape > 2) return fail(LBM_E_INVAL, "unknown shape");
+  if (bd->bc != LBM_BC_HALFWAY && bd->bc != LBM_BC_MLS) return fail(LBM_E_INVAL, "unknown boundary rule");
+  if (bd->me_mode < 0 || bd->me_mode > 2) return fail(LBM_E_INVAL, "unknown me_mode");
+  if (bd->motion < 0 || bd->motion > 4) return fail(LBM_E_INVAL, "unknown motion");
+  const int na = bd->shape == LBM_SHAPE_ELLIPSE ? d->D : 1;
+  for (int a = 0; a < na; ++a)
+    if (!(bd->axes[a] > 0)) return fail(LBM_E_INVAL, "axes must be positive");
+  if (bd->motion == LBM_MOTION_OSCILLATE && !(bd->period > 0)) return fail(LBM_E_INVAL, "period must be positive");
+  if (bd->motion == LBM_MOTION_TABLE && (!bd->pose_table || bd->pose_count <= 0))
+    return fail(LBM_E_INVAL, "TABLE motion needs rows");
+  if (bd->shape == LBM_SHAPE_OUTER_CIRCLE && bd->motion != LBM_MOTION_STATIC)
+    return fail(LBM_E_INVAL, "an outer circle must be static");
+  Body nb;
+  nb.desc = *bd;
+  nb.desc.pose_table = nullptr;
+  if (bd->motion == LBM_MOTION_TABLE) nb.table.assign(bd->pose_table, bd->pose_table + 8 * bd->pose_count);
+  nb.shape.shape = bd->shape;
+  nb.shape.D = d->D;
+  nb.shape.R = bd->axes[0];
+  nb.shape.ia2 = 1.0 / (bd->axes[0] * bd->axes[0]);
+  nb.shape.ib2 = bd->shape == LBM_SHAPE_ELLIPSE ? 1.0 / (bd->axes[1] * bd->axes[1]) : 0.0;
+  nb.shape.ic2 = (bd->shape == LBM_SHAPE_ELLIPSE && d->D == 3) ? 1.0 / (bd->axes[2] * bd->axes[2]) : 0.0;
+  const bool round = bd->shape != LBM_SHAPE_ELLIPSE;
+  nb.mask_moves = !(bd->motion == LBM_MOTION_STATIC || (round && bd->motion == LBM_MOTION_ROTATE));
+  // link capacity: (Q-1) links per node of a shell two nodes thick around the
+  // circumscribed circle/sphere, doubled
+  double rc = bd->axes[0];
+  if (bd->shape == LBM_SHAPE_ELLIPSE) rc = std::max(rc, std::max(bd->axes[1], d->D == 3 ? bd->axes[2] : 0.0));
+  double shell = d->D == 2 ? 2.0 * PI * (rc + 3.0) * 4.0 : 4.0 * PI * (rc + 3.0) * (rc + 3.0) * 4.0;
+  nb.cap = (int)std::min<double>(2.0 * (d->Q - 1) * shell + 1024.0, 2.0e9 / sizeof(Link));
+  b = std::move(nb);
+  HIP_TRY(hipMalloc(&b.links, (size_t)b.cap * sizeof(Link)));
+  HIP_TRY(hipMalloc(&b.n_links, sizeof(int)));
+  HIP_TRY(hipMemsetAsync(b.n_links, 0, sizeof(int), d->stream));
+  lbm_status s = ensure_poses(d, b, d->t, d->t + 1);
+  if (s != LBM_OK) {
+    (void)hipFree(b.links);
+    (void)hipFree(b.n_links);
+    b = Body();
+    return s;
+  }
+  HIP_TRY(launch_body_advance(d->lat, d->st, d->eq, d->A, d->mask, d->mask_next, b.links, b.n_links, b.cap,
+                              pose_at(b, d->t), b.shape, bd->bc, id, 0, d->g, d->ph, nullptr, nullptr, d->err,
+                              d->stream));
+  HIP_TRY(hipMemcpyAsync(&b.n_host, b.n_links, sizeof(int), hipMemcpyDeviceToHost, d->stream));
+  HIP_TRY(hipStreamSynchronize(d->stream));
+  b.active = true;
+  b.bc_ready = false;
+  return check_device_errors(d);
+}
+
+lbm_status lbm_step(lbm_domain d, int64_t nsteps) {
+  if (!d) return fail(LBM_E_INVAL, "null domain");
+  if (nsteps < 0) return fail(LBM_E_INVAL, "negative step count");
+  if (nsteps == 0) return LBM_OK;
+  for (auto& b : d->body)
+    if (b.active) {
+      lbm_status s = ensure_poses(d, b, d->t, d->t + nsteps);
+      if (s != LBM_OK) return s;
+    }
+  for (int64_t k = 0; k < nsteps; ++k) {
+    const int64_t t = d->t;
+    for (int id = 0; id < LBM_MAX_BODIES; ++id) {
+      Body& b = d->body[id];
+      if (!b.active || (b.mask_moves && b.bc_ready)) continue;
+      int grid = std::max(1, std::min(LINK_GRID_MAX, (b.n_host + 255) / 256));
+      HIP_TRY(launch_links(d->lat, d->st, d->eq, d->A, b.links, b.n_host, b.mask_moves ? b.n_links : nullptr, grid,
+                           pose_at(b, t), b.desc.bc, d->mask, d->g, d->ph, d->partials + id * LINK_GRID_MAX * 12,
+                           d->counters + id, rec_slot(d, t, id), d->stream));
+      if (b.mask_moves) b.bc_ready = true;
+    }
+    lbm_status sb = launch_bulk_timed(d);
+    if (sb != LBM_OK) return sb;
+    for (int id = 0; id < LBM_MAX_BODIES; ++id) {
+      Body& b = d->body[id];
+      if (!b.active || !b.mask_moves) continue;
+      HIP_TRY(launch_body_advance(d->lat, d->st, d->eq, d->B, d->mask, d->mask_next, b.links, b.n_links, b.cap,
+                                  pose_at(b, t), b.shape, b.desc.bc, id, 1, d->g, d->ph, rec_slot(d, t, id),
+                                  rec_slot(d, t + 1, id), d->err, d->stream));
+    }
+    std::swap(d->A, d->B);
+    d->t = t + 1;
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_synchronize(lbm_domain d) {
+  if (!d) return fail(LBM_E_INVAL, "null domain");
+  HIP_TRY(hipStreamSynchronize(d->stream));
+  return check_device_errors(d);
+}
+
+int64_t lbm_time(lbm_domain d) { return d ? d->t : -1; }
+
+lbm_status lbm_records(lbm_domain d, int32_t id, int64_t first, int64_t count, double* rec) {
+  if (!d || !rec) return fail(LBM_E_INVAL, "null argument");
+  if (id < 0 || id >= LBM_MAX_BODIES || !d->body[id].active) return fail(LBM_E_INVAL, "no such body");
+  if (count < 0 || first < 0 || first + count > d->t || first < d->t - d->rec_cap)
+    return fail(LBM_E_RANGE, "steps outside the record ring");
+  lbm_status s = lbm_synchronize(d);
+  if (s != LBM_OK) return s;
+  std::vector<double> buf;
+  int64_t k = 0;
+  while (k < count) {
+    int64_t slot = (first + k) % d->rec_cap;
+    int64_t run = std::min(count - k, d->rec_cap - slot);
+    buf.resize((size_t)run * LBM_MAX_BODIES * LBM_REC_LEN);
+    HIP_TRY(hipMemcpy(buf.data(), d->rec + slot * LBM_MAX_BODIES * LBM_REC_LEN, buf.size() * sizeof(double),
+                      hipMemcpyDeviceToHost));
+    for (int64_t j = 0; j < run; ++j)
+      memcpy(rec + (k + j) * LBM_REC_LEN, buf.data() + (j * LBM_MAX_BODIES + id) * LBM_REC_LEN,
+             LBM_REC_LEN * sizeof(double));
+    k += run;
+  }
+  for (int64_t j = 0; j < count * LBM_REC_LEN; ++j)
+    if (!isfinite(rec[j])) return fail(LBM_E_UNSTABLE, "non-finite force or torque");
+  return LBM_OK;
+}
+
+lbm_status lbm_force_torque(lbm_domain d, int32_t id, int64_t first, int64_t count, double* ft) {
+  if (!d || !ft) return fail(LBM_E_INVAL, "null argument");
+  std::vector<double> rec((size_t)std::max<int64_t>(count, 0) * LBM_REC_LEN);
+  lbm_status s = lbm_records(d, id, first, count, rec.data());
+  if (s != LBM_OK && s != LBM_E_UNSTABLE) return s;
+  const int mode = d->body[id].desc.me_mode;
+  for (int64_t k = 0; k < count; ++k) {
+    const double* r = rec.data() + k * LBM_REC_LEN;
+    for (int a = 0; a < 6; ++a) {
+      double v;
+      if (mode == LBM_ME_STATIC) v = r[LBM_REC_F_STATIC + a];
+      else if (mode == LBM_ME_LATTICE) v = r[LBM_REC_F_STATIC + a] + r[LBM_REC_F_NODES + a];
+      else v = r[LBM_REC_F_COMOVING + a];
+      ft[6 * k + a] = v;
+    }
+  }
+  return s;
+}
+
+lbm_status lbm_get_links(lbm_domain d, int32_t id, int64_t cap, int64_t* node, int32_t* dir, double* delta,
+                         int64_t* n) {
+  if (!d || !n) return fail(LBM_E_INVAL, "null argument");
+  if (id < 0 || id >= LBM_MAX_BODIES || !d->body[id].active) return fail(LBM_E_INVAL, "no such body");
+  lbm_status s = lbm_synchronize(d);
+  if (s != LBM_OK) return s;
+  Body& b = d->body[id];
+  int cnt = 0;
+  HIP_TRY(hipMemcpy(&cnt, b.n_links, sizeof(int), hipMemcpyDeviceToHost));
+  *n = cnt;
+  int64_t m = std::min<int64_t>(cap, cnt);
+  if (m <= 0) return LBM_OK;
+  std::vector<Link> L((size_t)m);
+  HIP_TRY(hipMemcpy(L.data(), b.links, m * sizeof(Link), hipMemcpyDeviceToHost));
+  for (int64_t k = 0; k < m; ++k) {
+    if (node) node[k] = L[k].x + (int64_t)d->g.nx * (L[k].y + (int64_t)d->g.ny * L[k].z);
+    if (dir) dir[k] = L[k].dir;
+    if (delta) delta[k] = L[k].delta;
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_get_types(lbm_domain d, int32_t* type) {
+  if (!d || !type) return fail(LBM_E_INVAL, "null argument");
+  lbm_status s = lbm_synchronize(d);
+  if (s != LBM_OK) return s;
+  std::vector<uint8_t> m((size_t)d->g.S);
+  HIP_TRY(hipMemcpy(m.data(), d->mask, m.size(), hipMemcpyDeviceToHost));
+  const Geom& g = d->g;
+  for (int z = 0; z < g.nz; ++z)
+    for (int y = 0; y < g.ny; ++y)
+      for (int x = 0; x < g.nx; ++x) type[x + (int64_t)g.nx * (y + (int64_t)g.ny * z)] = m[g.idx(x, y, z)];
+  return LBM_OK;
+}
+
+lbm_status lbm_get_fields(lbm_domain d, double* rho, double* u) {
+  if (!d || !rho || !u) return fail(LBM_E_INVAL, "null argument");
+  lbm_status s = lbm_synchronize(d);
+  if (s != LBM_OK) return s;
+  const Geom& g = d->g;
+  std::vector<uint8_t> m((size_t)g.S);
+  HIP_TRY(hipMemcpy(m.data(), d->mask, m.size(), hipMemcpyDeviceToHost));
+  std::vector<char> raw((size_t)d->Q * g.S * d->elem);
+  HIP_TRY(hipMemcpy(raw.data(), d->A, raw.size(), hipMemcpyDeviceToHost));
+  auto value = [&](int i, int64_t c) -> double {
+    int64_t k = i * g.S + c;
+    if (d->st == LBM_F64) return ((const double*)raw.data())[k];
+    if (d->st == LBM_F32) return ((const float*)raw.data())[k];
+    return (double)(float)((const _Float16*)raw.data())[k];
+  };
+  auto C = [&](int i, int a) -> int {
+    if (d->D == 2) {
+      const int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1}, cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+      return a == 0 ? cx[i] : (a == 1 ? cy[i] : 0);
+    }
+    return a == 0 ? D3Q19::cx(i) : (a == 1 ? D3Q19::cy(i) : D3Q19::cz(i));
+  };
+  bool finite = true;
+  for (int z = 0; z < g.nz; ++z)
+    for (int y = 0; y < g.ny; ++y)
+      for (int x = 0; x < g.nx; ++x) {
+        const int64_t n = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
+        const int64_t c = g.idx(x, y, z);
+        if (m[c] != MASK_FLUID) {
+          rho[n] = NAN;
+          u[3 * n] = u[3 * n + 1] = u[3 * n + 2] = NAN;
+          continue;
+        }
+        double dr = 0, j[3] = {0, 0, 0};
+        for (int i = 0; i < d->Q; ++i) {
+          double v = value(i, c);
+          dr += v;
+          for (int a = 0; a < 3; ++a) j[a] += C(i, a) * v;
+        }
+        const double r = d->ph.rho0 + dr;
+        const double den = d->eq ? d->ph.rho0 : r;
+        rho[n] = r;
+        for (int a = 0; a < 3; ++a) u[3 * n + a] = j[a] / den;
+        finite = finite && isfinite(r);
+      }
+  if (!finite) return fail(LBM_E_UNSTABLE, "non-finite density in the fluid");
+  return LBM_OK;
+}
+
+lbm_status lbm_timing_enable(lbm_domain d, int32_t enable) {
+  if (!d) return fail(LBM_E_INVAL, "null domain");
+  if (enable && !d->ev[0][0])
+    for (int k = 0; k < 64; ++k)
+      for (int j = 0; j < 2; ++j) HIP_TRY(hipEventCreate(&d->ev[j][k]));
+  HIP_TRY(hipStreamSynchronize(d->stream));
+  d->timing = enable != 0;
+  d->timed = d->folded = 0;
+  d->timed_ms = 0.0;
+  return LBM_OK;
+}
+
+lbm_status lbm_timing_read(lbm_domain d, double* total_ms, int64_t* launches) {
+  if (!d || !total_ms || !launches) return fail(LBM_E_INVAL, "null argument");
+  lbm_status s = fold_timing(d, 0);
+  if (s != LBM_OK) return s;
+  *total_ms = d->timed_ms;
+  *launches = d->timed;
+  return LBM_OK;
+}
+
+}  // extern "C"

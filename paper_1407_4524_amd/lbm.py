@@ -1,0 +1,265 @@
+"""ctypes binding of the C ABI in include/lbm.h (argument marshalling only).
+
+Every step of the lattice-Boltzmann update and the momentum-exchange sums
+runs in the HIP library ``liblbm.so``; this module only converts arguments.
+PyTorch, when it sees a GPU, provides the device memory (a caller-owned
+buffer sized by ``lbm_footprint_bytes``) and the current HIP stream.
+Importing this module on a machine without the built library raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbm.so")
+
+# enums of include/lbm.h
+LATTICE = {"D2Q9": 0, "D3Q19": 1}
+STORAGE = {"f64": 0, "f32": 1, "f16": 2, "f16_shifted": 2}
+EQ = {"bgk": 0, "heluo": 1}
+FACE = {"periodic": 0, "wall": 1, "inlet": 2, "outlet": 3, "outlet_velocity": 4}
+PROFILE = {"uniform": 0, "parabolic": 1}
+SHAPE = {"circle": 0, "sphere": 0, "ellipse": 1, "ellipsoid": 1, "outer_circle": 2}
+BC = {"halfway": 0, "mls": 1}
+ME = {"static": 0, "lattice": 1, "comoving": 2}
+MOTION = {"static": 0, "const_vel": 1, "rotate": 2, "oscillate": 3, "table": 4}
+STATUS = {0: "LBM_OK", -1: "LBM_E_INVAL", -2: "LBM_E_NOMEM", -3: "LBM_E_HIP", -4: "LBM_E_RANGE",
+          -5: "LBM_E_UNSTABLE", -6: "LBM_E_STATE"}
+REC_LEN = 20
+MAX_BODIES = 4
+
+EXPORTS = ["lbm_footprint_bytes", "lbm_create_domain", "lbm_destroy_domain", "lbm_set_body", "lbm_step",
+           "lbm_synchronize", "lbm_time", "lbm_force_torque", "lbm_records", "lbm_get_links",
+           "lbm_get_fields", "lbm_get_types", "lbm_timing_enable", "lbm_timing_read", "lbm_last_error"]
+
+
+class LbmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class DomainDesc(C.Structure):
+    _fields_ = [("lattice", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("tau", C.c_double), ("rho0", C.c_double), ("storage", C.c_int32), ("eq_model", C.c_int32),
+                ("face", C.c_int32 * 6), ("inlet_profile", C.c_int32), ("inlet_u", C.c_double),
+                ("init_rho", C.POINTER(C.c_double)), ("init_u", C.POINTER(C.c_double)),
+                ("stream", C.c_void_p), ("device_buffer", C.c_void_p), ("device_buffer_bytes", C.c_size_t),
+                ("record_capacity", C.c_int64)]
+
+
+class BodyDesc(C.Structure):
+    _fields_ = [("shape", C.c_int32), ("axes", C.c_double * 3), ("bc", C.c_int32), ("me_mode", C.c_int32),
+                ("motion", C.c_int32), ("c0", C.c_double * 3), ("theta0", C.c_double), ("vel", C.c_double * 3),
+                ("omega", C.c_double), ("amp", C.c_double * 3), ("period", C.c_double),
+                ("pose_table", C.POINTER(C.c_double)), ("pose_count", C.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it first (python -m paper_1407_4524_amd.build)")
+        L = C.CDLL(LIB_PATH)
+        L.lbm_footprint_bytes.argtypes = [C.POINTER(DomainDesc), C.POINTER(C.c_size_t)]
+        L.lbm_create_domain.argtypes = [C.POINTER(DomainDesc), C.POINTER(C.c_void_p)]
+        L.lbm_destroy_domain.argtypes = [C.c_void_p]
+        L.lbm_set_body.argtypes = [C.c_void_p, C.c_int32, C.POINTER(BodyDesc)]
+        L.lbm_step.argtypes = [C.c_void_p, C.c_int64]
+        L.lbm_synchronize.argtypes = [C.c_void_p]
+        L.lbm_time.argtypes = [C.c_void_p]
+        L.lbm_time.restype = C.c_int64
+        L.lbm_force_torque.argtypes = [C.c_void_p, C.c_int32, C.c_int64, C.c_int64, C.c_void_p]
+        L.lbm_records.argtypes = [C.c_void_p, C.c_int32, C.c_int64, C.c_int64, C.c_void_p]
+        L.lbm_get_links.argtypes = [C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.POINTER(C.c_int64)]
+        L.lbm_get_fields.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.lbm_get_types.argtypes = [C.c_void_p, C.c_void_p]
+        L.lbm_timing_enable.argtypes = [C.c_void_p, C.c_int32]
+        L.lbm_timing_read.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        L.lbm_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != 0:
+        raise LbmError(status, lib().lbm_last_error().decode())
+
+
+def _torch_cuda():
+    try:
+        import torch
+    except ImportError:
+        return None
+    return torch if torch.cuda.is_available() else None
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _enum(table, v):
+    return table[v] if isinstance(v, str) else int(v)
+
+
+class Domain:
+    """One simulation domain on the current GPU (see include/lbm.h)."""
+
+    def __init__(self, lattice="D2Q9", nx=64, ny=64, nz=1, tau=0.8, rho0=1.0, storage="f32", eq="bgk",
+                 faces=("periodic",) * 6, inlet_profile="uniform", inlet_u=0.0, init_rho=None, init_u=None,
+                 record_capacity=0, stream=None, torch_buffer=True):
+        d = DomainDesc()
+        d.lattice = _enum(LATTICE, lattice)
+        d.nx, d.ny, d.nz = nx, ny, nz if d.lattice == 1 else 1
+        d.tau, d.rho0 = tau, rho0
+        d.storage = _enum(STORAGE, storage)
+        d.eq_model = _enum(EQ, eq)
+        for k in range(6):
+            d.face[k] = _enum(FACE, faces[k])
+        d.inlet_profile = _enum(PROFILE, inlet_profile)
+        d.inlet_u = inlet_u
+        d.record_capacity = record_capacity
+        self.nx, self.ny, self.nz = nx, ny, (nz if d.lattice == 1 else 1)
+        self.N = self.nx * self.ny * self.nz
+        keep = []
+        if init_rho is not None:
+            r = np.ascontiguousarray(init_rho, dtype=np.float64).reshape(-1)
+            if r.size != self.N:
+                raise ValueError("init_rho size")
+            keep.append(r)
+            d.init_rho = _dptr(r)
+        if init_u is not None:
+            u = np.ascontiguousarray(init_u, dtype=np.float64).reshape(-1)
+            if u.size != 3 * self.N:
+                raise ValueError("init_u size")
+            keep.append(u)
+            d.init_u = _dptr(u)
+        torch = _torch_cuda()
+        self._buffer = None
+        if stream is not None:
+            d.stream = stream
+        elif torch is not None:
+            d.stream = torch.cuda.current_stream().cuda_stream
+        if torch is not None and torch_buffer:
+            nbytes = C.c_size_t(0)
+            _check(lib().lbm_footprint_bytes(C.byref(d), C.byref(nbytes)))
+            self._buffer = torch.empty(nbytes.value, dtype=torch.uint8, device="cuda")
+            d.device_buffer = self._buffer.data_ptr()
+            d.device_buffer_bytes = nbytes.value
+        self._h = C.c_void_p()
+        _check(lib().lbm_create_domain(C.byref(d), C.byref(self._h)))
+        self._bodies = {}
+
+    @classmethod
+    def from_spec(cls, w, init_rho=None, init_u=None, **kw):
+        """Build from a plain workload dictionary (lattice, nx, ny, nz, tau, rho0,
+        storage, eq, faces, inlet_profile, inlet_u, bodies)."""
+        faces = tuple(w["faces"])
+        dom = cls(lattice=w["lattice"], nx=w["nx"], ny=w["ny"], nz=w.get("nz", 1), tau=w["tau"],
+                  rho0=w.get("rho0", 1.0), storage=w.get("storage", "f32"), eq=w.get("eq", "bgk"),
+                  faces=faces, inlet_profile=w.get("inlet_profile", "uniform"), inlet_u=w.get("inlet_u", 0.0),
+                  init_rho=init_rho, init_u=init_u, **kw)
+        for k, b in enumerate(w.get("bodies", [])):
+            dom.set_body(k, **b)
+        return dom
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _check(lib().lbm_destroy_domain(self._h))
+            self._h = C.c_void_p()
+        self._buffer = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def footprint(self):
+        return None if self._buffer is None else self._buffer.numel()
+
+    def set_body(self, body_id, shape="circle", axes=(1.0,), bc="halfway", me="static", motion="static",
+                 c0=(0, 0, 0), theta0=0.0, vel=(0, 0, 0), omega=0.0, amp=(0, 0, 0), period=1.0, table=None):
+        b = BodyDesc()
+        b.shape = _enum(SHAPE, shape)
+        ax = list(axes) + [0.0] * (3 - len(axes))
+        if b.shape == 1 and len(axes) == 1:
+            ax = [axes[0]] * 3
+        for a in range(3):
+            b.axes[a] = ax[a]
+            b.c0[a] = c0[a] if a < len(c0) else 0.0
+            b.vel[a] = vel[a] if a < len(vel) else 0.0
+            b.amp[a] = amp[a] if a < len(amp) else 0.0
+        b.bc = _enum(BC, bc)
+        b.me_mode = _enum(ME, me)
+        b.motion = _enum(MOTION, motion)
+        b.theta0, b.omega, b.period = theta0, omega, period
+        if table is not None:
+            tab = np.ascontiguousarray(table, dtype=np.float64).reshape(-1, 8)
+            b.pose_table = _dptr(tab)
+            b.pose_count = tab.shape[0]
+        _check(lib().lbm_set_body(self._h, body_id, C.byref(b)))
+        self._bodies[body_id] = b
+
+    def step(self, n=1):
+        _check(lib().lbm_step(self._h, n))
+
+    def synchronize(self):
+        _check(lib().lbm_synchronize(self._h))
+
+    @property
+    def t(self):
+        return lib().lbm_time(self._h)
+
+    def force_torque(self, body_id=0, first=0, count=None):
+        if count is None:
+            count = self.t - first
+        out = np.zeros((count, 6))
+        _check(lib().lbm_force_torque(self._h, body_id, first, count, out.ctypes.data))
+        return out
+
+    def records(self, body_id=0, first=0, count=None):
+        if count is None:
+            count = self.t - first
+        out = np.zeros((count, REC_LEN))
+        _check(lib().lbm_records(self._h, body_id, first, count, out.ctypes.data))
+        return out
+
+    def links(self, body_id=0):
+        n = C.c_int64(0)
+        _check(lib().lbm_get_links(self._h, body_id, 0, None, None, None, C.byref(n)))
+        node = np.zeros(n.value, np.int64)
+        d = np.zeros(n.value, np.int32)
+        delta = np.zeros(n.value)
+        _check(lib().lbm_get_links(self._h, body_id, n.value, node.ctypes.data, d.ctypes.data,
+                                   delta.ctypes.data, C.byref(n)))
+        return node, d, delta
+
+    def fields(self):
+        rho = np.zeros(self.N)
+        u = np.zeros(3 * self.N)
+        _check(lib().lbm_get_fields(self._h, rho.ctypes.data, u.ctypes.data))
+        return rho, u.reshape(self.N, 3)
+
+    def timing_enable(self, on=True):
+        _check(lib().lbm_timing_enable(self._h, 1 if on else 0))
+
+    def timing_read(self):
+        """(summed stream-collide kernel time in ms, number of launches)"""
+        ms = C.c_double(0)
+        n = C.c_int64(0)
+        _check(lib().lbm_timing_read(self._h, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    def types(self):
+        t = np.zeros(self.N, np.int32)
+        _check(lib().lbm_get_types(self._h, t.ctypes.data))
+        return t

@@ -1,0 +1,56 @@
+"""CPU checks of the C-ABI library: it loads, exports every function that
+include/lbm.h declares, and the ctypes structures agree with the header's
+field lists. No compute call is made (no GPU here)."""
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", text)))
+
+
+def declared_struct_fields(name):
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct \{([^{}]*)\}\s*" + name + ";", text, re.S).group(1)
+    fields = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        names = decl.split(None, 1)[1] if not decl.startswith("const") else decl.split(None, 2)[2]
+        for n in names.split(","):
+            fields.append(re.sub(r"[\*\s]|\[.*\]", "", n))
+    return fields
+
+
+def test_library_exports_every_declared_function():
+    from paper_1407_4524_amd import lbm
+    L = lbm.lib()
+    names = declared_functions()
+    assert "lbm_step" in names and "lbm_force_torque" in names and len(names) >= 12
+    for n in names:
+        assert hasattr(L, n), f"{n} declared in include/lbm.h but not exported"
+    assert set(names) == set(lbm.EXPORTS)
+
+
+@pytest.mark.parametrize("cname,pyname", [("lbm_domain_desc", "DomainDesc"), ("lbm_body_desc", "BodyDesc")])
+def test_ctypes_structs_follow_header(cname, pyname):
+    from paper_1407_4524_amd import lbm
+    py = [f[0] for f in getattr(lbm, pyname)._fields_]
+    c = declared_struct_fields(cname)
+    assert c == py
+
+
+def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
+    from paper_1407_4524_amd import lbm
+    monkeypatch.setattr(lbm, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(lbm, "_lib", None)
+    with pytest.raises(ImportError):
+        lbm.lib()

@@ -139,36 +139,69 @@ __device__ __forceinline__ void collide(typename S::C* h, typename S::C rho0, ty
 
 constexpr int BULK_BLOCK = 256;
 
-template <class L, class S, int EQ>
-__global__ __launch_bounds__(BULK_BLOCK) void k_stream_collide(const typename S::T* __restrict__ A,
-                                                               typename S::T* __restrict__ B, Geom g, Phys ph,
-                                                               int nbx, int nrows, int nblocks) {
-  using C = typename S::C;
-  // XCD-aware mapping: hardware block k runs on XCD k % 8; give every XCD a
-  // contiguous run of logical blocks so that the cache lines shared by
-  // neighbouring blocks stay in one L2.
-  const int hw = blockIdx.x;
+// Logical block of hardware block hw: hardware block k runs on XCD k % 8, so
+// every XCD gets a contiguous run of logical blocks and the cache lines shared
+// by neighbouring blocks stay in one L2.
+__device__ inline int xcd_block(int hw, int nblocks) {
   const int q = nblocks >> 3, r = nblocks & 7;
   const int xcd = hw & 7, k = hw >> 3;
-  const int blk = xcd * q + (xcd < r ? xcd : r) + k;
+  return xcd * q + (xcd < r ? xcd : r) + k;
+}
+
+// One block updates BX*CPT consecutive nodes of one row; thread t takes
+// x = x0 + t + k*BX (k < CPT), so every load and store instruction of a
+// wavefront covers 64 consecutive nodes. All CPT*Q loads are issued before
+// any arithmetic.
+template <class L, class S, int EQ, int BX, int CPT, bool NT>
+__global__ __launch_bounds__(BX) void k_stream_collide(const typename S::T* __restrict__ A,
+                                                       typename S::T* __restrict__ B, Geom g, Phys ph, int nbx,
+                                                       int nrows, int nblocks, int remap) {
+  using C = typename S::C;
+  const int blk = remap ? xcd_block(blockIdx.x, nblocks) : blockIdx.x;
   const int bx = blk % nbx;
   const int row = blk / nbx;
   const int y = g.lo[1] + row % nrows;
   const int z = g.lo[2] + row / nrows;
-  const int x = g.lo[0] + bx * BULK_BLOCK + threadIdx.x;
-  if (x > g.hi[0]) return;
-  const int64_t c = g.idx(x, y, z);
-  C h[L::Q];
+  const int x0 = g.lo[0] + bx * (BX * CPT) + threadIdx.x;
+  if (x0 > g.hi[0]) return;
+  const int64_t c0 = g.idx(x0, y, z);
+  // Every load is unconditional (a node past the row end re-reads node x0)
+  // and lands in its own register before any conversion, so that all of them
+  // are in flight together; a guarded load would sit in its own basic block
+  // and be waited for at the block's end.
+  typename S::R raw[CPT][L::Q];
+  bool ok[CPT];
 #pragma unroll
-  for (int i = 0; i < L::Q; ++i)
-    h[i] = S::load(A + i * g.S + c - (L::cx(i) + L::cy(i) * g.sy + L::cz(i) * g.sz));
-  C rho;
-  collide<L, S, EQ>(h, (C)ph.rho0, (C)ph.omega, rho);
+  for (int k = 0; k < CPT; ++k) {
+    ok[k] = x0 + k * BX <= g.hi[0];
+    const int64_t ck = ok[k] ? c0 + k * BX : c0;
 #pragma unroll
-  for (int i = 0; i < L::Q; ++i) S::store(B + i * g.S + c, h[i]);
-  const bool near = x <= g.lo[0] || x >= g.hi[0] || y <= g.lo[1] || y >= g.hi[1] ||
-                    (L::D == 3 && (z <= g.lo[2] || z >= g.hi[2]));
-  if (near) write_faces<L, S>(B, g, ph, x, y, z, c, h, EQ ? (C)ph.rho0 : rho);
+    for (int i = 0; i < L::Q; ++i)
+      raw[k][i] = S::load_raw(A + i * g.S + ck - (L::cx(i) + L::cy(i) * g.sy + L::cz(i) * g.sz));
+  }
+  // keep the scheduler from sinking conversions between the loads
+  __builtin_amdgcn_sched_barrier(0);
+  C h[CPT][L::Q];
+#pragma unroll
+  for (int k = 0; k < CPT; ++k)
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) h[k][i] = S::from_raw(raw[k][i]);
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    if (!ok[k]) continue;
+    const int x = x0 + k * BX;
+    const int64_t c = c0 + k * BX;
+    C rho;
+    collide<L, S, EQ>(h[k], (C)ph.rho0, (C)ph.omega, rho);
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+      if (NT) S::store(B + i * g.S + c, h[k][i]);
+      else B[i * g.S + c] = (typename S::T)h[k][i];
+    }
+    const bool near = x <= g.lo[0] || x >= g.hi[0] || y <= g.lo[1] || y >= g.hi[1] ||
+                      (L::D == 3 && (z <= g.lo[2] || z >= g.hi[2]));
+    if (near) write_faces<L, S>(B, g, ph, x, y, z, c, h[k], EQ ? (C)ph.rho0 : rho);
+  }
 }
 
 // initial state: equilibrium deviations at (rho, u) per node, the face ghosts
@@ -392,11 +425,14 @@ constexpr int ADV_BLOCK = 1024;
 struct Region {
   int lo[3], n[3];
   int64_t total;
-  __device__ void at(int64_t k, int& x, int& y, int& z) const {
-    x = lo[0] + (int)(k % n[0]);
-    int64_t r = k / n[0];
-    y = lo[1] + (int)(r % n[1]);
-    z = lo[2] + (int)(r / n[1]);
+  __device__ void at(int64_t k64, int& x, int& y, int& z) const {
+    const unsigned k = (unsigned)k64;  // regions hold far fewer than 2^31 nodes
+    const unsigned n0 = (unsigned)n[0], n1 = (unsigned)n[1];
+    const unsigned r = k / n0;
+    x = lo[0] + (int)(k - r * n0);
+    const unsigned r2 = r / n1;
+    y = lo[1] + (int)(r - r2 * n1);
+    z = lo[2] + (int)r2;
   }
   __device__ bool contains(int x, int y, int z) const {
     return x >= lo[0] && x < lo[0] + n[0] && y >= lo[1] && y < lo[1] + n[1] && z >= lo[2] && z < lo[2] + n[2];
@@ -625,6 +661,219 @@ __global__ __launch_bounds__(ADV_BLOCK) void k_body_advance(typename S::T* B, ui
   }
 }
 
+// Same operation as k_body_advance with the old and new node status of the
+// region plus a one-node margin held in LDS (two bytes per node), so that
+// every neighbour lookup of the link search and of the refill stays on chip;
+// only the nodes whose status changes are written back to the global mask.
+// Used whenever that box fits the LDS budget.
+constexpr int ADV_LDS_CELLS = 32768;
+
+template <class L, class S, int EQ>
+__global__ __launch_bounds__(ADV_BLOCK) void k_body_advance_lds(typename S::T* B, uint8_t* mask, Link* links,
+                                                                int* n_links, int cap, const double* pose,
+                                                                BodyShape bs, int bc, int body, int mode, Geom g,
+                                                                Phys ph, double* rec_t, double* rec_t1, int* err) {
+  extern __shared__ uint8_t lds[];
+  __shared__ double sm[20 * ADV_BLOCK / 64];
+  __shared__ double red[20];
+  __shared__ int scan_sm[ADV_BLOCK / 64 + 1];
+  const Pose P0 = reinterpret_cast<const Pose*>(pose)[0];
+  const Pose P1 = reinterpret_cast<const Pose*>(pose)[mode];
+  const uint8_t self = (uint8_t)(MASK_BODY0 + body);
+  Region R, E;  // body region, and the region with a one-node margin
+  for (int a = 0; a < 3; ++a) {
+    int lo = (int)(P0.lo[a] < P1.lo[a] ? P0.lo[a] : P1.lo[a]);
+    int hi = (int)(P0.hi[a] > P1.hi[a] ? P0.hi[a] : P1.hi[a]);
+    R.lo[a] = lo;
+    R.n[a] = hi - lo + 1;
+    const int m = a < L::D ? 1 : 0;
+    E.lo[a] = lo - m;
+    E.n[a] = R.n[a] + 2 * m;
+  }
+  R.total = (int64_t)R.n[0] * R.n[1] * R.n[2];
+  E.total = (int64_t)E.n[0] * E.n[1] * E.n[2];
+  const int total = (int)E.total;
+  // lds[k] = status at t, lds[total + k] = status at t+1 of box node k
+#define ADV_STATUS(x, y, z, nw) \
+  lds[(nw) * total + ((x) - E.lo[0]) + E.n[0] * (((y) - E.lo[1]) + E.n[1] * ((z) - E.lo[2]))]
+  const bool outer = bs.shape == SHAPE_OUTER_CIRCLE;
+  double imp[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+
+  // phase A: status at the new pose, momentum of covered nodes, commit
+  // changes; the mask bytes of a thread's nodes are fetched in batches of 8
+  // so that their loads overlap
+  for (int k8 = 0; k8 < total; k8 += 8 * ADV_BLOCK) {
+    uint8_t olds[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = k8 + j * ADV_BLOCK + threadIdx.x;
+      int x, y, z;
+      E.at(k < total ? k : 0, x, y, z);
+      olds[j] = mask[g.idx(x, y, z)];
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+    const int k = k8 + j * ADV_BLOCK + threadIdx.x;
+    if (k >= total) break;
+    int x, y, z;
+    E.at(k, x, y, z);
+    const int64_t c = g.idx(x, y, z);
+    const uint8_t old = olds[j];
+    uint8_t nw = old;
+    if (R.contains(x, y, z)) {
+      const bool solid = shape_phi(bs, P1, (double)x, (double)y, (double)z) <= 0.0;
+      if (old == MASK_FLUID || old == self) nw = solid ? self : MASK_FLUID;
+      else if (solid && !outer) atomicOr(err, 2);
+    }
+    lds[k] = old;
+    lds[total + k] = nw;
+    if (nw != old) mask[c] = nw;
+    if (mode == 1 && old == MASK_FLUID && nw == self) {
+      double m[3] = {0, 0, 0};
+#pragma unroll
+      for (int q = 1; q < L::Q; ++q) {
+        const double v = (double)S::load(B + q * g.S + c);
+        m[0] += L::cx(q) * v;
+        m[1] += L::cy(q) * v;
+        m[2] += L::cz(q) * v;
+      }
+      const double r[3] = {x - P0.X[0], y - P0.X[1], z - P0.X[2]};
+      imp[0] += m[0];
+      imp[1] += m[1];
+      imp[2] += m[2];
+      imp[3] += r[1] * m[2] - r[2] * m[1];
+      imp[4] += r[2] * m[0] - r[0] * m[2];
+      imp[5] += r[0] * m[1] - r[1] * m[0];
+      imp[6] += 1.0;
+    }
+    }
+  }
+  __syncthreads();
+
+  // phase B: refill uncovered nodes and count the links of the new pose over
+  // contiguous chunks of the box (node order); margin nodes hold no links
+  const int chunk = (total + ADV_BLOCK - 1) / ADV_BLOCK;
+  const int k0 = threadIdx.x * chunk;
+  const int k1 = k0 + chunk < total ? k0 + chunk : total;
+  int my_links = 0;
+  for (int k = k0; k < k1; ++k) {
+    if (lds[total + k] != MASK_FLUID) continue;
+    int x, y, z;
+    E.at(k, x, y, z);
+    if (!R.contains(x, y, z)) continue;
+    if (mode == 1 && lds[k] == self) {
+      const int64_t c = g.idx(x, y, z);
+      double rs = 0, us[3] = {0, 0, 0};
+      int cnt = 0;
+#pragma unroll
+      for (int q = 1; q < L::Q; ++q) {
+        const int xn = x + L::cx(q), yn = y + L::cy(q), zn = z + L::cz(q);
+        if (ADV_STATUS(xn, yn, zn, 0) != MASK_FLUID || ADV_STATUS(xn, yn, zn, 1) != MASK_FLUID) continue;
+        double hn[L::Q], dn, un[3];
+        moments_at<L, S>(B, g, g.idx(xn, yn, zn), ph.rho0, EQ, hn, dn, un);
+        rs += ph.rho0 + dn;
+        us[0] += un[0];
+        us[1] += un[1];
+        us[2] += un[2];
+        cnt++;
+      }
+      double rb, ub[3];
+      if (cnt > 0) {
+        rb = rs / cnt;
+        for (int a = 0; a < 3; ++a) ub[a] = us[a] / cnt;
+      } else {
+        rb = ph.rho0;
+        ub[0] = P1.V[0] - P1.Om * (y - P1.X[1]);
+        ub[1] = P1.V[1] + P1.Om * (x - P1.X[0]);
+        ub[2] = P1.V[2];
+      }
+      if (L::D == 2) ub[2] = 0.0;
+      const double drb = rb - ph.rho0;
+      const double rhoU = EQ ? ph.rho0 : rb;
+      const double usq = 1.5 * (ub[0] * ub[0] + ub[1] * ub[1] + ub[2] * ub[2]);
+      double m[3] = {0, 0, 0};
+#pragma unroll
+      for (int q = 0; q < L::Q; ++q) {
+        const double cu = L::cx(q) * ub[0] + L::cy(q) * ub[1] + L::cz(q) * ub[2];
+        const double heq = L::w(q) * (drb + rhoU * (3.0 * cu + 4.5 * cu * cu - usq));
+        S::store_plain(B + q * g.S + c, heq);
+        const double v = S::round_trip(heq);
+        m[0] += L::cx(q) * v;
+        m[1] += L::cy(q) * v;
+        m[2] += L::cz(q) * v;
+      }
+      const double r[3] = {x - P0.X[0], y - P0.X[1], z - P0.X[2]};
+      imp[0] -= m[0];
+      imp[1] -= m[1];
+      imp[2] -= m[2];
+      imp[3] -= r[1] * m[2] - r[2] * m[1];
+      imp[4] -= r[2] * m[0] - r[0] * m[2];
+      imp[5] -= r[0] * m[1] - r[1] * m[0];
+      imp[7] += 1.0;
+    }
+#pragma unroll
+    for (int q = 1; q < L::Q; ++q)
+      if (ADV_STATUS(x - L::cx(q), y - L::cy(q), z - L::cz(q), 1) == self) my_links++;
+  }
+  int base = block_exclusive_scan(my_links, scan_sm);
+  const int nlinks = scan_sm[ADV_BLOCK / 64];
+  for (int k = k0; k < k1; ++k) {
+    if (lds[total + k] != MASK_FLUID) continue;
+    int x, y, z;
+    E.at(k, x, y, z);
+    if (!R.contains(x, y, z)) continue;
+#pragma unroll
+    for (int q = 1; q < L::Q; ++q) {
+      if (ADV_STATUS(x - L::cx(q), y - L::cy(q), z - L::cz(q), 1) != self) continue;
+      if (base < cap) {
+        Link lk;
+        lk.cell = (int32_t)g.idx(x, y, z);
+        lk.x = (int16_t)x;
+        lk.y = (int16_t)y;
+        lk.z = (int16_t)z;
+        lk.dir = (int16_t)q;
+        lk.delta = 0.5;
+        links[base] = lk;
+      }
+      base++;
+    }
+  }
+#undef ADV_STATUS
+  if (threadIdx.x == 0) {
+    *n_links = nlinks < cap ? nlinks : cap;
+    if (nlinks > cap) atomicOr(err, 1);
+  }
+  __syncthreads();
+
+  // phase C: Delta per link (FP64), then, when advancing, the boundary rule
+  // + momentum exchange of step t+1 -- one link per thread
+  const int nl = nlinks < cap ? nlinks : cap;
+  double acc[20];
+  for (int k = 0; k < 20; ++k) acc[k] = 0.0;
+  for (int k = threadIdx.x; k < nl; k += ADV_BLOCK) {
+    Link lk = links[k];
+    if (bc) {
+      const Dir<L> d = dir_of<L>(lk.dir);
+      lk.delta = link_delta(bs, P1, (double)lk.x, (double)lk.y, (double)lk.z, d.cx, d.cy, d.cz);
+      links[k].delta = lk.delta;
+    }
+    if (mode == 1) link_rule<L, S, EQ>(B, lk, P1, bc, mask, g, ph, acc);
+  }
+  if (mode == 0) return;
+  for (int k = 0; k < 8; ++k) acc[12 + k] = imp[k];
+  block_sum<20, ADV_BLOCK>(acc, red, sm);
+  if (threadIdx.x < 20) {
+    const int k = threadIdx.x;
+    const double v = red[k];
+    if (k < 6) rec_t1[k] = v;
+    else if (k < 12) rec_t1[k + 6] = v;
+    else if (k < 18) rec_t[k - 6] = v;
+    else rec_t[k] = v;
+    if (k < 6) rec_t1[6 + k] = 0.0;
+    if (k < 2) rec_t1[18 + k] = 0.0;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 
@@ -643,31 +892,66 @@ static void with_types(int lat, int st, int eq, F&& f) {
   else by_st(D3Q19{});
 }
 
-BulkShape bulk_shape(const Geom& g) {
+BulkShape bulk_shape(const Geom& g, int span) {
   BulkShape b;
-  b.nbx = (g.hi[0] - g.lo[0] + 1 + BULK_BLOCK - 1) / BULK_BLOCK;
+  b.nbx = (g.hi[0] - g.lo[0] + 1 + span - 1) / span;
   b.nrows = g.hi[1] - g.lo[1] + 1;
   b.nplanes = g.hi[2] - g.lo[2] + 1;
   b.nblocks = b.nbx * b.nrows * b.nplanes;
   return b;
 }
 
+// Launch configuration of the stream-collide kernel per (lattice, storage).
+// Measured on MI355X (plain stores beat non-temporal ones everywhere): while
+// both population buffers fit the 256 MB MALL, XCD-aware block order pays;
+// beyond it the hardware order is better, and large D2Q9 rows like two nodes
+// per thread.
+BulkConfig bulk_config(int lat, int st, size_t footprint) {
+  (void)st;
+  if (footprint <= (size_t)192 << 20) return BulkConfig{256, 1, 0, 1};
+  if (lat == 0) return BulkConfig{256, 2, 0, 0};
+  return BulkConfig{256, 1, 0, 0};
+}
+
+template <class L, class S, int EQ, int BX, int CPT, bool NT>
+static void launch_bulk_variant(const void* A, void* B, const Geom& g, const Phys& ph, int remap, hipStream_t s) {
+  BulkShape b = bulk_shape(g, BX * CPT);
+  hipLaunchKernelGGL((k_stream_collide<L, S, EQ, BX, CPT, NT>), dim3(b.nblocks), dim3(BX), 0, s,
+                     (const typename S::T*)A, (typename S::T*)B, g, ph, b.nbx, b.nrows, b.nblocks, remap);
+}
+
+template <class L, class S, int EQ>
+static void launch_bulk_cfg(const BulkConfig& c, const void* A, void* B, const Geom& g, const Phys& ph,
+                            hipStream_t s) {
+#define LBM_BULK_CASE(BX_, CPT_, NT_)                                                   \
+  if (c.block == BX_ && c.cells_per_thread == CPT_ && c.nontemporal == NT_) {           \
+    launch_bulk_variant<L, S, EQ, BX_, CPT_, (NT_ != 0)>(A, B, g, ph, c.remap, s);      \
+    return;                                                                             \
+  }
+  LBM_BULK_CASE(256, 1, 0)
+  LBM_BULK_CASE(256, 2, 0)
+  LBM_BULK_CASE(512, 1, 0)
+  LBM_BULK_CASE(128, 2, 0)
+  LBM_BULK_CASE(128, 4, 0)
+#undef LBM_BULK_CASE
+  launch_bulk_variant<L, S, EQ, 256, 1, false>(A, B, g, ph, c.remap, s);
+}
+
 hipError_t launch_stream_collide(int lat, int st, int eq, const void* A, void* B, const Geom& g, const Phys& ph,
-                                 hipStream_t s) {
-  BulkShape b = bulk_shape(g);
+                                 hipStream_t s, const BulkConfig* cfg) {
+  const BulkConfig c = cfg ? *cfg : BulkConfig{256, 1, 0, 1};
   with_types(lat, st, eq, [&](auto Lt, auto St, auto E) {
     using L = decltype(Lt);
     using S = decltype(St);
     constexpr int EQ = decltype(E)::value;
-    hipLaunchKernelGGL((k_stream_collide<L, S, EQ>), dim3(b.nblocks), dim3(BULK_BLOCK), 0, s,
-                       (const typename S::T*)A, (typename S::T*)B, g, ph, b.nbx, b.nrows, b.nblocks);
+    launch_bulk_cfg<L, S, EQ>(c, A, B, g, ph, s);
   });
   return hipGetLastError();
 }
 
 hipError_t launch_init(int lat, int st, int eq, void* A, uint8_t* mask, const Geom& g, const Phys& ph,
                        const double* rho, const double* u, hipStream_t s) {
-  BulkShape b = bulk_shape(g);
+  BulkShape b = bulk_shape(g, BULK_BLOCK);
   with_types(lat, st, eq, [&](auto Lt, auto St, auto E) {
     using L = decltype(Lt);
     using S = decltype(St);
@@ -694,13 +978,19 @@ hipError_t launch_links(int lat, int st, int eq, void* A, const Link* links, int
 hipError_t launch_body_advance(int lat, int st, int eq, void* B, uint8_t* mask, uint8_t* mask_next, Link* links,
                                int* n_links, int cap, const double* pose, const BodyShape& bs, int bc, int body,
                                int mode, const Geom& g, const Phys& ph, double* rec_t, double* rec_t1, int* err,
-                               hipStream_t s) {
+                               hipStream_t s, int64_t region_cells) {
   with_types(lat, st, eq, [&](auto Lt, auto St, auto E) {
     using L = decltype(Lt);
     using S = decltype(St);
     constexpr int EQ = decltype(E)::value;
-    hipLaunchKernelGGL((k_body_advance<L, S, EQ>), dim3(1), dim3(ADV_BLOCK), 0, s, (typename S::T*)B, mask,
-                       mask_next, links, n_links, cap, pose, bs, bc, body, mode, g, ph, rec_t, rec_t1, err);
+    if (region_cells > 0 && region_cells <= ADV_LDS_CELLS) {
+      const size_t lds = ((size_t)2 * region_cells + 15) / 16 * 16;
+      hipLaunchKernelGGL((k_body_advance_lds<L, S, EQ>), dim3(1), dim3(ADV_BLOCK), lds, s, (typename S::T*)B, mask,
+                         links, n_links, cap, pose, bs, bc, body, mode, g, ph, rec_t, rec_t1, err);
+    } else {
+      hipLaunchKernelGGL((k_body_advance<L, S, EQ>), dim3(1), dim3(ADV_BLOCK), 0, s, (typename S::T*)B, mask,
+                         mask_next, links, n_links, cap, pose, bs, bc, body, mode, g, ph, rec_t, rec_t1, err);
+    }
   });
   return hipGetLastError();
 }

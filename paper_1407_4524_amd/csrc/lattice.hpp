@@ -56,6 +56,9 @@ struct D3Q19 {
 struct StoreF64 {
   using T = double;
   using C = double;
+  using R = double;  // register form of a loaded element
+  __device__ static R load_raw(const T* p) { return *p; }
+  __device__ static C from_raw(R r) { return r; }
   __device__ static C load(const T* p) { return *p; }
   __device__ static void store(T* p, C v) { __builtin_nontemporal_store(v, p); }
   __device__ static void store_plain(T* p, double v) { *p = v; }
@@ -65,6 +68,9 @@ struct StoreF64 {
 struct StoreF32 {
   using T = float;
   using C = float;
+  using R = float;
+  __device__ static R load_raw(const T* p) { return *p; }
+  __device__ static C from_raw(R r) { return r; }
   __device__ static C load(const T* p) { return *p; }
   __device__ static void store(T* p, C v) { __builtin_nontemporal_store(v, p); }
   __device__ static void store_plain(T* p, double v) { *p = (float)v; }
@@ -75,6 +81,12 @@ struct StoreF32 {
 struct StoreF16 {
   using T = _Float16;
   using C = float;
+  // a loaded element is held zero-extended in a full 32-bit register, so
+  // that the loads of all populations can be in flight at once (two halves
+  // packed into one register would serialise them)
+  using R = uint32_t;
+  __device__ static R load_raw(const T* p) { return (uint32_t)*reinterpret_cast<const uint16_t*>(p); }
+  __device__ static C from_raw(R r) { return (float)__builtin_bit_cast(_Float16, (uint16_t)r); }
   __device__ static C load(const T* p) { return (float)*p; }
   __device__ static void store(T* p, C v) { *p = (_Float16)v; }
   __device__ static void store_plain(T* p, double v) { *p = (_Float16)(float)v; }

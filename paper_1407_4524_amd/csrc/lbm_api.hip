@@ -74,6 +74,7 @@ struct lbm_domain_s {
   unsigned* counters = nullptr;
   int64_t t = 0;
   Body body[LBM_MAX_BODIES];
+  BulkConfig bulk{};  // stream-collide launch shape
   // kernel timing ring
   bool timing = false;
   hipEvent_t ev[2][64] = {};
@@ -133,7 +134,7 @@ Layout make_layout(const lbm_domain_desc* d) {
   const int64_t planes = D == 3 ? g.nz + 2 : 1;
   g.sy = px;
   g.sz = px * rows;
-  g.S = (int64_t)align_up((size_t)(g.sz * planes), 64);
+  g.S = (int64_t)align_up((size_t)(g.sz * planes + px), 64);  // one spare row: V-wide loads may read past the last row
   g.base = xoff + g.sy + (D == 3 ? g.sz : 0);
   int n[3] = {g.nx, g.ny, g.nz};
   for (int a = 0; a < 3; ++a) {
@@ -274,6 +275,18 @@ lbm_status ensure_poses(lbm_domain d, Body& b, int64_t t0, int64_t t1) {
 
 const double* pose_at(const Body& b, int64_t t) { return b.pose_dev + (t - b.pose_base) * POSE_LEN; }
 
+// nodes of the box that covers the body region at steps t and t + mode,
+// with a one-node margin along each lattice axis (the LDS box of the body
+// kernel)
+int64_t region_cells(const Body& b, int D, int64_t t, int mode) {
+  const Pose* p0 = reinterpret_cast<const Pose*>(b.pose_pinned) + (t - b.pose_base);
+  const Pose* p1 = p0 + mode;
+  int64_t n = 1;
+  for (int a = 0; a < 3; ++a)
+    n *= (int64_t)(std::max(p0->hi[a], p1->hi[a]) - std::min(p0->lo[a], p1->lo[a]) + 1) + (a < D ? 2 : 0);
+  return n;
+}
+
 lbm_status check_device_errors(lbm_domain d) {
   int e[4] = {0, 0, 0, 0};
   HIP_TRY(hipMemcpy(e, d->err, sizeof(e), hipMemcpyDeviceToHost));
@@ -323,14 +336,14 @@ lbm_status fold_timing(lbm_domain d, int64_t keep) {
 
 lbm_status launch_bulk_timed(lbm_domain d) {
   if (!d->timing) {
-    HIP_TRY(launch_stream_collide(d->lat, d->st, d->eq, d->A, d->B, d->g, d->ph, d->stream));
+    HIP_TRY(launch_stream_collide(d->lat, d->st, d->eq, d->A, d->B, d->g, d->ph, d->stream, &d->bulk));
     return LBM_OK;
   }
   lbm_status s = fold_timing(d, 63);
   if (s != LBM_OK) return s;
   const int k = (int)(d->timed % 64);
   HIP_TRY(hipEventRecord(d->ev[0][k], d->stream));
-  HIP_TRY(launch_stream_collide(d->lat, d->st, d->eq, d->A, d->B, d->g, d->ph, d->stream));
+  HIP_TRY(launch_stream_collide(d->lat, d->st, d->eq, d->A, d->B, d->g, d->ph, d->stream, &d->bulk));
   HIP_TRY(hipEventRecord(d->ev[1][k], d->stream));
   d->timed++;
   return LBM_OK;
@@ -376,6 +389,7 @@ lbm_status lbm_create_domain(const lbm_domain_desc* desc, lbm_domain* out) {
   d->ph.inlet_u = desc->inlet_u;
   d->stream = (hipStream_t)desc->stream;
   d->rec_cap = L.rec_cap;
+  d->bulk = bulk_config(d->lat, d->st, 2 * L.pop_bytes);
   if (desc->device_buffer) {
     if (desc->device_buffer_bytes < L.total) {
       delete d;
@@ -484,7 +498,7 @@ lbm_status lbm_set_body(lbm_domain d, int32_t id, const lbm_body_desc* bd) {
   }
   HIP_TRY(launch_body_advance(d->lat, d->st, d->eq, d->A, d->mask, d->mask_next, b.links, b.n_links, b.cap,
                               pose_at(b, d->t), b.shape, bd->bc, id, 0, d->g, d->ph, nullptr, nullptr, d->err,
-                              d->stream));
+                              d->stream, region_cells(b, d->D, d->t, 0)));
   HIP_TRY(hipMemcpyAsync(&b.n_host, b.n_links, sizeof(int), hipMemcpyDeviceToHost, d->stream));
   HIP_TRY(hipStreamSynchronize(d->stream));
   b.active = true;
@@ -519,7 +533,7 @@ lbm_status lbm_step(lbm_domain d, int64_t nsteps) {
       if (!b.active || !b.mask_moves) continue;
       HIP_TRY(launch_body_advance(d->lat, d->st, d->eq, d->B, d->mask, d->mask_next, b.links, b.n_links, b.cap,
                                   pose_at(b, t), b.shape, b.desc.bc, id, 1, d->g, d->ph, rec_slot(d, t, id),
-                                  rec_slot(d, t + 1, id), d->err, d->stream));
+                                  rec_slot(d, t + 1, id), d->err, d->stream, region_cells(b, d->D, t, 1)));
     }
     std::swap(d->A, d->B);
     d->t = t + 1;

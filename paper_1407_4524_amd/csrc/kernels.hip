@@ -251,7 +251,7 @@ struct Dir {
 };
 
 template <class L>
-__device__ inline Dir<L> dir_of(int i) {
+__device__ __forceinline__ Dir<L> dir_of(int i) {
   Dir<L> d{0, 0, 0, 0, 0, 0.0};
 #pragma unroll
   for (int q = 1; q < L::Q; ++q)
@@ -260,7 +260,7 @@ __device__ inline Dir<L> dir_of(int i) {
 }
 
 template <class L, class S>
-__device__ inline void moments_at(const typename S::T* A, const Geom& g, int64_t c, double rho0, int eq,
+__device__ __forceinline__ void moments_at(const typename S::T* A, const Geom& g, int64_t c, double rho0, int eq,
                                   double h[L::Q], double& drho, double u[3]) {
   double jx = 0, jy = 0, jz = 0;
   drho = 0;
@@ -289,7 +289,7 @@ __device__ inline void moments_at(const typename S::T* A, const Geom& g, int64_t
 // outgoing direction (the sign that drives the fluid with the wall).
 // acc: [0..2] F static, [3..5] T static, [6..8] F comoving, [9..11] T comoving.
 template <class L, class S, int EQ>
-__device__ void link_rule(typename S::T* A, const Link& lk, const Pose& P, int bc, const uint8_t* mask,
+__device__ __forceinline__ void link_rule(typename S::T* A, const Link& lk, const Pose& P, int bc, const uint8_t* mask,
                           const Geom& g, const Phys& ph, double acc[12]) {
   const Dir<L> d = dir_of<L>(lk.dir);
   const int64_t c = lk.cell;
@@ -359,7 +359,7 @@ __device__ void link_rule(typename S::T* A, const Link& lk, const Pose& P, int b
 // Deterministic block sum of N doubles per thread: xor-shuffle tree inside
 // each 64-wide wavefront, then a fixed-order sum over wavefronts.
 template <int N, int NT>
-__device__ void block_sum(double v[N], double* out /* shared or global, N */, double* sm /* shared N*NT/64 */) {
+__device__ __forceinline__ void block_sum(double v[N], double* out /* shared or global, N */, double* sm /* shared N*NT/64 */) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < N; ++k) {
@@ -439,7 +439,8 @@ struct Region {
   }
 };
 
-__device__ inline int block_exclusive_scan(int v, int* sm /* ADV_BLOCK/64 + 1 */) {
+template <int NT = 1024>
+__device__ inline int block_exclusive_scan(int v, int* sm /* NT/64 + 1 */) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int x = v;
 #pragma unroll
@@ -451,12 +452,12 @@ __device__ inline int block_exclusive_scan(int v, int* sm /* ADV_BLOCK/64 + 1 */
   __syncthreads();
   if (threadIdx.x == 0) {
     int s = 0;
-    for (int w = 0; w < ADV_BLOCK / 64; ++w) {
+    for (int w = 0; w < NT / 64; ++w) {
       int t = sm[w];
       sm[w] = s;
       s += t;
     }
-    sm[ADV_BLOCK / 64] = s;
+    sm[NT / 64] = s;
   }
   __syncthreads();
   return sm[wave] + x - v;
@@ -661,12 +662,84 @@ __global__ __launch_bounds__(ADV_BLOCK) void k_body_advance(typename S::T* B, ui
   }
 }
 
+// Solid x-interval [a, b] of the row (y, z) at pose p (the body is convex in
+// x); false if the row misses the body. Rounding of a and b is absorbed by
+// the margin of the windows built from them; the status itself always comes
+// from shape_phi.
+__device__ inline bool row_chord(const BodyShape& b, const Pose& p, int y, int z, double& a, double& bb) {
+  const double dy = y - p.X[1], dz = b.D == 3 ? z - p.X[2] : 0.0;
+  if (b.shape == SHAPE_CIRCLE) {
+    const double q = b.R * b.R - dy * dy - dz * dz;
+    if (q < 0.0) return false;
+    const double h = sqrt(q);
+    a = p.X[0] - h;
+    bb = p.X[0] + h;
+    return true;
+  }
+  const double A = p.ct * p.ct * b.ia2 + p.st * p.st * b.ib2;
+  const double Bh = dy * p.ct * p.st * (b.ia2 - b.ib2);
+  const double C = dy * dy * (p.st * p.st * b.ia2 + p.ct * p.ct * b.ib2) + dz * dz * b.ic2 - 1.0;
+  const double disc = Bh * Bh - A * C;
+  if (disc < 0.0) return false;
+  const double h = sqrt(disc);
+  a = p.X[0] + (-Bh - h) / A;
+  bb = p.X[0] + (-Bh + h) / A;
+  return true;
+}
+
+// Node windows [w0,w1] and [w2,w3] (x, inclusive) of row (y,z) outside
+// which nothing can change between poses P0 and P1, nor hold a link at P1:
+// around both ends of the solid interval, over the row and its lattice
+// neighbour rows, widened by `m` nodes. Returns the number of windows.
+__device__ inline int row_windows(const BodyShape& b, const Pose& P0, const Pose& P1, int y, int z, int D, int m,
+                                  int xlo, int xhi, int w[4]) {
+  double amin = 1e300, amax = -1e300, bmin = 1e300, bmax = -1e300;
+  bool any = false, gap = false;
+  for (int dz = (D == 3 ? -1 : 0); dz <= (D == 3 ? 1 : 0); ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int k = 0; k < 2; ++k) {
+        double a, bb;
+        if (row_chord(b, k ? P1 : P0, y + dy, z + dz, a, bb)) {
+          any = true;
+          amin = fmin(amin, a);
+          amax = fmax(amax, a);
+          bmin = fmin(bmin, bb);
+          bmax = fmax(bmax, bb);
+        } else {
+          gap = true;
+        }
+      }
+  if (!any) return 0;
+  int n;
+  if (gap) {  // a cap row: one window over the whole hull
+    w[0] = (int)floor(amin) - m;
+    w[1] = (int)ceil(bmax) + m;
+    n = 1;
+  } else {
+    w[0] = (int)floor(amin) - m;
+    w[1] = (int)ceil(amax) + m;
+    w[2] = (int)floor(bmin) - m;
+    w[3] = (int)ceil(bmax) + m;
+    n = 2;
+    if (w[2] <= w[1] + 1) {
+      w[1] = w[3];
+      n = 1;
+    }
+  }
+  for (int k = 0; k < n; ++k) {
+    w[2 * k] = w[2 * k] < xlo ? xlo : w[2 * k];
+    w[2 * k + 1] = w[2 * k + 1] > xhi ? xhi : w[2 * k + 1];
+  }
+  return n;
+}
+
 // Same operation as k_body_advance with the old and new node status of the
 // region plus a one-node margin held in LDS (two bytes per node), so that
 // every neighbour lookup of the link search and of the refill stays on chip;
 // only the nodes whose status changes are written back to the global mask.
 // Used whenever that box fits the LDS budget.
-constexpr int ADV_LDS_CELLS = 32768;
+constexpr int ADV_LDS_CELLS = 20480;  // 2 bytes each + the window table stay within 64 KB of LDS
+constexpr int ADV_WIN_ROWS = 2048;
 
 template <class L, class S, int EQ>
 __global__ __launch_bounds__(ADV_BLOCK) void k_body_advance_lds(typename S::T* B, uint8_t* mask, Link* links,
@@ -675,6 +748,9 @@ __global__ __launch_bounds__(ADV_BLOCK) void k_body_advance_lds(typename S::T* B
                                                                 Phys ph, double* rec_t, double* rec_t1, int* err) {
   extern __shared__ uint8_t lds[];
   __shared__ double sm[20 * ADV_BLOCK / 64];
+  // per region row: x-windows (advance only) outside which nothing changes
+  __shared__ int16_t win[ADV_WIN_ROWS][4];
+  __shared__ int8_t nwin[ADV_WIN_ROWS];
   __shared__ double red[20];
   __shared__ int scan_sm[ADV_BLOCK / 64 + 1];
   const Pose P0 = reinterpret_cast<const Pose*>(pose)[0];
@@ -698,7 +774,27 @@ __global__ __launch_bounds__(ADV_BLOCK) void k_body_advance_lds(typename S::T* B
   lds[(nw) * total + ((x) - E.lo[0]) + E.n[0] * (((y) - E.lo[1]) + E.n[1] * ((z) - E.lo[2]))]
   const bool outer = bs.shape == SHAPE_OUTER_CIRCLE;
   double imp[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  // advancing a body whose rows fit the window table: a node outside its
+  // row's windows (around the ends of the solid interval at both poses,
+  // widened by two nodes) can neither change status nor hold a link
+  const int nrow = R.n[1] * R.n[2];
+  const bool windowed = mode == 1 && !outer && nrow <= ADV_WIN_ROWS;
+  if (windowed)
+    for (int r = threadIdx.x; r < nrow; r += ADV_BLOCK) {
+      int w[4] = {0, -1, 0, -1};
+      const int n = row_windows(bs, P0, P1, R.lo[1] + r % R.n[1], R.lo[2] + r / R.n[1], L::D, 2, R.lo[0],
+                                R.lo[0] + R.n[0] - 1, w);
+      nwin[r] = (int8_t)n;
+      for (int q = 0; q < 4; ++q) win[r][q] = (int16_t)w[q];
+    }
+  auto in_window = [&](int x, int y, int z) -> bool {
+    if (!windowed) return true;
+    const int r = (y - R.lo[1]) + R.n[1] * (z - R.lo[2]);
+    const int n = nwin[r];
+    return (n > 0 && x >= win[r][0] && x <= win[r][1]) || (n > 1 && x >= win[r][2] && x <= win[r][3]);
+  };
 
+  __syncthreads();
   // phase A: status at the new pose, momentum of covered nodes, commit
   // changes; the mask bytes of a thread's nodes are fetched in batches of 8
   // so that their loads overlap
@@ -720,7 +816,7 @@ __global__ __launch_bounds__(ADV_BLOCK) void k_body_advance_lds(typename S::T* B
     const int64_t c = g.idx(x, y, z);
     const uint8_t old = olds[j];
     uint8_t nw = old;
-    if (R.contains(x, y, z)) {
+    if (R.contains(x, y, z) && in_window(x, y, z)) {
       const bool solid = shape_phi(bs, P1, (double)x, (double)y, (double)z) <= 0.0;
       if (old == MASK_FLUID || old == self) nw = solid ? self : MASK_FLUID;
       else if (solid && !outer) atomicOr(err, 2);
@@ -760,7 +856,7 @@ __global__ __launch_bounds__(ADV_BLOCK) void k_body_advance_lds(typename S::T* B
     if (lds[total + k] != MASK_FLUID) continue;
     int x, y, z;
     E.at(k, x, y, z);
-    if (!R.contains(x, y, z)) continue;
+    if (!R.contains(x, y, z) || !in_window(x, y, z)) continue;
     if (mode == 1 && lds[k] == self) {
       const int64_t c = g.idx(x, y, z);
       double rs = 0, us[3] = {0, 0, 0};
@@ -821,7 +917,7 @@ __global__ __launch_bounds__(ADV_BLOCK) void k_body_advance_lds(typename S::T* B
     if (lds[total + k] != MASK_FLUID) continue;
     int x, y, z;
     E.at(k, x, y, z);
-    if (!R.contains(x, y, z)) continue;
+    if (!R.contains(x, y, z) || !in_window(x, y, z)) continue;
 #pragma unroll
     for (int q = 1; q < L::Q; ++q) {
       if (ADV_STATUS(x - L::cx(q), y - L::cy(q), z - L::cz(q), 1) != self) continue;
@@ -862,6 +958,331 @@ __global__ __launch_bounds__(ADV_BLOCK) void k_body_advance_lds(typename S::T* B
   if (mode == 0) return;
   for (int k = 0; k < 8; ++k) acc[12 + k] = imp[k];
   block_sum<20, ADV_BLOCK>(acc, red, sm);
+  if (threadIdx.x < 20) {
+    const int k = threadIdx.x;
+    const double v = red[k];
+    if (k < 6) rec_t1[k] = v;
+    else if (k < 12) rec_t1[k + 6] = v;
+    else if (k < 18) rec_t[k - 6] = v;
+    else rec_t[k] = v;
+    if (k < 6) rec_t1[6 + k] = 0.0;
+    if (k < 2) rec_t1[18 + k] = 0.0;
+  }
+}
+
+// Advance of a moving body (the operation of k_body_advance, mode 1) for a
+// region whose status box fits LDS: the per-row windows (around the ends of
+// the solid x-interval at both poses and in the neighbouring rows, widened
+// by two nodes) are gathered into one node list in node order, and every
+// per-node phase walks that list only -- a node outside it can neither change
+// status nor hold a link. One workgroup (1024 threads in 2D, 512 in 3D, so
+// that the per-link work is spread wide without register spills).
+constexpr int STEP_ROWS = 1024;   // region rows covered by the window table
+constexpr int STEP_LIST = 2048;   // window nodes
+constexpr int STEP_CELLS = 20480; // status box nodes (two bytes each)
+
+// Sum of a double over the 64 lanes of a wavefront without the LDS
+// crossbar: DPP row shifts give every lane 15, 31, 47, 63 its row's total,
+// then the four row totals are read out and added in a fixed order
+// (deterministic). Every lane returns the wavefront total.
+__device__ __forceinline__ double wave_sum(double v) {
+  int lo = __double2loint(v), hi = __double2hiint(v);
+#define WAVE_SUM_STEP(CTRL)                                                              \
+  {                                                                                      \
+    const int l2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xf, 0xf, false);            \
+    const int h2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xf, 0xf, false);            \
+    const double t = __hiloint2double(h2, l2) + __hiloint2double(hi, lo);                \
+    lo = __double2loint(t);                                                              \
+    hi = __double2hiint(t);                                                              \
+  }
+  WAVE_SUM_STEP(0x111)  // row_shr:1
+  WAVE_SUM_STEP(0x112)  // row_shr:2
+  WAVE_SUM_STEP(0x114)  // row_shr:4
+  WAVE_SUM_STEP(0x118)  // row_shr:8
+#undef WAVE_SUM_STEP
+  double tot = 0.0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    tot += __hiloint2double(__builtin_amdgcn_readlane(hi, 16 * r + 15), __builtin_amdgcn_readlane(lo, 16 * r + 15));
+  return tot;
+}
+
+template <int NT, int D>
+__device__ __forceinline__ void block_sum_ft(double v[20], double* out, double* sm) {
+  // in 2D only Fx, Fy, Tz of each group (and the two counts) can be non-zero
+  constexpr int K2[11] = {0, 1, 5, 6, 7, 11, 12, 13, 17, 18, 19};
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int N = D == 2 ? 11 : 20;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    const double x = wave_sum(v[D == 2 ? K2[j] : j]);
+    if (lane == 0) sm[wave * N + j] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < 20) out[threadIdx.x] = 0.0;
+  __syncthreads();
+  if (threadIdx.x < N) {
+    double t = 0;
+    for (int w = 0; w < NT / 64; ++w) t += sm[w * N + threadIdx.x];
+    out[D == 2 ? K2[threadIdx.x] : threadIdx.x] = t;
+  }
+  __syncthreads();
+}
+
+template <class L, class S, int EQ, int NT>
+__global__ __launch_bounds__(NT) void k_body_step(typename S::T* B, uint8_t* mask, Link* links, int* n_links,
+                                                         int cap, const double* pose, BodyShape bs, int bc, int body,
+                                                         Geom g, Phys ph, double* rec_t, double* rec_t1, int* err) {
+  extern __shared__ uint8_t lds[];  // status box: [0,total) at t, [total,2 total) at t+1
+  __shared__ double sm[20 * NT / 64];
+  __shared__ double red[20];
+  __shared__ int scan_sm[NT / 64 + 1];
+  __shared__ int16_t win[STEP_ROWS][4];
+  __shared__ int8_t nwin[STEP_ROWS];
+  __shared__ uint32_t list[STEP_LIST];  // (x - R.lo[0]) | row << 16
+  __shared__ int list_n;
+  const Pose P0 = reinterpret_cast<const Pose*>(pose)[0];
+  const Pose P1 = reinterpret_cast<const Pose*>(pose)[1];
+  const uint8_t self = (uint8_t)(MASK_BODY0 + body);
+  Region R, E;
+  for (int a = 0; a < 3; ++a) {
+    int lo = (int)(P0.lo[a] < P1.lo[a] ? P0.lo[a] : P1.lo[a]);
+    int hi = (int)(P0.hi[a] > P1.hi[a] ? P0.hi[a] : P1.hi[a]);
+    R.lo[a] = lo;
+    R.n[a] = hi - lo + 1;
+    const int m = a < L::D ? 1 : 0;
+    E.lo[a] = lo - m;
+    E.n[a] = R.n[a] + 2 * m;
+  }
+  const int total = E.n[0] * E.n[1] * E.n[2];
+  const int nrow = R.n[1] * R.n[2];
+#define STEP_STATUS(x, y, z, nw) \
+  lds[(nw) * total + ((x) - E.lo[0]) + E.n[0] * (((y) - E.lo[1]) + E.n[1] * ((z) - E.lo[2]))]
+
+  // status box at t, copied with 4-byte loads (every box row starts at the
+  // same offset modulo 4, since row and plane pitches are multiples of 16)
+  {
+    const int64_t c00 = g.idx(E.lo[0], E.lo[1], E.lo[2]);
+    const int off = (int)(c00 & 3);
+    const int wpr = (off + E.n[0] + 3) >> 2;  // words per box row
+    const int nrE = E.n[1] * E.n[2];
+    const int words = wpr * nrE;
+    for (int w0 = 0; w0 < words; w0 += 4 * NT) {
+      uint32_t v[4];
+      int64_t base[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        int w = w0 + j * NT + threadIdx.x;
+        w = w < words ? w : 0;
+        const int r = w / wpr, wi = w - r * wpr;
+        const int y = E.lo[1] + r % E.n[1], z = E.lo[2] + r / E.n[1];
+        base[j] = g.idx(E.lo[0], y, z) - off + 4 * wi;
+        v[j] = *reinterpret_cast<const uint32_t*>(mask + base[j]);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int w = w0 + j * NT + threadIdx.x;
+        if (w >= words) break;
+        const int r = w / wpr, wi = w - r * wpr;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int x = 4 * wi + b - off;
+          if (x >= 0 && x < E.n[0]) {
+            const uint8_t st = (uint8_t)(v[j] >> (8 * b));
+            lds[r * E.n[0] + x] = st;
+            lds[total + r * E.n[0] + x] = st;
+          }
+        }
+      }
+    }
+  }
+  // windows of every region row, in row order
+  const int rchunk = (nrow + NT - 1) / NT;
+  const int r0 = threadIdx.x * rchunk;
+  const int r1 = r0 + rchunk < nrow ? r0 + rchunk : nrow;
+  int my_cells = 0;
+  for (int r = r0; r < r1; ++r) {
+    int w[4] = {0, -1, 0, -1};
+    const int n = row_windows(bs, P0, P1, R.lo[1] + r % R.n[1], R.lo[2] + r / R.n[1], L::D, 2, R.lo[0],
+                              R.lo[0] + R.n[0] - 1, w);
+    nwin[r] = (int8_t)n;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) win[r][q] = (int16_t)w[q];
+    if (n > 0) my_cells += w[1] - w[0] + 1;
+    if (n > 1) my_cells += w[3] - w[2] + 1;
+  }
+  int lbase = block_exclusive_scan<NT>(my_cells, scan_sm);
+  if (threadIdx.x == 0) {
+    list_n = scan_sm[NT / 64];
+    if (list_n > STEP_LIST) atomicOr(err, 4);
+  }
+  for (int r = r0; r < r1; ++r) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      if (q >= nwin[r]) break;
+      for (int x = win[r][2 * q]; x <= win[r][2 * q + 1]; ++x) {
+        if (lbase < STEP_LIST) list[lbase] = (uint32_t)(x - R.lo[0]) | ((uint32_t)r << 16);
+        lbase++;
+      }
+    }
+  }
+  __syncthreads();
+  const int nlist = list_n < STEP_LIST ? list_n : STEP_LIST;
+  auto node = [&](int k, int& x, int& y, int& z) {
+    const uint32_t e = list[k];
+    const int r = (int)(e >> 16);
+    x = R.lo[0] + (int)(e & 0xffff);
+    y = R.lo[1] + r % R.n[1];
+    z = R.lo[2] + r / R.n[1];
+  };
+  double imp[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+
+  // phase A: new status of the listed nodes, momentum of covered ones
+  for (int k = threadIdx.x; k < nlist; k += NT) {
+    int x, y, z;
+    node(k, x, y, z);
+    const uint8_t old = STEP_STATUS(x, y, z, 0);
+    const bool solid = shape_phi(bs, P1, (double)x, (double)y, (double)z) <= 0.0;
+    if (old != MASK_FLUID && old != self) {
+      if (solid) atomicOr(err, 2);
+      continue;
+    }
+    const uint8_t nw = solid ? self : MASK_FLUID;
+    if (nw == old) continue;
+    STEP_STATUS(x, y, z, 1) = nw;
+    const int64_t c = g.idx(x, y, z);
+    mask[c] = nw;
+    if (old == MASK_FLUID) {  // covered
+      double m[3] = {0, 0, 0};
+#pragma unroll
+      for (int i = 1; i < L::Q; ++i) {
+        const double v = (double)S::load(B + i * g.S + c);
+        m[0] += L::cx(i) * v;
+        m[1] += L::cy(i) * v;
+        m[2] += L::cz(i) * v;
+      }
+      const double rr[3] = {x - P0.X[0], y - P0.X[1], z - P0.X[2]};
+      imp[0] += m[0];
+      imp[1] += m[1];
+      imp[2] += m[2];
+      imp[3] += rr[1] * m[2] - rr[2] * m[1];
+      imp[4] += rr[2] * m[0] - rr[0] * m[2];
+      imp[5] += rr[0] * m[1] - rr[1] * m[0];
+      imp[6] += 1.0;
+    }
+  }
+  __syncthreads();
+
+  // phase B: refill uncovered nodes and count links, over contiguous runs of
+  // the list (node order)
+  const int kchunk = (nlist + NT - 1) / NT;
+  const int k0 = threadIdx.x * kchunk;
+  const int k1 = k0 + kchunk < nlist ? k0 + kchunk : nlist;
+  int my_links = 0;
+  for (int k = k0; k < k1; ++k) {
+    int x, y, z;
+    node(k, x, y, z);
+    if (STEP_STATUS(x, y, z, 1) != MASK_FLUID) continue;
+    if (STEP_STATUS(x, y, z, 0) == self) {  // uncovered: refill
+      const int64_t c = g.idx(x, y, z);
+      double rs = 0, us[3] = {0, 0, 0};
+      int cnt = 0;
+#pragma unroll
+      for (int i = 1; i < L::Q; ++i) {
+        const int xn = x + L::cx(i), yn = y + L::cy(i), zn = z + L::cz(i);
+        if (STEP_STATUS(xn, yn, zn, 0) != MASK_FLUID || STEP_STATUS(xn, yn, zn, 1) != MASK_FLUID) continue;
+        double hn[L::Q], dn, un[3];
+        moments_at<L, S>(B, g, g.idx(xn, yn, zn), ph.rho0, EQ, hn, dn, un);
+        rs += ph.rho0 + dn;
+        us[0] += un[0];
+        us[1] += un[1];
+        us[2] += un[2];
+        cnt++;
+      }
+      double rb, ub[3];
+      if (cnt > 0) {
+        rb = rs / cnt;
+        for (int a = 0; a < 3; ++a) ub[a] = us[a] / cnt;
+      } else {
+        rb = ph.rho0;
+        ub[0] = P1.V[0] - P1.Om * (y - P1.X[1]);
+        ub[1] = P1.V[1] + P1.Om * (x - P1.X[0]);
+        ub[2] = P1.V[2];
+      }
+      if (L::D == 2) ub[2] = 0.0;
+      const double drb = rb - ph.rho0;
+      const double rhoU = EQ ? ph.rho0 : rb;
+      const double usq = 1.5 * (ub[0] * ub[0] + ub[1] * ub[1] + ub[2] * ub[2]);
+      double m[3] = {0, 0, 0};
+#pragma unroll
+      for (int i = 0; i < L::Q; ++i) {
+        const double cu = L::cx(i) * ub[0] + L::cy(i) * ub[1] + L::cz(i) * ub[2];
+        const double heq = L::w(i) * (drb + rhoU * (3.0 * cu + 4.5 * cu * cu - usq));
+        S::store_plain(B + i * g.S + c, heq);
+        const double v = S::round_trip(heq);
+        m[0] += L::cx(i) * v;
+        m[1] += L::cy(i) * v;
+        m[2] += L::cz(i) * v;
+      }
+      const double rr[3] = {x - P0.X[0], y - P0.X[1], z - P0.X[2]};
+      imp[0] -= m[0];
+      imp[1] -= m[1];
+      imp[2] -= m[2];
+      imp[3] -= rr[1] * m[2] - rr[2] * m[1];
+      imp[4] -= rr[2] * m[0] - rr[0] * m[2];
+      imp[5] -= rr[0] * m[1] - rr[1] * m[0];
+      imp[7] += 1.0;
+    }
+#pragma unroll
+    for (int i = 1; i < L::Q; ++i)
+      if (STEP_STATUS(x - L::cx(i), y - L::cy(i), z - L::cz(i), 1) == self) my_links++;
+  }
+  int base = block_exclusive_scan<NT>(my_links, scan_sm);
+  const int nlinks = scan_sm[NT / 64];
+  for (int k = k0; k < k1; ++k) {
+    int x, y, z;
+    node(k, x, y, z);
+    if (STEP_STATUS(x, y, z, 1) != MASK_FLUID) continue;
+#pragma unroll
+    for (int i = 1; i < L::Q; ++i) {
+      if (STEP_STATUS(x - L::cx(i), y - L::cy(i), z - L::cz(i), 1) != self) continue;
+      if (base < cap) {
+        Link lk;
+        lk.cell = (int32_t)g.idx(x, y, z);
+        lk.x = (int16_t)x;
+        lk.y = (int16_t)y;
+        lk.z = (int16_t)z;
+        lk.dir = (int16_t)i;
+        lk.delta = 0.5;
+        links[base] = lk;
+      }
+      base++;
+    }
+  }
+#undef STEP_STATUS
+  if (threadIdx.x == 0) {
+    *n_links = nlinks < cap ? nlinks : cap;
+    if (nlinks > cap) atomicOr(err, 1);
+  }
+  __syncthreads();
+
+  // phase C: Delta, boundary rule and momentum exchange of step t+1
+  const int nl = nlinks < cap ? nlinks : cap;
+  double acc[20];
+#pragma unroll
+  for (int k = 0; k < 20; ++k) acc[k] = 0.0;
+  for (int k = threadIdx.x; k < nl; k += NT) {
+    Link lk = links[k];
+    if (bc) {
+      const Dir<L> d = dir_of<L>(lk.dir);
+      lk.delta = link_delta(bs, P1, (double)lk.x, (double)lk.y, (double)lk.z, d.cx, d.cy, d.cz);
+      links[k].delta = lk.delta;
+    }
+    link_rule<L, S, EQ>(B, lk, P1, bc, mask, g, ph, acc);
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) acc[12 + k] = imp[k];
+  block_sum_ft<NT, L::D>(acc, red, sm);
   if (threadIdx.x < 20) {
     const int k = threadIdx.x;
     const double v = red[k];
@@ -978,12 +1399,18 @@ hipError_t launch_links(int lat, int st, int eq, void* A, const Link* links, int
 hipError_t launch_body_advance(int lat, int st, int eq, void* B, uint8_t* mask, uint8_t* mask_next, Link* links,
                                int* n_links, int cap, const double* pose, const BodyShape& bs, int bc, int body,
                                int mode, const Geom& g, const Phys& ph, double* rec_t, double* rec_t1, int* err,
-                               hipStream_t s, int64_t region_cells) {
+                               hipStream_t s, int64_t region_cells, int64_t region_rows) {
   with_types(lat, st, eq, [&](auto Lt, auto St, auto E) {
     using L = decltype(Lt);
     using S = decltype(St);
     constexpr int EQ = decltype(E)::value;
-    if (region_cells > 0 && region_cells <= ADV_LDS_CELLS) {
+    if (mode == 1 && bs.shape != SHAPE_OUTER_CIRCLE && region_cells > 0 && region_cells <= STEP_CELLS &&
+        region_rows <= STEP_ROWS) {
+      const size_t lds = ((size_t)2 * region_cells + 15) / 16 * 16;
+      constexpr int NT = L::D == 2 ? 1024 : 512;  // 2D fits the 128 VGPRs of 1024-thread blocks
+      hipLaunchKernelGGL((k_body_step<L, S, EQ, NT>), dim3(1), dim3(NT), lds, s, (typename S::T*)B, mask, links,
+                         n_links, cap, pose, bs, bc, body, g, ph, rec_t, rec_t1, err);
+    } else if (region_cells > 0 && region_cells <= ADV_LDS_CELLS) {
       const size_t lds = ((size_t)2 * region_cells + 15) / 16 * 16;
       hipLaunchKernelGGL((k_body_advance_lds<L, S, EQ>), dim3(1), dim3(ADV_BLOCK), lds, s, (typename S::T*)B, mask,
                          links, n_links, cap, pose, bs, bc, body, mode, g, ph, rec_t, rec_t1, err);

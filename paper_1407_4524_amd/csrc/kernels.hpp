@@ -30,6 +30,6 @@ hipError_t launch_links(int lat, int st, int eq, void* A, const Link* links, int
 hipError_t launch_body_advance(int lat, int st, int eq, void* B, uint8_t* mask, uint8_t* mask_next, Link* links,
                                int* n_links, int cap, const double* pose, const BodyShape& bs, int bc, int body,
                                int mode, const Geom& g, const Phys& ph, double* rec_t, double* rec_t1, int* err,
-                               hipStream_t s, int64_t region_cells);
+                               hipStream_t s, int64_t region_cells, int64_t region_rows);
 
 }  // namespace lbm

@@ -287,11 +287,22 @@ int64_t region_cells(const Body& b, int D, int64_t t, int mode) {
   return n;
 }
 
+// rows (y,z) of the same box without the margin
+int64_t region_rows(const Body& b, int64_t t, int mode) {
+  const Pose* p0 = reinterpret_cast<const Pose*>(b.pose_pinned) + (t - b.pose_base);
+  const Pose* p1 = p0 + mode;
+  int64_t n = 1;
+  for (int a = 1; a < 3; ++a)
+    n *= (int64_t)(std::max(p0->hi[a], p1->hi[a]) - std::min(p0->lo[a], p1->lo[a]) + 1);
+  return n;
+}
+
 lbm_status check_device_errors(lbm_domain d) {
   int e[4] = {0, 0, 0, 0};
   HIP_TRY(hipMemcpy(e, d->err, sizeof(e), hipMemcpyDeviceToHost));
   if (e[0] & 1) return fail(LBM_E_NOMEM, "boundary-link list overflowed its capacity");
   if (e[0] & 2) return fail(LBM_E_RANGE, "a body overlaps a wall layer or another body");
+  if (e[0] & 4) return fail(LBM_E_NOMEM, "the surface-node list of a moving body overflowed");
   return LBM_OK;
 }
 
@@ -498,7 +509,7 @@ lbm_status lbm_set_body(lbm_domain d, int32_t id, const lbm_body_desc* bd) {
   }
   HIP_TRY(launch_body_advance(d->lat, d->st, d->eq, d->A, d->mask, d->mask_next, b.links, b.n_links, b.cap,
                               pose_at(b, d->t), b.shape, bd->bc, id, 0, d->g, d->ph, nullptr, nullptr, d->err,
-                              d->stream, region_cells(b, d->D, d->t, 0)));
+                              d->stream, region_cells(b, d->D, d->t, 0), region_rows(b, d->t, 0)));
   HIP_TRY(hipMemcpyAsync(&b.n_host, b.n_links, sizeof(int), hipMemcpyDeviceToHost, d->stream));
   HIP_TRY(hipStreamSynchronize(d->stream));
   b.active = true;
@@ -533,7 +544,7 @@ lbm_status lbm_step(lbm_domain d, int64_t nsteps) {
       if (!b.active || !b.mask_moves) continue;
       HIP_TRY(launch_body_advance(d->lat, d->st, d->eq, d->B, d->mask, d->mask_next, b.links, b.n_links, b.cap,
                                   pose_at(b, t), b.shape, b.desc.bc, id, 1, d->g, d->ph, rec_slot(d, t, id),
-                                  rec_slot(d, t + 1, id), d->err, d->stream, region_cells(b, d->D, t, 1)));
+                                  rec_slot(d, t + 1, id), d->err, d->stream, region_cells(b, d->D, t, 1), region_rows(b, t, 1)));
     }
     std::swap(d->A, d->B);
     d->t = t + 1;

@@ -16,7 +16,6 @@ against 8 TB/s. `cpu_baseline` is the FP64 CPU oracle on a bounded sample of
 the same workload.
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -62,58 +61,91 @@ def bytes_per_node(w):
     return 2 * q * s
 
 
-def kernel_source_hash():
-    h = hashlib.sha256()
-    for f in ("kernels.hip", "lattice.hpp", "geom.hpp"):
-        with open(os.path.join(ROOT, "paper_1407_4524_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
-def measured_traffic(name):
-    """HBM bytes per stream-collide launch from the committed rocprofv3
+def measured_traffic(name, symbol):
+    """HBM bytes per launch of the kernel from the committed rocprofv3
     counter summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", f"stream_collide_{name}_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"{symbol}_{name}_traffic.json")
     try:
         with open(path) as fh:
             rec = json.load(fh)
     except OSError:
         return None
+    from paper_1407_4524_amd.hbm_traffic import kernel_source_hash
     if rec.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
     return rec.get("hbm_bytes_per_launch")
 
 
-def run_gpu(name, steps, warmup):
+KERNEL_SYMBOLS = {"stream_collide": "k_stream_collide", "body": "k_links/k_body_step",
+                  "near_box": "k_stream_collide (near box)"}
+
+
+TIMING_EVERY = 16  # every 16th launch of each kernel carries start/stop events
+
+
+def run_gpu(name, steps, warmup, plain_schedule=False):
     import torch
     from paper_1407_4524_amd import Domain
     w = workload(name)
-    dom = Domain.from_spec(w)
+    dom = Domain.from_spec(w, plain_schedule=plain_schedule)
     dom.step(warmup)
     dom.synchronize()
-    dom.timing_enable(True)
+    dom.timing_enable(TIMING_EVERY)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     dom.step(steps)
     dom.synchronize()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    kms, launches = dom.timing_read()
+    sec = t1 - t0
+    kernels = {}
+    for k in ("stream_collide", "near_box", "body"):
+        kms, timed, nodes = dom.timing_read(k)
+        if not timed:
+            continue
+        avg_s = kms / timed / 1e3
+        per_step = timed * TIMING_EVERY / steps  # launches per step (timed ones are every 16th)
+        entry = dict(symbol=KERNEL_SYMBOLS[k], launches_per_step=round(per_step, 3), avg_us=round(avg_s * 1e6, 3),
+                     share_of_step=round(avg_s * per_step / (sec / steps), 4), timed_launches=timed)
+        if nodes:
+            algo = nodes * bytes_per_node(w) / timed  # algorithmic bytes per launch
+            entry.update(algorithmic_bytes_per_launch=round(algo), achieved_gbs=round(algo / avg_s / 1e9, 1))
+        kernels[k] = entry
+    kd = kernels["stream_collide"]
     ft = dom.force_torque(0, dom.t - 1, 1)[0]
     cells = w["nx"] * w["ny"] * (w["nz"] if w["lattice"] == "D3Q19" else 1)
-    sec = t1 - t0
-    avg_s = kms / launches / 1e3
-    algo = active_nodes(w) * bytes_per_node(w)
-    achieved = algo / avg_s / 1e9
     out = dict(
         w=w, cells=cells, seconds=sec, ms_per_step=sec / steps * 1e3, mlups=cells * steps / sec / 1e6,
-        kernel_avg_us=avg_s * 1e6, roofline=dict(
-            bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-            frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(name),
-            algorithmic_bytes_per_launch=algo),
+        kernels=kernels, roofline=dict(
+            bound="hbm", achieved=kd["achieved_gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
+            frac=round(kd["achieved_gbs"] / HBM_PEAK_GBS, 4), traffic=measured_traffic(name, kd["symbol"]),
+            kernel=kd["symbol"], avg_us=kd["avg_us"],
+            algorithmic_bytes_per_launch=kd["algorithmic_bytes_per_launch"]),
         last_force_torque=[float(x) for x in ft])
     dom.close()
     return out
+
+
+def copy_ceiling(nbytes, reps=20):
+    """A plain device-to-device copy moving nbytes (half read, half written)
+    per launch, as torch issues it: the copy ceiling at the stream-collide
+    launch's footprint, and the reference kernel for scaling HBM counters."""
+    import torch
+    n = max(1, nbytes // 8)  # float32 elements per buffer
+    a = torch.rand(n, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    moved = 2 * n * 4
+    return dict(bytes_per_copy=moved, avg_us=round(sec * 1e6, 3), gbs=round(moved / sec / 1e9, 1))
 
 
 def cpu_baseline(name, budget_s):
@@ -146,6 +178,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--no-copy-ceiling", action="store_true",
+                    help="skip the plain-copy reference at the stream-collide footprint")
+    ap.add_argument("--plain-schedule", action="store_true",
+                    help="run link rule, stream-collide and body advance one after another (no overlap)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -154,7 +190,7 @@ def main():
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
 
-    main_run = run_gpu(args.workload, args.steps, args.warmup)
+    main_run = run_gpu(args.workload, args.steps, args.warmup, args.plain_schedule)
     w = main_run["w"]
     line = {
         "metric": METRIC,
@@ -172,16 +208,20 @@ def main():
         "config": {"workload": w["name"], "lattice": w["lattice"], "nx": w["nx"], "ny": w["ny"],
                    "nz": w["nz"], "tau": w["tau"], "storage": w["storage"],
                    "force_accumulation": "f64", "bodies": len(w["bodies"]),
-                   "me": w["bodies"][0]["me"] if w["bodies"] else None, "parallelism": "single-gpu"},
+                   "me": w["bodies"][0]["me"] if w["bodies"] else None, "parallelism": "single-gpu",
+                   "schedule": "plain" if args.plain_schedule else "overlapped"},
         "roofline": main_run["roofline"],
-        "kernel_avg_us": round(main_run["kernel_avg_us"], 3),
+        "kernels": main_run["kernels"],
     }
+    if not args.no_copy_ceiling:
+        line["copy_ceiling"] = copy_ceiling(main_run["roofline"]["algorithmic_bytes_per_launch"])
     if not args.no_secondary and args.workload == "channel_oscillating_f32":
         sec = {}
         for name in ("duct_sphere_f32", "duct_sphere_f16"):
-            r = run_gpu(name, 500, 50)
+            r = run_gpu(name, 500, 50, args.plain_schedule)
             sec[r["w"]["name"]] = dict(value=round(r["mlups"], 1), unit="MLUPS",
-                                       ms_per_step=round(r["ms_per_step"], 5), roofline=r["roofline"])
+                                       ms_per_step=round(r["ms_per_step"], 5), roofline=r["roofline"],
+                                       kernels=r["kernels"])
         line["secondary"] = sec
     if not args.no_cpu_baseline and rank == 0:
         line["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)

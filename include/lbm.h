@@ -61,7 +61,9 @@
  * every host pointer; the library copies what it keeps. The stream is
  * borrowed. One thread per domain at a time. lbm_step only enqueues work and
  * never synchronises; errors raised on the device surface at the next call
- * that reads results (lbm_force_torque, lbm_records, lbm_get_*).
+ * that reads results (lbm_force_torque, lbm_records, lbm_get_*). Work the
+ * caller enqueues on the stream after lbm_step sees the whole step (see
+ * plain_schedule for the second stream a domain may use).
  * No exception crosses this interface; every call returns lbm_status and
  * lbm_last_error() gives a thread-local message.
  */
@@ -127,6 +129,12 @@ typedef struct {
   void* device_buffer;      /* optional caller-owned device memory; NULL = library allocates */
   size_t device_buffer_bytes;
   int64_t record_capacity;  /* steps kept in each body's record ring; 0 = 65536 */
+  int32_t plain_schedule;   /* 1: each step runs the link rule, the stream-collide update and
+                               the body advance one after another on `stream`; 0: with a
+                               single moving body, the update of the nodes away from it
+                               runs on a second stream the domain owns (default priority),
+                               overlapping the body's advance, and every call leaves
+                               `stream` waiting for it. Results are bitwise the same */
 } lbm_domain_desc;
 
 typedef struct {
@@ -144,8 +152,10 @@ typedef struct {
 } lbm_body_desc;
 
 /* Device bytes a domain with this descriptor needs (for admission by HBM
-   footprint and for sizing device_buffer). Bodies add a small per-body amount
-   reported by lbm_body_footprint_bytes. */
+   footprint and for sizing device_buffer). Each body allocates its own link
+   list and pose window at lbm_set_body on top of this: 24 bytes per link of
+   capacity (about 16 (Q-1) pi (R+3) links in 2D, 16 (Q-1) pi (R+3)^2 in 3D)
+   plus 128 bytes per step of an 8192-step window. */
 lbm_status lbm_footprint_bytes(const lbm_domain_desc* desc, size_t* bytes);
 
 /* Creates the domain and initialises every node to the equilibrium at
@@ -197,12 +207,21 @@ lbm_status lbm_get_fields(lbm_domain dom, double* rho, double* u);
 /* Node types at the current step: 0 fluid, 1 wall layer, 2+b body b. */
 lbm_status lbm_get_types(lbm_domain dom, int32_t* type);
 
-/* Kernel timing, for measurement: while enabled, HIP events recorded on the
-   domain's stream around every launch of the stream-collide kernel time it;
-   lbm_timing_read waits for the stream and returns the summed duration in
-   milliseconds and the number of launches since the last enable. */
-lbm_status lbm_timing_enable(lbm_domain dom, int32_t enable);
-lbm_status lbm_timing_read(lbm_domain dom, double* total_ms, int64_t* launches);
+/* Kernel timing, for measurement. With every = n >= 1, every n-th launch
+   of each kind carries HIP events recorded at the kernel's own start and
+   end; every = 0 turns timing off. Kinds: LBM_KERNEL_STREAM_COLLIDE, the
+   stream-collide update of all nodes, or of all but the near box of a split
+   step; LBM_KERNEL_BODY, the boundary rule + momentum exchange and the
+   advance of a moving body; LBM_KERNEL_NEAR_BOX, the update of the near box
+   of a split step. Each call waits for the domain's work and restarts the
+   totals. lbm_timing_read waits for the events and returns, for one kind and
+   since the last enable, the summed duration of the timed launches in
+   milliseconds, their number and the node updates they made (zero for the
+   body kernels). */
+enum { LBM_KERNEL_STREAM_COLLIDE = 0, LBM_KERNEL_BODY = 1, LBM_KERNEL_NEAR_BOX = 2 };
+lbm_status lbm_timing_enable(lbm_domain dom, int32_t every);
+lbm_status lbm_timing_read(lbm_domain dom, int32_t kernel, double* total_ms, int64_t* launches,
+                           int64_t* nodes);
 
 /* Thread-local description of the last error. */
 const char* lbm_last_error(void);

@@ -18,6 +18,8 @@
 // structure-of-arrays layout; momentum exchange accumulates in FP64.
 #include "kernels.hpp"
 
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 #include <type_traits>
 
@@ -148,32 +150,34 @@ __device__ inline int xcd_block(int hw, int nblocks) {
   return xcd * q + (xcd < r ? xcd : r) + k;
 }
 
-// One block updates BX*CPT consecutive nodes of one row; thread t takes
-// x = x0 + t + k*BX (k < CPT), so every load and store instruction of a
-// wavefront covers 64 consecutive nodes. All CPT*Q loads are issued before
-// any arithmetic.
+// BX*CPT consecutive nodes of one row up to xlast, starting at x0; thread t
+// of a block takes x = x0 + k*BX (k < CPT), so every load and store
+// instruction of a wavefront covers 64 consecutive nodes. Nodes inside the
+// hole box (x0, x1, y0, y1, z0, z1; empty when x0 > x1) are left alone. All
+// CPT*Q loads are issued before any arithmetic.
 template <class L, class S, int EQ, int BX, int CPT, bool NT>
-__global__ __launch_bounds__(BX) void k_stream_collide(const typename S::T* __restrict__ A,
-                                                       typename S::T* __restrict__ B, Geom g, Phys ph, int nbx,
-                                                       int nrows, int nblocks, int remap) {
+__device__ __forceinline__ void stream_collide_span(const typename S::T* __restrict__ A,
+                                                    typename S::T* __restrict__ B, const Geom& g, const Phys& ph,
+                                                    int x0, int y, int z, int xlast, const int* hole) {
   using C = typename S::C;
-  const int blk = remap ? xcd_block(blockIdx.x, nblocks) : blockIdx.x;
-  const int bx = blk % nbx;
-  const int row = blk / nbx;
-  const int y = g.lo[1] + row % nrows;
-  const int z = g.lo[2] + row / nrows;
-  const int x0 = g.lo[0] + bx * (BX * CPT) + threadIdx.x;
-  if (x0 > g.hi[0]) return;
+  const bool hole_row = y >= hole[2] && y <= hole[3] && z >= hole[4] && z <= hole[5];
+  bool ok[CPT];
+  bool any = false;
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    const int x = x0 + k * BX;
+    ok[k] = x <= xlast && !(hole_row && x >= hole[0] && x <= hole[1]);
+    any = any || ok[k];
+  }
+  if (!any) return;
   const int64_t c0 = g.idx(x0, y, z);
-  // Every load is unconditional (a node past the row end re-reads node x0)
+  // Every load is unconditional (a node that is not updated re-reads node x0)
   // and lands in its own register before any conversion, so that all of them
   // are in flight together; a guarded load would sit in its own basic block
   // and be waited for at the block's end.
   typename S::R raw[CPT][L::Q];
-  bool ok[CPT];
 #pragma unroll
   for (int k = 0; k < CPT; ++k) {
-    ok[k] = x0 + k * BX <= g.hi[0];
     const int64_t ck = ok[k] ? c0 + k * BX : c0;
 #pragma unroll
     for (int i = 0; i < L::Q; ++i)
@@ -202,6 +206,24 @@ __global__ __launch_bounds__(BX) void k_stream_collide(const typename S::T* __re
                       (L::D == 3 && (z <= g.lo[2] || z >= g.hi[2]));
     if (near) write_faces<L, S>(B, g, ph, x, y, z, c, h[k], EQ ? (C)ph.rho0 : rho);
   }
+}
+
+// tile k of a sweep: the span of BX*CPT nodes at which thread 0 starts
+__device__ __forceinline__ void sweep_tile(const Sweep& sw, int k, int span, int& x, int& y, int& z) {
+  const int bx = k % sw.nbx, r = k / sw.nbx;
+  x = sw.x0 + bx * span;
+  y = sw.y0 + r % sw.ny;
+  z = sw.z0 + r / sw.ny;
+}
+
+// one block per tile of the sweep
+template <class L, class S, int EQ, int BX, int CPT, bool NT>
+__global__ __launch_bounds__(BX) void k_stream_collide(const typename S::T* __restrict__ A,
+                                                       typename S::T* __restrict__ B, Geom g, Phys ph, Sweep sw) {
+  const int blk = sw.remap ? xcd_block(blockIdx.x, sw.ntiles) : blockIdx.x;
+  int x, y, z;
+  sweep_tile(sw, blk, BX * CPT, x, y, z);
+  stream_collide_span<L, S, EQ, BX, CPT, NT>(A, B, g, ph, x + threadIdx.x, y, z, sw.xlast, sw.hole);
 }
 
 // initial state: equilibrium deviations at (rho, u) per node, the face ghosts
@@ -382,39 +404,86 @@ constexpr int LINK_BLOCK = 256;
 // Boundary rule + momentum exchange over a body's link list at step t. The
 // last block to finish sums the per-block partials in block order and writes
 // the step's record (static and comoving sums; node terms zero).
+// Sum of a double over the 64 lanes of a wavefront without the LDS
+// crossbar: DPP row shifts give every lane 15, 31, 47, 63 its row's total,
+// then the four row totals are read out and added in a fixed order
+// (deterministic). Every lane returns the wavefront total.
+__device__ __forceinline__ double wave_sum(double v) {
+  int lo = __double2loint(v), hi = __double2hiint(v);
+#define WAVE_SUM_STEP(CTRL)                                                              \
+  {                                                                                      \
+    const int l2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xf, 0xf, false);            \
+    const int h2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xf, 0xf, false);            \
+    const double t = __hiloint2double(h2, l2) + __hiloint2double(hi, lo);                \
+    lo = __double2loint(t);                                                              \
+    hi = __double2hiint(t);                                                              \
+  }
+  WAVE_SUM_STEP(0x111)  // row_shr:1
+  WAVE_SUM_STEP(0x112)  // row_shr:2
+  WAVE_SUM_STEP(0x114)  // row_shr:4
+  WAVE_SUM_STEP(0x118)  // row_shr:8
+#undef WAVE_SUM_STEP
+  double tot = 0.0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    tot += __hiloint2double(__builtin_amdgcn_readlane(hi, 16 * r + 15), __builtin_amdgcn_readlane(lo, 16 * r + 15));
+  return tot;
+}
+
+// block blk of nblk (NTL threads each) working on one body's links. Wave w
+// of the grid takes the chunks of 64 consecutive links c = w, w + waves, ...
+// and sums each chunk with a fixed shuffle tree into partials[c]; the first
+// wave of the last block to finish adds the chunk sums, lane l over chunks
+// l, l + 64, ... in order, then across lanes with the same tree. The result
+// therefore does not depend on the block size or the grid.
+template <class L, class S, int EQ, int NTL>
+__device__ __forceinline__ void links_block(typename S::T* A, const Link* __restrict__ links, int n,
+                                            const double* __restrict__ pose, int bc,
+                                            const uint8_t* __restrict__ mask, const Geom& g, const Phys& ph,
+                                            double* partials, unsigned* counter, double* rec, int blk, int nblk) {
+  __shared__ int last;
+  const Pose P = *reinterpret_cast<const Pose*>(pose);
+  const int lane = threadIdx.x & 63;
+  const int nchunks = (n + 63) >> 6;
+  const int waves = nblk * (NTL / 64);
+  for (int c = blk * (NTL / 64) + (int)(threadIdx.x >> 6); c < nchunks; c += waves) {
+    double acc[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const int k = c * 64 + lane;
+    if (k < n) link_rule<L, S, EQ>(A, links[k], P, bc, mask, g, ph, acc);
+#pragma unroll
+    for (int j = 0; j < 12; ++j) {
+      const double v = wave_sum(acc[j]);
+      if (lane == j) partials[c * 12 + j] = v;
+    }
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = (atomicAdd(counter, 1u) == (unsigned)nblk - 1);
+  __syncthreads();
+  if (last && threadIdx.x < 64) {
+    __threadfence();
+    double acc[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int c = lane; c < nchunks; c += 64)
+#pragma unroll
+      for (int j = 0; j < 12; ++j) acc[j] += __builtin_nontemporal_load(partials + c * 12 + j);
+#pragma unroll
+    for (int j = 0; j < 12; ++j) {
+      const double v = wave_sum(acc[j]);
+      if (lane == j) rec[j < 6 ? j : j + 6] = v;  // static -> 0..5, comoving -> 12..17
+    }
+    if (lane >= 12 && lane < 18) rec[lane - 6] = 0.0;  // node terms 6..11
+    if (lane >= 18 && lane < 20) rec[lane] = 0.0;      // counts 18, 19
+    if (lane == 0) *counter = 0u;
+  }
+}
+
 template <class L, class S, int EQ>
 __global__ __launch_bounds__(LINK_BLOCK) void k_links(typename S::T* A, const Link* __restrict__ links, int n_host,
                                                       const int* __restrict__ n_dev, const double* __restrict__ pose,
                                                       int bc, const uint8_t* __restrict__ mask, Geom g, Phys ph,
                                                       double* partials, unsigned* counter, double* rec) {
-  __shared__ double sm[12 * LINK_BLOCK / 64];
-  __shared__ double part[12];
-  __shared__ int last;
   const int n = n_dev ? *n_dev : n_host;
-  const Pose P = *reinterpret_cast<const Pose*>(pose);
-  double acc[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-  for (int k = blockIdx.x * LINK_BLOCK + threadIdx.x; k < n; k += gridDim.x * LINK_BLOCK)
-    link_rule<L, S, EQ>(A, links[k], P, bc, mask, g, ph, acc);
-  block_sum<12, LINK_BLOCK>(acc, part, sm);
-  if (threadIdx.x < 12) partials[blockIdx.x * 12 + threadIdx.x] = part[threadIdx.x];
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) last = (atomicAdd(counter, 1u) == gridDim.x - 1);
-  __syncthreads();
-  if (last) {
-    __threadfence();
-    if (threadIdx.x < 12) {
-      double s = 0;
-      for (unsigned b = 0; b < gridDim.x; ++b) s += __builtin_nontemporal_load(partials + b * 12 + threadIdx.x);
-      const int k = threadIdx.x;
-      rec[k < 6 ? k : k + 6] = s;  // static -> 0..5, comoving -> 12..17
-    } else if (threadIdx.x < 18) {
-      rec[threadIdx.x - 6] = 0.0;  // node terms 6..11
-    } else if (threadIdx.x < 20) {
-      rec[threadIdx.x] = 0.0;      // counts 18, 19
-    }
-    if (threadIdx.x == 0) *counter = 0u;
-  }
+  links_block<L, S, EQ, LINK_BLOCK>(A, links, n, pose, bc, mask, g, ph, partials, counter, rec, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -981,31 +1050,6 @@ constexpr int STEP_ROWS = 1024;   // region rows covered by the window table
 constexpr int STEP_LIST = 2048;   // window nodes
 constexpr int STEP_CELLS = 20480; // status box nodes (two bytes each)
 
-// Sum of a double over the 64 lanes of a wavefront without the LDS
-// crossbar: DPP row shifts give every lane 15, 31, 47, 63 its row's total,
-// then the four row totals are read out and added in a fixed order
-// (deterministic). Every lane returns the wavefront total.
-__device__ __forceinline__ double wave_sum(double v) {
-  int lo = __double2loint(v), hi = __double2hiint(v);
-#define WAVE_SUM_STEP(CTRL)                                                              \
-  {                                                                                      \
-    const int l2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xf, 0xf, false);            \
-    const int h2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xf, 0xf, false);            \
-    const double t = __hiloint2double(h2, l2) + __hiloint2double(hi, lo);                \
-    lo = __double2loint(t);                                                              \
-    hi = __double2hiint(t);                                                              \
-  }
-  WAVE_SUM_STEP(0x111)  // row_shr:1
-  WAVE_SUM_STEP(0x112)  // row_shr:2
-  WAVE_SUM_STEP(0x114)  // row_shr:4
-  WAVE_SUM_STEP(0x118)  // row_shr:8
-#undef WAVE_SUM_STEP
-  double tot = 0.0;
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-    tot += __hiloint2double(__builtin_amdgcn_readlane(hi, 16 * r + 15), __builtin_amdgcn_readlane(lo, 16 * r + 15));
-  return tot;
-}
 
 template <int NT, int D>
 __device__ __forceinline__ void block_sum_ft(double v[20], double* out, double* sm) {
@@ -1030,9 +1074,9 @@ __device__ __forceinline__ void block_sum_ft(double v[20], double* out, double* 
 }
 
 template <class L, class S, int EQ, int NT>
-__global__ __launch_bounds__(NT) void k_body_step(typename S::T* B, uint8_t* mask, Link* links, int* n_links,
-                                                         int cap, const double* pose, BodyShape bs, int bc, int body,
-                                                         Geom g, Phys ph, double* rec_t, double* rec_t1, int* err) {
+__device__ __forceinline__ void body_step(typename S::T* B, uint8_t* mask, Link* links, int* n_links, int cap,
+                                          const double* pose, const BodyShape& bs, int bc, int body, const Geom& g,
+                                          const Phys& ph, double* rec_t, double* rec_t1, int* err) {
   extern __shared__ uint8_t lds[];  // status box: [0,total) at t, [total,2 total) at t+1
   __shared__ double sm[20 * NT / 64];
   __shared__ double red[20];
@@ -1295,6 +1339,64 @@ __global__ __launch_bounds__(NT) void k_body_step(typename S::T* B, uint8_t* mas
   }
 }
 
+template <class L, class S, int EQ, int NT>
+__global__ __launch_bounds__(NT) void k_body_step(typename S::T* B, uint8_t* mask, Link* links, int* n_links,
+                                                  int cap, const double* pose, BodyShape bs, int bc, int body,
+                                                  Geom g, Phys ph, double* rec_t, double* rec_t1, int* err) {
+  body_step<L, S, EQ, NT>(B, mask, links, n_links, cap, pose, bs, bc, body, g, ph, rec_t, rec_t1, err);
+}
+
+// ---------------------------------------------------------------------------
+// batches: many domains per launch; every argument that differs between
+// domains comes from a device table, the batch step s from the launch
+
+__device__ __forceinline__ double* batch_rec(const BatchBody& b, int64_t t) {
+  return b.rec + (t % b.rec_cap) * b.rec_stride;
+}
+
+template <class L, class S, int EQ, int BX, int CPT>
+__global__ __launch_bounds__(BX) void k_stream_collide_batch(const BatchDomain* __restrict__ doms,
+                                                             const BatchTile* __restrict__ tiles, int ntiles,
+                                                             int remap, int64_t s) {
+  const int blk = remap ? xcd_block(blockIdx.x, ntiles) : blockIdx.x;
+  const BatchTile tl = tiles[blk];
+  const BatchDomain& D = doms[tl.dom];
+  const Geom g = D.g;
+  const Phys ph = D.ph;
+  const auto* A = (const typename S::T*)D.buf[s & 1];
+  auto* B = (typename S::T*)D.buf[(s + 1) & 1];
+  const int nrows = g.hi[1] - g.lo[1] + 1;
+  const int y = g.lo[1] + tl.row % nrows;
+  const int z = g.lo[2] + tl.row / nrows;
+  const int no_hole[6] = {1, 0, 1, 0, 1, 0};
+  stream_collide_span<L, S, EQ, BX, CPT, false>(A, B, g, ph, g.lo[0] + tl.bx * (BX * CPT) + threadIdx.x, y, z,
+                                                g.hi[0], no_hole);
+}
+
+// grid (blocks per body, bodies): the boundary rule + momentum exchange of
+// batch step s before its bulk update, on the source buffer
+template <class L, class S, int EQ>
+__global__ __launch_bounds__(LINK_BLOCK) void k_links_batch(const BatchDomain* __restrict__ doms,
+                                                            const BatchBody* __restrict__ bodies, int64_t s) {
+  const BatchBody& b = bodies[blockIdx.y];
+  const BatchDomain& D = doms[b.dom];
+  const int64_t t = b.t0 + s;
+  links_block<L, S, EQ, LINK_BLOCK>((typename S::T*)D.buf[s & 1], b.links, b.n_host, b.pose + (t - b.pose_base) * POSE_DOUBLES,
+                        b.bc, b.mask, D.g, D.ph, b.partials, b.counter, batch_rec(b, t), blockIdx.x, gridDim.x);
+}
+
+// one workgroup per moving body: its advance after batch step s's bulk update
+template <class L, class S, int EQ, int NT>
+__global__ __launch_bounds__(NT) void k_body_step_batch(const BatchDomain* __restrict__ doms,
+                                                        const BatchBody* __restrict__ bodies, int64_t s) {
+  const BatchBody& b = bodies[blockIdx.x];
+  const BatchDomain& D = doms[b.dom];
+  const int64_t t = b.t0 + s;
+  body_step<L, S, EQ, NT>((typename S::T*)D.buf[(s + 1) & 1], b.mask, b.links, b.n_links, b.cap,
+                          b.pose + (t - b.pose_base) * POSE_DOUBLES, b.bs, b.bc, b.body, D.g, D.ph,
+                          batch_rec(b, t), batch_rec(b, t + 1), b.err);
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 
@@ -1335,19 +1437,22 @@ BulkConfig bulk_config(int lat, int st, size_t footprint) {
 }
 
 template <class L, class S, int EQ, int BX, int CPT, bool NT>
-static void launch_bulk_variant(const void* A, void* B, const Geom& g, const Phys& ph, int remap, hipStream_t s) {
-  BulkShape b = bulk_shape(g, BX * CPT);
-  hipLaunchKernelGGL((k_stream_collide<L, S, EQ, BX, CPT, NT>), dim3(b.nblocks), dim3(BX), 0, s,
-                     (const typename S::T*)A, (typename S::T*)B, g, ph, b.nbx, b.nrows, b.nblocks, remap);
+static void launch_bulk_variant(const void* A, void* B, const Geom& g, const Phys& ph, const Sweep& sw,
+                                hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  auto kern = k_stream_collide<L, S, EQ, BX, CPT, NT>;
+  const auto* a = (const typename S::T*)A;
+  auto* o = (typename S::T*)B;
+  if (e0) hipExtLaunchKernelGGL(kern, dim3(sw.ntiles), dim3(BX), 0, s, e0, e1, 0, a, o, g, ph, sw);
+  else hipLaunchKernelGGL(kern, dim3(sw.ntiles), dim3(BX), 0, s, a, o, g, ph, sw);
 }
 
 template <class L, class S, int EQ>
 static void launch_bulk_cfg(const BulkConfig& c, const void* A, void* B, const Geom& g, const Phys& ph,
-                            hipStream_t s) {
-#define LBM_BULK_CASE(BX_, CPT_, NT_)                                                   \
-  if (c.block == BX_ && c.cells_per_thread == CPT_ && c.nontemporal == NT_) {           \
-    launch_bulk_variant<L, S, EQ, BX_, CPT_, (NT_ != 0)>(A, B, g, ph, c.remap, s);      \
-    return;                                                                             \
+                            const Sweep& sw, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+#define LBM_BULK_CASE(BX_, CPT_, NT_)                                                 \
+  if (c.block == BX_ && c.cells_per_thread == CPT_ && c.nontemporal == NT_) {         \
+    launch_bulk_variant<L, S, EQ, BX_, CPT_, (NT_ != 0)>(A, B, g, ph, sw, s, e0, e1); \
+    return;                                                                           \
   }
   LBM_BULK_CASE(256, 1, 0)
   LBM_BULK_CASE(256, 2, 0)
@@ -1355,17 +1460,44 @@ static void launch_bulk_cfg(const BulkConfig& c, const void* A, void* B, const G
   LBM_BULK_CASE(128, 2, 0)
   LBM_BULK_CASE(128, 4, 0)
 #undef LBM_BULK_CASE
-  launch_bulk_variant<L, S, EQ, 256, 1, false>(A, B, g, ph, c.remap, s);
+}
+
+bool bulk_supported(const BulkConfig& c) {
+  const int v[5][2] = {{256, 1}, {256, 2}, {512, 1}, {128, 2}, {128, 4}};
+  for (const auto& e : v)
+    if (c.block == e[0] && c.cells_per_thread == e[1] && c.nontemporal == 0) return true;
+  return false;
+}
+
+Sweep make_sweep(const int lo[3], const int hi[3], int span, const int* hole, int remap) {
+  Sweep sw{};
+  sw.x0 = lo[0];
+  sw.y0 = lo[1];
+  sw.z0 = lo[2];
+  sw.xlast = hi[0];
+  sw.ny = hi[1] - lo[1] + 1;
+  sw.nbx = (hi[0] - lo[0] + span) / span;
+  sw.ntiles = sw.nbx * sw.ny * (hi[2] - lo[2] + 1);
+  sw.remap = remap;
+  for (int k = 0; k < 6; ++k) sw.hole[k] = hole ? hole[k] : (k & 1 ? 0 : 1);
+  return sw;
 }
 
 hipError_t launch_stream_collide(int lat, int st, int eq, const void* A, void* B, const Geom& g, const Phys& ph,
-                                 hipStream_t s, const BulkConfig* cfg) {
-  const BulkConfig c = cfg ? *cfg : BulkConfig{256, 1, 0, 1};
+                                 hipStream_t s, const BulkConfig& cfg, const Sweep& sw, hipEvent_t ev_start,
+                                 hipEvent_t ev_stop) {
+  if (sw.ntiles <= 0 || !bulk_supported(cfg)) return hipErrorInvalidValue;
+  if (sw.x0 < g.lo[0] || sw.xlast > g.hi[0] || sw.y0 < g.lo[1] || sw.z0 < g.lo[2]) return hipErrorInvalidValue;
+  if (sw.y0 + sw.ny - 1 > g.hi[1] || sw.z0 + sw.ntiles / (sw.nbx * sw.ny) - 1 > g.hi[2])
+    return hipErrorInvalidValue;
+  if (sw.nbx != (sw.xlast - sw.x0 + cfg.block * cfg.cells_per_thread) / (cfg.block * cfg.cells_per_thread))
+    return hipErrorInvalidValue;
+  if ((ev_start == nullptr) != (ev_stop == nullptr)) return hipErrorInvalidValue;
   with_types(lat, st, eq, [&](auto Lt, auto St, auto E) {
     using L = decltype(Lt);
     using S = decltype(St);
     constexpr int EQ = decltype(E)::value;
-    launch_bulk_cfg<L, S, EQ>(c, A, B, g, ph, s);
+    launch_bulk_cfg<L, S, EQ>(cfg, A, B, g, ph, sw, s, ev_start, ev_stop);
   });
   return hipGetLastError();
 }
@@ -1383,15 +1515,24 @@ hipError_t launch_init(int lat, int st, int eq, void* A, uint8_t* mask, const Ge
   return hipGetLastError();
 }
 
+// a launch that carries start/stop events when they are given
+template <class K, class... Args>
+static void launch_timed(K kern, dim3 grid, dim3 block, size_t lds, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+                         Args... args) {
+  if (e0) hipExtLaunchKernelGGL(kern, grid, block, (uint32_t)lds, s, e0, e1, 0, args...);
+  else hipLaunchKernelGGL(kern, grid, block, lds, s, args...);
+}
+
 hipError_t launch_links(int lat, int st, int eq, void* A, const Link* links, int n_host, const int* n_dev,
                         int grid, const double* pose, int bc, const uint8_t* mask, const Geom& g, const Phys& ph,
-                        double* partials, unsigned* counter, double* rec, hipStream_t s) {
+                        double* partials, unsigned* counter, double* rec, hipStream_t s, hipEvent_t e0,
+                        hipEvent_t e1) {
   with_types(lat, st, eq, [&](auto Lt, auto St, auto E) {
     using L = decltype(Lt);
     using S = decltype(St);
     constexpr int EQ = decltype(E)::value;
-    hipLaunchKernelGGL((k_links<L, S, EQ>), dim3(grid), dim3(LINK_BLOCK), 0, s, (typename S::T*)A, links, n_host,
-                       n_dev, pose, bc, mask, g, ph, partials, counter, rec);
+    launch_timed(k_links<L, S, EQ>, dim3(grid), dim3(LINK_BLOCK), 0, s, e0, e1, (typename S::T*)A, links, n_host,
+                 n_dev, pose, bc, mask, g, ph, partials, counter, rec);
   });
   return hipGetLastError();
 }
@@ -1399,25 +1540,94 @@ hipError_t launch_links(int lat, int st, int eq, void* A, const Link* links, int
 hipError_t launch_body_advance(int lat, int st, int eq, void* B, uint8_t* mask, uint8_t* mask_next, Link* links,
                                int* n_links, int cap, const double* pose, const BodyShape& bs, int bc, int body,
                                int mode, const Geom& g, const Phys& ph, double* rec_t, double* rec_t1, int* err,
-                               hipStream_t s, int64_t region_cells, int64_t region_rows) {
+                               hipStream_t s, int64_t region_cells, int64_t region_rows, hipEvent_t e0,
+                               hipEvent_t e1) {
   with_types(lat, st, eq, [&](auto Lt, auto St, auto E) {
     using L = decltype(Lt);
     using S = decltype(St);
     constexpr int EQ = decltype(E)::value;
+    auto* b = (typename S::T*)B;
+    const size_t lds = ((size_t)2 * region_cells + 15) / 16 * 16;
     if (mode == 1 && bs.shape != SHAPE_OUTER_CIRCLE && region_cells > 0 && region_cells <= STEP_CELLS &&
         region_rows <= STEP_ROWS) {
-      const size_t lds = ((size_t)2 * region_cells + 15) / 16 * 16;
       constexpr int NT = L::D == 2 ? 1024 : 512;  // 2D fits the 128 VGPRs of 1024-thread blocks
-      hipLaunchKernelGGL((k_body_step<L, S, EQ, NT>), dim3(1), dim3(NT), lds, s, (typename S::T*)B, mask, links,
-                         n_links, cap, pose, bs, bc, body, g, ph, rec_t, rec_t1, err);
+      launch_timed(k_body_step<L, S, EQ, NT>, dim3(1), dim3(NT), lds, s, e0, e1, b, mask, links, n_links, cap, pose,
+                   bs, bc, body, g, ph, rec_t, rec_t1, err);
     } else if (region_cells > 0 && region_cells <= ADV_LDS_CELLS) {
-      const size_t lds = ((size_t)2 * region_cells + 15) / 16 * 16;
-      hipLaunchKernelGGL((k_body_advance_lds<L, S, EQ>), dim3(1), dim3(ADV_BLOCK), lds, s, (typename S::T*)B, mask,
-                         links, n_links, cap, pose, bs, bc, body, mode, g, ph, rec_t, rec_t1, err);
+      launch_timed(k_body_advance_lds<L, S, EQ>, dim3(1), dim3(ADV_BLOCK), lds, s, e0, e1, b, mask, links, n_links,
+                   cap, pose, bs, bc, body, mode, g, ph, rec_t, rec_t1, err);
     } else {
-      hipLaunchKernelGGL((k_body_advance<L, S, EQ>), dim3(1), dim3(ADV_BLOCK), 0, s, (typename S::T*)B, mask,
-                         mask_next, links, n_links, cap, pose, bs, bc, body, mode, g, ph, rec_t, rec_t1, err);
+      launch_timed(k_body_advance<L, S, EQ>, dim3(1), dim3(ADV_BLOCK), 0, s, e0, e1, b, mask, mask_next, links,
+                   n_links, cap, pose, bs, bc, body, mode, g, ph, rec_t, rec_t1, err);
     }
+  });
+  return hipGetLastError();
+}
+
+bool body_step_fits(int64_t region_cells, int64_t region_rows) {
+  return region_cells > 0 && region_cells <= STEP_CELLS && region_rows <= STEP_ROWS;
+}
+
+template <class L, class S, int EQ, int BX, int CPT>
+static void launch_batch_variant(const BatchDomain* doms, const BatchTile* tiles, int ntiles, int remap, int64_t step,
+                                 hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  auto kern = k_stream_collide_batch<L, S, EQ, BX, CPT>;
+  if (e0) hipExtLaunchKernelGGL(kern, dim3(ntiles), dim3(BX), 0, s, e0, e1, 0, doms, tiles, ntiles, remap, step);
+  else hipLaunchKernelGGL(kern, dim3(ntiles), dim3(BX), 0, s, doms, tiles, ntiles, remap, step);
+}
+
+bool batch_bulk_supported(int block, int cells_per_thread) {
+  for (const auto& v : BATCH_BULK_VARIANTS)
+    if (v[0] == block && v[1] == cells_per_thread) return true;
+  return false;
+}
+
+hipError_t launch_batch_bulk(int lat, int st, int eq, const BatchDomain* doms, const BatchTile* tiles, int ntiles,
+                             const BulkConfig& cfg, int64_t step, hipStream_t s, hipEvent_t ev_start,
+                             hipEvent_t ev_stop) {
+  if (ntiles <= 0 || !batch_bulk_supported(cfg.block, cfg.cells_per_thread)) return hipErrorInvalidValue;
+  if ((ev_start == nullptr) != (ev_stop == nullptr)) return hipErrorInvalidValue;
+  with_types(lat, st, eq, [&](auto Lt, auto St, auto E) {
+    using L = decltype(Lt);
+    using S = decltype(St);
+    constexpr int EQ = decltype(E)::value;
+#define LBM_BATCH_CASE(BX_, CPT_)                                                                          \
+  if (cfg.block == BX_ && cfg.cells_per_thread == CPT_) {                                                  \
+    launch_batch_variant<L, S, EQ, BX_, CPT_>(doms, tiles, ntiles, cfg.remap, step, s, ev_start, ev_stop); \
+    return;                                                                                                \
+  }
+    LBM_BATCH_CASE(64, 1)
+    LBM_BATCH_CASE(128, 1)
+    LBM_BATCH_CASE(256, 1)
+    LBM_BATCH_CASE(64, 2)
+    LBM_BATCH_CASE(128, 2)
+#undef LBM_BATCH_CASE
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_links(int lat, int st, int eq, const BatchDomain* doms, const BatchBody* bodies, int nbodies,
+                              int grid, int64_t step, hipStream_t s) {
+  if (nbodies <= 0 || grid <= 0 || grid > 64) return hipErrorInvalidValue;
+  with_types(lat, st, eq, [&](auto Lt, auto St, auto E) {
+    using L = decltype(Lt);
+    using S = decltype(St);
+    constexpr int EQ = decltype(E)::value;
+    hipLaunchKernelGGL((k_links_batch<L, S, EQ>), dim3(grid, nbodies), dim3(LINK_BLOCK), 0, s, doms, bodies, step);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_body_step(int lat, int st, int eq, const BatchDomain* doms, const BatchBody* bodies,
+                                  int nbodies, int64_t max_region_cells, int64_t step, hipStream_t s) {
+  if (nbodies <= 0 || max_region_cells <= 0 || max_region_cells > STEP_CELLS) return hipErrorInvalidValue;
+  const size_t lds = ((size_t)2 * max_region_cells + 15) / 16 * 16;
+  with_types(lat, st, eq, [&](auto Lt, auto St, auto E) {
+    using L = decltype(Lt);
+    using S = decltype(St);
+    constexpr int EQ = decltype(E)::value;
+    constexpr int NT = L::D == 2 ? 1024 : 512;
+    hipLaunchKernelGGL((k_body_step_batch<L, S, EQ, NT>), dim3(nbodies), dim3(NT), lds, s, doms, bodies, step);
   });
   return hipGetLastError();
 }

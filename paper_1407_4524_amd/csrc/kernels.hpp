@@ -20,16 +20,86 @@ struct BulkConfig {
 };
 BulkConfig bulk_config(int lat, int st, size_t footprint);
 
+// Node box swept by one stream-collide launch, in tiles of `span`
+// consecutive x of one (y, z) row: tile k is span k % nbx of row k / nbx,
+// rows running y-fastest. Nodes inside the hole box (x0, x1, y0, y1, z0, z1;
+// empty when x0 > x1) are skipped.
+struct Sweep {
+  int x0, y0, z0, xlast, ny, nbx, ntiles, remap;
+  int hole[6];
+};
+Sweep make_sweep(const int lo[3], const int hi[3], int span, const int* hole, int remap);
+bool bulk_supported(const BulkConfig& c);
+
+// ev_start/ev_stop (both or neither, here and below): events recorded at the
+// start and the end of the kernel itself
 hipError_t launch_stream_collide(int lat, int st, int eq, const void* A, void* B, const Geom& g, const Phys& ph,
-                                 hipStream_t s, const BulkConfig* cfg = nullptr);
+                                 hipStream_t s, const BulkConfig& cfg, const Sweep& sw,
+                                 hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+
 hipError_t launch_init(int lat, int st, int eq, void* A, uint8_t* mask, const Geom& g, const Phys& ph,
                        const double* rho, const double* u, hipStream_t s);
 hipError_t launch_links(int lat, int st, int eq, void* A, const Link* links, int n_host, const int* n_dev,
                         int grid, const double* pose, int bc, const uint8_t* mask, const Geom& g, const Phys& ph,
-                        double* partials, unsigned* counter, double* rec, hipStream_t s);
+                        double* partials, unsigned* counter, double* rec, hipStream_t s, hipEvent_t ev_start = nullptr,
+                        hipEvent_t ev_stop = nullptr);
 hipError_t launch_body_advance(int lat, int st, int eq, void* B, uint8_t* mask, uint8_t* mask_next, Link* links,
                                int* n_links, int cap, const double* pose, const BodyShape& bs, int bc, int body,
                                int mode, const Geom& g, const Phys& ph, double* rec_t, double* rec_t1, int* err,
-                               hipStream_t s, int64_t region_cells, int64_t region_rows);
+                               hipStream_t s, int64_t region_cells, int64_t region_rows,
+                               hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+
+// True when the per-step advance of a moving body whose region (node box of
+// poses t and t+1 plus a margin) has this many nodes and rows runs in the
+// single-workgroup LDS kernel (the batched path needs it).
+bool body_step_fits(int64_t region_cells, int64_t region_rows);
+
+// ---------------------------------------------------------------------------
+// batches of domains advanced by the same launches
+
+constexpr int POSE_DOUBLES = 16;  // doubles per Pose record
+
+// one member domain; the source buffer of batch step s is buf[s & 1]
+struct BatchDomain {
+  Geom g;
+  Phys ph;
+  void* buf[2];
+};
+
+// one block of the batched stream-collide launch: span bx of row `row` of
+// member `dom` (rows numbered as in RowRange)
+struct BatchTile {
+  uint16_t dom, bx;
+  int32_t row;
+};
+
+// one body of a member domain
+struct BatchBody {
+  int dom, body, bc, cap, n_host;
+  Link* links;
+  int* n_links;
+  const double* pose;  // device pose window; record k is step pose_base + k
+  int64_t pose_base;
+  BodyShape bs;
+  uint8_t* mask;
+  double* rec;         // this body's record in ring slot 0
+  int64_t rec_cap, rec_stride;
+  double* partials;
+  unsigned* counter;
+  int* err;
+  int64_t t0;          // the member's step at batch step 0
+};
+
+// (block, nodes per thread) of the batched stream-collide variants
+constexpr int BATCH_BULK_VARIANTS[5][2] = {{64, 1}, {128, 1}, {256, 1}, {64, 2}, {128, 2}};
+bool batch_bulk_supported(int block, int cells_per_thread);
+
+hipError_t launch_batch_bulk(int lat, int st, int eq, const BatchDomain* doms, const BatchTile* tiles, int ntiles,
+                             const BulkConfig& cfg, int64_t step, hipStream_t s, hipEvent_t ev_start = nullptr,
+                             hipEvent_t ev_stop = nullptr);
+hipError_t launch_batch_links(int lat, int st, int eq, const BatchDomain* doms, const BatchBody* bodies, int nbodies,
+                              int grid, int64_t step, hipStream_t s);
+hipError_t launch_batch_body_step(int lat, int st, int eq, const BatchDomain* doms, const BatchBody* bodies,
+                                  int nbodies, int64_t max_region_cells, int64_t step, hipStream_t s);
 
 }  // namespace lbm

@@ -43,6 +43,7 @@ struct Body {
   std::vector<double> table;
   Link* links = nullptr;
   int* n_links = nullptr;
+  double* partials = nullptr;  // one 12-double sum per chunk of 64 links
   int cap = 0;
   int n_host = 0;
   double* pose_dev = nullptr;
@@ -70,23 +71,30 @@ struct lbm_domain_s {
   double* rec = nullptr;
   int64_t rec_cap = 0;
   int* err = nullptr;
-  double* partials = nullptr;  // [LBM_MAX_BODIES][LINK_GRID_MAX][12]
   unsigned* counters = nullptr;
   int64_t t = 0;
   Body body[LBM_MAX_BODIES];
   BulkConfig bulk{};  // stream-collide launch shape
-  // kernel timing ring
+  // second stream: the far update of a split step; created on first use
+  hipStream_t aux = nullptr;
+  hipEvent_t e_near = nullptr, e_far = nullptr;
+  // kernel timing ring, by kind (LBM_KERNEL_*), every timing_every-th launch
+  // of each kind
+  int timing_every = 0;
+  int64_t kind_count[3] = {0, 0, 0};
   bool timing = false;
   hipEvent_t ev[2][64] = {};
+  int ev_kind[64] = {};
   int64_t timed = 0, folded = 0;
-  double timed_ms = 0.0;
+  int64_t kind_launches[3] = {0, 0, 0}, kind_nodes[3] = {0, 0, 0};
+  double kind_ms[3] = {0.0, 0.0, 0.0};
 };
 
 namespace {
 
 struct Layout {
   Geom g;
-  size_t pop_bytes, mask_bytes, rec_bytes, err_bytes, part_bytes, cnt_bytes, total;
+  size_t pop_bytes, mask_bytes, rec_bytes, err_bytes, cnt_bytes, total;
   int64_t rec_cap;
 };
 
@@ -150,9 +158,8 @@ Layout make_layout(const lbm_domain_desc* d) {
   L.mask_bytes = align_up((size_t)g.S, 256);
   L.rec_bytes = align_up((size_t)L.rec_cap * LBM_MAX_BODIES * LBM_REC_LEN * sizeof(double), 256);
   L.err_bytes = 256;
-  L.part_bytes = align_up((size_t)LBM_MAX_BODIES * LINK_GRID_MAX * 12 * sizeof(double), 256);
   L.cnt_bytes = 256;
-  L.total = 2 * L.pop_bytes + 2 * L.mask_bytes + L.rec_bytes + L.err_bytes + L.part_bytes + L.cnt_bytes;
+  L.total = 2 * L.pop_bytes + 2 * L.mask_bytes + L.rec_bytes + L.err_bytes + L.cnt_bytes;
   return L;
 }
 
@@ -311,7 +318,7 @@ lbm_status check_device_errors(lbm_domain d) {
 lbm_status init_state(lbm_domain d, const Layout& L, const lbm_domain_desc* desc) {
   HIP_TRY(hipMemsetAsync(d->A, 0, 2 * L.pop_bytes, d->stream));
   HIP_TRY(hipMemsetAsync(d->mask, MASK_WALL, 2 * L.mask_bytes, d->stream));
-  HIP_TRY(hipMemsetAsync(d->rec, 0, L.rec_bytes + L.err_bytes + L.part_bytes + L.cnt_bytes, d->stream));
+  HIP_TRY(hipMemsetAsync(d->rec, 0, L.rec_bytes + L.err_bytes + L.cnt_bytes, d->stream));
   const int64_t N = (int64_t)d->g.nx * d->g.ny * d->g.nz;
   double* rho_dev = nullptr;
   double* u_dev = nullptr;
@@ -332,32 +339,90 @@ lbm_status init_state(lbm_domain d, const Layout& L, const lbm_domain_desc* desc
   return LBM_OK;
 }
 
-// fold the oldest event pairs of the timing ring into the running total
+// fold the oldest event pairs of the timing ring into the running totals
 lbm_status fold_timing(lbm_domain d, int64_t keep) {
   while (d->folded < d->timed - keep) {
     const int k = (int)(d->folded % 64);
     HIP_TRY(hipEventSynchronize(d->ev[1][k]));
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, d->ev[0][k], d->ev[1][k]));
-    d->timed_ms += ms;
+    d->kind_ms[d->ev_kind[k]] += ms;
     d->folded++;
   }
   return LBM_OK;
 }
 
-lbm_status launch_bulk_timed(lbm_domain d) {
-  if (!d->timing) {
-    HIP_TRY(launch_stream_collide(d->lat, d->st, d->eq, d->A, d->B, d->g, d->ph, d->stream, &d->bulk));
-    return LBM_OK;
-  }
-  lbm_status s = fold_timing(d, 63);
-  if (s != LBM_OK) return s;
+// nodes a sweep updates
+int64_t sweep_nodes(const Sweep& sw) {
+  const int nz = sw.ntiles / (sw.nbx * sw.ny);
+  int64_t n = (int64_t)(sw.xlast - sw.x0 + 1) * sw.ny * nz;
+  const int lo[3] = {sw.x0, sw.y0, sw.z0}, hi[3] = {sw.xlast, sw.y0 + sw.ny - 1, sw.z0 + nz - 1};
+  int64_t h = 1;
+  for (int a = 0; a < 3; ++a)
+    h *= std::max(0, std::min(hi[a], sw.hole[2 * a + 1]) - std::max(lo[a], sw.hole[2 * a]) + 1);
+  return n - h;
+}
+
+// start/stop events of the next timed launch of this kind (null when off)
+lbm_status timing_slot(lbm_domain d, int kind, int64_t nodes, hipEvent_t& e0, hipEvent_t& e1) {
+  e0 = e1 = nullptr;
+  if (!d->timing) return LBM_OK;
+  if (d->kind_count[kind]++ % d->timing_every != 0) return LBM_OK;
+  lbm_status st = fold_timing(d, 63);
+  if (st != LBM_OK) return st;
   const int k = (int)(d->timed % 64);
-  HIP_TRY(hipEventRecord(d->ev[0][k], d->stream));
-  HIP_TRY(launch_stream_collide(d->lat, d->st, d->eq, d->A, d->B, d->g, d->ph, d->stream, &d->bulk));
-  HIP_TRY(hipEventRecord(d->ev[1][k], d->stream));
+  e0 = d->ev[0][k];
+  e1 = d->ev[1][k];
+  d->ev_kind[k] = kind;
   d->timed++;
+  d->kind_launches[kind]++;
+  d->kind_nodes[kind] += nodes;
   return LBM_OK;
+}
+
+// launch shape of the near-box update: a small box, no block reordering,
+// and a shape no full sweep uses, so the near update is a kernel of its own
+// in profiles
+const BulkConfig NEAR_CFG{128, 2, 0, 0};
+
+// one stream-collide launch over a sweep of the current source buffer,
+// timed as `kind`
+lbm_status launch_sweep(lbm_domain d, const BulkConfig& cfg, const Sweep& sw, int kind) {
+  hipEvent_t e0, e1;
+  lbm_status st = timing_slot(d, kind, sweep_nodes(sw), e0, e1);
+  if (st != LBM_OK) return st;
+  HIP_TRY(launch_stream_collide(d->lat, d->st, d->eq, d->A, d->B, d->g, d->ph, d->stream, cfg, sw, e0, e1));
+  return LBM_OK;
+}
+
+// The advance of body `id` from step t to t+1 on the current source buffer
+// (which holds the state of t+1), as its own launch.
+lbm_status launch_advance(lbm_domain d, int id, int64_t t) {
+  Body& b = d->body[id];
+  hipEvent_t e0, e1;
+  lbm_status s = timing_slot(d, LBM_KERNEL_BODY, 0, e0, e1);
+  if (s != LBM_OK) return s;
+  HIP_TRY(launch_body_advance(d->lat, d->st, d->eq, d->A, d->mask, d->mask_next, b.links, b.n_links, b.cap,
+                              pose_at(b, t), b.shape, b.desc.bc, id, 1, d->g, d->ph, rec_slot(d, t, id),
+                              rec_slot(d, t + 1, id), d->err, d->stream, region_cells(b, d->D, t, 1),
+                              region_rows(b, t, 1), e0, e1));
+  return LBM_OK;
+}
+
+// Near box of a fused step: the node boxes of the poses t0..t1 that the
+// step's body work touches, plus one layer, within the active nodes.
+void near_box(lbm_domain d, const Body& b, int64_t t0, int64_t t1, int lo[3], int hi[3]) {
+  const Geom& g = d->g;
+  for (int a = 0; a < 3; ++a) {
+    double l = 1e300, h = -1e300;
+    for (int64_t k = t0; k <= t1; ++k) {
+      const Pose* p = reinterpret_cast<const Pose*>(b.pose_pinned) + (k - b.pose_base);
+      l = std::min(l, p->lo[a]);
+      h = std::max(h, p->hi[a]);
+    }
+    lo[a] = std::max<int>(g.lo[a], (int)l - 1);
+    hi[a] = std::min<int>(g.hi[a], (int)h + 1);
+  }
 }
 
 static_assert(sizeof(Pose) == POSE_LEN * sizeof(double), "pose record layout");
@@ -429,8 +494,6 @@ lbm_status lbm_create_domain(const lbm_domain_desc* desc, lbm_domain* out) {
   p += L.rec_bytes;
   d->err = (int*)p;
   p += L.err_bytes;
-  d->partials = (double*)p;
-  p += L.part_bytes;
   d->counters = (unsigned*)p;
   p += L.cnt_bytes;
   s = init_state(d, L, desc);
@@ -449,8 +512,16 @@ lbm_status lbm_destroy_domain(lbm_domain d) {
   for (auto& b : d->body) {
     if (b.links) (void)hipFree(b.links);
     if (b.n_links) (void)hipFree(b.n_links);
+    if (b.partials) (void)hipFree(b.partials);
     if (b.pose_dev) (void)hipFree(b.pose_dev);
     if (b.pose_pinned) (void)hipHostFree(b.pose_pinned);
+  }
+  if (d->aux) {
+    hipError_t ea = hipStreamSynchronize(d->aux);
+    if (e == hipSuccess) e = ea;
+    (void)hipStreamDestroy(d->aux);
+    (void)hipEventDestroy(d->e_near);
+    (void)hipEventDestroy(d->e_far);
   }
   if (d->owns_pool) (void)hipFree(d->pool);
   for (int k = 0; k < 64; ++k)
@@ -499,6 +570,7 @@ lbm_status lbm_set_body(lbm_domain d, int32_t id, const lbm_body_desc* bd) {
   b = std::move(nb);
   HIP_TRY(hipMalloc(&b.links, (size_t)b.cap * sizeof(Link)));
   HIP_TRY(hipMalloc(&b.n_links, sizeof(int)));
+  HIP_TRY(hipMalloc(&b.partials, (size_t)((b.cap + 63) / 64) * 12 * sizeof(double)));
   HIP_TRY(hipMemsetAsync(b.n_links, 0, sizeof(int), d->stream));
   lbm_status s = ensure_poses(d, b, d->t, d->t + 1);
   if (s != LBM_OK) {
@@ -517,38 +589,92 @@ lbm_status lbm_set_body(lbm_domain d, int32_t id, const lbm_body_desc* bd) {
   return check_device_errors(d);
 }
 
+// One step is, in order: the boundary rule + momentum exchange of bodies
+// whose links are fixed (k_links, on the source buffer), the stream-collide
+// update of every node, and the advance of bodies whose solid set moves (on
+// the new state). With a single body whose solid set moves (and no plain
+// schedule asked for) the update is split in two: the nodes of a near box
+// around the body are updated on the domain's stream, followed there by the
+// body's advance, while every other node is updated on the domain's second
+// stream. The far update of step t waits for the near update of step t-1,
+// and the near update of step t for the far update of step t-1, so the
+// advance of step t-1 overlaps the far update of step t. The near box holds
+// the node boxes of poses t-1, t and t+1 plus one layer: every node an
+// advance touches lies inside it, away from the rows the far update reads.
+// Every node is updated from the same values either way.
 lbm_status lbm_step(lbm_domain d, int64_t nsteps) {
   if (!d) return fail(LBM_E_INVAL, "null domain");
   if (nsteps < 0) return fail(LBM_E_INVAL, "negative step count");
   if (nsteps == 0) return LBM_OK;
-  for (auto& b : d->body)
-    if (b.active) {
-      lbm_status s = ensure_poses(d, b, d->t, d->t + nsteps);
+  int only = -1, nactive = 0;
+  for (int id = 0; id < LBM_MAX_BODIES; ++id)
+    if (d->body[id].active) {
+      lbm_status s = ensure_poses(d, d->body[id], d->t, d->t + nsteps);
       if (s != LBM_OK) return s;
+      only = id;
+      nactive++;
     }
+  const bool split = !d->desc.plain_schedule && nactive == 1 && d->body[only].mask_moves &&
+                     d->body[only].desc.shape != LBM_SHAPE_OUTER_CIRCLE;
+  if (split && !d->aux) {
+    HIP_TRY(hipStreamCreateWithFlags(&d->aux, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&d->e_near, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&d->e_far, hipEventDisableTiming));
+  }
+  const Geom& g = d->g;
+  const int full_lo[3] = {g.lo[0], g.lo[1], g.lo[2]}, full_hi[3] = {g.hi[0], g.hi[1], g.hi[2]};
+  const Sweep full = make_sweep(full_lo, full_hi, d->bulk.block * d->bulk.cells_per_thread, nullptr, d->bulk.remap);
+  bool far_open = false;  // a far update on the second stream is not yet waited for
   for (int64_t k = 0; k < nsteps; ++k) {
     const int64_t t = d->t;
+    lbm_status s = LBM_OK;
+    hipEvent_t e0, e1;
+    Sweep near{};
+    if (split) {
+      Body& b = d->body[only];
+      int lo[3], hi[3];
+      near_box(d, b, t - 1 >= b.pose_base ? t - 1 : t, t + 1, lo, hi);
+      const int hole[6] = {lo[0], hi[0], lo[1], hi[1], lo[2], hi[2]};
+      const Sweep far = make_sweep(full_lo, full_hi, d->bulk.block * d->bulk.cells_per_thread, hole, d->bulk.remap);
+      near = make_sweep(lo, hi, NEAR_CFG.block * NEAR_CFG.cells_per_thread, nullptr, 0);
+      // the far update of step t after the near update of step t-1 (at the
+      // first split step: after all earlier work of the domain's stream)
+      if (far_open) HIP_TRY(hipStreamWaitEvent(d->stream, d->e_far, 0));
+      else HIP_TRY(hipEventRecord(d->e_near, d->stream));
+      HIP_TRY(hipStreamWaitEvent(d->aux, d->e_near, 0));
+      if ((s = timing_slot(d, LBM_KERNEL_STREAM_COLLIDE, sweep_nodes(far), e0, e1)) != LBM_OK) return s;
+      HIP_TRY(launch_stream_collide(d->lat, d->st, d->eq, d->A, d->B, g, d->ph, d->aux, d->bulk, far, e0, e1));
+      HIP_TRY(hipEventRecord(d->e_far, d->aux));
+      far_open = true;
+    }
     for (int id = 0; id < LBM_MAX_BODIES; ++id) {
       Body& b = d->body[id];
       if (!b.active || (b.mask_moves && b.bc_ready)) continue;
       int grid = std::max(1, std::min(LINK_GRID_MAX, (b.n_host + 255) / 256));
+      if ((s = timing_slot(d, LBM_KERNEL_BODY, 0, e0, e1)) != LBM_OK) return s;
       HIP_TRY(launch_links(d->lat, d->st, d->eq, d->A, b.links, b.n_host, b.mask_moves ? b.n_links : nullptr, grid,
-                           pose_at(b, t), b.desc.bc, d->mask, d->g, d->ph, d->partials + id * LINK_GRID_MAX * 12,
-                           d->counters + id, rec_slot(d, t, id), d->stream));
+                           pose_at(b, t), b.desc.bc, d->mask, g, d->ph, b.partials, d->counters + id,
+                           rec_slot(d, t, id), d->stream, e0, e1));
       if (b.mask_moves) b.bc_ready = true;
     }
-    lbm_status sb = launch_bulk_timed(d);
-    if (sb != LBM_OK) return sb;
+    if (split) {
+      if ((s = launch_sweep(d, NEAR_CFG, near, LBM_KERNEL_NEAR_BOX)) != LBM_OK) return s;
+      HIP_TRY(hipEventRecord(d->e_near, d->stream));
+    } else {
+      if ((s = launch_sweep(d, d->bulk, full, LBM_KERNEL_STREAM_COLLIDE)) != LBM_OK) return s;
+    }
+    std::swap(d->A, d->B);  // the advance works on the new state
     for (int id = 0; id < LBM_MAX_BODIES; ++id) {
       Body& b = d->body[id];
       if (!b.active || !b.mask_moves) continue;
-      HIP_TRY(launch_body_advance(d->lat, d->st, d->eq, d->B, d->mask, d->mask_next, b.links, b.n_links, b.cap,
-                                  pose_at(b, t), b.shape, b.desc.bc, id, 1, d->g, d->ph, rec_slot(d, t, id),
-                                  rec_slot(d, t + 1, id), d->err, d->stream, region_cells(b, d->D, t, 1), region_rows(b, t, 1)));
+      if ((s = launch_advance(d, id, t)) != LBM_OK) {
+        std::swap(d->A, d->B);
+        return s;
+      }
     }
-    std::swap(d->A, d->B);
     d->t = t + 1;
   }
+  if (far_open) HIP_TRY(hipStreamWaitEvent(d->stream, d->e_far, 0));
   return LBM_OK;
 }
 
@@ -688,24 +814,32 @@ lbm_status lbm_get_fields(lbm_domain d, double* rho, double* u) {
   return LBM_OK;
 }
 
-lbm_status lbm_timing_enable(lbm_domain d, int32_t enable) {
+lbm_status lbm_timing_enable(lbm_domain d, int32_t every) {
   if (!d) return fail(LBM_E_INVAL, "null domain");
-  if (enable && !d->ev[0][0])
+  if (every < 0) return fail(LBM_E_INVAL, "negative timing period");
+  if (every && !d->ev[0][0])
     for (int k = 0; k < 64; ++k)
       for (int j = 0; j < 2; ++j) HIP_TRY(hipEventCreate(&d->ev[j][k]));
   HIP_TRY(hipStreamSynchronize(d->stream));
-  d->timing = enable != 0;
+  if (d->aux) HIP_TRY(hipStreamSynchronize(d->aux));
+  d->timing = every != 0;
+  d->timing_every = every;
   d->timed = d->folded = 0;
-  d->timed_ms = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    d->kind_ms[k] = 0.0;
+    d->kind_launches[k] = d->kind_nodes[k] = d->kind_count[k] = 0;
+  }
   return LBM_OK;
 }
 
-lbm_status lbm_timing_read(lbm_domain d, double* total_ms, int64_t* launches) {
-  if (!d || !total_ms || !launches) return fail(LBM_E_INVAL, "null argument");
+lbm_status lbm_timing_read(lbm_domain d, int32_t kernel, double* total_ms, int64_t* launches, int64_t* nodes) {
+  if (!d || !total_ms || !launches || !nodes) return fail(LBM_E_INVAL, "null argument");
+  if (kernel < LBM_KERNEL_STREAM_COLLIDE || kernel > LBM_KERNEL_NEAR_BOX) return fail(LBM_E_INVAL, "unknown kernel");
   lbm_status s = fold_timing(d, 0);
   if (s != LBM_OK) return s;
-  *total_ms = d->timed_ms;
-  *launches = d->timed;
+  *total_ms = d->kind_ms[kernel];
+  *launches = d->kind_launches[kernel];
+  *nodes = d->kind_nodes[kernel];
   return LBM_OK;
 }
 

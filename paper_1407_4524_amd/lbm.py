@@ -26,6 +26,7 @@ SHAPE = {"circle": 0, "sphere": 0, "ellipse": 1, "ellipsoid": 1, "outer_circle":
 BC = {"halfway": 0, "mls": 1}
 ME = {"static": 0, "lattice": 1, "comoving": 2}
 MOTION = {"static": 0, "const_vel": 1, "rotate": 2, "oscillate": 3, "table": 4}
+KERNEL = {"stream_collide": 0, "body": 1, "near_box": 2}
 STATUS = {0: "LBM_OK", -1: "LBM_E_INVAL", -2: "LBM_E_NOMEM", -3: "LBM_E_HIP", -4: "LBM_E_RANGE",
           -5: "LBM_E_UNSTABLE", -6: "LBM_E_STATE"}
 REC_LEN = 20
@@ -48,7 +49,7 @@ class DomainDesc(C.Structure):
                 ("face", C.c_int32 * 6), ("inlet_profile", C.c_int32), ("inlet_u", C.c_double),
                 ("init_rho", C.POINTER(C.c_double)), ("init_u", C.POINTER(C.c_double)),
                 ("stream", C.c_void_p), ("device_buffer", C.c_void_p), ("device_buffer_bytes", C.c_size_t),
-                ("record_capacity", C.c_int64)]
+                ("record_capacity", C.c_int64), ("plain_schedule", C.c_int32)]
 
 
 class BodyDesc(C.Structure):
@@ -83,7 +84,8 @@ def lib():
         L.lbm_get_fields.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         L.lbm_get_types.argtypes = [C.c_void_p, C.c_void_p]
         L.lbm_timing_enable.argtypes = [C.c_void_p, C.c_int32]
-        L.lbm_timing_read.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        L.lbm_timing_read.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64),
+                                      C.POINTER(C.c_int64)]
         L.lbm_last_error.restype = C.c_char_p
         _lib = L
     return _lib
@@ -115,7 +117,7 @@ class Domain:
 
     def __init__(self, lattice="D2Q9", nx=64, ny=64, nz=1, tau=0.8, rho0=1.0, storage="f32", eq="bgk",
                  faces=("periodic",) * 6, inlet_profile="uniform", inlet_u=0.0, init_rho=None, init_u=None,
-                 record_capacity=0, stream=None, torch_buffer=True):
+                 record_capacity=0, stream=None, torch_buffer=True, plain_schedule=False):
         d = DomainDesc()
         d.lattice = _enum(LATTICE, lattice)
         d.nx, d.ny, d.nz = nx, ny, nz if d.lattice == 1 else 1
@@ -127,6 +129,7 @@ class Domain:
         d.inlet_profile = _enum(PROFILE, inlet_profile)
         d.inlet_u = inlet_u
         d.record_capacity = record_capacity
+        d.plain_schedule = 1 if plain_schedule else 0
         self.nx, self.ny, self.nz = nx, ny, (nz if d.lattice == 1 else 1)
         self.N = self.nx * self.ny * self.nz
         keep = []
@@ -249,15 +252,19 @@ class Domain:
         _check(lib().lbm_get_fields(self._h, rho.ctypes.data, u.ctypes.data))
         return rho, u.reshape(self.N, 3)
 
-    def timing_enable(self, on=True):
-        _check(lib().lbm_timing_enable(self._h, 1 if on else 0))
+    def timing_enable(self, every=1):
+        """time every n-th launch of each kernel (True = 1, False/0 = off)"""
+        _check(lib().lbm_timing_enable(self._h, int(every)))
 
-    def timing_read(self):
-        """(summed stream-collide kernel time in ms, number of launches)"""
+    def timing_read(self, kernel="stream_collide"):
+        """(summed kernel time in ms, number of launches, node updates made
+        by them) of the kernels "stream_collide", "body" or "near_box" since
+        the last timing_enable"""
         ms = C.c_double(0)
         n = C.c_int64(0)
-        _check(lib().lbm_timing_read(self._h, C.byref(ms), C.byref(n)))
-        return ms.value, n.value
+        nodes = C.c_int64(0)
+        _check(lib().lbm_timing_read(self._h, _enum(KERNEL, kernel), C.byref(ms), C.byref(n), C.byref(nodes)))
+        return ms.value, n.value, nodes.value
 
     def types(self):
         t = np.zeros(self.N, np.int32)

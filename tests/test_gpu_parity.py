@@ -210,3 +210,49 @@ def test_oscillating_cylinder_full_size_first_steps():
     du = velocity_error(g, o)
     print(f"F {eF:.2e} T {eT:.2e} u {du:.2e}")
     assert eF < 1e-4 and eT < 1e-4 and du < 5e-6
+
+
+# ---------------------------------------------------------------------------
+# the split schedule (the nodes away from a moving body updated on a second
+# stream, overlapping the body's advance) against the plain one: bitwise the
+# same
+
+
+def _moving(case):
+    import copy
+    if case == "oscillating_f32":
+        return W.channel_oscillating_f32(scale=10), 300
+    if case == "ellipse_f64":
+        w = copy.deepcopy(W.channel_cylinder_f64())
+        w["bodies"] = [dict(shape="ellipse", axes=(6.0, 3.0), bc="mls", me="lattice", motion="rotate",
+                            c0=(25.0, 25.0, 0.0), theta0=0.3, omega=0.01)]
+        return w, 200
+    w = copy.deepcopy(W.duct_sphere(scale=4, storage="f16"))
+    w["bodies"][0].update(motion="oscillate", amp=(0.0, 0.0, 2.0), period=100.0, me="lattice")
+    return w, 100
+
+
+@pytest.mark.parametrize("case", ["oscillating_f32", "ellipse_f64", "duct_f16"])
+def test_split_schedule_bitwise_equals_plain(case):
+    w, steps = _moving(case)
+    print(f"split vs plain schedule: {w['name']} ({case}), {steps} steps", flush=True)
+    a = make_gpu(w)
+    b = make_gpu(w, plain_schedule=True)
+    a.timing_enable(1)
+    b.timing_enable(1)
+    for chunk in (1, steps // 2 - 1, steps - steps // 2):  # several calls: the hand-over between them
+        a.step(chunk)
+        b.step(chunk)
+    _, na, nodes_a = a.timing_read("stream_collide")
+    _, nn, nodes_n = a.timing_read("near_box")
+    _, nb, nodes_b = b.timing_read("stream_collide")
+    assert na == nn == nb == steps, "every split step is a far and a near launch"
+    assert b.timing_read("near_box")[1] == 0
+    assert nodes_a + nodes_n == nodes_b
+    assert a.timing_read("body")[1] == b.timing_read("body")[1]
+    assert np.array_equal(a.records(0), b.records(0))
+    rho_a, u_a = a.fields()
+    rho_b, u_b = b.fields()
+    assert np.array_equal(rho_a, rho_b, equal_nan=True) and np.array_equal(u_a, u_b, equal_nan=True)
+    a.close()
+    b.close()

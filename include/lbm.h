@@ -223,6 +223,61 @@ lbm_status lbm_timing_enable(lbm_domain dom, int32_t every);
 lbm_status lbm_timing_read(lbm_domain dom, int32_t kernel, double* total_ms, int64_t* launches,
                            int64_t* nodes);
 
+/* ---------------------------------------------------------------------------
+   Batches: many independent domains of one lattice, storage and equilibrium
+   advanced by the same launches every step -- one boundary-rule launch over
+   all bodies with fixed links, one stream-collide launch over a table of
+   row tiles of every member, one launch with a workgroup per moving body.
+   The arithmetic of every node and link is the one of lbm_step, so a member
+   ends bitwise where lbm_step would have taken it. */
+typedef struct lbm_batch_s* lbm_batch;
+
+/* Launch shape of a batch. block x cells_per_thread nodes per tile, one of
+   (64,1) (128,1) (256,1) (64,2) (128,2); remap 1 = blocks ordered so that
+   each XCD takes a contiguous run of tiles; order 0 = tiles member by
+   member, 1 = largest members first, 2 = rows of all members interleaved.
+   us_per_step is filled in by lbm_batch_tune. */
+typedef struct {
+  int32_t block, cells_per_thread, remap, order;
+  double us_per_step;
+} lbm_batch_config;
+
+/* Creates an empty batch whose launches go to `stream` (hipStream_t,
+   borrowed; NULL = the default stream). */
+lbm_status lbm_batch_create(void* stream, lbm_batch* out);
+
+/* Waits for the batch's stream, then releases every member back to its own
+   stream and frees the batch (the members stay valid). */
+lbm_status lbm_batch_destroy(lbm_batch batch);
+
+/* Adds a domain. From then on all of the domain's work (lbm_step and
+   lbm_batch_step alike) and its synchronisation use the batch's stream.
+   LBM_E_INVAL if lattice, storage or equilibrium differ from the first
+   member's; LBM_E_STATE if the domain already belongs to a batch.
+   Destroying a member removes it. */
+lbm_status lbm_batch_add(lbm_batch batch, lbm_domain dom);
+
+/* Removes a domain (waits for the batch's stream first); the domain uses its
+   own stream again. */
+lbm_status lbm_batch_remove(lbm_batch batch, lbm_domain dom);
+
+/* Advances every member by nsteps steps (members may be at different
+   steps). Waits for the batch's previous work once, to refresh its device
+   tables, then only enqueues. */
+lbm_status lbm_batch_step(lbm_batch batch, int64_t nsteps);
+
+/* Sets the launch shape (LBM_E_INVAL for an unsupported one). */
+lbm_status lbm_batch_set_config(lbm_batch batch, const lbm_batch_config* cfg);
+lbm_status lbm_batch_get_config(lbm_batch batch, lbm_batch_config* cfg);
+
+/* Autotuner: runs trial_steps real steps of the batch under every candidate
+   launch shape (the members advance by ntrials x trial_steps steps), times
+   each on the batch's stream with HIP events, keeps the fastest and returns
+   it in *chosen; up to trial_cap trials are written to `trials` (host, may
+   be NULL) and their number to *ntrials. */
+lbm_status lbm_batch_tune(lbm_batch batch, int32_t trial_steps, lbm_batch_config* chosen,
+                          lbm_batch_config* trials, int32_t trial_cap, int32_t* ntrials);
+
 /* Thread-local description of the last error. */
 const char* lbm_last_error(void);
 

@@ -10,7 +10,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "liblbm.so")
-SOURCES = ["kernels.hip", "lbm_api.hip"]
+SOURCES = ["kernels.hip", "lbm_api.hip", "batch_api.hip"]
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
 
 

@@ -1,0 +1,332 @@
+// Batches of domains (include/lbm.h, lbm_batch_*): the member tables the
+// batched kernels read, the per-step launch sequence and the autotuner of
+// the batched stream-collide launch shape.
+#include <string.h>
+
+#include <algorithm>
+#include <numeric>
+#include <vector>
+
+#include "domain.hpp"
+
+using namespace lbm;
+using namespace lbm::host;
+
+struct lbm_batch_s {
+  hipStream_t stream = nullptr;
+  std::vector<lbm_domain> members;
+  lbm_batch_config cfg{256, 1, 1, 0, 0.0};
+  // device tables and their pinned staging copy, grown as needed
+  char* dev = nullptr;
+  size_t dev_cap = 0;
+  char* pinned = nullptr;
+  size_t pinned_cap = 0;
+};
+
+namespace {
+
+size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+bool config_ok(const lbm_batch_config& c) {
+  return batch_bulk_supported(c.block, c.cells_per_thread) && (c.remap == 0 || c.remap == 1) && c.order >= 0 &&
+         c.order <= 2;
+}
+
+int64_t active_nodes(const Geom& g) {
+  return (int64_t)(g.hi[0] - g.lo[0] + 1) * (g.hi[1] - g.lo[1] + 1) * (g.hi[2] - g.lo[2] + 1);
+}
+
+// row tiles of every member in the configured order
+std::vector<BatchTile> make_tiles(const std::vector<lbm_domain>& m, const lbm_batch_config& c) {
+  const int span = c.block * c.cells_per_thread;
+  std::vector<int> order(m.size());
+  std::iota(order.begin(), order.end(), 0);
+  if (c.order == 1)
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return active_nodes(m[a]->g) > active_nodes(m[b]->g); });
+  auto nbx = [&](int i) { return (m[i]->g.hi[0] - m[i]->g.lo[0] + span) / span; };
+  auto nrows = [&](int i) {
+    const Geom& g = m[i]->g;
+    return (g.hi[1] - g.lo[1] + 1) * (g.hi[2] - g.lo[2] + 1);
+  };
+  std::vector<BatchTile> tiles;
+  if (c.order == 2) {
+    int maxrows = 0;
+    for (size_t i = 0; i < m.size(); ++i) maxrows = std::max(maxrows, nrows((int)i));
+    for (int r = 0; r < maxrows; ++r)
+      for (int i : order)
+        if (r < nrows(i))
+          for (int bx = 0; bx < nbx(i); ++bx) tiles.push_back(BatchTile{(uint16_t)i, (uint16_t)bx, r});
+  } else {
+    for (int i : order)
+      for (int r = 0; r < nrows(i); ++r)
+        for (int bx = 0; bx < nbx(i); ++bx) tiles.push_back(BatchTile{(uint16_t)i, (uint16_t)bx, r});
+  }
+  return tiles;
+}
+
+struct Plan {
+  std::vector<BatchDomain> doms;
+  std::vector<BatchTile> tiles;
+  std::vector<BatchBody> links, moving;
+  std::vector<std::pair<int, int>> fallback;  // (member, body) advanced by its own launches
+  int link_grid = 1;
+  int64_t max_cells = 0;
+  size_t off_tiles = 0, off_links = 0, off_moving = 0, bytes = 0;
+};
+
+BatchBody batch_body(lbm_domain d, int member, int id) {
+  Body& b = d->body[id];
+  BatchBody bb{};
+  bb.dom = member;
+  bb.body = id;
+  bb.bc = b.desc.bc;
+  bb.cap = b.cap;
+  bb.n_host = b.n_host;
+  bb.links = b.links;
+  bb.n_links = b.n_links;
+  bb.pose = b.pose_dev;
+  bb.pose_base = b.pose_base;
+  bb.bs = b.shape;
+  bb.mask = d->mask;
+  bb.rec = d->rec + id * LBM_REC_LEN;
+  bb.rec_cap = d->rec_cap;
+  bb.rec_stride = LBM_MAX_BODIES * LBM_REC_LEN;
+  bb.partials = b.partials;
+  bb.counter = d->counters + id;
+  bb.err = d->err;
+  bb.t0 = d->t;
+  return bb;
+}
+
+// Poses for the next n steps, the first link rule of moving bodies that have
+// not had one, and the tables of this call.
+lbm_status make_plan(lbm_batch B, int64_t n, Plan& P) {
+  const auto& m = B->members;
+  for (lbm_domain d : m)
+    for (int id = 0; id < LBM_MAX_BODIES; ++id) {
+      Body& b = d->body[id];
+      if (!b.active) continue;
+      lbm_status s = ensure_poses(d, b, d->t, d->t + n);
+      if (s != LBM_OK) return s;
+      if (b.mask_moves && !b.bc_ready) {
+        const int grid = std::max(1, std::min(LINK_GRID_MAX, (b.n_host + 255) / 256));
+        HIP_TRY(launch_links(d->lat, d->st, d->eq, d->A, b.links, b.n_host, b.n_links, grid, pose_at(b, d->t),
+                             b.desc.bc, d->mask, d->g, d->ph, b.partials, d->counters + id, rec_slot(d, d->t, id),
+                             B->stream));
+        b.bc_ready = true;
+      }
+    }
+  for (size_t i = 0; i < m.size(); ++i) {
+    lbm_domain d = m[i];
+    P.doms.push_back(BatchDomain{d->g, d->ph, {d->A, d->B}});
+    for (int id = 0; id < LBM_MAX_BODIES; ++id) {
+      Body& b = d->body[id];
+      if (!b.active) continue;
+      BatchBody bb = batch_body(d, (int)i, id);
+      if (!b.mask_moves) {
+        P.links.push_back(bb);
+        P.link_grid = std::max(P.link_grid, std::min(LINK_GRID_MAX, (b.n_host + 255) / 256));
+        continue;
+      }
+      bool fits = b.desc.shape != LBM_SHAPE_OUTER_CIRCLE;
+      int64_t cells = 0;
+      for (int64_t k = 0; k < n && fits; ++k) {
+        const int64_t c = region_cells(b, d->D, d->t + k, 1);
+        fits = body_step_fits(c, region_rows(b, d->t + k, 1));
+        cells = std::max(cells, c);
+      }
+      if (fits) {
+        P.moving.push_back(bb);
+        P.max_cells = std::max(P.max_cells, cells);
+      } else {
+        P.fallback.push_back({(int)i, id});
+      }
+    }
+  }
+  P.tiles = make_tiles(m, B->cfg);
+  P.off_tiles = align256(P.doms.size() * sizeof(BatchDomain));
+  P.off_links = P.off_tiles + align256(P.tiles.size() * sizeof(BatchTile));
+  P.off_moving = P.off_links + align256(P.links.size() * sizeof(BatchBody));
+  P.bytes = P.off_moving + align256(P.moving.size() * sizeof(BatchBody));
+  return LBM_OK;
+}
+
+// copies the tables to the device (after the previous copy has been used)
+lbm_status upload(lbm_batch B, const Plan& P) {
+  HIP_TRY(hipStreamSynchronize(B->stream));
+  if (P.bytes > B->dev_cap) {
+    if (B->dev) HIP_TRY(hipFree(B->dev));
+    if (B->pinned) HIP_TRY(hipHostFree(B->pinned));
+    B->dev = nullptr;
+    B->pinned = nullptr;
+    const size_t cap = P.bytes * 2;
+    HIP_TRY(hipMalloc(&B->dev, cap));
+    HIP_TRY(hipHostMalloc(&B->pinned, cap, hipHostMallocDefault));
+    B->dev_cap = B->pinned_cap = cap;
+  }
+  memcpy(B->pinned, P.doms.data(), P.doms.size() * sizeof(BatchDomain));
+  memcpy(B->pinned + P.off_tiles, P.tiles.data(), P.tiles.size() * sizeof(BatchTile));
+  memcpy(B->pinned + P.off_links, P.links.data(), P.links.size() * sizeof(BatchBody));
+  memcpy(B->pinned + P.off_moving, P.moving.data(), P.moving.size() * sizeof(BatchBody));
+  HIP_TRY(hipMemcpyAsync(B->dev, B->pinned, P.bytes, hipMemcpyHostToDevice, B->stream));
+  return LBM_OK;
+}
+
+// n steps of every member; e0 (optional) is recorded once the tables are on
+// their way and e1 after the last launch
+lbm_status batch_step(lbm_batch B, int64_t n, hipEvent_t e0, hipEvent_t e1) {
+  if (n <= 0 || B->members.empty()) return LBM_OK;
+  const lbm_domain first = B->members[0];
+  Plan P;
+  lbm_status s = make_plan(B, n, P);
+  if (s != LBM_OK) return s;
+  s = upload(B, P);
+  if (s != LBM_OK) return s;
+  if (e0) HIP_TRY(hipEventRecord(e0, B->stream));
+  const auto* doms = reinterpret_cast<const BatchDomain*>(B->dev);
+  const auto* tiles = reinterpret_cast<const BatchTile*>(B->dev + P.off_tiles);
+  const auto* links = reinterpret_cast<const BatchBody*>(B->dev + P.off_links);
+  const auto* moving = reinterpret_cast<const BatchBody*>(B->dev + P.off_moving);
+  const BulkConfig bc{B->cfg.block, B->cfg.cells_per_thread, 0, B->cfg.remap};
+  const int lat = first->lat, st = first->st, eq = first->eq;
+  for (int64_t k = 0; k < n; ++k) {
+    if (!P.links.empty())
+      HIP_TRY(launch_batch_links(lat, st, eq, doms, links, (int)P.links.size(), P.link_grid, k, B->stream));
+    HIP_TRY(launch_batch_bulk(lat, st, eq, doms, tiles, (int)P.tiles.size(), bc, k, B->stream));
+    if (!P.moving.empty())
+      HIP_TRY(launch_batch_body_step(lat, st, eq, doms, moving, (int)P.moving.size(), P.max_cells, k, B->stream));
+    for (const auto& f : P.fallback) {
+      lbm_domain d = B->members[f.first];
+      Body& b = d->body[f.second];
+      const int64_t t = d->t + k;
+      void* cur = (k & 1) ? d->A : d->B;  // the state of t+1
+      HIP_TRY(launch_body_advance(d->lat, d->st, d->eq, cur, d->mask, d->mask_next, b.links, b.n_links, b.cap,
+                                  pose_at(b, t), b.shape, b.desc.bc, f.second, 1, d->g, d->ph, rec_slot(d, t, f.second),
+                                  rec_slot(d, t + 1, f.second), d->err, B->stream, region_cells(b, d->D, t, 1),
+                                  region_rows(b, t, 1)));
+    }
+  }
+  if (e1) HIP_TRY(hipEventRecord(e1, B->stream));
+  for (lbm_domain d : B->members) {
+    d->t += n;
+    if (n & 1) std::swap(d->A, d->B);
+  }
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_batch_create(void* stream, lbm_batch* out) {
+  if (!out) return fail(LBM_E_INVAL, "null output");
+  lbm_batch B = new lbm_batch_s();
+  B->stream = (hipStream_t)stream;
+  *out = B;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_destroy(lbm_batch B) {
+  if (!B) return fail(LBM_E_INVAL, "null batch");
+  hipError_t e = hipStreamSynchronize(B->stream);
+  for (lbm_domain d : B->members) {
+    d->stream = d->own_stream;
+    d->batch = nullptr;
+  }
+  if (B->dev) (void)hipFree(B->dev);
+  if (B->pinned) (void)hipHostFree(B->pinned);
+  delete B;
+  if (e != hipSuccess) return fail(LBM_E_HIP, hipGetErrorString(e));
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_add(lbm_batch B, lbm_domain d) {
+  if (!B || !d) return fail(LBM_E_INVAL, "null argument");
+  if (d->batch) return fail(LBM_E_STATE, "the domain already belongs to a batch");
+  if (B->members.size() >= 65535) return fail(LBM_E_INVAL, "a batch holds at most 65535 domains");
+  if (!B->members.empty()) {
+    const lbm_domain f = B->members[0];
+    if (f->lat != d->lat || f->st != d->st || f->eq != d->eq)
+      return fail(LBM_E_INVAL, "batch members share lattice, storage and equilibrium");
+  }
+  const Geom& g = d->g;
+  if ((g.hi[0] - g.lo[0]) / 64 + 1 > 65535) return fail(LBM_E_INVAL, "rows too long for a batch tile index");
+  HIP_TRY(hipStreamSynchronize(d->stream));
+  if (d->aux) HIP_TRY(hipStreamSynchronize(d->aux));
+  d->stream = B->stream;
+  d->batch = B;
+  B->members.push_back(d);
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_remove(lbm_batch B, lbm_domain d) {
+  if (!B || !d) return fail(LBM_E_INVAL, "null argument");
+  auto it = std::find(B->members.begin(), B->members.end(), d);
+  if (it == B->members.end()) return fail(LBM_E_INVAL, "the domain is not a member of this batch");
+  HIP_TRY(hipStreamSynchronize(B->stream));
+  B->members.erase(it);
+  d->stream = d->own_stream;
+  d->batch = nullptr;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_step(lbm_batch B, int64_t nsteps) {
+  if (!B) return fail(LBM_E_INVAL, "null batch");
+  if (nsteps < 0) return fail(LBM_E_INVAL, "negative step count");
+  return batch_step(B, nsteps, nullptr, nullptr);
+}
+
+lbm_status lbm_batch_set_config(lbm_batch B, const lbm_batch_config* cfg) {
+  if (!B || !cfg) return fail(LBM_E_INVAL, "null argument");
+  if (!config_ok(*cfg)) return fail(LBM_E_INVAL, "unsupported batch launch shape");
+  B->cfg = *cfg;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_get_config(lbm_batch B, lbm_batch_config* cfg) {
+  if (!B || !cfg) return fail(LBM_E_INVAL, "null argument");
+  *cfg = B->cfg;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_tune(lbm_batch B, int32_t trial_steps, lbm_batch_config* chosen, lbm_batch_config* trials,
+                          int32_t trial_cap, int32_t* ntrials) {
+  if (!B || !chosen) return fail(LBM_E_INVAL, "null argument");
+  if (trial_steps <= 0) return fail(LBM_E_INVAL, "trial_steps must be positive");
+  if (B->members.empty()) return fail(LBM_E_STATE, "empty batch");
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  lbm_batch_config best{};
+  best.us_per_step = 1e300;
+  int count = 0;
+  lbm_status s = LBM_OK;
+  for (const auto& v : BATCH_BULK_VARIANTS)
+    for (int remap = 0; remap <= 1 && s == LBM_OK; ++remap)
+      for (int order = 0; order <= 2 && s == LBM_OK; ++order) {
+        B->cfg = lbm_batch_config{v[0], v[1], remap, order, 0.0};
+        s = batch_step(B, trial_steps, e0, e1);
+        if (s != LBM_OK) break;
+        hipError_t e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+          s = fail(LBM_E_HIP, std::string("autotuner timing: ") + hipGetErrorString(e));
+          break;
+        }
+        B->cfg.us_per_step = ms * 1e3 / trial_steps;
+        if (trials && count < trial_cap) trials[count] = B->cfg;
+        count++;
+        if (B->cfg.us_per_step < best.us_per_step) best = B->cfg;
+      }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (s != LBM_OK) return s;
+  B->cfg = best;
+  *chosen = best;
+  if (ntrials) *ntrials = count;
+  return LBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,102 @@
+// Host-side state of a domain and the helpers shared by the files that
+// implement the C ABI (include/lbm.h).
+#pragma once
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "lbm.h"
+
+namespace lbm {
+namespace host {
+
+// records `msg` as the thread's last error and returns `code`
+lbm_status fail(lbm_status code, const std::string& msg);
+
+#define HIP_TRY(expr)                                                                                  \
+  do {                                                                                                 \
+    hipError_t e_ = (expr);                                                                            \
+    if (e_ != hipSuccess) return ::lbm::host::fail(LBM_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr double PI = 3.14159265358979323846;
+constexpr int POSE_LEN = 16;  // doubles per Pose record
+constexpr int LINK_GRID_MAX = 64;
+constexpr int64_t POSE_WINDOW = 8192;
+
+struct Body {
+  bool active = false;
+  lbm_body_desc desc{};
+  BodyShape shape{};
+  bool mask_moves = false;  // the solid set changes with the pose
+  std::vector<double> table;
+  Link* links = nullptr;
+  int* n_links = nullptr;
+  double* partials = nullptr;  // one 12-double sum per chunk of 64 links
+  int cap = 0;
+  int n_host = 0;
+  double* pose_dev = nullptr;
+  double* pose_pinned = nullptr;
+  int64_t pose_base = 0, pose_cap = 0, pose_valid = 0;
+  bool bc_ready = false;
+};
+
+}  // namespace host
+}  // namespace lbm
+
+struct lbm_domain_s {
+  lbm_domain_desc desc{};
+  int lat = 0, st = 0, eq = 0, Q = 9, D = 2;
+  size_t elem = 8;
+  lbm::Geom g{};
+  lbm::Phys ph{};
+  hipStream_t stream = nullptr;
+  hipStream_t own_stream = nullptr;  // the descriptor's stream (a batch may lend its own)
+  struct lbm_batch_s* batch = nullptr;  // the batch the domain belongs to, if any
+  bool owns_pool = false;
+  char* pool = nullptr;
+  size_t pool_bytes = 0;
+  void* A = nullptr;
+  void* B = nullptr;
+  uint8_t* mask = nullptr;
+  uint8_t* mask_next = nullptr;
+  double* rec = nullptr;
+  int64_t rec_cap = 0;
+  int* err = nullptr;
+  unsigned* counters = nullptr;
+  int64_t t = 0;
+  lbm::host::Body body[LBM_MAX_BODIES];
+  lbm::BulkConfig bulk{};  // stream-collide launch shape
+  // second stream: the far update of a split step; created on first use
+  hipStream_t aux = nullptr;
+  hipEvent_t e_near = nullptr, e_far = nullptr;
+  // kernel timing ring, by kind (LBM_KERNEL_*), every timing_every-th launch
+  // of each kind
+  int timing_every = 0;
+  int64_t kind_count[3] = {0, 0, 0};
+  bool timing = false;
+  hipEvent_t ev[2][64] = {};
+  int ev_kind[64] = {};
+  int64_t timed = 0, folded = 0;
+  int64_t kind_launches[3] = {0, 0, 0}, kind_nodes[3] = {0, 0, 0};
+  double kind_ms[3] = {0.0, 0.0, 0.0};
+};
+
+namespace lbm {
+namespace host {
+
+double* rec_slot(lbm_domain d, int64_t t, int b);
+// makes the device pose table of body b cover steps [t0, t1]
+lbm_status ensure_poses(lbm_domain d, Body& b, int64_t t0, int64_t t1);
+const double* pose_at(const Body& b, int64_t t);
+// nodes (with the one-node margin) and rows of the region of poses t, t+mode
+int64_t region_cells(const Body& b, int D, int64_t t, int mode);
+int64_t region_rows(const Body& b, int64_t t, int mode);
+lbm_status check_device_errors(lbm_domain d);
+// the advance of body `id` from step t to t+1 on the current source buffer
+lbm_status launch_advance(lbm_domain d, int id, int64_t t);
+// start/stop events of the next timed launch of this kind (null when off)
+lbm_status timing_slot(lbm_domain d, int kind, int64_t nodes, hipEvent_t& e0, hipEvent_t& e1);
+
+}  // namespace host
+}  // namespace lbm

@@ -8,89 +8,23 @@
 #include <string>
 #include <vector>
 
-#include "kernels.hpp"
-#include "lbm.h"
+#include "domain.hpp"
 
 using namespace lbm;
+using namespace lbm::host;
 
 namespace {
 
 thread_local std::string g_last_error;
 
-lbm_status fail(lbm_status code, const std::string& msg) {
-  g_last_error = msg;
-  return code;
-}
-
-#define HIP_TRY(expr)                                                                    \
-  do {                                                                                   \
-    hipError_t e_ = (expr);                                                              \
-    if (e_ != hipSuccess) return fail(LBM_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
-  } while (0)
-
-constexpr double PI = 3.14159265358979323846;
-constexpr int POSE_LEN = 16;  // doubles per Pose record
-constexpr int LINK_GRID_MAX = 64;
-constexpr int64_t POSE_WINDOW = 8192;
-
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
-
-struct Body {
-  bool active = false;
-  lbm_body_desc desc{};
-  BodyShape shape{};
-  bool mask_moves = false;  // the solid set changes with the pose
-  std::vector<double> table;
-  Link* links = nullptr;
-  int* n_links = nullptr;
-  double* partials = nullptr;  // one 12-double sum per chunk of 64 links
-  int cap = 0;
-  int n_host = 0;
-  double* pose_dev = nullptr;
-  double* pose_pinned = nullptr;
-  int64_t pose_base = 0, pose_cap = 0, pose_valid = 0;
-  bool bc_ready = false;
-};
 
 }  // namespace
 
-struct lbm_domain_s {
-  lbm_domain_desc desc{};
-  int lat = 0, st = 0, eq = 0, Q = 9, D = 2;
-  size_t elem = 8;
-  Geom g{};
-  Phys ph{};
-  hipStream_t stream = nullptr;
-  bool owns_pool = false;
-  char* pool = nullptr;
-  size_t pool_bytes = 0;
-  void* A = nullptr;
-  void* B = nullptr;
-  uint8_t* mask = nullptr;
-  uint8_t* mask_next = nullptr;
-  double* rec = nullptr;
-  int64_t rec_cap = 0;
-  int* err = nullptr;
-  unsigned* counters = nullptr;
-  int64_t t = 0;
-  Body body[LBM_MAX_BODIES];
-  BulkConfig bulk{};  // stream-collide launch shape
-  // second stream: the far update of a split step; created on first use
-  hipStream_t aux = nullptr;
-  hipEvent_t e_near = nullptr, e_far = nullptr;
-  // kernel timing ring, by kind (LBM_KERNEL_*), every timing_every-th launch
-  // of each kind
-  int timing_every = 0;
-  int64_t kind_count[3] = {0, 0, 0};
-  bool timing = false;
-  hipEvent_t ev[2][64] = {};
-  int ev_kind[64] = {};
-  int64_t timed = 0, folded = 0;
-  int64_t kind_launches[3] = {0, 0, 0}, kind_nodes[3] = {0, 0, 0};
-  double kind_ms[3] = {0.0, 0.0, 0.0};
-};
-
-namespace {
+lbm_status lbm::host::fail(lbm_status code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
 
 struct Layout {
   Geom g;
@@ -98,7 +32,7 @@ struct Layout {
   int64_t rec_cap;
 };
 
-lbm_status check_desc(const lbm_domain_desc* d) {
+static lbm_status check_desc(const lbm_domain_desc* d) {
   if (!d) return fail(LBM_E_INVAL, "null descriptor");
   if (d->lattice != LBM_D2Q9 && d->lattice != LBM_D3Q19) return fail(LBM_E_INVAL, "unknown lattice");
   const int D = d->lattice == LBM_D2Q9 ? 2 : 3;
@@ -124,7 +58,7 @@ lbm_status check_desc(const lbm_domain_desc* d) {
   return LBM_OK;
 }
 
-Layout make_layout(const lbm_domain_desc* d) {
+static Layout make_layout(const lbm_domain_desc* d) {
   Layout L{};
   Geom& g = L.g;
   const int D = d->lattice == LBM_D2Q9 ? 2 : 3;
@@ -164,7 +98,7 @@ Layout make_layout(const lbm_domain_desc* d) {
 }
 
 // Pose of a body at integer step t, by the rules of include/lbm.h.
-Pose body_pose(const Body& b, const Geom& g, int64_t t) {
+static Pose body_pose(const Body& b, const Geom& g, int64_t t) {
 #pragma clang fp contract(off)
   Pose p{};
   const lbm_body_desc& d = b.desc;
@@ -237,18 +171,18 @@ Pose body_pose(const Body& b, const Geom& g, int64_t t) {
   return p;
 }
 
-bool pose_inside(const Pose& p, const Geom& g) {
+static bool pose_inside(const Pose& p, const Geom& g) {
   for (int a = 0; a < g.D; ++a)
     if (p.lo[a] < g.lo[a] || p.hi[a] > g.hi[a]) return false;
   return true;
 }
 
-double* rec_slot(lbm_domain d, int64_t t, int b) {
+double* lbm::host::rec_slot(lbm_domain d, int64_t t, int b) {
   return d->rec + ((t % d->rec_cap) * LBM_MAX_BODIES + b) * LBM_REC_LEN;
 }
 
 // make sure the device pose table of body b covers steps [t0, t1]
-lbm_status ensure_poses(lbm_domain d, Body& b, int64_t t0, int64_t t1) {
+lbm_status lbm::host::ensure_poses(lbm_domain d, Body& b, int64_t t0, int64_t t1) {
   if (t0 >= b.pose_base && t1 < b.pose_base + b.pose_valid) return LBM_OK;
   int64_t need = t1 - t0 + 1;
   int64_t cap = std::max<int64_t>(need, POSE_WINDOW);
@@ -280,12 +214,12 @@ lbm_status ensure_poses(lbm_domain d, Body& b, int64_t t0, int64_t t1) {
   return LBM_OK;
 }
 
-const double* pose_at(const Body& b, int64_t t) { return b.pose_dev + (t - b.pose_base) * POSE_LEN; }
+const double* lbm::host::pose_at(const Body& b, int64_t t) { return b.pose_dev + (t - b.pose_base) * POSE_LEN; }
 
 // nodes of the box that covers the body region at steps t and t + mode,
 // with a one-node margin along each lattice axis (the LDS box of the body
 // kernel)
-int64_t region_cells(const Body& b, int D, int64_t t, int mode) {
+int64_t lbm::host::region_cells(const Body& b, int D, int64_t t, int mode) {
   const Pose* p0 = reinterpret_cast<const Pose*>(b.pose_pinned) + (t - b.pose_base);
   const Pose* p1 = p0 + mode;
   int64_t n = 1;
@@ -295,7 +229,7 @@ int64_t region_cells(const Body& b, int D, int64_t t, int mode) {
 }
 
 // rows (y,z) of the same box without the margin
-int64_t region_rows(const Body& b, int64_t t, int mode) {
+int64_t lbm::host::region_rows(const Body& b, int64_t t, int mode) {
   const Pose* p0 = reinterpret_cast<const Pose*>(b.pose_pinned) + (t - b.pose_base);
   const Pose* p1 = p0 + mode;
   int64_t n = 1;
@@ -304,7 +238,7 @@ int64_t region_rows(const Body& b, int64_t t, int mode) {
   return n;
 }
 
-lbm_status check_device_errors(lbm_domain d) {
+lbm_status lbm::host::check_device_errors(lbm_domain d) {
   int e[4] = {0, 0, 0, 0};
   HIP_TRY(hipMemcpy(e, d->err, sizeof(e), hipMemcpyDeviceToHost));
   if (e[0] & 1) return fail(LBM_E_NOMEM, "boundary-link list overflowed its capacity");
@@ -315,7 +249,7 @@ lbm_status check_device_errors(lbm_domain d) {
 
 // rest state everywhere (deviation 0), every node non-fluid until k_init
 // marks the active ones, then the equilibrium of the initial fields
-lbm_status init_state(lbm_domain d, const Layout& L, const lbm_domain_desc* desc) {
+static lbm_status init_state(lbm_domain d, const Layout& L, const lbm_domain_desc* desc) {
   HIP_TRY(hipMemsetAsync(d->A, 0, 2 * L.pop_bytes, d->stream));
   HIP_TRY(hipMemsetAsync(d->mask, MASK_WALL, 2 * L.mask_bytes, d->stream));
   HIP_TRY(hipMemsetAsync(d->rec, 0, L.rec_bytes + L.err_bytes + L.cnt_bytes, d->stream));
@@ -340,7 +274,7 @@ lbm_status init_state(lbm_domain d, const Layout& L, const lbm_domain_desc* desc
 }
 
 // fold the oldest event pairs of the timing ring into the running totals
-lbm_status fold_timing(lbm_domain d, int64_t keep) {
+static lbm_status fold_timing(lbm_domain d, int64_t keep) {
   while (d->folded < d->timed - keep) {
     const int k = (int)(d->folded % 64);
     HIP_TRY(hipEventSynchronize(d->ev[1][k]));
@@ -353,7 +287,7 @@ lbm_status fold_timing(lbm_domain d, int64_t keep) {
 }
 
 // nodes a sweep updates
-int64_t sweep_nodes(const Sweep& sw) {
+static int64_t sweep_nodes(const Sweep& sw) {
   const int nz = sw.ntiles / (sw.nbx * sw.ny);
   int64_t n = (int64_t)(sw.xlast - sw.x0 + 1) * sw.ny * nz;
   const int lo[3] = {sw.x0, sw.y0, sw.z0}, hi[3] = {sw.xlast, sw.y0 + sw.ny - 1, sw.z0 + nz - 1};
@@ -364,7 +298,7 @@ int64_t sweep_nodes(const Sweep& sw) {
 }
 
 // start/stop events of the next timed launch of this kind (null when off)
-lbm_status timing_slot(lbm_domain d, int kind, int64_t nodes, hipEvent_t& e0, hipEvent_t& e1) {
+lbm_status lbm::host::timing_slot(lbm_domain d, int kind, int64_t nodes, hipEvent_t& e0, hipEvent_t& e1) {
   e0 = e1 = nullptr;
   if (!d->timing) return LBM_OK;
   if (d->kind_count[kind]++ % d->timing_every != 0) return LBM_OK;
@@ -383,11 +317,11 @@ lbm_status timing_slot(lbm_domain d, int kind, int64_t nodes, hipEvent_t& e0, hi
 // launch shape of the near-box update: a small box, no block reordering,
 // and a shape no full sweep uses, so the near update is a kernel of its own
 // in profiles
-const BulkConfig NEAR_CFG{128, 2, 0, 0};
+static const BulkConfig NEAR_CFG{128, 2, 0, 0};
 
 // one stream-collide launch over a sweep of the current source buffer,
 // timed as `kind`
-lbm_status launch_sweep(lbm_domain d, const BulkConfig& cfg, const Sweep& sw, int kind) {
+static lbm_status launch_sweep(lbm_domain d, const BulkConfig& cfg, const Sweep& sw, int kind) {
   hipEvent_t e0, e1;
   lbm_status st = timing_slot(d, kind, sweep_nodes(sw), e0, e1);
   if (st != LBM_OK) return st;
@@ -397,7 +331,7 @@ lbm_status launch_sweep(lbm_domain d, const BulkConfig& cfg, const Sweep& sw, in
 
 // The advance of body `id` from step t to t+1 on the current source buffer
 // (which holds the state of t+1), as its own launch.
-lbm_status launch_advance(lbm_domain d, int id, int64_t t) {
+lbm_status lbm::host::launch_advance(lbm_domain d, int id, int64_t t) {
   Body& b = d->body[id];
   hipEvent_t e0, e1;
   lbm_status s = timing_slot(d, LBM_KERNEL_BODY, 0, e0, e1);
@@ -411,7 +345,7 @@ lbm_status launch_advance(lbm_domain d, int id, int64_t t) {
 
 // Near box of a fused step: the node boxes of the poses t0..t1 that the
 // step's body work touches, plus one layer, within the active nodes.
-void near_box(lbm_domain d, const Body& b, int64_t t0, int64_t t1, int lo[3], int hi[3]) {
+static void near_box(lbm_domain d, const Body& b, int64_t t0, int64_t t1, int lo[3], int hi[3]) {
   const Geom& g = d->g;
   for (int a = 0; a < 3; ++a) {
     double l = 1e300, h = -1e300;
@@ -427,7 +361,6 @@ void near_box(lbm_domain d, const Body& b, int64_t t0, int64_t t1, int lo[3], in
 
 static_assert(sizeof(Pose) == POSE_LEN * sizeof(double), "pose record layout");
 
-}  // namespace
 
 extern "C" {
 
@@ -464,6 +397,7 @@ lbm_status lbm_create_domain(const lbm_domain_desc* desc, lbm_domain* out) {
   d->ph.inlet_profile = desc->inlet_profile;
   d->ph.inlet_u = desc->inlet_u;
   d->stream = (hipStream_t)desc->stream;
+  d->own_stream = d->stream;
   d->rec_cap = L.rec_cap;
   d->bulk = bulk_config(d->lat, d->st, 2 * L.pop_bytes);
   if (desc->device_buffer) {
@@ -508,6 +442,10 @@ lbm_status lbm_create_domain(const lbm_domain_desc* desc, lbm_domain* out) {
 
 lbm_status lbm_destroy_domain(lbm_domain d) {
   if (!d) return fail(LBM_E_INVAL, "null domain");
+  if (d->batch) {
+    lbm_status s = lbm_batch_remove(d->batch, d);
+    if (s != LBM_OK) return s;
+  }
   hipError_t e = hipStreamSynchronize(d->stream);
   for (auto& b : d->body) {
     if (b.links) (void)hipFree(b.links);

@@ -34,7 +34,9 @@ MAX_BODIES = 4
 
 EXPORTS = ["lbm_footprint_bytes", "lbm_create_domain", "lbm_destroy_domain", "lbm_set_body", "lbm_step",
            "lbm_synchronize", "lbm_time", "lbm_force_torque", "lbm_records", "lbm_get_links",
-           "lbm_get_fields", "lbm_get_types", "lbm_timing_enable", "lbm_timing_read", "lbm_last_error"]
+           "lbm_get_fields", "lbm_get_types", "lbm_timing_enable", "lbm_timing_read", "lbm_last_error",
+           "lbm_batch_create", "lbm_batch_destroy", "lbm_batch_add", "lbm_batch_remove", "lbm_batch_step",
+           "lbm_batch_set_config", "lbm_batch_get_config", "lbm_batch_tune"]
 
 
 class LbmError(RuntimeError):
@@ -50,6 +52,14 @@ class DomainDesc(C.Structure):
                 ("init_rho", C.POINTER(C.c_double)), ("init_u", C.POINTER(C.c_double)),
                 ("stream", C.c_void_p), ("device_buffer", C.c_void_p), ("device_buffer_bytes", C.c_size_t),
                 ("record_capacity", C.c_int64), ("plain_schedule", C.c_int32)]
+
+
+class BatchConfig(C.Structure):
+    _fields_ = [("block", C.c_int32), ("cells_per_thread", C.c_int32), ("remap", C.c_int32), ("order", C.c_int32),
+                ("us_per_step", C.c_double)]
+
+    def as_dict(self):
+        return {f[0]: getattr(self, f[0]) for f in self._fields_}
 
 
 class BodyDesc(C.Structure):
@@ -86,6 +96,15 @@ def lib():
         L.lbm_timing_enable.argtypes = [C.c_void_p, C.c_int32]
         L.lbm_timing_read.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                       C.POINTER(C.c_int64)]
+        L.lbm_batch_create.argtypes = [C.c_void_p, C.POINTER(C.c_void_p)]
+        L.lbm_batch_destroy.argtypes = [C.c_void_p]
+        L.lbm_batch_add.argtypes = [C.c_void_p, C.c_void_p]
+        L.lbm_batch_remove.argtypes = [C.c_void_p, C.c_void_p]
+        L.lbm_batch_step.argtypes = [C.c_void_p, C.c_int64]
+        L.lbm_batch_set_config.argtypes = [C.c_void_p, C.POINTER(BatchConfig)]
+        L.lbm_batch_get_config.argtypes = [C.c_void_p, C.POINTER(BatchConfig)]
+        L.lbm_batch_tune.argtypes = [C.c_void_p, C.c_int32, C.POINTER(BatchConfig), C.POINTER(BatchConfig),
+                                     C.c_int32, C.POINTER(C.c_int32)]
         L.lbm_last_error.restype = C.c_char_p
         _lib = L
     return _lib
@@ -270,3 +289,61 @@ class Domain:
         t = np.zeros(self.N, np.int32)
         _check(lib().lbm_get_types(self._h, t.ctypes.data))
         return t
+
+
+class Batch:
+    """Domains of one lattice, storage and equilibrium advanced by the same
+    launches (see include/lbm.h, lbm_batch_*). Members keep their own
+    handles; while they are members their work runs on the batch's stream."""
+
+    def __init__(self, stream=None):
+        torch = _torch_cuda()
+        if stream is None and torch is not None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self._h = C.c_void_p()
+        _check(lib().lbm_batch_create(C.c_void_p(stream or 0), C.byref(self._h)))
+        self.members = []
+
+    def add(self, dom):
+        _check(lib().lbm_batch_add(self._h, dom._h))
+        self.members.append(dom)
+
+    def remove(self, dom):
+        _check(lib().lbm_batch_remove(self._h, dom._h))
+        self.members.remove(dom)
+
+    def step(self, n=1):
+        _check(lib().lbm_batch_step(self._h, int(n)))
+
+    @property
+    def config(self):
+        c = BatchConfig()
+        _check(lib().lbm_batch_get_config(self._h, C.byref(c)))
+        return c.as_dict()
+
+    @config.setter
+    def config(self, d):
+        c = BatchConfig(**{k: v for k, v in d.items() if k != "us_per_step"})
+        _check(lib().lbm_batch_set_config(self._h, C.byref(c)))
+
+    def tune(self, trial_steps=10):
+        """runs every candidate launch shape for trial_steps real steps, keeps
+        the fastest; returns (chosen, [all trials]) as dictionaries"""
+        chosen = BatchConfig()
+        trials = (BatchConfig * 64)()
+        n = C.c_int32(0)
+        _check(lib().lbm_batch_tune(self._h, int(trial_steps), C.byref(chosen), trials, 64, C.byref(n)))
+        return chosen.as_dict(), [trials[i].as_dict() for i in range(n.value)]
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _check(lib().lbm_batch_destroy(self._h))
+            self._h = C.c_void_p()
+            self.members = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+

@@ -21,6 +21,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -126,6 +128,66 @@ def run_gpu(name, steps, warmup, plain_schedule=False):
     return out
 
 
+def run_batch(steps, count=64, seed=0, tune_steps=5):
+    """The 64-domain batch (sides 64..512, one circle or ellipse each, half of
+    them rotating, tau in [0.52, 1]): every domain advanced `steps` steps by
+    the batched launches (launch shape chosen by the autotuner on a separate
+    copy of the batch), against the same domains advanced one after another
+    by lbm_step, one domain per launch. Both runs are timed whole."""
+    import torch
+    import lbm_workloads as W
+    from paper_1407_4524_amd import Batch, Domain
+    ws = W.batched_domains(count=count, seed=seed)
+    nodes = sum(w["nx"] * w["ny"] for w in ws)
+
+    def fresh():
+        return [Domain.from_spec(w) for w in ws]
+
+    tb = Batch()
+    tdoms = fresh()
+    for d in tdoms:
+        tb.add(d)
+    chosen, trials = tb.tune(trial_steps=tune_steps)
+    tb.close()
+    for d in tdoms:
+        d.close()
+
+    doms = fresh()
+    batch = Batch()
+    for d in doms:
+        batch.add(d)
+    cfg = dict(chosen)
+    batch.config = cfg
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.step(steps)
+    for d in doms:
+        d.synchronize()
+    t_batch = time.perf_counter() - t0
+    finite = sum(bool(np.isfinite(d.records(0, steps - 1, 1)).all()) for d in doms)
+    batch.close()
+    for d in doms:
+        d.close()
+
+    doms = fresh()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for d in doms:
+        d.step(steps)
+    for d in doms:
+        d.synchronize()
+    t_plain = time.perf_counter() - t0
+    for d in doms:
+        d.close()
+    return dict(workload=f"batch{count}_channels_f32", domains=count, steps_per_domain=steps, nodes=nodes,
+                batched=dict(seconds=round(t_batch, 4), solves_per_s=round(count / t_batch, 3),
+                             mlups=round(nodes * steps / t_batch / 1e6, 1), us_per_step=round(t_batch / steps * 1e6, 2)),
+                plain=dict(seconds=round(t_plain, 4), solves_per_s=round(count / t_plain, 3),
+                           mlups=round(nodes * steps / t_plain / 1e6, 1)),
+                speedup=round(t_plain / t_batch, 2), config=cfg, tuner_trials=len(trials),
+                finite_members=finite)
+
+
 def copy_ceiling(nbytes, reps=20):
     """A plain device-to-device copy moving nbytes (half read, half written)
     per launch, as torch issues it: the copy ceiling at the stream-collide
@@ -178,6 +240,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-domain batched line")
+    ap.add_argument("--batch-steps", type=int, default=5000)
     ap.add_argument("--no-copy-ceiling", action="store_true",
                     help="skip the plain-copy reference at the stream-collide footprint")
     ap.add_argument("--plain-schedule", action="store_true",
@@ -223,6 +287,8 @@ def main():
                                        ms_per_step=round(r["ms_per_step"], 5), roofline=r["roofline"],
                                        kernels=r["kernels"])
         line["secondary"] = sec
+    if not args.no_batch and args.workload == "channel_oscillating_f32":
+        line["batched"] = run_batch(args.batch_steps)
     if not args.no_cpu_baseline and rank == 0:
         line["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)
     if rank == 0:

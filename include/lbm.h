@@ -158,6 +158,11 @@ typedef struct {
    plus 128 bytes per step of an 8192-step window. */
 lbm_status lbm_footprint_bytes(const lbm_domain_desc* desc, size_t* bytes);
 
+/* Device bytes that lbm_set_body allocates for this body in a domain with
+   this descriptor (link list, chunk sums, pose window): with
+   lbm_footprint_bytes, the admission figure of a request. */
+lbm_status lbm_body_footprint_bytes(const lbm_domain_desc* desc, const lbm_body_desc* body, size_t* bytes);
+
 /* Creates the domain and initialises every node to the equilibrium at
    (init_rho, init_u) (Eq. Fillipova_equilibrium's truncated Maxwellian), step
    counter 0. Enqueued on desc->stream. */
@@ -199,6 +204,15 @@ lbm_status lbm_records(lbm_domain dom, int32_t body_id, int64_t first_step, int6
    entries and the total count to *n. Synchronises. */
 lbm_status lbm_get_links(lbm_domain dom, int32_t body_id, int64_t cap, int64_t* node,
                          int32_t* dir, double* delta, int64_t* n);
+
+/* Steady-state test on the device, in FP64, from the record ring: the
+   relative change |F_x(t-1) - F_x(t-1-window)| / |F_x(t-1)| of the body's
+   drag (the x-force of the momentum-exchange form its me_mode selects) up to
+   the current step t; *steady = 1 when that change is below tol, else 0.
+   LBM_E_RANGE unless 0 <= t-1-window and window < the record capacity.
+   Synchronises. */
+lbm_status lbm_steady_state(lbm_domain dom, int32_t body_id, int64_t window, double tol, int32_t* steady,
+                            double* rel_change);
 
 /* Density and velocity of every node at the current step (host arrays of
    nx*ny*nz and 3*nx*ny*nz doubles); solid nodes get NaN. Synchronises. */
@@ -277,6 +291,13 @@ lbm_status lbm_batch_get_config(lbm_batch batch, lbm_batch_config* cfg);
    be NULL) and their number to *ntrials. */
 lbm_status lbm_batch_tune(lbm_batch batch, int32_t trial_steps, lbm_batch_config* chosen,
                           lbm_batch_config* trials, int32_t trial_cap, int32_t* ntrials);
+
+/* The steady-state test of lbm_steady_state for body 0 of every member, in
+   one launch. steady and rel_change are host arrays with one entry per
+   member, in the order the members were added; a member without a body or
+   with too few steps gets steady = -1 and rel_change = NaN. Synchronises. */
+lbm_status lbm_batch_steady_state(lbm_batch batch, int64_t window, double tol, int32_t* steady,
+                                  double* rel_change);
 
 /* Thread-local description of the last error. */
 const char* lbm_last_error(void);

@@ -143,3 +143,56 @@ def batched_domains(count=64, seed=0):
                          me="lattice", motion="rotate" if rotating else "static",
                          c0=(cx, cy, 0.0), theta0=theta0, omega=omega)]))
     return out
+
+
+def serving_requests(count=256, seed=0, rate=200.0, max_steps=50000, scale=1, d3_fraction=0.2):
+    """Seeded stream of drag/torque solve requests: Poisson arrivals at `rate`
+    per second; 80 % D2Q9 channels with sides U{128..1024}, 20 % D3Q19 ducts
+    with sides U{48..160} (sides divided by `scale`); one circle/sphere or
+    ellipse/ellipsoid each, static or rotating at Omega in [0, 1e-3]
+    rad/step; storage FP32 or FP16-shifted at 50/50; Re ~ U[10, 100] on the
+    body diameter with parabolic inflow u_max = 0.04, tau = 1/2 + 3 u_max D /
+    Re, at least 0.52. Each request runs until its drag changes by less than
+    the tolerance over the steady window, or to max_steps."""
+    rng = np.random.default_rng(seed)
+    u_max = 0.04
+    t = 0.0
+    out = []
+    for k in range(count):
+        t += float(rng.exponential(1.0 / rate))
+        is3d = bool(rng.random() < d3_fraction)
+        storage = "f16" if rng.random() < 0.5 else "f32"
+        re = float(rng.uniform(10.0, 100.0))
+        ellipse = bool(rng.integers(0, 2))
+        rotating = bool(rng.integers(0, 2))
+        omega = float(rng.uniform(0.0, 1e-3)) if rotating else 0.0
+        theta0 = float(rng.uniform(0.0, math.pi))
+        if not is3d:
+            nx = max(64, int(rng.integers(128, 1025)) // scale)
+            ny = max(32, int(rng.integers(128, 1025)) // scale)
+            a = float(rng.uniform(4.0, max(4.0, min(nx, ny) / 8)))
+            b = float(rng.uniform(4.0, a)) if ellipse else a
+            cx = float(rng.uniform(a + 4, max(a + 4.5, nx / 3)))
+            cy = float(rng.uniform(a + 5, ny - a - 6))
+            w = dict(name=f"req{k}_d2q9_{storage}_{nx}x{ny}", lattice="D2Q9", nx=nx, ny=ny, nz=1,
+                     faces=CHANNEL_FACES, c0=(cx, cy, 0.0), axes=(a, b))
+        else:
+            nx, ny, nz = (max(32, int(rng.integers(48, 161)) // scale) for _ in range(3))
+            a = float(rng.uniform(4.0, max(4.0, min(nx, ny, nz) / 6)))
+            b = float(rng.uniform(4.0, a)) if ellipse else a
+            c = float(rng.uniform(4.0, a)) if ellipse else a
+            cx = float(rng.uniform(a + 4, max(a + 4.5, nx / 3)))
+            cy = float(rng.uniform(a + 5, ny - a - 6))
+            cz = float(rng.uniform(a + 5, nz - a - 6))
+            w = dict(name=f"req{k}_d3q19_{storage}_{nx}x{ny}x{nz}", lattice="D3Q19", nx=nx, ny=ny, nz=nz,
+                     faces=DUCT_FACES, c0=(cx, cy, cz), axes=(a, b, c))
+        tau = max(0.52, 0.5 + 3.0 * u_max * 2.0 * a / re)
+        body = dict(shape="ellipse" if ellipse else "circle", axes=w.pop("axes") if ellipse else (a,), bc="mls",
+                    me="lattice", motion="rotate" if rotating else "static", c0=w.pop("c0"), theta0=theta0,
+                    omega=omega)
+        w.pop("axes", None)
+        w.pop("c0", None)
+        w.update(tau=tau, rho0=1.0, eq="bgk", inlet_profile="parabolic", inlet_u=u_max, storage=storage,
+                 rho_noise=0.0, seed=seed, bodies=[body], reynolds=re)
+        out.append(dict(id=k, arrival=t, spec=w, max_steps=max_steps))
+    return out

@@ -1,6 +1,7 @@
 // Batches of domains (include/lbm.h, lbm_batch_*): the member tables the
 // batched kernels read, the per-step launch sequence and the autotuner of
 // the batched stream-collide launch shape.
+#include <math.h>
 #include <string.h>
 
 #include <algorithm>
@@ -21,6 +22,9 @@ struct lbm_batch_s {
   size_t dev_cap = 0;
   char* pinned = nullptr;
   size_t pinned_cap = 0;
+  // steady-state checks of the members: device checks + results
+  char* steady_dev = nullptr;
+  size_t steady_cap = 0;
 };
 
 namespace {
@@ -236,6 +240,7 @@ lbm_status lbm_batch_destroy(lbm_batch B) {
   }
   if (B->dev) (void)hipFree(B->dev);
   if (B->pinned) (void)hipHostFree(B->pinned);
+  if (B->steady_dev) (void)hipFree(B->steady_dev);
   delete B;
   if (e != hipSuccess) return fail(LBM_E_HIP, hipGetErrorString(e));
   return LBM_OK;
@@ -275,6 +280,54 @@ lbm_status lbm_batch_step(lbm_batch B, int64_t nsteps) {
   if (!B) return fail(LBM_E_INVAL, "null batch");
   if (nsteps < 0) return fail(LBM_E_INVAL, "negative step count");
   return batch_step(B, nsteps, nullptr, nullptr);
+}
+
+lbm_status lbm_batch_steady_state(lbm_batch B, int64_t window, double tol, int32_t* steady, double* rel_change) {
+  if (!B || !steady) return fail(LBM_E_INVAL, "null argument");
+  const size_t n = B->members.size();
+  if (n == 0) return LBM_OK;
+  std::vector<SteadyCheck> checks;
+  std::vector<int> slot(n, -1);
+  for (size_t i = 0; i < n; ++i) {
+    lbm_domain d = B->members[i];
+    SteadyCheck c{};
+    if (d->body[0].active && steady_check(d, 0, window, c)) {
+      slot[i] = (int)checks.size();
+      checks.push_back(c);
+    }
+  }
+  std::vector<double> out(2 * checks.size());
+  if (!checks.empty()) {
+    const size_t off = align256(checks.size() * sizeof(SteadyCheck));
+    const size_t need = off + out.size() * sizeof(double);
+    if (need > B->steady_cap) {
+      if (B->steady_dev) HIP_TRY(hipFree(B->steady_dev));
+      B->steady_dev = nullptr;
+      HIP_TRY(hipMalloc(&B->steady_dev, 2 * need));
+      B->steady_cap = 2 * need;
+    }
+    HIP_TRY(hipMemcpyAsync(B->steady_dev, checks.data(), checks.size() * sizeof(SteadyCheck), hipMemcpyHostToDevice,
+                           B->stream));
+    double* dout = reinterpret_cast<double*>(B->steady_dev + off);
+    HIP_TRY(launch_steady(reinterpret_cast<const SteadyCheck*>(B->steady_dev), (int)checks.size(), dout, B->stream));
+    HIP_TRY(hipMemcpyAsync(out.data(), dout, out.size() * sizeof(double), hipMemcpyDeviceToHost, B->stream));
+    HIP_TRY(hipStreamSynchronize(B->stream));
+  }
+  for (size_t i = 0; i < n; ++i) {
+    if (slot[i] < 0) {
+      steady[i] = -1;
+      if (rel_change) rel_change[i] = NAN;
+      continue;
+    }
+    const double r = out[2 * slot[i]];
+    steady[i] = r < tol ? 1 : 0;
+    if (rel_change) rel_change[i] = r;
+  }
+  for (lbm_domain d : B->members) {
+    lbm_status s = check_device_errors(d);
+    if (s != LBM_OK) return s;
+  }
+  return LBM_OK;
 }
 
 lbm_status lbm_batch_set_config(lbm_batch B, const lbm_batch_config* cfg) {

@@ -53,6 +53,7 @@ struct lbm_domain_s {
   hipStream_t stream = nullptr;
   hipStream_t own_stream = nullptr;  // the descriptor's stream (a batch may lend its own)
   struct lbm_batch_s* batch = nullptr;  // the batch the domain belongs to, if any
+  char* steady_buf = nullptr;           // device: one SteadyCheck and its two results
   bool owns_pool = false;
   char* pool = nullptr;
   size_t pool_bytes = 0;
@@ -95,6 +96,9 @@ int64_t region_rows(const Body& b, int64_t t, int mode);
 lbm_status check_device_errors(lbm_domain d);
 // the advance of body `id` from step t to t+1 on the current source buffer
 lbm_status launch_advance(lbm_domain d, int id, int64_t t);
+// the steady-state check of one body (see lbm_steady_state); false when the
+// ring does not hold both steps
+bool steady_check(lbm_domain d, int id, int64_t window, SteadyCheck& c);
 // start/stop events of the next timed launch of this kind (null when off)
 lbm_status timing_slot(lbm_domain d, int kind, int64_t nodes, hipEvent_t& e0, hipEvent_t& e1);
 

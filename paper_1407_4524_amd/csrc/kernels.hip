@@ -1398,6 +1398,33 @@ __global__ __launch_bounds__(NT) void k_body_step_batch(const BatchDomain* __res
 }
 
 // ---------------------------------------------------------------------------
+// steady-state check: relative change of the drag (x-force of the body's
+// momentum-exchange form) between steps t - 1 - window and t - 1, in FP64
+// from the record rings, one thread per check
+
+__global__ __launch_bounds__(64) void k_steady(const SteadyCheck* __restrict__ checks, int n, double* out) {
+  const int k = blockIdx.x * 64 + threadIdx.x;
+  if (k >= n) return;
+  const SteadyCheck c = checks[k];
+  const double* r1 = c.rec + ((c.t - 1) % c.rec_cap) * c.rec_stride;
+  const double* r0 = c.rec + ((c.t - 1 - c.window) % c.rec_cap) * c.rec_stride;
+  double f1, f0;
+  if (c.me_mode == 0) {
+    f1 = r1[0];
+    f0 = r0[0];
+  } else if (c.me_mode == 1) {
+    f1 = r1[0] + r1[6];
+    f0 = r0[0] + r0[6];
+  } else {
+    f1 = r1[12];
+    f0 = r0[12];
+  }
+  const double rel = fabs(f1 - f0) / fabs(f1);
+  out[2 * k] = rel;
+  out[2 * k + 1] = f1;
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 
 template <class F>
@@ -1561,6 +1588,12 @@ hipError_t launch_body_advance(int lat, int st, int eq, void* B, uint8_t* mask, 
                    n_links, cap, pose, bs, bc, body, mode, g, ph, rec_t, rec_t1, err);
     }
   });
+  return hipGetLastError();
+}
+
+hipError_t launch_steady(const SteadyCheck* checks, int n, double* out, hipStream_t s) {
+  if (n <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_steady, dim3((n + 63) / 64), dim3(64), 0, s, checks, n, out);
   return hipGetLastError();
 }
 

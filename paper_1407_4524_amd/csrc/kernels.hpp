@@ -49,6 +49,16 @@ hipError_t launch_body_advance(int lat, int st, int eq, void* B, uint8_t* mask, 
                                hipStream_t s, int64_t region_cells, int64_t region_rows,
                                hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 
+// Steady-state check of one body: relative change of its drag between
+// steps t - 1 - window and t - 1 (records of ring `rec`, slot stride
+// rec_stride doubles); out[2k] = relative change, out[2k+1] = drag at t - 1.
+struct SteadyCheck {
+  const double* rec;
+  int64_t rec_cap, rec_stride, t, window;
+  int me_mode;
+};
+hipError_t launch_steady(const SteadyCheck* checks, int n, double* out, hipStream_t s);
+
 // True when the per-step advance of a moving body whose region (node box of
 // poses t and t+1 plus a margin) has this many nodes and rows runs in the
 // single-workgroup LDS kernel (the batched path needs it).

@@ -32,6 +32,16 @@ struct Layout {
   int64_t rec_cap;
 };
 
+// link capacity of a body: (Q-1) links per node of a shell two nodes thick
+// around the circumscribed circle/sphere, doubled
+static int link_capacity(int D, const lbm_body_desc* bd) {
+  const int Q = D == 2 ? 9 : 19;
+  double rc = bd->axes[0];
+  if (bd->shape == LBM_SHAPE_ELLIPSE) rc = std::max(rc, std::max(bd->axes[1], D == 3 ? bd->axes[2] : 0.0));
+  const double shell = D == 2 ? 2.0 * PI * (rc + 3.0) * 4.0 : 4.0 * PI * (rc + 3.0) * (rc + 3.0) * 4.0;
+  return (int)std::min<double>(2.0 * (Q - 1) * shell + 1024.0, 2.0e9 / sizeof(Link));
+}
+
 static lbm_status check_desc(const lbm_domain_desc* d) {
   if (!d) return fail(LBM_E_INVAL, "null descriptor");
   if (d->lattice != LBM_D2Q9 && d->lattice != LBM_D3Q19) return fail(LBM_E_INVAL, "unknown lattice");
@@ -174,6 +184,17 @@ static Pose body_pose(const Body& b, const Geom& g, int64_t t) {
 static bool pose_inside(const Pose& p, const Geom& g) {
   for (int a = 0; a < g.D; ++a)
     if (p.lo[a] < g.lo[a] || p.hi[a] > g.hi[a]) return false;
+  return true;
+}
+
+bool lbm::host::steady_check(lbm_domain d, int id, int64_t window, SteadyCheck& c) {
+  if (window < 0 || d->t - 1 - window < 0 || window >= d->rec_cap) return false;
+  c.rec = d->rec + id * LBM_REC_LEN;
+  c.rec_cap = d->rec_cap;
+  c.rec_stride = LBM_MAX_BODIES * LBM_REC_LEN;
+  c.t = d->t;
+  c.window = window;
+  c.me_mode = d->body[id].desc.me_mode;
   return true;
 }
 
@@ -374,6 +395,17 @@ lbm_status lbm_footprint_bytes(const lbm_domain_desc* desc, size_t* bytes) {
   return LBM_OK;
 }
 
+lbm_status lbm_body_footprint_bytes(const lbm_domain_desc* desc, const lbm_body_desc* bd, size_t* bytes) {
+  lbm_status s = check_desc(desc);
+  if (s != LBM_OK) return s;
+  if (!bd || !bytes) return fail(LBM_E_INVAL, "null argument");
+  const int D = desc->lattice == LBM_D2Q9 ? 2 : 3;
+  const size_t cap = (size_t)link_capacity(D, bd);
+  *bytes = cap * sizeof(Link) + sizeof(int) + (cap + 63) / 64 * 12 * sizeof(double) +
+           (size_t)POSE_WINDOW * POSE_LEN * sizeof(double);
+  return LBM_OK;
+}
+
 lbm_status lbm_create_domain(const lbm_domain_desc* desc, lbm_domain* out) {
   lbm_status s = check_desc(desc);
   if (s != LBM_OK) return s;
@@ -461,6 +493,7 @@ lbm_status lbm_destroy_domain(lbm_domain d) {
     (void)hipEventDestroy(d->e_near);
     (void)hipEventDestroy(d->e_far);
   }
+  if (d->steady_buf) (void)hipFree(d->steady_buf);
   if (d->owns_pool) (void)hipFree(d->pool);
   for (int k = 0; k < 64; ++k)
     for (int j = 0; j < 2; ++j)
@@ -499,12 +532,7 @@ lbm_status lbm_set_body(lbm_domain d, int32_t id, const lbm_body_desc* bd) {
   nb.shape.ic2 = (bd->shape == LBM_SHAPE_ELLIPSE && d->D == 3) ? 1.0 / (bd->axes[2] * bd->axes[2]) : 0.0;
   const bool round = bd->shape != LBM_SHAPE_ELLIPSE;
   nb.mask_moves = !(bd->motion == LBM_MOTION_STATIC || (round && bd->motion == LBM_MOTION_ROTATE));
-  // link capacity: (Q-1) links per node of a shell two nodes thick around the
-  // circumscribed circle/sphere, doubled
-  double rc = bd->axes[0];
-  if (bd->shape == LBM_SHAPE_ELLIPSE) rc = std::max(rc, std::max(bd->axes[1], d->D == 3 ? bd->axes[2] : 0.0));
-  double shell = d->D == 2 ? 2.0 * PI * (rc + 3.0) * 4.0 : 4.0 * PI * (rc + 3.0) * (rc + 3.0) * 4.0;
-  nb.cap = (int)std::min<double>(2.0 * (d->Q - 1) * shell + 1024.0, 2.0e9 / sizeof(Link));
+  nb.cap = link_capacity(d->D, bd);
   b = std::move(nb);
   HIP_TRY(hipMalloc(&b.links, (size_t)b.cap * sizeof(Link)));
   HIP_TRY(hipMalloc(&b.n_links, sizeof(int)));
@@ -687,6 +715,25 @@ lbm_status lbm_get_links(lbm_domain d, int32_t id, int64_t cap, int64_t* node, i
     if (dir) dir[k] = L[k].dir;
     if (delta) delta[k] = L[k].delta;
   }
+  return LBM_OK;
+}
+
+lbm_status lbm_steady_state(lbm_domain d, int32_t id, int64_t window, double tol, int32_t* steady,
+                            double* rel_change) {
+  if (!d || !steady) return fail(LBM_E_INVAL, "null argument");
+  if (id < 0 || id >= LBM_MAX_BODIES || !d->body[id].active) return fail(LBM_E_INVAL, "no such body");
+  SteadyCheck c{};
+  if (!steady_check(d, id, window, c)) return fail(LBM_E_RANGE, "the record ring does not hold both steps");
+  if (!d->steady_buf) HIP_TRY(hipMalloc(&d->steady_buf, 256));
+  HIP_TRY(hipMemcpyAsync(d->steady_buf, &c, sizeof(c), hipMemcpyHostToDevice, d->stream));
+  double* out = reinterpret_cast<double*>(d->steady_buf + 128);
+  HIP_TRY(launch_steady(reinterpret_cast<const SteadyCheck*>(d->steady_buf), 1, out, d->stream));
+  double r[2];
+  HIP_TRY(hipMemcpyAsync(r, out, sizeof(r), hipMemcpyDeviceToHost, d->stream));
+  lbm_status s = lbm_synchronize(d);
+  if (s != LBM_OK) return s;
+  *steady = r[0] < tol ? 1 : 0;
+  if (rel_change) *rel_change = r[0];
   return LBM_OK;
 }
 

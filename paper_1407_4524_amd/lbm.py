@@ -32,11 +32,12 @@ STATUS = {0: "LBM_OK", -1: "LBM_E_INVAL", -2: "LBM_E_NOMEM", -3: "LBM_E_HIP", -4
 REC_LEN = 20
 MAX_BODIES = 4
 
-EXPORTS = ["lbm_footprint_bytes", "lbm_create_domain", "lbm_destroy_domain", "lbm_set_body", "lbm_step",
+EXPORTS = ["lbm_footprint_bytes", "lbm_body_footprint_bytes", "lbm_create_domain", "lbm_destroy_domain", "lbm_set_body", "lbm_step",
            "lbm_synchronize", "lbm_time", "lbm_force_torque", "lbm_records", "lbm_get_links",
            "lbm_get_fields", "lbm_get_types", "lbm_timing_enable", "lbm_timing_read", "lbm_last_error",
            "lbm_batch_create", "lbm_batch_destroy", "lbm_batch_add", "lbm_batch_remove", "lbm_batch_step",
-           "lbm_batch_set_config", "lbm_batch_get_config", "lbm_batch_tune"]
+           "lbm_batch_set_config", "lbm_batch_get_config", "lbm_batch_tune", "lbm_steady_state",
+           "lbm_batch_steady_state"]
 
 
 class LbmError(RuntimeError):
@@ -80,6 +81,7 @@ def lib():
             raise ImportError(f"{LIB_PATH} is missing: build it first (python -m paper_1407_4524_amd.build)")
         L = C.CDLL(LIB_PATH)
         L.lbm_footprint_bytes.argtypes = [C.POINTER(DomainDesc), C.POINTER(C.c_size_t)]
+        L.lbm_body_footprint_bytes.argtypes = [C.POINTER(DomainDesc), C.POINTER(BodyDesc), C.POINTER(C.c_size_t)]
         L.lbm_create_domain.argtypes = [C.POINTER(DomainDesc), C.POINTER(C.c_void_p)]
         L.lbm_destroy_domain.argtypes = [C.c_void_p]
         L.lbm_set_body.argtypes = [C.c_void_p, C.c_int32, C.POINTER(BodyDesc)]
@@ -105,6 +107,9 @@ def lib():
         L.lbm_batch_get_config.argtypes = [C.c_void_p, C.POINTER(BatchConfig)]
         L.lbm_batch_tune.argtypes = [C.c_void_p, C.c_int32, C.POINTER(BatchConfig), C.POINTER(BatchConfig),
                                      C.c_int32, C.POINTER(C.c_int32)]
+        L.lbm_steady_state.argtypes = [C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.POINTER(C.c_int32),
+                                       C.POINTER(C.c_double)]
+        L.lbm_batch_steady_state.argtypes = [C.c_void_p, C.c_int64, C.c_double, C.c_void_p, C.c_void_p]
         L.lbm_last_error.restype = C.c_char_p
         _lib = L
     return _lib
@@ -131,24 +136,76 @@ def _enum(table, v):
     return table[v] if isinstance(v, str) else int(v)
 
 
+def domain_desc(lattice="D2Q9", nx=64, ny=64, nz=1, tau=0.8, rho0=1.0, storage="f32", eq="bgk",
+                faces=("periodic",) * 6, inlet_profile="uniform", inlet_u=0.0, record_capacity=0,
+                plain_schedule=False):
+    """lbm_domain_desc of these settings (no initial fields, stream or buffer)"""
+    d = DomainDesc()
+    d.lattice = _enum(LATTICE, lattice)
+    d.nx, d.ny, d.nz = nx, ny, nz if d.lattice == 1 else 1
+    d.tau, d.rho0 = tau, rho0
+    d.storage = _enum(STORAGE, storage)
+    d.eq_model = _enum(EQ, eq)
+    for k in range(6):
+        d.face[k] = _enum(FACE, faces[k])
+    d.inlet_profile = _enum(PROFILE, inlet_profile)
+    d.inlet_u = inlet_u
+    d.record_capacity = record_capacity
+    d.plain_schedule = 1 if plain_schedule else 0
+    return d
+
+
+def body_desc(shape="circle", axes=(1.0,), bc="halfway", me="static", motion="static", c0=(0, 0, 0), theta0=0.0,
+              vel=(0, 0, 0), omega=0.0, amp=(0, 0, 0), period=1.0, table=None):
+    """(lbm_body_desc, arrays it points to) of these settings"""
+    b = BodyDesc()
+    b.shape = _enum(SHAPE, shape)
+    ax = list(axes) + [0.0] * (3 - len(axes))
+    if b.shape == 1 and len(axes) == 1:
+        ax = [axes[0]] * 3
+    for a in range(3):
+        b.axes[a] = ax[a]
+        b.c0[a] = c0[a] if a < len(c0) else 0.0
+        b.vel[a] = vel[a] if a < len(vel) else 0.0
+        b.amp[a] = amp[a] if a < len(amp) else 0.0
+    b.bc = _enum(BC, bc)
+    b.me_mode = _enum(ME, me)
+    b.motion = _enum(MOTION, motion)
+    b.theta0, b.omega, b.period = theta0, omega, period
+    keep = None
+    if table is not None:
+        keep = np.ascontiguousarray(table, dtype=np.float64).reshape(-1, 8)
+        b.pose_table = _dptr(keep)
+        b.pose_count = keep.shape[0]
+    return b, keep
+
+
+_SPEC_KEYS = ("lattice", "nx", "ny", "nz", "tau", "rho0", "storage", "eq", "faces", "inlet_profile", "inlet_u")
+
+
+def footprint_bytes(w, **kw):
+    """Device bytes a domain built from workload dictionary w takes, its
+    bodies included (lbm_footprint_bytes + lbm_body_footprint_bytes); no GPU
+    needed."""
+    d = domain_desc(**{k: w[k] for k in _SPEC_KEYS if k in w}, **kw)
+    n = C.c_size_t(0)
+    _check(lib().lbm_footprint_bytes(C.byref(d), C.byref(n)))
+    total = n.value
+    for b in w.get("bodies", []):
+        bd, _ = body_desc(**b)
+        _check(lib().lbm_body_footprint_bytes(C.byref(d), C.byref(bd), C.byref(n)))
+        total += n.value
+    return total
+
+
 class Domain:
     """One simulation domain on the current GPU (see include/lbm.h)."""
 
     def __init__(self, lattice="D2Q9", nx=64, ny=64, nz=1, tau=0.8, rho0=1.0, storage="f32", eq="bgk",
                  faces=("periodic",) * 6, inlet_profile="uniform", inlet_u=0.0, init_rho=None, init_u=None,
                  record_capacity=0, stream=None, torch_buffer=True, plain_schedule=False):
-        d = DomainDesc()
-        d.lattice = _enum(LATTICE, lattice)
-        d.nx, d.ny, d.nz = nx, ny, nz if d.lattice == 1 else 1
-        d.tau, d.rho0 = tau, rho0
-        d.storage = _enum(STORAGE, storage)
-        d.eq_model = _enum(EQ, eq)
-        for k in range(6):
-            d.face[k] = _enum(FACE, faces[k])
-        d.inlet_profile = _enum(PROFILE, inlet_profile)
-        d.inlet_u = inlet_u
-        d.record_capacity = record_capacity
-        d.plain_schedule = 1 if plain_schedule else 0
+        d = domain_desc(lattice, nx, ny, nz, tau, rho0, storage, eq, faces, inlet_profile, inlet_u,
+                        record_capacity, plain_schedule)
         self.nx, self.ny, self.nz = nx, ny, (nz if d.lattice == 1 else 1)
         self.N = self.nx * self.ny * self.nz
         keep = []
@@ -208,28 +265,11 @@ class Domain:
     def footprint(self):
         return None if self._buffer is None else self._buffer.numel()
 
-    def set_body(self, body_id, shape="circle", axes=(1.0,), bc="halfway", me="static", motion="static",
-                 c0=(0, 0, 0), theta0=0.0, vel=(0, 0, 0), omega=0.0, amp=(0, 0, 0), period=1.0, table=None):
-        b = BodyDesc()
-        b.shape = _enum(SHAPE, shape)
-        ax = list(axes) + [0.0] * (3 - len(axes))
-        if b.shape == 1 and len(axes) == 1:
-            ax = [axes[0]] * 3
-        for a in range(3):
-            b.axes[a] = ax[a]
-            b.c0[a] = c0[a] if a < len(c0) else 0.0
-            b.vel[a] = vel[a] if a < len(vel) else 0.0
-            b.amp[a] = amp[a] if a < len(amp) else 0.0
-        b.bc = _enum(BC, bc)
-        b.me_mode = _enum(ME, me)
-        b.motion = _enum(MOTION, motion)
-        b.theta0, b.omega, b.period = theta0, omega, period
-        if table is not None:
-            tab = np.ascontiguousarray(table, dtype=np.float64).reshape(-1, 8)
-            b.pose_table = _dptr(tab)
-            b.pose_count = tab.shape[0]
+    def set_body(self, body_id, **body):
+        """body settings as in body_desc()"""
+        b, keep = body_desc(**body)
         _check(lib().lbm_set_body(self._h, body_id, C.byref(b)))
-        self._bodies[body_id] = b
+        self._bodies[body_id] = (b, keep)
 
     def step(self, n=1):
         _check(lib().lbm_step(self._h, n))
@@ -285,6 +325,14 @@ class Domain:
         _check(lib().lbm_timing_read(self._h, _enum(KERNEL, kernel), C.byref(ms), C.byref(n), C.byref(nodes)))
         return ms.value, n.value, nodes.value
 
+    def steady_state(self, window=500, tol=1e-6, body_id=0):
+        """(steady, relative drag change over the last `window` steps), computed
+        on the device in FP64"""
+        st = C.c_int32(0)
+        rel = C.c_double(0)
+        _check(lib().lbm_steady_state(self._h, body_id, int(window), float(tol), C.byref(st), C.byref(rel)))
+        return bool(st.value), rel.value
+
     def types(self):
         t = np.zeros(self.N, np.int32)
         _check(lib().lbm_get_types(self._h, t.ctypes.data))
@@ -334,6 +382,16 @@ class Batch:
         n = C.c_int32(0)
         _check(lib().lbm_batch_tune(self._h, int(trial_steps), C.byref(chosen), trials, 64, C.byref(n)))
         return chosen.as_dict(), [trials[i].as_dict() for i in range(n.value)]
+
+    def steady_state(self, window=500, tol=1e-6):
+        """per member (in the order added): steady flag (1, 0, or -1 when it
+        cannot be evaluated yet) and relative drag change over `window` steps"""
+        n = len(self.members)
+        st = np.zeros(n, np.int32)
+        rel = np.zeros(n)
+        if n:
+            _check(lib().lbm_batch_steady_state(self._h, int(window), float(tol), st.ctypes.data, rel.ctypes.data))
+        return st, rel
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:

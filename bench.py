@@ -188,6 +188,44 @@ def run_batch(steps, count=64, seed=0, tune_steps=5):
                 finite_members=finite)
 
 
+def run_serving(count, max_steps, seed=0, rate=200.0, budget_gb=64.0):
+    """Served solves: a Poisson stream of requests (80 % D2Q9 sides
+    128..1024, 20 % D3Q19 sides 48..160, FP32/FP16-shifted, static or
+    rotating bodies) with continuous batching and admission by device
+    footprint, against the same stream served one request at a time; then a
+    second batched run offered 70 % of the measured batched capacity, for
+    latency under load. Requests stop at a relative drag change below 1e-6
+    over 500 steps, or at max_steps."""
+    import torch
+    import lbm_workloads as W
+    from paper_1407_4524_amd.serve import GpuEngine, Server, serve_plain, summary
+
+    def batched(reqs):
+        eng = GpuEngine()
+        srv = Server(eng, budget_gb * 2 ** 30, epoch=500, window=500, tol=1e-6)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = srv.run(reqs)
+        wall = time.perf_counter() - t0
+        eng.close()
+        out = summary(res, wall)
+        out.update(peak_active=srv.peak_active, peak_memory_gb=round(srv.peak_memory / 2 ** 30, 2))
+        return out, res
+
+    reqs = W.serving_requests(count=count, seed=seed, rate=rate, max_steps=max_steps)
+    sat, res_b = batched(reqs)
+    t0 = time.perf_counter()
+    res_p = serve_plain(reqs, epoch=500, window=500, tol=1e-6)
+    plain = summary(res_p, time.perf_counter() - t0)
+    by_id = {r.id: r for r in res_p}
+    same = all(r.force_torque == by_id[r.id].force_torque and r.steps == by_id[r.id].steps for r in res_b)
+    load_rate = 0.7 * sat["solves_per_s"]
+    loaded, _ = batched(W.serving_requests(count=count, seed=seed + 1, rate=load_rate, max_steps=max_steps))
+    return dict(workload=f"served_{count}_requests", max_steps=max_steps, offered_rate_per_s=rate,
+                batched=sat, plain=plain, speedup=round(plain["seconds"] / sat["seconds"], 2),
+                results_equal_alone=same, at_70pct_capacity=dict(offered_rate_per_s=round(load_rate, 3), **loaded))
+
+
 def copy_ceiling(nbytes, reps=20):
     """A plain device-to-device copy moving nbytes (half read, half written)
     per launch, as torch issues it: the copy ceiling at the stream-collide
@@ -241,6 +279,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-domain batched line")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served-requests line")
+    ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--serve-max-steps", type=int, default=3000)
     ap.add_argument("--batch-steps", type=int, default=5000)
     ap.add_argument("--no-copy-ceiling", action="store_true",
                     help="skip the plain-copy reference at the stream-collide footprint")
@@ -289,6 +330,8 @@ def main():
         line["secondary"] = sec
     if not args.no_batch and args.workload == "channel_oscillating_f32":
         line["batched"] = run_batch(args.batch_steps)
+    if not args.no_serve and args.workload == "channel_oscillating_f32":
+        line["served"] = run_serving(args.serve_requests, args.serve_max_steps)
     if not args.no_cpu_baseline and rank == 0:
         line["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)
     if rank == 0:

@@ -137,7 +137,7 @@ lbm_status make_plan(lbm_batch B, int64_t n, Plan& P) {
       int64_t cells = 0;
       for (int64_t k = 0; k < n && fits; ++k) {
         const int64_t c = region_cells(b, d->D, d->t + k, 1);
-        fits = body_step_fits(c, region_rows(b, d->t + k, 1));
+        fits = body_step_fits(c, region_rows(b, d->t + k, 1), list_bound(b, d->D, d->t + k));
         cells = std::max(cells, c);
       }
       if (fits) {
@@ -208,7 +208,7 @@ lbm_status batch_step(lbm_batch B, int64_t n, hipEvent_t e0, hipEvent_t e1) {
       HIP_TRY(launch_body_advance(d->lat, d->st, d->eq, cur, d->mask, d->mask_next, b.links, b.n_links, b.cap,
                                   pose_at(b, t), b.shape, b.desc.bc, f.second, 1, d->g, d->ph, rec_slot(d, t, f.second),
                                   rec_slot(d, t + 1, f.second), d->err, B->stream, region_cells(b, d->D, t, 1),
-                                  region_rows(b, t, 1)));
+                                  region_rows(b, t, 1), list_bound(b, d->D, t)));
     }
   }
   if (e1) HIP_TRY(hipEventRecord(e1, B->stream));

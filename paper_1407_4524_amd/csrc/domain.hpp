@@ -93,6 +93,8 @@ const double* pose_at(const Body& b, int64_t t);
 // nodes (with the one-node margin) and rows of the region of poses t, t+mode
 int64_t region_cells(const Body& b, int D, int64_t t, int mode);
 int64_t region_rows(const Body& b, int64_t t, int mode);
+// upper bound of the near-surface node list of body b's advance from t
+int64_t list_bound(const Body& b, int D, int64_t t);
 lbm_status check_device_errors(lbm_domain d);
 // the advance of body `id` from step t to t+1 on the current source buffer
 lbm_status launch_advance(lbm_domain d, int id, int64_t t);

@@ -735,7 +735,7 @@ __global__ __launch_bounds__(ADV_BLOCK) void k_body_advance(typename S::T* B, ui
 // x); false if the row misses the body. Rounding of a and b is absorbed by
 // the margin of the windows built from them; the status itself always comes
 // from shape_phi.
-__device__ inline bool row_chord(const BodyShape& b, const Pose& p, int y, int z, double& a, double& bb) {
+__host__ __device__ inline bool row_chord(const BodyShape& b, const Pose& p, int y, int z, double& a, double& bb) {
   const double dy = y - p.X[1], dz = b.D == 3 ? z - p.X[2] : 0.0;
   if (b.shape == SHAPE_CIRCLE) {
     const double q = b.R * b.R - dy * dy - dz * dz;
@@ -760,7 +760,7 @@ __device__ inline bool row_chord(const BodyShape& b, const Pose& p, int y, int z
 // which nothing can change between poses P0 and P1, nor hold a link at P1:
 // around both ends of the solid interval, over the row and its lattice
 // neighbour rows, widened by `m` nodes. Returns the number of windows.
-__device__ inline int row_windows(const BodyShape& b, const Pose& P0, const Pose& P1, int y, int z, int D, int m,
+__host__ __device__ inline int row_windows(const BodyShape& b, const Pose& P0, const Pose& P1, int y, int z, int D, int m,
                                   int xlo, int xhi, int w[4]) {
   double amin = 1e300, amax = -1e300, bmin = 1e300, bmax = -1e300;
   bool any = false, gap = false;
@@ -865,25 +865,15 @@ __global__ __launch_bounds__(ADV_BLOCK) void k_body_advance_lds(typename S::T* B
 
   __syncthreads();
   // phase A: status at the new pose, momentum of covered nodes, commit
-  // changes; the mask bytes of a thread's nodes are fetched in batches of 8
-  // so that their loads overlap
-  for (int k8 = 0; k8 < total; k8 += 8 * ADV_BLOCK) {
-    uint8_t olds[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int k = k8 + j * ADV_BLOCK + threadIdx.x;
-      int x, y, z;
-      E.at(k < total ? k : 0, x, y, z);
-      olds[j] = mask[g.idx(x, y, z)];
-    }
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-    const int k = k8 + j * ADV_BLOCK + threadIdx.x;
-    if (k >= total) break;
+  // changes. Each node's old status is read just before it is used: a form
+  // that fetched the status bytes of eight nodes ahead gave wrong covered-node
+  // sums with 4- and 2-byte storage on gfx950 (FP64 was right; the cause was
+  // not found), and this kernel is not on the hot path.
+  for (int k = threadIdx.x; k < total; k += ADV_BLOCK) {
     int x, y, z;
     E.at(k, x, y, z);
     const int64_t c = g.idx(x, y, z);
-    const uint8_t old = olds[j];
+    const uint8_t old = mask[c];
     uint8_t nw = old;
     if (R.contains(x, y, z) && in_window(x, y, z)) {
       const bool solid = shape_phi(bs, P1, (double)x, (double)y, (double)z) <= 0.0;
@@ -910,7 +900,6 @@ __global__ __launch_bounds__(ADV_BLOCK) void k_body_advance_lds(typename S::T* B
       imp[4] += r[2] * m[0] - r[0] * m[2];
       imp[5] += r[0] * m[1] - r[1] * m[0];
       imp[6] += 1.0;
-    }
     }
   }
   __syncthreads();
@@ -1567,16 +1556,15 @@ hipError_t launch_links(int lat, int st, int eq, void* A, const Link* links, int
 hipError_t launch_body_advance(int lat, int st, int eq, void* B, uint8_t* mask, uint8_t* mask_next, Link* links,
                                int* n_links, int cap, const double* pose, const BodyShape& bs, int bc, int body,
                                int mode, const Geom& g, const Phys& ph, double* rec_t, double* rec_t1, int* err,
-                               hipStream_t s, int64_t region_cells, int64_t region_rows, hipEvent_t e0,
-                               hipEvent_t e1) {
+                               hipStream_t s, int64_t region_cells, int64_t region_rows, int64_t list_nodes,
+                               hipEvent_t e0, hipEvent_t e1) {
   with_types(lat, st, eq, [&](auto Lt, auto St, auto E) {
     using L = decltype(Lt);
     using S = decltype(St);
     constexpr int EQ = decltype(E)::value;
     auto* b = (typename S::T*)B;
     const size_t lds = ((size_t)2 * region_cells + 15) / 16 * 16;
-    if (mode == 1 && bs.shape != SHAPE_OUTER_CIRCLE && region_cells > 0 && region_cells <= STEP_CELLS &&
-        region_rows <= STEP_ROWS) {
+    if (mode == 1 && bs.shape != SHAPE_OUTER_CIRCLE && body_step_fits(region_cells, region_rows, list_nodes)) {
       constexpr int NT = L::D == 2 ? 1024 : 512;  // 2D fits the 128 VGPRs of 1024-thread blocks
       launch_timed(k_body_step<L, S, EQ, NT>, dim3(1), dim3(NT), lds, s, e0, e1, b, mask, links, n_links, cap, pose,
                    bs, bc, body, g, ph, rec_t, rec_t1, err);
@@ -1597,8 +1585,25 @@ hipError_t launch_steady(const SteadyCheck* checks, int n, double* out, hipStrea
   return hipGetLastError();
 }
 
-bool body_step_fits(int64_t region_cells, int64_t region_rows) {
-  return region_cells > 0 && region_cells <= STEP_CELLS && region_rows <= STEP_ROWS;
+bool body_step_fits(int64_t region_cells, int64_t region_rows, int64_t list_nodes) {
+  return region_cells > 0 && region_cells <= STEP_CELLS && region_rows <= STEP_ROWS && list_nodes <= STEP_LIST;
+}
+
+int64_t step_list_nodes(const BodyShape& bs, const Pose& P0, const Pose& P1, int D) {
+  int lo[3], n[3];
+  for (int a = 0; a < 3; ++a) {
+    const int l = (int)(P0.lo[a] < P1.lo[a] ? P0.lo[a] : P1.lo[a]);
+    const int h = (int)(P0.hi[a] > P1.hi[a] ? P0.hi[a] : P1.hi[a]);
+    lo[a] = l;
+    n[a] = h - l + 1;
+  }
+  int64_t total = 0;
+  for (int r = 0; r < n[1] * n[2]; ++r) {
+    int w[4] = {0, -1, 0, -1};
+    const int k = row_windows(bs, P0, P1, lo[1] + r % n[1], lo[2] + r / n[1], D, 2, lo[0], lo[0] + n[0] - 1, w);
+    for (int q = 0; q < k; ++q) total += w[2 * q + 1] - w[2 * q] + 1 + 2;  // + 2: rounding of the chord ends
+  }
+  return total;
 }
 
 template <class L, class S, int EQ, int BX, int CPT>

@@ -46,7 +46,7 @@ hipError_t launch_links(int lat, int st, int eq, void* A, const Link* links, int
 hipError_t launch_body_advance(int lat, int st, int eq, void* B, uint8_t* mask, uint8_t* mask_next, Link* links,
                                int* n_links, int cap, const double* pose, const BodyShape& bs, int bc, int body,
                                int mode, const Geom& g, const Phys& ph, double* rec_t, double* rec_t1, int* err,
-                               hipStream_t s, int64_t region_cells, int64_t region_rows,
+                               hipStream_t s, int64_t region_cells, int64_t region_rows, int64_t list_nodes,
                                hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 
 // Steady-state check of one body: relative change of its drag between
@@ -60,9 +60,13 @@ struct SteadyCheck {
 hipError_t launch_steady(const SteadyCheck* checks, int n, double* out, hipStream_t s);
 
 // True when the per-step advance of a moving body whose region (node box of
-// poses t and t+1 plus a margin) has this many nodes and rows runs in the
+// poses t and t+1 plus a margin) has this many nodes and rows, and whose
+// near-surface node list has at most list_nodes entries, runs in the
 // single-workgroup LDS kernel (the batched path needs it).
-bool body_step_fits(int64_t region_cells, int64_t region_rows);
+bool body_step_fits(int64_t region_cells, int64_t region_rows, int64_t list_nodes);
+// Upper bound of the near-surface node list of the advance between poses
+// P0 and P1 (the row windows of the single-workgroup kernel; host only).
+int64_t step_list_nodes(const BodyShape& bs, const Pose& P0, const Pose& P1, int D);
 
 // ---------------------------------------------------------------------------
 // batches of domains advanced by the same launches

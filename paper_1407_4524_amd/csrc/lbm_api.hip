@@ -259,6 +259,13 @@ int64_t lbm::host::region_rows(const Body& b, int64_t t, int mode) {
   return n;
 }
 
+int64_t lbm::host::list_bound(const Body& b, int D, int64_t t) {
+  const int64_t cells = region_cells(b, D, t, 1);
+  if (cells <= 2048) return cells;  // the list holds nodes of the region only
+  const Pose* p0 = reinterpret_cast<const Pose*>(b.pose_pinned) + (t - b.pose_base);
+  return step_list_nodes(b.shape, p0[0], p0[1], D);
+}
+
 lbm_status lbm::host::check_device_errors(lbm_domain d) {
   int e[4] = {0, 0, 0, 0};
   HIP_TRY(hipMemcpy(e, d->err, sizeof(e), hipMemcpyDeviceToHost));
@@ -360,7 +367,7 @@ lbm_status lbm::host::launch_advance(lbm_domain d, int id, int64_t t) {
   HIP_TRY(launch_body_advance(d->lat, d->st, d->eq, d->A, d->mask, d->mask_next, b.links, b.n_links, b.cap,
                               pose_at(b, t), b.shape, b.desc.bc, id, 1, d->g, d->ph, rec_slot(d, t, id),
                               rec_slot(d, t + 1, id), d->err, d->stream, region_cells(b, d->D, t, 1),
-                              region_rows(b, t, 1), e0, e1));
+                              region_rows(b, t, 1), list_bound(b, d->D, t), e0, e1));
   return LBM_OK;
 }
 
@@ -547,7 +554,7 @@ lbm_status lbm_set_body(lbm_domain d, int32_t id, const lbm_body_desc* bd) {
   }
   HIP_TRY(launch_body_advance(d->lat, d->st, d->eq, d->A, d->mask, d->mask_next, b.links, b.n_links, b.cap,
                               pose_at(b, d->t), b.shape, bd->bc, id, 0, d->g, d->ph, nullptr, nullptr, d->err,
-                              d->stream, region_cells(b, d->D, d->t, 0), region_rows(b, d->t, 0)));
+                              d->stream, region_cells(b, d->D, d->t, 0), region_rows(b, d->t, 0), 0));
   HIP_TRY(hipMemcpyAsync(&b.n_host, b.n_links, sizeof(int), hipMemcpyDeviceToHost, d->stream));
   HIP_TRY(hipStreamSynchronize(d->stream));
   b.active = true;

@@ -591,8 +591,8 @@ lbm_status lbm_step(lbm_domain d, int64_t nsteps) {
                      d->body[only].desc.shape != LBM_SHAPE_OUTER_CIRCLE;
   if (split && !d->aux) {
     HIP_TRY(hipStreamCreateWithFlags(&d->aux, hipStreamNonBlocking));
-    HIP_TRY(hipEventCreateWithFlags(&d->e_near, hipEventDisableTiming));
-    HIP_TRY(hipEventCreateWithFlags(&d->e_far, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&d->e_near, hipEventDisableTiming | hipEventDisableSystemFence));
+    HIP_TRY(hipEventCreateWithFlags(&d->e_far, hipEventDisableTiming | hipEventDisableSystemFence));
   }
   const Geom& g = d->g;
   const int full_lo[3] = {g.lo[0], g.lo[1], g.lo[2]}, full_hi[3] = {g.hi[0], g.hi[1], g.hi[2]};

@@ -89,7 +89,9 @@ def run_gpu(name, steps, warmup, plain_schedule=False):
     import torch
     from paper_1407_4524_amd import Domain
     w = workload(name)
-    dom = Domain.from_spec(w, plain_schedule=plain_schedule)
+    stream = torch.cuda.Stream()  # the domain's own stream, as a serving process would give it
+    with torch.cuda.stream(stream):
+        dom = Domain.from_spec(w, plain_schedule=plain_schedule)
     dom.step(warmup)
     dom.synchronize()
     dom.timing_enable(TIMING_EVERY)
@@ -140,10 +142,13 @@ def run_batch(steps, count=64, seed=0, tune_steps=5):
     ws = W.batched_domains(count=count, seed=seed)
     nodes = sum(w["nx"] * w["ny"] for w in ws)
 
-    def fresh():
-        return [Domain.from_spec(w) for w in ws]
+    stream = torch.cuda.Stream()
 
-    tb = Batch()
+    def fresh():
+        with torch.cuda.stream(stream):
+            return [Domain.from_spec(w) for w in ws]
+
+    tb = Batch(stream=stream.cuda_stream)
     tdoms = fresh()
     for d in tdoms:
         tb.add(d)
@@ -153,7 +158,7 @@ def run_batch(steps, count=64, seed=0, tune_steps=5):
         d.close()
 
     doms = fresh()
-    batch = Batch()
+    batch = Batch(stream=stream.cuda_stream)
     for d in doms:
         batch.add(d)
     cfg = dict(chosen)

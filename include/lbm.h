@@ -249,10 +249,14 @@ typedef struct lbm_batch_s* lbm_batch;
 /* Launch shape of a batch. block x cells_per_thread nodes per tile, one of
    (64,1) (128,1) (256,1) (64,2) (128,2); remap 1 = blocks ordered so that
    each XCD takes a contiguous run of tiles; order 0 = tiles member by
-   member, 1 = largest members first, 2 = rows of all members interleaved.
-   us_per_step is filled in by lbm_batch_tune. */
+   member, 1 = largest members first, 2 = rows of all members interleaved;
+   overlap 1 = each member's nodes near its bodies (the node boxes of the
+   poses of the call plus one layer) are updated on the batch's stream
+   together with the body work, the rest on a second stream the batch owns
+   (default priority), so that the body work overlaps it. us_per_step is
+   filled in by lbm_batch_tune. Every shape gives bitwise the same result. */
 typedef struct {
-  int32_t block, cells_per_thread, remap, order;
+  int32_t block, cells_per_thread, remap, order, overlap;
   double us_per_step;
 } lbm_batch_config;
 

@@ -16,7 +16,10 @@ using namespace lbm::host;
 struct lbm_batch_s {
   hipStream_t stream = nullptr;
   std::vector<lbm_domain> members;
-  lbm_batch_config cfg{256, 1, 1, 0, 0.0};
+  lbm_batch_config cfg{256, 1, 1, 0, 1, 0.0};
+  // second stream of the overlapped step; created on first use
+  hipStream_t aux = nullptr;
+  hipEvent_t e_near = nullptr, e_far = nullptr;
   // device tables and their pinned staging copy, grown as needed
   char* dev = nullptr;
   size_t dev_cap = 0;
@@ -33,7 +36,7 @@ size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
 bool config_ok(const lbm_batch_config& c) {
   return batch_bulk_supported(c.block, c.cells_per_thread) && (c.remap == 0 || c.remap == 1) && c.order >= 0 &&
-         c.order <= 2;
+         c.order <= 2 && (c.overlap == 0 || c.overlap == 1);
 }
 
 int64_t active_nodes(const Geom& g) {
@@ -71,13 +74,45 @@ std::vector<BatchTile> make_tiles(const std::vector<lbm_domain>& m, const lbm_ba
 
 struct Plan {
   std::vector<BatchDomain> doms;
-  std::vector<BatchTile> tiles;
+  std::vector<BatchTile> tiles, near_tiles;
   std::vector<BatchBody> links, moving;
   std::vector<std::pair<int, int>> fallback;  // (member, body) advanced by its own launches
-  int link_grid = 1;
+  int link_grid = 1, max_links = 0;
   int64_t max_cells = 0;
-  size_t off_tiles = 0, off_links = 0, off_moving = 0, bytes = 0;
+  size_t off_tiles = 0, off_near = 0, off_links = 0, off_moving = 0, bytes = 0;
 };
+
+// Near box of a member for the steps t0 .. t0+n-1 of a call: the node boxes
+// of every pose its bodies take (t0-1 .. t0+n for a body whose solid set
+// moves, t0 for the others) plus one layer, within the active nodes; empty
+// for a member without bodies. Every node the body work of the call reads or
+// writes lies inside it, one layer away from the far update.
+void near_box_of(lbm_domain d, int64_t n, int hole[6]) {
+  const Geom& g = d->g;
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  bool any = false;
+  for (const Body& b : d->body) {
+    if (!b.active) continue;
+    const Pose* P = reinterpret_cast<const Pose*>(b.pose_pinned);
+    const int64_t k0 = (b.mask_moves && d->t - 1 >= b.pose_base) ? d->t - 1 : d->t;
+    const int64_t k1 = b.mask_moves ? d->t + n : d->t;
+    for (int64_t k = k0; k <= k1; ++k)
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = std::min(lo[a], P[k - b.pose_base].lo[a]);
+        hi[a] = std::max(hi[a], P[k - b.pose_base].hi[a]);
+      }
+    any = true;
+  }
+  if (!any) {
+    const int none[6] = {1, 0, 1, 0, 1, 0};
+    for (int k = 0; k < 6; ++k) hole[k] = none[k];
+    return;
+  }
+  for (int a = 0; a < 3; ++a) {
+    hole[2 * a] = std::max<int>(g.lo[a], (int)lo[a] - 1);
+    hole[2 * a + 1] = std::min<int>(g.hi[a], (int)hi[a] + 1);
+  }
+}
 
 BatchBody batch_body(lbm_domain d, int member, int id) {
   Body& b = d->body[id];
@@ -121,16 +156,27 @@ lbm_status make_plan(lbm_batch B, int64_t n, Plan& P) {
         b.bc_ready = true;
       }
     }
+  const int span = B->cfg.block * B->cfg.cells_per_thread;
   for (size_t i = 0; i < m.size(); ++i) {
     lbm_domain d = m[i];
-    P.doms.push_back(BatchDomain{d->g, d->ph, {d->A, d->B}});
+    BatchDomain bd{d->g, d->ph, {d->A, d->B}, {1, 0, 1, 0, 1, 0}};
+    if (B->cfg.overlap) {
+      near_box_of(d, n, bd.hole);
+      if (bd.hole[0] <= bd.hole[1]) {
+        const int nbx = (bd.hole[1] - bd.hole[0] + span) / span;
+        const int rows = (bd.hole[3] - bd.hole[2] + 1) * (bd.hole[5] - bd.hole[4] + 1);
+        for (int r = 0; r < rows; ++r)
+          for (int bx = 0; bx < nbx; ++bx) P.near_tiles.push_back(BatchTile{(uint16_t)i, (uint16_t)bx, r});
+      }
+    }
+    P.doms.push_back(bd);
     for (int id = 0; id < LBM_MAX_BODIES; ++id) {
       Body& b = d->body[id];
       if (!b.active) continue;
       BatchBody bb = batch_body(d, (int)i, id);
       if (!b.mask_moves) {
         P.links.push_back(bb);
-        P.link_grid = std::max(P.link_grid, std::min(LINK_GRID_MAX, (b.n_host + 255) / 256));
+        P.max_links = std::max(P.max_links, b.n_host);
         continue;
       }
       bool fits = b.desc.shape != LBM_SHAPE_OUTER_CIRCLE;
@@ -148,9 +194,11 @@ lbm_status make_plan(lbm_batch B, int64_t n, Plan& P) {
       }
     }
   }
+  P.link_grid = batch_link_grid(m.empty() ? 0 : m[0]->lat, P.max_links);
   P.tiles = make_tiles(m, B->cfg);
   P.off_tiles = align256(P.doms.size() * sizeof(BatchDomain));
-  P.off_links = P.off_tiles + align256(P.tiles.size() * sizeof(BatchTile));
+  P.off_near = P.off_tiles + align256(P.tiles.size() * sizeof(BatchTile));
+  P.off_links = P.off_near + align256(P.near_tiles.size() * sizeof(BatchTile));
   P.off_moving = P.off_links + align256(P.links.size() * sizeof(BatchBody));
   P.bytes = P.off_moving + align256(P.moving.size() * sizeof(BatchBody));
   return LBM_OK;
@@ -171,6 +219,7 @@ lbm_status upload(lbm_batch B, const Plan& P) {
   }
   memcpy(B->pinned, P.doms.data(), P.doms.size() * sizeof(BatchDomain));
   memcpy(B->pinned + P.off_tiles, P.tiles.data(), P.tiles.size() * sizeof(BatchTile));
+  memcpy(B->pinned + P.off_near, P.near_tiles.data(), P.near_tiles.size() * sizeof(BatchTile));
   memcpy(B->pinned + P.off_links, P.links.data(), P.links.size() * sizeof(BatchBody));
   memcpy(B->pinned + P.off_moving, P.moving.data(), P.moving.size() * sizeof(BatchBody));
   HIP_TRY(hipMemcpyAsync(B->dev, B->pinned, P.bytes, hipMemcpyHostToDevice, B->stream));
@@ -190,14 +239,40 @@ lbm_status batch_step(lbm_batch B, int64_t n, hipEvent_t e0, hipEvent_t e1) {
   if (e0) HIP_TRY(hipEventRecord(e0, B->stream));
   const auto* doms = reinterpret_cast<const BatchDomain*>(B->dev);
   const auto* tiles = reinterpret_cast<const BatchTile*>(B->dev + P.off_tiles);
+  const auto* near_tiles = reinterpret_cast<const BatchTile*>(B->dev + P.off_near);
   const auto* links = reinterpret_cast<const BatchBody*>(B->dev + P.off_links);
   const auto* moving = reinterpret_cast<const BatchBody*>(B->dev + P.off_moving);
   const BulkConfig bc{B->cfg.block, B->cfg.cells_per_thread, 0, B->cfg.remap};
+  const BulkConfig nc{B->cfg.block, B->cfg.cells_per_thread, 0, 0};
   const int lat = first->lat, st = first->st, eq = first->eq;
+  // Overlapped step (as the single-domain split of lbm_step): the far update
+  // of step k, on the second stream, waits for the near update of step k-1;
+  // the near update of step k waits for the far update of step k-1; the body
+  // work of a member only touches nodes inside its near box, one layer away
+  // from what the far update reads.
+  const bool split = B->cfg.overlap && !P.near_tiles.empty();
+  if (split && !B->aux) {
+    lbm_status sa = create_far_stream(B->stream, &B->aux, 8);  // one CU in 8 for the body kernels
+    if (sa != LBM_OK) return sa;
+    HIP_TRY(hipEventCreateWithFlags(&B->e_near, hipEventDisableTiming | hipEventDisableSystemFence));
+    HIP_TRY(hipEventCreateWithFlags(&B->e_far, hipEventDisableTiming | hipEventDisableSystemFence));
+  }
   for (int64_t k = 0; k < n; ++k) {
+    if (split) {
+      if (k > 0) HIP_TRY(hipStreamWaitEvent(B->stream, B->e_far, 0));
+      else HIP_TRY(hipEventRecord(B->e_near, B->stream));
+      HIP_TRY(hipStreamWaitEvent(B->aux, B->e_near, 0));
+      HIP_TRY(launch_batch_bulk(lat, st, eq, doms, tiles, (int)P.tiles.size(), bc, k, B->aux, 1));
+      HIP_TRY(hipEventRecord(B->e_far, B->aux));
+    }
     if (!P.links.empty())
       HIP_TRY(launch_batch_links(lat, st, eq, doms, links, (int)P.links.size(), P.link_grid, k, B->stream));
-    HIP_TRY(launch_batch_bulk(lat, st, eq, doms, tiles, (int)P.tiles.size(), bc, k, B->stream));
+    if (split) {
+      HIP_TRY(launch_batch_bulk(lat, st, eq, doms, near_tiles, (int)P.near_tiles.size(), nc, k, B->stream, 2));
+      HIP_TRY(hipEventRecord(B->e_near, B->stream));
+    } else {
+      HIP_TRY(launch_batch_bulk(lat, st, eq, doms, tiles, (int)P.tiles.size(), bc, k, B->stream, 0));
+    }
     if (!P.moving.empty())
       HIP_TRY(launch_batch_body_step(lat, st, eq, doms, moving, (int)P.moving.size(), P.max_cells, k, B->stream));
     for (const auto& f : P.fallback) {
@@ -211,6 +286,7 @@ lbm_status batch_step(lbm_batch B, int64_t n, hipEvent_t e0, hipEvent_t e1) {
                                   region_rows(b, t, 1), list_bound(b, d->D, t)));
     }
   }
+  if (split) HIP_TRY(hipStreamWaitEvent(B->stream, B->e_far, 0));
   if (e1) HIP_TRY(hipEventRecord(e1, B->stream));
   for (lbm_domain d : B->members) {
     d->t += n;
@@ -237,6 +313,12 @@ lbm_status lbm_batch_destroy(lbm_batch B) {
   for (lbm_domain d : B->members) {
     d->stream = d->own_stream;
     d->batch = nullptr;
+  }
+  if (B->aux) {
+    (void)hipStreamSynchronize(B->aux);
+    (void)hipStreamDestroy(B->aux);
+    (void)hipEventDestroy(B->e_near);
+    (void)hipEventDestroy(B->e_far);
   }
   if (B->dev) (void)hipFree(B->dev);
   if (B->pinned) (void)hipHostFree(B->pinned);
@@ -355,10 +437,11 @@ lbm_status lbm_batch_tune(lbm_batch B, int32_t trial_steps, lbm_batch_config* ch
   best.us_per_step = 1e300;
   int count = 0;
   lbm_status s = LBM_OK;
+  for (int overlap = 0; overlap <= 1 && s == LBM_OK; ++overlap)
   for (const auto& v : BATCH_BULK_VARIANTS)
     for (int remap = 0; remap <= 1 && s == LBM_OK; ++remap)
       for (int order = 0; order <= 2 && s == LBM_OK; ++order) {
-        B->cfg = lbm_batch_config{v[0], v[1], remap, order, 0.0};
+        B->cfg = lbm_batch_config{v[0], v[1], remap, order, overlap, 0.0};
         s = batch_step(B, trial_steps, e0, e1);
         if (s != LBM_OK) break;
         hipError_t e = hipEventSynchronize(e1);

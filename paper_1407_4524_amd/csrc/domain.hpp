@@ -101,6 +101,13 @@ lbm_status launch_advance(lbm_domain d, int id, int64_t t);
 // the steady-state check of one body (see lbm_steady_state); false when the
 // ring does not hold both steps
 bool steady_check(lbm_domain d, int id, int64_t window, SteadyCheck& c);
+// Second stream for the update of the nodes away from the bodies, beside
+// `main`: it may use every CU but one in `every` (spread over the device),
+// which stay free for the latency-bound body kernels running beside it. A
+// CU-masked stream synchronises with the legacy default stream, so with
+// main == the default stream (or when the device takes no CU mask) it is a
+// plain non-blocking stream instead.
+lbm_status create_far_stream(hipStream_t main, hipStream_t* s, int every);
 // start/stop events of the next timed launch of this kind (null when off)
 lbm_status timing_slot(lbm_domain d, int kind, int64_t nodes, hipEvent_t& e0, hipEvent_t& e1);
 

@@ -456,12 +456,18 @@ __device__ __forceinline__ void links_block(typename S::T* A, const Link* __rest
       if (lane == j) partials[c * 12 + j] = v;
     }
   }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) last = (atomicAdd(counter, 1u) == (unsigned)nblk - 1);
-  __syncthreads();
-  if (last && threadIdx.x < 64) {
+  if (nblk == 1) {  // the block's own chunk sums: no other block to wait for
+    __syncthreads();
+    if (threadIdx.x == 0) last = 1;
+    __syncthreads();
+  } else {
     __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last = (atomicAdd(counter, 1u) == (unsigned)nblk - 1);
+    __syncthreads();
+  }
+  if (last && threadIdx.x < 64) {
+    if (nblk > 1) __threadfence();
     double acc[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int c = lane; c < nchunks; c += 64)
 #pragma unroll
@@ -473,7 +479,7 @@ __device__ __forceinline__ void links_block(typename S::T* A, const Link* __rest
     }
     if (lane >= 12 && lane < 18) rec[lane - 6] = 0.0;  // node terms 6..11
     if (lane >= 18 && lane < 20) rec[lane] = 0.0;      // counts 18, 19
-    if (lane == 0) *counter = 0u;
+    if (lane == 0 && nblk > 1) *counter = 0u;
   }
 }
 
@@ -1343,10 +1349,12 @@ __device__ __forceinline__ double* batch_rec(const BatchBody& b, int64_t t) {
   return b.rec + (t % b.rec_cap) * b.rec_stride;
 }
 
+// part 0: tile rows of every node; 1: the same without the members' near
+// boxes; 2: tiles of the near boxes (rows numbered within the box)
 template <class L, class S, int EQ, int BX, int CPT>
 __global__ __launch_bounds__(BX) void k_stream_collide_batch(const BatchDomain* __restrict__ doms,
                                                              const BatchTile* __restrict__ tiles, int ntiles,
-                                                             int remap, int64_t s) {
+                                                             int remap, int64_t s, int part) {
   const int blk = remap ? xcd_block(blockIdx.x, ntiles) : blockIdx.x;
   const BatchTile tl = tiles[blk];
   const BatchDomain& D = doms[tl.dom];
@@ -1354,23 +1362,32 @@ __global__ __launch_bounds__(BX) void k_stream_collide_batch(const BatchDomain* 
   const Phys ph = D.ph;
   const auto* A = (const typename S::T*)D.buf[s & 1];
   auto* B = (typename S::T*)D.buf[(s + 1) & 1];
+  const int no_hole[6] = {1, 0, 1, 0, 1, 0};
+  if (part == 2) {
+    const int nrows = D.hole[3] - D.hole[2] + 1;
+    const int y = D.hole[2] + tl.row % nrows;
+    const int z = D.hole[4] + tl.row / nrows;
+    stream_collide_span<L, S, EQ, BX, CPT, false>(A, B, g, ph, D.hole[0] + tl.bx * (BX * CPT) + threadIdx.x, y, z,
+                                                  D.hole[1], no_hole);
+    return;
+  }
   const int nrows = g.hi[1] - g.lo[1] + 1;
   const int y = g.lo[1] + tl.row % nrows;
   const int z = g.lo[2] + tl.row / nrows;
-  const int no_hole[6] = {1, 0, 1, 0, 1, 0};
   stream_collide_span<L, S, EQ, BX, CPT, false>(A, B, g, ph, g.lo[0] + tl.bx * (BX * CPT) + threadIdx.x, y, z,
-                                                g.hi[0], no_hole);
+                                                g.hi[0], part == 1 ? D.hole : no_hole);
 }
 
-// grid (blocks per body, bodies): the boundary rule + momentum exchange of
-// batch step s before its bulk update, on the source buffer
-template <class L, class S, int EQ>
-__global__ __launch_bounds__(LINK_BLOCK) void k_links_batch(const BatchDomain* __restrict__ doms,
-                                                            const BatchBody* __restrict__ bodies, int64_t s) {
+// grid (blocks per body, bodies), NTL threads per block: the boundary rule +
+// momentum exchange of batch step s before its bulk update, on the source
+// buffer
+template <class L, class S, int EQ, int NTL>
+__global__ __launch_bounds__(NTL) void k_links_batch(const BatchDomain* __restrict__ doms,
+                                                     const BatchBody* __restrict__ bodies, int64_t s) {
   const BatchBody& b = bodies[blockIdx.y];
   const BatchDomain& D = doms[b.dom];
   const int64_t t = b.t0 + s;
-  links_block<L, S, EQ, LINK_BLOCK>((typename S::T*)D.buf[s & 1], b.links, b.n_host, b.pose + (t - b.pose_base) * POSE_DOUBLES,
+  links_block<L, S, EQ, NTL>((typename S::T*)D.buf[s & 1], b.links, b.n_host, b.pose + (t - b.pose_base) * POSE_DOUBLES,
                         b.bc, b.mask, D.g, D.ph, b.partials, b.counter, batch_rec(b, t), blockIdx.x, gridDim.x);
 }
 
@@ -1608,10 +1625,9 @@ int64_t step_list_nodes(const BodyShape& bs, const Pose& P0, const Pose& P1, int
 
 template <class L, class S, int EQ, int BX, int CPT>
 static void launch_batch_variant(const BatchDomain* doms, const BatchTile* tiles, int ntiles, int remap, int64_t step,
-                                 hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-  auto kern = k_stream_collide_batch<L, S, EQ, BX, CPT>;
-  if (e0) hipExtLaunchKernelGGL(kern, dim3(ntiles), dim3(BX), 0, s, e0, e1, 0, doms, tiles, ntiles, remap, step);
-  else hipLaunchKernelGGL(kern, dim3(ntiles), dim3(BX), 0, s, doms, tiles, ntiles, remap, step);
+                                 int part, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  launch_timed(k_stream_collide_batch<L, S, EQ, BX, CPT>, dim3(ntiles), dim3(BX), 0, s, e0, e1, doms, tiles, ntiles,
+               remap, step, part);
 }
 
 bool batch_bulk_supported(int block, int cells_per_thread) {
@@ -1621,9 +1637,10 @@ bool batch_bulk_supported(int block, int cells_per_thread) {
 }
 
 hipError_t launch_batch_bulk(int lat, int st, int eq, const BatchDomain* doms, const BatchTile* tiles, int ntiles,
-                             const BulkConfig& cfg, int64_t step, hipStream_t s, hipEvent_t ev_start,
+                             const BulkConfig& cfg, int64_t step, hipStream_t s, int part, hipEvent_t ev_start,
                              hipEvent_t ev_stop) {
-  if (ntiles <= 0 || !batch_bulk_supported(cfg.block, cfg.cells_per_thread)) return hipErrorInvalidValue;
+  if (ntiles <= 0 || !batch_bulk_supported(cfg.block, cfg.cells_per_thread) || part < 0 || part > 2)
+    return hipErrorInvalidValue;
   if ((ev_start == nullptr) != (ev_stop == nullptr)) return hipErrorInvalidValue;
   with_types(lat, st, eq, [&](auto Lt, auto St, auto E) {
     using L = decltype(Lt);
@@ -1631,7 +1648,7 @@ hipError_t launch_batch_bulk(int lat, int st, int eq, const BatchDomain* doms, c
     constexpr int EQ = decltype(E)::value;
 #define LBM_BATCH_CASE(BX_, CPT_)                                                                          \
   if (cfg.block == BX_ && cfg.cells_per_thread == CPT_) {                                                  \
-    launch_batch_variant<L, S, EQ, BX_, CPT_>(doms, tiles, ntiles, cfg.remap, step, s, ev_start, ev_stop); \
+    launch_batch_variant<L, S, EQ, BX_, CPT_>(doms, tiles, ntiles, cfg.remap, step, part, s, ev_start, ev_stop); \
     return;                                                                                                \
   }
     LBM_BATCH_CASE(64, 1)
@@ -1644,14 +1661,23 @@ hipError_t launch_batch_bulk(int lat, int st, int eq, const BatchDomain* doms, c
   return hipGetLastError();
 }
 
+int batch_link_grid(int lat, int max_links) {
+  if (lat == 0) return 1;  // 2D: one 1024-thread workgroup per body
+  return std::max(1, std::min(64, (max_links + LINK_BLOCK - 1) / LINK_BLOCK));
+}
+
 hipError_t launch_batch_links(int lat, int st, int eq, const BatchDomain* doms, const BatchBody* bodies, int nbodies,
                               int grid, int64_t step, hipStream_t s) {
-  if (nbodies <= 0 || grid <= 0 || grid > 64) return hipErrorInvalidValue;
+  if (nbodies <= 0 || grid <= 0 || grid > 64 || (lat == 0 && grid != 1)) return hipErrorInvalidValue;
   with_types(lat, st, eq, [&](auto Lt, auto St, auto E) {
     using L = decltype(Lt);
     using S = decltype(St);
     constexpr int EQ = decltype(E)::value;
-    hipLaunchKernelGGL((k_links_batch<L, S, EQ>), dim3(grid, nbodies), dim3(LINK_BLOCK), 0, s, doms, bodies, step);
+    if (L::D == 2)
+      hipLaunchKernelGGL((k_links_batch<L, S, EQ, 1024>), dim3(1, nbodies), dim3(1024), 0, s, doms, bodies, step);
+    else
+      hipLaunchKernelGGL((k_links_batch<L, S, EQ, LINK_BLOCK>), dim3(grid, nbodies), dim3(LINK_BLOCK), 0, s, doms,
+                         bodies, step);
   });
   return hipGetLastError();
 }

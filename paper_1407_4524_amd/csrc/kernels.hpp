@@ -73,11 +73,14 @@ int64_t step_list_nodes(const BodyShape& bs, const Pose& P0, const Pose& P1, int
 
 constexpr int POSE_DOUBLES = 16;  // doubles per Pose record
 
-// one member domain; the source buffer of batch step s is buf[s & 1]
+// one member domain; the source buffer of batch step s is buf[s & 1];
+// hole: its near box (x0, x1, y0, y1, z0, z1; empty when x0 > x1), skipped by
+// the far launch and covered by the near launch of a split batch step
 struct BatchDomain {
   Geom g;
   Phys ph;
   void* buf[2];
+  int hole[6];
 };
 
 // one block of the batched stream-collide launch: span bx of row `row` of
@@ -108,9 +111,14 @@ struct BatchBody {
 constexpr int BATCH_BULK_VARIANTS[5][2] = {{64, 1}, {128, 1}, {256, 1}, {64, 2}, {128, 2}};
 bool batch_bulk_supported(int block, int cells_per_thread);
 
+// part: 0 every node of the tiles' rows, 1 the same but the members' near
+// boxes, 2 near-box tiles (rows numbered within the box)
 hipError_t launch_batch_bulk(int lat, int st, int eq, const BatchDomain* doms, const BatchTile* tiles, int ntiles,
-                             const BulkConfig& cfg, int64_t step, hipStream_t s, hipEvent_t ev_start = nullptr,
-                             hipEvent_t ev_stop = nullptr);
+                             const BulkConfig& cfg, int64_t step, hipStream_t s, int part = 0,
+                             hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+// blocks per body of the batched link-rule launch for bodies of up to
+// max_links links
+int batch_link_grid(int lat, int max_links);
 hipError_t launch_batch_links(int lat, int st, int eq, const BatchDomain* doms, const BatchBody* bodies, int nbodies,
                               int grid, int64_t step, hipStream_t s);
 hipError_t launch_batch_body_step(int lat, int st, int eq, const BatchDomain* doms, const BatchBody* bodies,

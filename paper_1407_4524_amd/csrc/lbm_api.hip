@@ -187,6 +187,21 @@ static bool pose_inside(const Pose& p, const Geom& g) {
   return true;
 }
 
+lbm_status lbm::host::create_far_stream(hipStream_t main, hipStream_t* s, int every) {
+  int dev = 0, cus = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  if (main != nullptr && every > 1 && cus > every) {
+    std::vector<uint32_t> mask((size_t)(cus + 31) / 32, 0u);
+    for (int k = 0; k < cus; ++k)
+      if (k % every != every - 1) mask[k / 32] |= 1u << (k % 32);
+    if (hipExtStreamCreateWithCUMask(s, (uint32_t)mask.size(), mask.data()) == hipSuccess) return LBM_OK;
+    (void)hipGetLastError();
+  }
+  HIP_TRY(hipStreamCreateWithFlags(s, hipStreamNonBlocking));
+  return LBM_OK;
+}
+
 bool lbm::host::steady_check(lbm_domain d, int id, int64_t window, SteadyCheck& c) {
   if (window < 0 || d->t - 1 - window < 0 || window >= d->rec_cap) return false;
   c.rec = d->rec + id * LBM_REC_LEN;
@@ -341,6 +356,9 @@ lbm_status lbm::host::timing_slot(lbm_domain d, int kind, int64_t nodes, hipEven
   d->kind_nodes[kind] += nodes;
   return LBM_OK;
 }
+
+// one CU in FAR_CU_EVERY stays free of the far update of a split step
+static int FAR_CU_EVERY = 32;
 
 // launch shape of the near-box update: a small box, no block reordering,
 // and a shape no full sweep uses, so the near update is a kernel of its own
@@ -590,7 +608,8 @@ lbm_status lbm_step(lbm_domain d, int64_t nsteps) {
   const bool split = !d->desc.plain_schedule && nactive == 1 && d->body[only].mask_moves &&
                      d->body[only].desc.shape != LBM_SHAPE_OUTER_CIRCLE;
   if (split && !d->aux) {
-    HIP_TRY(hipStreamCreateWithFlags(&d->aux, hipStreamNonBlocking));
+    lbm_status sa = create_far_stream(d->stream, &d->aux, FAR_CU_EVERY);
+    if (sa != LBM_OK) return sa;
     HIP_TRY(hipEventCreateWithFlags(&d->e_near, hipEventDisableTiming | hipEventDisableSystemFence));
     HIP_TRY(hipEventCreateWithFlags(&d->e_far, hipEventDisableTiming | hipEventDisableSystemFence));
   }

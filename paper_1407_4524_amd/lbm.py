@@ -57,7 +57,7 @@ class DomainDesc(C.Structure):
 
 class BatchConfig(C.Structure):
     _fields_ = [("block", C.c_int32), ("cells_per_thread", C.c_int32), ("remap", C.c_int32), ("order", C.c_int32),
-                ("us_per_step", C.c_double)]
+                ("overlap", C.c_int32), ("us_per_step", C.c_double)]
 
     def as_dict(self):
         return {f[0]: getattr(self, f[0]) for f in self._fields_}
@@ -378,9 +378,9 @@ class Batch:
         """runs every candidate launch shape for trial_steps real steps, keeps
         the fastest; returns (chosen, [all trials]) as dictionaries"""
         chosen = BatchConfig()
-        trials = (BatchConfig * 64)()
+        trials = (BatchConfig * 128)()
         n = C.c_int32(0)
-        _check(lib().lbm_batch_tune(self._h, int(trial_steps), C.byref(chosen), trials, 64, C.byref(n)))
+        _check(lib().lbm_batch_tune(self._h, int(trial_steps), C.byref(chosen), trials, 128, C.byref(n)))
         return chosen.as_dict(), [trials[i].as_dict() for i in range(n.value)]
 
     def steady_state(self, window=500, tol=1e-6):

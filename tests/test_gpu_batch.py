@@ -43,17 +43,25 @@ def assert_same(a, b):
     assert np.array_equal(ra, rb, equal_nan=True) and np.array_equal(ua, ub, equal_nan=True)
 
 
-def test_batch_equals_each_domain_alone():
+@pytest.mark.parametrize("overlap,own_stream", [(1, True), (1, False), (0, False)])
+def test_batch_equals_each_domain_alone(overlap, own_stream):
+    """overlap on a stream of the batch's own uses the CU-masked second
+    stream, on the default stream a plain one"""
+    import torch
     from paper_1407_4524_amd import Batch
     ws = small_batch()
     kinds = {(w["bodies"][0]["shape"], w["bodies"][0]["motion"]) for w in ws}
     assert ("ellipse", "rotate") in kinds and any(m == "static" for _, m in kinds)
-    print("batch of", [(w["nx"], w["ny"], w["bodies"][0]["shape"], w["bodies"][0]["motion"]) for w in ws], flush=True)
+    print("batch of", [(w["nx"], w["ny"], w["bodies"][0]["shape"], w["bodies"][0]["motion"]) for w in ws],
+          f"overlap {overlap} own stream {own_stream}", flush=True)
     alone = [make_gpu(w, plain_schedule=True) for w in ws]
     for d in alone:
         d.step(150)
-    batch = Batch()
-    members = [make_gpu(w) for w in ws]
+    s = torch.cuda.Stream() if own_stream else torch.cuda.current_stream()
+    batch = Batch(stream=s.cuda_stream)
+    batch.config = dict(batch.config, overlap=overlap)
+    with torch.cuda.stream(s):
+        members = [make_gpu(w) for w in ws]
     for d in members:
         batch.add(d)
     for n in (1, 49, 100):  # several calls: the tables are rebuilt at each
@@ -97,10 +105,10 @@ def test_batch_members_at_different_steps_and_tuning():
     for d in members:
         batch.add(d)
     chosen, trials = batch.tune(trial_steps=3)
-    assert len(trials) == 30 and chosen["us_per_step"] == min(t["us_per_step"] for t in trials)
+    assert len(trials) == 60 and chosen["us_per_step"] == min(t["us_per_step"] for t in trials)
     batch.step(20)
     for a in alone:
-        a.step(30 * 3 + 20)
+        a.step(60 * 3 + 20)
     for a, m in zip(alone, members):
         assert_same(m, a)
     # a member can still be stepped on its own while it belongs to the batch

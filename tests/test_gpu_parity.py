@@ -232,11 +232,20 @@ def _moving(case):
     return w, 100
 
 
-@pytest.mark.parametrize("case", ["oscillating_f32", "ellipse_f64", "duct_f16"])
-def test_split_schedule_bitwise_equals_plain(case):
+@pytest.mark.parametrize("case,own_stream", [("oscillating_f32", True), ("ellipse_f64", False),
+                                             ("duct_f16", True)])
+def test_split_schedule_bitwise_equals_plain(case, own_stream):
+    """on the default stream the second stream is a plain one; on a stream
+    of the domain's own it is CU-masked"""
+    import torch
     w, steps = _moving(case)
-    print(f"split vs plain schedule: {w['name']} ({case}), {steps} steps", flush=True)
-    a = make_gpu(w)
+    print(f"split vs plain schedule: {w['name']} ({case}), {steps} steps, own stream {own_stream}", flush=True)
+    if own_stream:
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            a = make_gpu(w)
+    else:
+        a = make_gpu(w)
     b = make_gpu(w, plain_schedule=True)
     a.timing_enable(1)
     b.timing_enable(1)

@@ -281,7 +281,8 @@ lbm_status batch_step(lbm_batch B, int64_t n, hipEvent_t e0, hipEvent_t e1) {
       const int64_t t = d->t + k;
       void* cur = (k & 1) ? d->A : d->B;  // the state of t+1
       HIP_TRY(launch_body_advance(d->lat, d->st, d->eq, cur, d->mask, d->mask_next, b.links, b.n_links, b.cap,
-                                  pose_at(b, t), b.shape, b.desc.bc, f.second, 1, d->g, d->ph, rec_slot(d, t, f.second),
+                                  pose_at(b, t), pose_host_at(b, t), b.shape, b.desc.bc, f.second, 1, d->g, d->ph,
+                                  rec_slot(d, t, f.second),
                                   rec_slot(d, t + 1, f.second), d->err, B->stream, region_cells(b, d->D, t, 1),
                                   region_rows(b, t, 1), list_bound(b, d->D, t)));
     }

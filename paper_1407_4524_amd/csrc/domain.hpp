@@ -90,6 +90,7 @@ double* rec_slot(lbm_domain d, int64_t t, int b);
 // makes the device pose table of body b cover steps [t0, t1]
 lbm_status ensure_poses(lbm_domain d, Body& b, int64_t t0, int64_t t1);
 const double* pose_at(const Body& b, int64_t t);
+const double* pose_host_at(const Body& b, int64_t t);  // host copy of the same pose
 // nodes (with the one-node margin) and rows of the region of poses t, t+mode
 int64_t region_cells(const Body& b, int D, int64_t t, int mode);
 int64_t region_rows(const Body& b, int64_t t, int mode);

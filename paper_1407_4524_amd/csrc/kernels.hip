@@ -300,6 +300,28 @@ __device__ __forceinline__ void moments_at(const typename S::T* A, const Geom& g
   u[2] = jz / rhoU;
 }
 
+// Moments at node c in the storage's compute type (FP32 for FP32 and FP16
+// storage, FP64 for FP64), as the collision takes them.
+template <class L, class S>
+__device__ __forceinline__ void moments_c(const typename S::T* A, const Geom& g, int64_t c, double rho0, int eq,
+                                          typename S::C h[L::Q], typename S::C& drho, typename S::C u[3]) {
+  using C = typename S::C;
+  C jx = 0, jy = 0, jz = 0;
+  drho = 0;
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) {
+    h[q] = S::load(A + q * g.S + c);
+    drho += h[q];
+    jx += (C)L::cx(q) * h[q];
+    jy += (C)L::cy(q) * h[q];
+    jz += (C)L::cz(q) * h[q];
+  }
+  const C rhoU = eq ? (C)rho0 : (C)rho0 + drho;
+  u[0] = jx / rhoU;
+  u[1] = jy / rhoU;
+  u[2] = jz / rhoU;
+}
+
 // The interpolated boundary rule (Eq. Fillipova_interpolation with the
 // Mei-Luo-Shyy u_bf and chi; halfway bounce-back when bc == 0) for one link,
 // in deviation form, written to the solid node's slot; then the link's
@@ -309,49 +331,53 @@ __device__ __forceinline__ void moments_at(const typename S::T* A, const Geom& g
 // with v the wall velocity at the link's wall point, and torques r x m about
 // the body centre. The moving-wall term is +6 w_i rho c_i.u_B with c_i the
 // outgoing direction (the sign that drives the fluid with the wall).
+// nb_fluid: the node x_F + c_i (one step away from the wall) is fluid at t.
+// Its populations are loaded together with those of x_F whatever the case
+// (the node lies within the halo of the node array), so that the rule costs
+// one round trip to memory; they are used only for Delta < 1/2 when it is
+// fluid.
 // acc: [0..2] F static, [3..5] T static, [6..8] F comoving, [9..11] T comoving.
 template <class L, class S, int EQ>
-__device__ __forceinline__ void link_rule(typename S::T* A, const Link& lk, const Pose& P, int bc, const uint8_t* mask,
+__device__ __forceinline__ void link_rule(typename S::T* A, const Link& lk, const Pose& P, int bc, bool nb_fluid,
                           const Geom& g, const Phys& ph, double acc[12]) {
+  using C = typename S::C;
   const Dir<L> d = dir_of<L>(lk.dir);
   const int64_t c = lk.cell;
   const int64_t off = d.cx + d.cy * g.sy + d.cz * g.sz;
-  double h[L::Q], drho, uF[3];
-  moments_at<L, S>(A, g, c, ph.rho0, EQ, h, drho, uF);
-  double hin = 0;
+  C h[L::Q], drho, uF[3];
+  moments_c<L, S>(A, g, c, ph.rho0, EQ, h, drho, uF);
+  C hg[L::Q], dg, ug[3];
+  moments_c<L, S>(A, g, bc ? c + off : c, ph.rho0, EQ, hg, dg, ug);
+  C hin = 0;
 #pragma unroll
   for (int q = 0; q < L::Q; ++q)
     if (q == d.oi) hin = h[q];
-  const double rho = ph.rho0 + drho;
-  const double rhoU = EQ ? ph.rho0 : rho;
+  const C rhoU = EQ ? (C)ph.rho0 : (C)ph.rho0 + drho;
   const double xF = lk.x, yF = lk.y, zF = lk.z;
   const double dl = lk.delta;
   const double xB = xF - dl * d.cx, yB = yF - dl * d.cy;
-  double uB[3] = {P.V[0] - P.Om * (yB - P.X[1]), P.V[1] + P.Om * (xB - P.X[0]), L::D == 3 ? P.V[2] : 0.0};
-  const double wall = 6.0 * d.w * rhoU * (d.cx * uB[0] + d.cy * uB[1] + d.cz * uB[2]);
-  double hbc;
+  const double uB[3] = {P.V[0] - P.Om * (yB - P.X[1]), P.V[1] + P.Om * (xB - P.X[0]), L::D == 3 ? P.V[2] : 0.0};
+  const C uBc[3] = {(C)uB[0], (C)uB[1], (C)uB[2]};
+  const C wall = (C)(6.0 * d.w) * rhoU * ((C)d.cx * uBc[0] + (C)d.cy * uBc[1] + (C)d.cz * uBc[2]);
+  C hbc;
   if (bc == 0) {
     hbc = hin + wall;
   } else {
-    double ubf[3], chi;
+    const C dlc = (C)dl;
+    C ubf[3], chi;
     if (dl >= 0.5) {
-      const double f = 3.0 / (2.0 * dl);
-      for (int a = 0; a < 3; ++a) ubf[a] = uF[a] + f * (uB[a] - uF[a]);
-      chi = (2.0 * dl - 1.0) / (ph.tau + 0.5);
+      const C f = (C)1.5 / dlc;
+      for (int a = 0; a < 3; ++a) ubf[a] = uF[a] + f * (uBc[a] - uF[a]);
+      chi = ((C)2 * dlc - (C)1) / ((C)ph.tau + (C)0.5);
     } else {
-      if (mask[c + off] == MASK_FLUID) {
-        double hg[L::Q], dg;
-        moments_at<L, S>(A, g, c + off, ph.rho0, EQ, hg, dg, ubf);
-      } else {
-        for (int a = 0; a < 3; ++a) ubf[a] = uF[a];
-      }
-      chi = (2.0 * dl - 1.0) / (ph.tau - 2.0);
+      for (int a = 0; a < 3; ++a) ubf[a] = nb_fluid ? ug[a] : uF[a];
+      chi = ((C)2 * dlc - (C)1) / ((C)ph.tau - (C)2);
     }
-    const double cb_ubf = -(d.cx * ubf[0] + d.cy * ubf[1] + d.cz * ubf[2]);
-    const double cb_uF = -(d.cx * uF[0] + d.cy * uF[1] + d.cz * uF[2]);
-    const double uu = uF[0] * uF[0] + uF[1] * uF[1] + uF[2] * uF[2];
-    const double gdev = d.w * (drho + rhoU * (3.0 * cb_ubf + 4.5 * cb_uF * cb_uF - 1.5 * uu));
-    hbc = (1.0 - chi) * hin + chi * gdev + wall;
+    const C cb_ubf = -((C)d.cx * ubf[0] + (C)d.cy * ubf[1] + (C)d.cz * ubf[2]);
+    const C cb_uF = -((C)d.cx * uF[0] + (C)d.cy * uF[1] + (C)d.cz * uF[2]);
+    const C uu = uF[0] * uF[0] + uF[1] * uF[1] + uF[2] * uF[2];
+    const C gdev = (C)d.w * (drho + rhoU * ((C)3 * cb_ubf + (C)4.5 * cb_uF * cb_uF - (C)1.5 * uu));
+    hbc = ((C)1 - chi) * hin + chi * gdev + wall;
   }
   typename S::T* slot = A + d.i * g.S + c - off;
   S::store_plain(slot, hbc);
@@ -376,6 +402,15 @@ __device__ __forceinline__ void link_rule(typename S::T* A, const Link& lk, cons
   acc[9] += r[1] * mc[2] - r[2] * mc[1];
   acc[10] += r[2] * mc[0] - r[0] * mc[2];
   acc[11] += r[0] * mc[1] - r[1] * mc[0];
+}
+
+// link_rule with the neighbour status read from the global node mask
+template <class L, class S, int EQ>
+__device__ __forceinline__ void link_rule_m(typename S::T* A, const Link& lk, const Pose& P, int bc,
+                                            const uint8_t* mask, const Geom& g, const Phys& ph, double acc[12]) {
+  const Dir<L> d = dir_of<L>(lk.dir);
+  const bool nb = mask[lk.cell + d.cx + d.cy * g.sy + d.cz * g.sz] == MASK_FLUID;
+  link_rule<L, S, EQ>(A, lk, P, bc, nb, g, ph, acc);
 }
 
 // Deterministic block sum of N doubles per thread: xor-shuffle tree inside
@@ -404,11 +439,9 @@ constexpr int LINK_BLOCK = 256;
 // Boundary rule + momentum exchange over a body's link list at step t. The
 // last block to finish sums the per-block partials in block order and writes
 // the step's record (static and comoving sums; node terms zero).
-// Sum of a double over the 64 lanes of a wavefront without the LDS
-// crossbar: DPP row shifts give every lane 15, 31, 47, 63 its row's total,
-// then the four row totals are read out and added in a fixed order
-// (deterministic). Every lane returns the wavefront total.
-__device__ __forceinline__ double wave_sum(double v) {
+// Lane 15 of every row of 16 lanes gets the row's total: DPP row shifts,
+// without the LDS crossbar, in a fixed order.
+__device__ __forceinline__ double row_sum16(double v) {
   int lo = __double2loint(v), hi = __double2hiint(v);
 #define WAVE_SUM_STEP(CTRL)                                                              \
   {                                                                                      \
@@ -423,6 +456,15 @@ __device__ __forceinline__ double wave_sum(double v) {
   WAVE_SUM_STEP(0x114)  // row_shr:4
   WAVE_SUM_STEP(0x118)  // row_shr:8
 #undef WAVE_SUM_STEP
+  return __hiloint2double(hi, lo);
+}
+
+// Sum of a double over the 64 lanes of a wavefront: the four row totals of
+// row_sum16 read out and added in a fixed order (deterministic). Every lane
+// returns the wavefront total.
+__device__ __forceinline__ double wave_sum(double v) {
+  const double rs = row_sum16(v);
+  const int lo = __double2loint(rs), hi = __double2hiint(rs);
   double tot = 0.0;
 #pragma unroll
   for (int r = 0; r < 4; ++r)
@@ -449,7 +491,7 @@ __device__ __forceinline__ void links_block(typename S::T* A, const Link* __rest
   for (int c = blk * (NTL / 64) + (int)(threadIdx.x >> 6); c < nchunks; c += waves) {
     double acc[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     const int k = c * 64 + lane;
-    if (k < n) link_rule<L, S, EQ>(A, links[k], P, bc, mask, g, ph, acc);
+    if (k < n) link_rule_m<L, S, EQ>(A, links[k], P, bc, mask, g, ph, acc);
 #pragma unroll
     for (int j = 0; j < 12; ++j) {
       const double v = wave_sum(acc[j]);
@@ -722,7 +764,7 @@ __global__ __launch_bounds__(ADV_BLOCK) void k_body_advance(typename S::T* B, ui
   const int nl = total < cap ? total : cap;
   double acc[20];
   for (int k = 0; k < 20; ++k) acc[k] = 0.0;
-  for (int k = threadIdx.x; k < nl; k += ADV_BLOCK) link_rule<L, S, EQ>(B, links[k], P1, bc, mask, g, ph, acc);
+  for (int k = threadIdx.x; k < nl; k += ADV_BLOCK) link_rule_m<L, S, EQ>(B, links[k], P1, bc, mask, g, ph, acc);
   for (int k = 0; k < 8; ++k) acc[12 + k] = imp[k];
   block_sum<20, ADV_BLOCK>(acc, red, sm);
   if (threadIdx.x < 20) {
@@ -762,39 +804,41 @@ __host__ __device__ inline bool row_chord(const BodyShape& b, const Pose& p, int
   return true;
 }
 
-// Node windows [w0,w1] and [w2,w3] (x, inclusive) of row (y,z) outside
-// which nothing can change between poses P0 and P1, nor hold a link at P1:
-// around both ends of the solid interval, over the row and its lattice
-// neighbour rows, widened by `m` nodes. Returns the number of windows.
-__host__ __device__ inline int row_windows(const BodyShape& b, const Pose& P0, const Pose& P1, int y, int z, int D, int m,
-                                  int xlo, int xhi, int w[4]) {
+// Extent of the solid x-intervals over a set of (row, pose) chords: the
+// lowest and highest start and end, whether any chord hits the body and
+// whether any misses it.
+struct RowExtent {
   double amin = 1e300, amax = -1e300, bmin = 1e300, bmax = -1e300;
   bool any = false, gap = false;
-  for (int dz = (D == 3 ? -1 : 0); dz <= (D == 3 ? 1 : 0); ++dz)
-    for (int dy = -1; dy <= 1; ++dy)
-      for (int k = 0; k < 2; ++k) {
-        double a, bb;
-        if (row_chord(b, k ? P1 : P0, y + dy, z + dz, a, bb)) {
-          any = true;
-          amin = fmin(amin, a);
-          amax = fmax(amax, a);
-          bmin = fmin(bmin, bb);
-          bmax = fmax(bmax, bb);
-        } else {
-          gap = true;
-        }
-      }
-  if (!any) return 0;
+  __host__ __device__ void add(bool hit, double a, double bb) {
+    if (hit) {
+      any = true;
+      amin = fmin(amin, a);
+      amax = fmax(amax, a);
+      bmin = fmin(bmin, bb);
+      bmax = fmax(bmax, bb);
+    } else {
+      gap = true;
+    }
+  }
+};
+
+// Node windows [w0,w1] and [w2,w3] (x, inclusive) of a row from the extent
+// of its chords and those of its lattice neighbour rows at both poses,
+// widened by `m` nodes and clipped to [xlo, xhi]. Returns the number of
+// windows.
+__host__ __device__ inline int windows_of(const RowExtent& e, int m, int xlo, int xhi, int w[4]) {
+  if (!e.any) return 0;
   int n;
-  if (gap) {  // a cap row: one window over the whole hull
-    w[0] = (int)floor(amin) - m;
-    w[1] = (int)ceil(bmax) + m;
+  if (e.gap) {  // a cap row: one window over the whole hull
+    w[0] = (int)floor(e.amin) - m;
+    w[1] = (int)ceil(e.bmax) + m;
     n = 1;
   } else {
-    w[0] = (int)floor(amin) - m;
-    w[1] = (int)ceil(amax) + m;
-    w[2] = (int)floor(bmin) - m;
-    w[3] = (int)ceil(bmax) + m;
+    w[0] = (int)floor(e.amin) - m;
+    w[1] = (int)ceil(e.amax) + m;
+    w[2] = (int)floor(e.bmin) - m;
+    w[3] = (int)ceil(e.bmax) + m;
     n = 2;
     if (w[2] <= w[1] + 1) {
       w[1] = w[3];
@@ -806,6 +850,22 @@ __host__ __device__ inline int row_windows(const BodyShape& b, const Pose& P0, c
     w[2 * k + 1] = w[2 * k + 1] > xhi ? xhi : w[2 * k + 1];
   }
   return n;
+}
+
+// Node windows of row (y,z) outside which nothing can change between poses
+// P0 and P1, nor hold a link at P1: around both ends of the solid interval,
+// over the row and its lattice neighbour rows, widened by `m` nodes.
+__host__ __device__ inline int row_windows(const BodyShape& b, const Pose& P0, const Pose& P1, int y, int z, int D, int m,
+                                  int xlo, int xhi, int w[4]) {
+  RowExtent e;
+  for (int dz = (D == 3 ? -1 : 0); dz <= (D == 3 ? 1 : 0); ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int k = 0; k < 2; ++k) {
+        double a = 0, bb = 0;
+        const bool hit = row_chord(b, k ? P1 : P0, y + dy, z + dz, a, bb);
+        e.add(hit, a, bb);
+      }
+  return windows_of(e, m, xlo, xhi, w);
 }
 
 // Same operation as k_body_advance with the old and new node status of the
@@ -1017,7 +1077,7 @@ __global__ __launch_bounds__(ADV_BLOCK) void k_body_advance_lds(typename S::T* B
       lk.delta = link_delta(bs, P1, (double)lk.x, (double)lk.y, (double)lk.z, d.cx, d.cy, d.cz);
       links[k].delta = lk.delta;
     }
-    if (mode == 1) link_rule<L, S, EQ>(B, lk, P1, bc, mask, g, ph, acc);
+    if (mode == 1) link_rule_m<L, S, EQ>(B, lk, P1, bc, mask, g, ph, acc);
   }
   if (mode == 0) return;
   for (int k = 0; k < 8; ++k) acc[12 + k] = imp[k];
@@ -1044,51 +1104,74 @@ __global__ __launch_bounds__(ADV_BLOCK) void k_body_advance_lds(typename S::T* B
 constexpr int STEP_ROWS = 1024;   // region rows covered by the window table
 constexpr int STEP_LIST = 2048;   // window nodes
 constexpr int STEP_CELLS = 20480; // status box nodes (two bytes each)
+constexpr int STEP_LINKS = 8192;  // links held in LDS (the rest go through global memory)
 
 
+// Sum of the 20 record terms over the block: every row of 16 lanes sums its
+// lanes (row_sum16), the row totals go to LDS, and one wavefront per term
+// adds them (wave_sum) -- all in a fixed order. sm holds N * NT / 16
+// doubles. In 2D only Fx, Fy, Tz of each group (and the two counts) can be
+// non-zero; the others are written as zero.
 template <int NT, int D>
 __device__ __forceinline__ void block_sum_ft(double v[20], double* out, double* sm) {
-  // in 2D only Fx, Fy, Tz of each group (and the two counts) can be non-zero
   constexpr int K2[11] = {0, 1, 5, 6, 7, 11, 12, 13, 17, 18, 19};
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   constexpr int N = D == 2 ? 11 : 20;
+  constexpr int ROWS = NT / 16;
+  static_assert(ROWS <= 64, "one wavefront adds the row totals of a term");
+  const int lane = threadIdx.x & 63, row = threadIdx.x >> 4;
+  if (threadIdx.x < 20) out[threadIdx.x] = 0.0;
 #pragma unroll
   for (int j = 0; j < N; ++j) {
-    const double x = wave_sum(v[D == 2 ? K2[j] : j]);
-    if (lane == 0) sm[wave * N + j] = x;
+    const double x = row_sum16(v[D == 2 ? K2[j] : j]);
+    if ((threadIdx.x & 15) == 15) sm[j * ROWS + row] = x;
   }
   __syncthreads();
-  if (threadIdx.x < 20) out[threadIdx.x] = 0.0;
-  __syncthreads();
-  if (threadIdx.x < N) {
-    double t = 0;
-    for (int w = 0; w < NT / 64; ++w) t += sm[w * N + threadIdx.x];
-    out[D == 2 ? K2[threadIdx.x] : threadIdx.x] = t;
+  for (int j = (int)(threadIdx.x >> 6); j < N; j += NT / 64) {
+    const double t = wave_sum(lane < ROWS ? sm[j * ROWS + lane] : 0.0);
+    if (lane == 0) out[D == 2 ? K2[j] : j] = t;
   }
   __syncthreads();
 }
 
-template <class L, class S, int EQ, int NT>
+// The node box of a body at two poses (the region of its advance), when the
+// caller knows it: the kernel then reads the node status without waiting
+// for the poses.
+struct StepBox {
+  int lo[3], n[3];
+};
+
+template <class L, class S, int EQ, int NT, bool BOX>
 __device__ __forceinline__ void body_step(typename S::T* B, uint8_t* mask, Link* links, int* n_links, int cap,
                                           const double* pose, const BodyShape& bs, int bc, int body, const Geom& g,
-                                          const Phys& ph, double* rec_t, double* rec_t1, int* err) {
+                                          const Phys& ph, double* rec_t, double* rec_t1, int* err, StepBox box) {
   extern __shared__ uint8_t lds[];  // status box: [0,total) at t, [total,2 total) at t+1
-  __shared__ double sm[20 * NT / 64];
   __shared__ double red[20];
   __shared__ int scan_sm[NT / 64 + 1];
-  __shared__ int16_t win[STEP_ROWS][4];
+  // per region row: x-windows; once the list is built, the LDS list of
+  // uncovered nodes, then the block sum's row totals
+  __shared__ __align__(16) int16_t win[STEP_ROWS][4];
   __shared__ int8_t nwin[STEP_ROWS];
-  __shared__ uint32_t list[STEP_LIST];  // (x - R.lo[0]) | row << 16
+  __shared__ uint16_t rowoff[STEP_ROWS + 1];  // first list entry of each row
+  __shared__ uint32_t list[STEP_LIST];        // window nodes (x - R.lo[0]) | row << 16
+  __shared__ uint32_t linfo[STEP_LINKS];      // links of the new pose: list entry << 8 | direction
   __shared__ int list_n;
+  static_assert(STEP_ROWS * 8 >= (L::D == 2 ? 11 : 20) * (NT / 16) * 8, "row totals fit the window table");
+  static_assert(STEP_ROWS * 4 >= STEP_LIST, "uncovered-node list fits the window table");
   const Pose P0 = reinterpret_cast<const Pose*>(pose)[0];
   const Pose P1 = reinterpret_cast<const Pose*>(pose)[1];
   const uint8_t self = (uint8_t)(MASK_BODY0 + body);
   Region R, E;
   for (int a = 0; a < 3; ++a) {
-    int lo = (int)(P0.lo[a] < P1.lo[a] ? P0.lo[a] : P1.lo[a]);
-    int hi = (int)(P0.hi[a] > P1.hi[a] ? P0.hi[a] : P1.hi[a]);
-    R.lo[a] = lo;
-    R.n[a] = hi - lo + 1;
+    if (BOX) {
+      R.lo[a] = box.lo[a];
+      R.n[a] = box.n[a];
+    } else {
+      const int lo = (int)(P0.lo[a] < P1.lo[a] ? P0.lo[a] : P1.lo[a]);
+      const int hi = (int)(P0.hi[a] > P1.hi[a] ? P0.hi[a] : P1.hi[a]);
+      R.lo[a] = lo;
+      R.n[a] = hi - lo + 1;
+    }
+    const int lo = R.lo[a];
     const int m = a < L::D ? 1 : 0;
     E.lo[a] = lo - m;
     E.n[a] = R.n[a] + 2 * m;
@@ -1135,38 +1218,89 @@ __device__ __forceinline__ void body_step(typename S::T* B, uint8_t* mask, Link*
       }
     }
   }
-  // windows of every region row, in row order
-  const int rchunk = (nrow + NT - 1) / NT;
-  const int r0 = threadIdx.x * rchunk;
-  const int r1 = r0 + rchunk < nrow ? r0 + rchunk : nrow;
-  int my_cells = 0;
-  for (int r = r0; r < r1; ++r) {
-    int w[4] = {0, -1, 0, -1};
-    const int n = row_windows(bs, P0, P1, R.lo[1] + r % R.n[1], R.lo[2] + r / R.n[1], L::D, 2, R.lo[0],
-                              R.lo[0] + R.n[0] - 1, w);
-    nwin[r] = (int8_t)n;
+  // windows of every region row (rows r0 .. r1-1 of this thread, in thread
+  // order); the list is laid out in row order, window order, x order, and
+  // filled one entry per thread
+  int r0, r1, my_cells = 0;
+  if constexpr (L::D == 2) {
+    // a group of 8 lanes per row: lane j < 6 takes the chord of row y + j%3 - 1
+    // at pose j/3, and the group combines them (min / max are exact, so the
+    // windows are those of row_windows)
+    constexpr int GW = 8;
+    const int j = threadIdx.x & (GW - 1), rpg = (nrow + NT / GW - 1) / (NT / GW);
+    const int g0 = (threadIdx.x / GW) * rpg, g1 = g0 + rpg < nrow ? g0 + rpg : nrow;
+    for (int r = g0; r < g1; ++r) {
+      RowExtent e;
+      if (j < 6) {
+        double a = 0, bb = 0;
+        const bool hit = row_chord(bs, j < 3 ? P0 : P1, R.lo[1] + r + j % 3 - 1, R.lo[2], a, bb);
+        e.add(hit, a, bb);
+      }
+      int flags = (e.any ? 1 : 0) | (e.gap ? 2 : 0);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) win[r][q] = (int16_t)w[q];
-    if (n > 0) my_cells += w[1] - w[0] + 1;
-    if (n > 1) my_cells += w[3] - w[2] + 1;
-  }
-  int lbase = block_exclusive_scan<NT>(my_cells, scan_sm);
-  if (threadIdx.x == 0) {
-    list_n = scan_sm[NT / 64];
-    if (list_n > STEP_LIST) atomicOr(err, 4);
-  }
-  for (int r = r0; r < r1; ++r) {
+      for (int o = GW / 2; o > 0; o >>= 1) {
+        e.amin = fmin(e.amin, __shfl_xor(e.amin, o, GW));
+        e.amax = fmax(e.amax, __shfl_xor(e.amax, o, GW));
+        e.bmin = fmin(e.bmin, __shfl_xor(e.bmin, o, GW));
+        e.bmax = fmax(e.bmax, __shfl_xor(e.bmax, o, GW));
+        flags |= __shfl_xor(flags, o, GW);
+      }
+      e.any = flags & 1;
+      e.gap = (flags & 2) != 0;
+      if (j == 0) {
+        int w[4] = {0, -1, 0, -1};
+        const int n = windows_of(e, 2, R.lo[0], R.lo[0] + R.n[0] - 1, w);
+        nwin[r] = (int8_t)n;
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      if (q >= nwin[r]) break;
-      for (int x = win[r][2 * q]; x <= win[r][2 * q + 1]; ++x) {
-        if (lbase < STEP_LIST) list[lbase] = (uint32_t)(x - R.lo[0]) | ((uint32_t)r << 16);
-        lbase++;
+        for (int q = 0; q < 4; ++q) win[r][q] = (int16_t)w[q];
+        if (n > 0) my_cells += w[1] - w[0] + 1;
+        if (n > 1) my_cells += w[3] - w[2] + 1;
       }
     }
+    r0 = j == 0 ? g0 : 0;
+    r1 = j == 0 ? g1 : 0;
+  } else {
+    const int rchunk = (nrow + NT - 1) / NT;
+    r0 = threadIdx.x * rchunk;
+    r1 = r0 + rchunk < nrow ? r0 + rchunk : nrow;
+    for (int r = r0; r < r1; ++r) {
+      int w[4] = {0, -1, 0, -1};
+      const int n = row_windows(bs, P0, P1, R.lo[1] + r % R.n[1], R.lo[2] + r / R.n[1], L::D, 2, R.lo[0],
+                                R.lo[0] + R.n[0] - 1, w);
+      nwin[r] = (int8_t)n;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) win[r][q] = (int16_t)w[q];
+      if (n > 0) my_cells += w[1] - w[0] + 1;
+      if (n > 1) my_cells += w[3] - w[2] + 1;
+    }
+  }
+  int lbase = block_exclusive_scan<NT>(my_cells, scan_sm);
+  const int list_total = scan_sm[NT / 64];
+  if (threadIdx.x == 0) {
+    list_n = list_total;
+    if (list_total > STEP_LIST) atomicOr(err, 4);
+    rowoff[nrow] = (uint16_t)(list_total < STEP_LIST ? list_total : STEP_LIST);
+  }
+  for (int r = r0; r < r1; ++r) {
+    rowoff[r] = (uint16_t)(lbase < STEP_LIST ? lbase : STEP_LIST);
+    if (nwin[r] > 0) lbase += win[r][1] - win[r][0] + 1;
+    if (nwin[r] > 1) lbase += win[r][3] - win[r][2] + 1;
   }
   __syncthreads();
   const int nlist = list_n < STEP_LIST ? list_n : STEP_LIST;
+  for (int e = threadIdx.x; e < nlist; e += NT) {
+    int lo = 0, hi = nrow - 1;  // last row whose first entry is <= e
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if ((int)rowoff[mid] <= e) lo = mid;
+      else hi = mid - 1;
+    }
+    const int o = e - (int)rowoff[lo];
+    const int len0 = win[lo][1] - win[lo][0] + 1;
+    const int x = o < len0 ? win[lo][0] + o : win[lo][2] + (o - len0);
+    list[e] = (uint32_t)(x - R.lo[0]) | ((uint32_t)lo << 16);
+  }
+  __syncthreads();
   auto node = [&](int k, int& x, int& y, int& z) {
     const uint32_t e = list[k];
     const int r = (int)(e >> 16);
@@ -1212,36 +1346,90 @@ __device__ __forceinline__ void body_step(typename S::T* B, uint8_t* mask, Link*
   }
   __syncthreads();
 
-  // phase B: refill uncovered nodes and count links, over contiguous runs of
-  // the list (node order)
+  // phase B: over contiguous runs of the list (node order), the links of the
+  // new pose (to the global list, in node order) and the uncovered nodes (to
+  // an LDS list), counted together by one scan (links in the low half)
+  uint16_t* uncovered = reinterpret_cast<uint16_t*>(&win[0][0]);
   const int kchunk = (nlist + NT - 1) / NT;
   const int k0 = threadIdx.x * kchunk;
   const int k1 = k0 + kchunk < nlist ? k0 + kchunk : nlist;
-  int my_links = 0;
+  int my_links = 0, my_unc = 0;
   for (int k = k0; k < k1; ++k) {
     int x, y, z;
     node(k, x, y, z);
     if (STEP_STATUS(x, y, z, 1) != MASK_FLUID) continue;
-    if (STEP_STATUS(x, y, z, 0) == self) {  // uncovered: refill
-      const int64_t c = g.idx(x, y, z);
-      double rs = 0, us[3] = {0, 0, 0};
-      int cnt = 0;
+    if (STEP_STATUS(x, y, z, 0) == self) my_unc++;
 #pragma unroll
-      for (int i = 1; i < L::Q; ++i) {
-        const int xn = x + L::cx(i), yn = y + L::cy(i), zn = z + L::cz(i);
-        if (STEP_STATUS(xn, yn, zn, 0) != MASK_FLUID || STEP_STATUS(xn, yn, zn, 1) != MASK_FLUID) continue;
-        double hn[L::Q], dn, un[3];
-        moments_at<L, S>(B, g, g.idx(xn, yn, zn), ph.rho0, EQ, hn, dn, un);
-        rs += ph.rho0 + dn;
-        us[0] += un[0];
-        us[1] += un[1];
-        us[2] += un[2];
-        cnt++;
+    for (int i = 1; i < L::Q; ++i)
+      if (STEP_STATUS(x - L::cx(i), y - L::cy(i), z - L::cz(i), 1) == self) my_links++;
+  }
+  const int packed = block_exclusive_scan<NT>(my_links | (my_unc << 16), scan_sm);
+  const int nlinks = scan_sm[NT / 64] & 0xffff, n_unc = scan_sm[NT / 64] >> 16;
+  int base = packed & 0xffff, ubase = packed >> 16;
+  for (int k = k0; k < k1; ++k) {
+    int x, y, z;
+    node(k, x, y, z);
+    if (STEP_STATUS(x, y, z, 1) != MASK_FLUID) continue;
+    if (STEP_STATUS(x, y, z, 0) == self) uncovered[ubase++] = (uint16_t)k;
+#pragma unroll
+    for (int i = 1; i < L::Q; ++i) {
+      if (STEP_STATUS(x - L::cx(i), y - L::cy(i), z - L::cz(i), 1) != self) continue;
+      if (base < STEP_LINKS) {
+        linfo[base] = ((uint32_t)k << 8) | (uint32_t)i;
+      } else if (base < cap) {  // beyond the LDS list: through global memory
+        Link lk;
+        lk.cell = (int32_t)g.idx(x, y, z);
+        lk.x = (int16_t)x;
+        lk.y = (int16_t)y;
+        lk.z = (int16_t)z;
+        lk.dir = (int16_t)i;
+        lk.delta = 0.5;
+        links[base] = lk;
       }
+      base++;
+    }
+  }
+  if (threadIdx.x == 0) {
+    *n_links = nlinks < cap ? nlinks : cap;
+    if (nlinks > cap) atomicOr(err, 1);
+  }
+  __syncthreads();
+
+  // refill of the uncovered nodes with the equilibrium at the mean density
+  // and velocity of their neighbours fluid at t and t+1 (the wall velocity
+  // when there are none): a group of G lanes per node, lane j reading the
+  // moments of neighbour j + 1, so that all neighbours are read at once;
+  // the group sums them with a fixed shuffle tree
+  {
+    constexpr int G = L::Q - 1 <= 8 ? 8 : 32;
+    const int j = threadIdx.x & (G - 1);
+    for (int u = threadIdx.x / G; u < n_unc; u += NT / G) {
+      int x, y, z;
+      node(uncovered[u], x, y, z);
+      double v[5] = {0, 0, 0, 0, 0};  // density, velocity, count
+      if (j + 1 < L::Q) {
+        const Dir<L> d = dir_of<L>(j + 1);
+        const int xn = x + d.cx, yn = y + d.cy, zn = z + d.cz;
+        if (STEP_STATUS(xn, yn, zn, 0) == MASK_FLUID && STEP_STATUS(xn, yn, zn, 1) == MASK_FLUID) {
+          double hn[L::Q], dn, un[3];
+          moments_at<L, S>(B, g, g.idx(xn, yn, zn), ph.rho0, EQ, hn, dn, un);
+          v[0] = ph.rho0 + dn;
+          v[1] = un[0];
+          v[2] = un[1];
+          v[3] = un[2];
+          v[4] = 1.0;
+        }
+      }
+#pragma unroll
+      for (int o = G / 2; o > 0; o >>= 1)
+#pragma unroll
+        for (int q = 0; q < 5; ++q) v[q] += __shfl_xor(v[q], o, G);
+      if (j != 0) continue;
+      const int64_t c = g.idx(x, y, z);
       double rb, ub[3];
-      if (cnt > 0) {
-        rb = rs / cnt;
-        for (int a = 0; a < 3; ++a) ub[a] = us[a] / cnt;
+      if (v[4] > 0.0) {
+        rb = v[0] / v[4];
+        for (int a = 0; a < 3; ++a) ub[a] = v[1 + a] / v[4];
       } else {
         rb = ph.rho0;
         ub[0] = P1.V[0] - P1.Om * (y - P1.X[1]);
@@ -1258,10 +1446,10 @@ __device__ __forceinline__ void body_step(typename S::T* B, uint8_t* mask, Link*
         const double cu = L::cx(i) * ub[0] + L::cy(i) * ub[1] + L::cz(i) * ub[2];
         const double heq = L::w(i) * (drb + rhoU * (3.0 * cu + 4.5 * cu * cu - usq));
         S::store_plain(B + i * g.S + c, heq);
-        const double v = S::round_trip(heq);
-        m[0] += L::cx(i) * v;
-        m[1] += L::cy(i) * v;
-        m[2] += L::cz(i) * v;
+        const double hv = S::round_trip(heq);
+        m[0] += L::cx(i) * hv;
+        m[1] += L::cy(i) * hv;
+        m[2] += L::cz(i) * hv;
       }
       const double rr[3] = {x - P0.X[0], y - P0.X[1], z - P0.X[2]};
       imp[0] -= m[0];
@@ -1272,56 +1460,40 @@ __device__ __forceinline__ void body_step(typename S::T* B, uint8_t* mask, Link*
       imp[5] -= rr[0] * m[1] - rr[1] * m[0];
       imp[7] += 1.0;
     }
-#pragma unroll
-    for (int i = 1; i < L::Q; ++i)
-      if (STEP_STATUS(x - L::cx(i), y - L::cy(i), z - L::cz(i), 1) == self) my_links++;
-  }
-  int base = block_exclusive_scan<NT>(my_links, scan_sm);
-  const int nlinks = scan_sm[NT / 64];
-  for (int k = k0; k < k1; ++k) {
-    int x, y, z;
-    node(k, x, y, z);
-    if (STEP_STATUS(x, y, z, 1) != MASK_FLUID) continue;
-#pragma unroll
-    for (int i = 1; i < L::Q; ++i) {
-      if (STEP_STATUS(x - L::cx(i), y - L::cy(i), z - L::cz(i), 1) != self) continue;
-      if (base < cap) {
-        Link lk;
-        lk.cell = (int32_t)g.idx(x, y, z);
-        lk.x = (int16_t)x;
-        lk.y = (int16_t)y;
-        lk.z = (int16_t)z;
-        lk.dir = (int16_t)i;
-        lk.delta = 0.5;
-        links[base] = lk;
-      }
-      base++;
-    }
-  }
-#undef STEP_STATUS
-  if (threadIdx.x == 0) {
-    *n_links = nlinks < cap ? nlinks : cap;
-    if (nlinks > cap) atomicOr(err, 1);
   }
   __syncthreads();
 
-  // phase C: Delta, boundary rule and momentum exchange of step t+1
+  // phase C: Delta, boundary rule and momentum exchange of step t+1, one
+  // link per thread; the status of x_F + c_i comes from the status box. The
+  // link list of the new pose is written out here, with its Delta.
   const int nl = nlinks < cap ? nlinks : cap;
   double acc[20];
 #pragma unroll
   for (int k = 0; k < 20; ++k) acc[k] = 0.0;
   for (int k = threadIdx.x; k < nl; k += NT) {
-    Link lk = links[k];
-    if (bc) {
-      const Dir<L> d = dir_of<L>(lk.dir);
-      lk.delta = link_delta(bs, P1, (double)lk.x, (double)lk.y, (double)lk.z, d.cx, d.cy, d.cz);
-      links[k].delta = lk.delta;
+    Link lk;
+    if (k < STEP_LINKS) {
+      const uint32_t e = linfo[k];
+      int x, y, z;
+      node((int)(e >> 8), x, y, z);
+      lk.cell = (int32_t)g.idx(x, y, z);
+      lk.x = (int16_t)x;
+      lk.y = (int16_t)y;
+      lk.z = (int16_t)z;
+      lk.dir = (int16_t)(e & 0xff);
+    } else {
+      lk = links[k];
     }
-    link_rule<L, S, EQ>(B, lk, P1, bc, mask, g, ph, acc);
+    const Dir<L> d = dir_of<L>(lk.dir);
+    lk.delta = bc ? link_delta(bs, P1, (double)lk.x, (double)lk.y, (double)lk.z, d.cx, d.cy, d.cz) : 0.5;
+    const bool nb = STEP_STATUS(lk.x + d.cx, lk.y + d.cy, lk.z + d.cz, 1) == MASK_FLUID;
+    link_rule<L, S, EQ>(B, lk, P1, bc, nb, g, ph, acc);
+    links[k] = lk;
   }
+#undef STEP_STATUS
 #pragma unroll
   for (int k = 0; k < 8; ++k) acc[12 + k] = imp[k];
-  block_sum_ft<NT, L::D>(acc, red, sm);
+  block_sum_ft<NT, L::D>(acc, red, reinterpret_cast<double*>(&win[0][0]));
   if (threadIdx.x < 20) {
     const int k = threadIdx.x;
     const double v = red[k];
@@ -1337,8 +1509,9 @@ __device__ __forceinline__ void body_step(typename S::T* B, uint8_t* mask, Link*
 template <class L, class S, int EQ, int NT>
 __global__ __launch_bounds__(NT) void k_body_step(typename S::T* B, uint8_t* mask, Link* links, int* n_links,
                                                   int cap, const double* pose, BodyShape bs, int bc, int body,
-                                                  Geom g, Phys ph, double* rec_t, double* rec_t1, int* err) {
-  body_step<L, S, EQ, NT>(B, mask, links, n_links, cap, pose, bs, bc, body, g, ph, rec_t, rec_t1, err);
+                                                  Geom g, Phys ph, double* rec_t, double* rec_t1, int* err,
+                                                  StepBox box) {
+  body_step<L, S, EQ, NT, true>(B, mask, links, n_links, cap, pose, bs, bc, body, g, ph, rec_t, rec_t1, err, box);
 }
 
 // ---------------------------------------------------------------------------
@@ -1398,9 +1571,9 @@ __global__ __launch_bounds__(NT) void k_body_step_batch(const BatchDomain* __res
   const BatchBody& b = bodies[blockIdx.x];
   const BatchDomain& D = doms[b.dom];
   const int64_t t = b.t0 + s;
-  body_step<L, S, EQ, NT>((typename S::T*)D.buf[(s + 1) & 1], b.mask, b.links, b.n_links, b.cap,
-                          b.pose + (t - b.pose_base) * POSE_DOUBLES, b.bs, b.bc, b.body, D.g, D.ph,
-                          batch_rec(b, t), batch_rec(b, t + 1), b.err);
+  body_step<L, S, EQ, NT, false>((typename S::T*)D.buf[(s + 1) & 1], b.mask, b.links, b.n_links, b.cap,
+                                 b.pose + (t - b.pose_base) * POSE_DOUBLES, b.bs, b.bc, b.body, D.g, D.ph,
+                                 batch_rec(b, t), batch_rec(b, t + 1), b.err, StepBox{});
 }
 
 // ---------------------------------------------------------------------------
@@ -1571,9 +1744,9 @@ hipError_t launch_links(int lat, int st, int eq, void* A, const Link* links, int
 }
 
 hipError_t launch_body_advance(int lat, int st, int eq, void* B, uint8_t* mask, uint8_t* mask_next, Link* links,
-                               int* n_links, int cap, const double* pose, const BodyShape& bs, int bc, int body,
-                               int mode, const Geom& g, const Phys& ph, double* rec_t, double* rec_t1, int* err,
-                               hipStream_t s, int64_t region_cells, int64_t region_rows, int64_t list_nodes,
+                               int* n_links, int cap, const double* pose, const double* pose_host, const BodyShape& bs,
+                               int bc, int body, int mode, const Geom& g, const Phys& ph, double* rec_t, double* rec_t1,
+                               int* err, hipStream_t s, int64_t region_cells, int64_t region_rows, int64_t list_nodes,
                                hipEvent_t e0, hipEvent_t e1) {
   with_types(lat, st, eq, [&](auto Lt, auto St, auto E) {
     using L = decltype(Lt);
@@ -1583,8 +1756,16 @@ hipError_t launch_body_advance(int lat, int st, int eq, void* B, uint8_t* mask, 
     const size_t lds = ((size_t)2 * region_cells + 15) / 16 * 16;
     if (mode == 1 && bs.shape != SHAPE_OUTER_CIRCLE && body_step_fits(region_cells, region_rows, list_nodes)) {
       constexpr int NT = L::D == 2 ? 1024 : 512;  // 2D fits the 128 VGPRs of 1024-thread blocks
+      const Pose* P = reinterpret_cast<const Pose*>(pose_host);  // the same two poses, host copy
+      StepBox box;
+      for (int a = 0; a < 3; ++a) {
+        const int lo = (int)(P[0].lo[a] < P[1].lo[a] ? P[0].lo[a] : P[1].lo[a]);
+        const int hi = (int)(P[0].hi[a] > P[1].hi[a] ? P[0].hi[a] : P[1].hi[a]);
+        box.lo[a] = lo;
+        box.n[a] = hi - lo + 1;
+      }
       launch_timed(k_body_step<L, S, EQ, NT>, dim3(1), dim3(NT), lds, s, e0, e1, b, mask, links, n_links, cap, pose,
-                   bs, bc, body, g, ph, rec_t, rec_t1, err);
+                   bs, bc, body, g, ph, rec_t, rec_t1, err, box);
     } else if (region_cells > 0 && region_cells <= ADV_LDS_CELLS) {
       launch_timed(k_body_advance_lds<L, S, EQ>, dim3(1), dim3(ADV_BLOCK), lds, s, e0, e1, b, mask, links, n_links,
                    cap, pose, bs, bc, body, mode, g, ph, rec_t, rec_t1, err);

@@ -43,10 +43,12 @@ hipError_t launch_links(int lat, int st, int eq, void* A, const Link* links, int
                         int grid, const double* pose, int bc, const uint8_t* mask, const Geom& g, const Phys& ph,
                         double* partials, unsigned* counter, double* rec, hipStream_t s, hipEvent_t ev_start = nullptr,
                         hipEvent_t ev_stop = nullptr);
+// pose: the poses of t and t+1 on the device; pose_host: the same two on the
+// host (read at the call)
 hipError_t launch_body_advance(int lat, int st, int eq, void* B, uint8_t* mask, uint8_t* mask_next, Link* links,
-                               int* n_links, int cap, const double* pose, const BodyShape& bs, int bc, int body,
-                               int mode, const Geom& g, const Phys& ph, double* rec_t, double* rec_t1, int* err,
-                               hipStream_t s, int64_t region_cells, int64_t region_rows, int64_t list_nodes,
+                               int* n_links, int cap, const double* pose, const double* pose_host, const BodyShape& bs,
+                               int bc, int body, int mode, const Geom& g, const Phys& ph, double* rec_t, double* rec_t1,
+                               int* err, hipStream_t s, int64_t region_cells, int64_t region_rows, int64_t list_nodes,
                                hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 
 // Steady-state check of one body: relative change of its drag between

@@ -251,6 +251,9 @@ lbm_status lbm::host::ensure_poses(lbm_domain d, Body& b, int64_t t0, int64_t t1
 }
 
 const double* lbm::host::pose_at(const Body& b, int64_t t) { return b.pose_dev + (t - b.pose_base) * POSE_LEN; }
+const double* lbm::host::pose_host_at(const Body& b, int64_t t) {
+  return b.pose_pinned + (t - b.pose_base) * POSE_LEN;
+}
 
 // nodes of the box that covers the body region at steps t and t + mode,
 // with a one-node margin along each lattice axis (the LDS box of the body
@@ -383,7 +386,8 @@ lbm_status lbm::host::launch_advance(lbm_domain d, int id, int64_t t) {
   lbm_status s = timing_slot(d, LBM_KERNEL_BODY, 0, e0, e1);
   if (s != LBM_OK) return s;
   HIP_TRY(launch_body_advance(d->lat, d->st, d->eq, d->A, d->mask, d->mask_next, b.links, b.n_links, b.cap,
-                              pose_at(b, t), b.shape, b.desc.bc, id, 1, d->g, d->ph, rec_slot(d, t, id),
+                              pose_at(b, t), pose_host_at(b, t), b.shape, b.desc.bc, id, 1, d->g, d->ph,
+                              rec_slot(d, t, id),
                               rec_slot(d, t + 1, id), d->err, d->stream, region_cells(b, d->D, t, 1),
                               region_rows(b, t, 1), list_bound(b, d->D, t), e0, e1));
   return LBM_OK;
@@ -571,7 +575,8 @@ lbm_status lbm_set_body(lbm_domain d, int32_t id, const lbm_body_desc* bd) {
     return s;
   }
   HIP_TRY(launch_body_advance(d->lat, d->st, d->eq, d->A, d->mask, d->mask_next, b.links, b.n_links, b.cap,
-                              pose_at(b, d->t), b.shape, bd->bc, id, 0, d->g, d->ph, nullptr, nullptr, d->err,
+                              pose_at(b, d->t), pose_host_at(b, d->t), b.shape, bd->bc, id, 0, d->g, d->ph, nullptr,
+                              nullptr, d->err,
                               d->stream, region_cells(b, d->D, d->t, 0), region_rows(b, d->t, 0), 0));
   HIP_TRY(hipMemcpyAsync(&b.n_host, b.n_links, sizeof(int), hipMemcpyDeviceToHost, d->stream));
   HIP_TRY(hipStreamSynchronize(d->stream));

@@ -262,14 +262,14 @@ lbm_status batch_step(lbm_batch B, int64_t n, hipEvent_t e0, hipEvent_t e1) {
       if (k > 0) HIP_TRY(hipStreamWaitEvent(B->stream, B->e_far, 0));
       else HIP_TRY(hipEventRecord(B->e_near, B->stream));
       HIP_TRY(hipStreamWaitEvent(B->aux, B->e_near, 0));
-      HIP_TRY(launch_batch_bulk(lat, st, eq, doms, tiles, (int)P.tiles.size(), bc, k, B->aux, 1));
-      HIP_TRY(hipEventRecord(B->e_far, B->aux));
+      // the launch records the completion event itself
+      HIP_TRY(launch_batch_bulk(lat, st, eq, doms, tiles, (int)P.tiles.size(), bc, k, B->aux, 1, nullptr, B->e_far));
     }
     if (!P.links.empty())
       HIP_TRY(launch_batch_links(lat, st, eq, doms, links, (int)P.links.size(), P.link_grid, k, B->stream));
     if (split) {
-      HIP_TRY(launch_batch_bulk(lat, st, eq, doms, near_tiles, (int)P.near_tiles.size(), nc, k, B->stream, 2));
-      HIP_TRY(hipEventRecord(B->e_near, B->stream));
+      HIP_TRY(launch_batch_bulk(lat, st, eq, doms, near_tiles, (int)P.near_tiles.size(), nc, k, B->stream, 2, nullptr,
+                                B->e_near));
     } else {
       HIP_TRY(launch_batch_bulk(lat, st, eq, doms, tiles, (int)P.tiles.size(), bc, k, B->stream, 0));
     }

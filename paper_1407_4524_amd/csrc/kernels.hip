@@ -1648,7 +1648,7 @@ static void launch_bulk_variant(const void* A, void* B, const Geom& g, const Phy
   auto kern = k_stream_collide<L, S, EQ, BX, CPT, NT>;
   const auto* a = (const typename S::T*)A;
   auto* o = (typename S::T*)B;
-  if (e0) hipExtLaunchKernelGGL(kern, dim3(sw.ntiles), dim3(BX), 0, s, e0, e1, 0, a, o, g, ph, sw);
+  if (e0 || e1) hipExtLaunchKernelGGL(kern, dim3(sw.ntiles), dim3(BX), 0, s, e0, e1, 0, a, o, g, ph, sw);
   else hipLaunchKernelGGL(kern, dim3(sw.ntiles), dim3(BX), 0, s, a, o, g, ph, sw);
 }
 
@@ -1698,7 +1698,7 @@ hipError_t launch_stream_collide(int lat, int st, int eq, const void* A, void* B
     return hipErrorInvalidValue;
   if (sw.nbx != (sw.xlast - sw.x0 + cfg.block * cfg.cells_per_thread) / (cfg.block * cfg.cells_per_thread))
     return hipErrorInvalidValue;
-  if ((ev_start == nullptr) != (ev_stop == nullptr)) return hipErrorInvalidValue;
+  if (ev_start != nullptr && ev_stop == nullptr) return hipErrorInvalidValue;
   with_types(lat, st, eq, [&](auto Lt, auto St, auto E) {
     using L = decltype(Lt);
     using S = decltype(St);
@@ -1725,7 +1725,7 @@ hipError_t launch_init(int lat, int st, int eq, void* A, uint8_t* mask, const Ge
 template <class K, class... Args>
 static void launch_timed(K kern, dim3 grid, dim3 block, size_t lds, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
                          Args... args) {
-  if (e0) hipExtLaunchKernelGGL(kern, grid, block, (uint32_t)lds, s, e0, e1, 0, args...);
+  if (e0 || e1) hipExtLaunchKernelGGL(kern, grid, block, (uint32_t)lds, s, e0, e1, 0, args...);
   else hipLaunchKernelGGL(kern, grid, block, lds, s, args...);
 }
 
@@ -1822,7 +1822,7 @@ hipError_t launch_batch_bulk(int lat, int st, int eq, const BatchDomain* doms, c
                              hipEvent_t ev_stop) {
   if (ntiles <= 0 || !batch_bulk_supported(cfg.block, cfg.cells_per_thread) || part < 0 || part > 2)
     return hipErrorInvalidValue;
-  if ((ev_start == nullptr) != (ev_stop == nullptr)) return hipErrorInvalidValue;
+  if (ev_start != nullptr && ev_stop == nullptr) return hipErrorInvalidValue;
   with_types(lat, st, eq, [&](auto Lt, auto St, auto E) {
     using L = decltype(Lt);
     using S = decltype(St);

@@ -31,8 +31,10 @@ struct Sweep {
 Sweep make_sweep(const int lo[3], const int hi[3], int span, const int* hole, int remap);
 bool bulk_supported(const BulkConfig& c);
 
-// ev_start/ev_stop (both or neither, here and below): events recorded at the
-// start and the end of the kernel itself
+// ev_start/ev_stop (here and below): events recorded at the start and the
+// end of the kernel itself by the launch; a start event needs a stop event,
+// a stop event alone marks the kernel's completion (in place of a record
+// after the launch)
 hipError_t launch_stream_collide(int lat, int st, int eq, const void* A, void* B, const Geom& g, const Phys& ph,
                                  hipStream_t s, const BulkConfig& cfg, const Sweep& sw,
                                  hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);

@@ -369,12 +369,16 @@ static int FAR_CU_EVERY = 32;
 static const BulkConfig NEAR_CFG{128, 2, 0, 0};
 
 // one stream-collide launch over a sweep of the current source buffer,
-// timed as `kind`
-static lbm_status launch_sweep(lbm_domain d, const BulkConfig& cfg, const Sweep& sw, int kind) {
+// timed as `kind`, on stream s; *done (optional) becomes an event that
+// completes with the kernel (its timing stop event when timed, else
+// `marker`, recorded by the launch itself)
+static lbm_status launch_sweep(lbm_domain d, const BulkConfig& cfg, const Sweep& sw, int kind, hipStream_t s,
+                               hipEvent_t marker = nullptr, hipEvent_t* done = nullptr) {
   hipEvent_t e0, e1;
   lbm_status st = timing_slot(d, kind, sweep_nodes(sw), e0, e1);
   if (st != LBM_OK) return st;
-  HIP_TRY(launch_stream_collide(d->lat, d->st, d->eq, d->A, d->B, d->g, d->ph, d->stream, cfg, sw, e0, e1));
+  if (done) *done = e1 ? e1 : marker;
+  HIP_TRY(launch_stream_collide(d->lat, d->st, d->eq, d->A, d->B, d->g, d->ph, s, cfg, sw, e0, e1 ? e1 : marker));
   return LBM_OK;
 }
 
@@ -622,6 +626,7 @@ lbm_status lbm_step(lbm_domain d, int64_t nsteps) {
   const int full_lo[3] = {g.lo[0], g.lo[1], g.lo[2]}, full_hi[3] = {g.hi[0], g.hi[1], g.hi[2]};
   const Sweep full = make_sweep(full_lo, full_hi, d->bulk.block * d->bulk.cells_per_thread, nullptr, d->bulk.remap);
   bool far_open = false;  // a far update on the second stream is not yet waited for
+  hipEvent_t far_done = nullptr, near_done = nullptr;  // completion of the last far / near update
   for (int64_t k = 0; k < nsteps; ++k) {
     const int64_t t = d->t;
     lbm_status s = LBM_OK;
@@ -635,13 +640,18 @@ lbm_status lbm_step(lbm_domain d, int64_t nsteps) {
       const Sweep far = make_sweep(full_lo, full_hi, d->bulk.block * d->bulk.cells_per_thread, hole, d->bulk.remap);
       near = make_sweep(lo, hi, NEAR_CFG.block * NEAR_CFG.cells_per_thread, nullptr, 0);
       // the far update of step t after the near update of step t-1 (at the
-      // first split step: after all earlier work of the domain's stream)
-      if (far_open) HIP_TRY(hipStreamWaitEvent(d->stream, d->e_far, 0));
-      else HIP_TRY(hipEventRecord(d->e_near, d->stream));
-      HIP_TRY(hipStreamWaitEvent(d->aux, d->e_near, 0));
-      if ((s = timing_slot(d, LBM_KERNEL_STREAM_COLLIDE, sweep_nodes(far), e0, e1)) != LBM_OK) return s;
-      HIP_TRY(launch_stream_collide(d->lat, d->st, d->eq, d->A, d->B, g, d->ph, d->aux, d->bulk, far, e0, e1));
-      HIP_TRY(hipEventRecord(d->e_far, d->aux));
+      // first split step: after all earlier work of the domain's stream);
+      // the near update after the far update of step t-1. Each completion
+      // event is recorded by its kernel's launch.
+      if (far_open) {
+        HIP_TRY(hipStreamWaitEvent(d->stream, far_done, 0));
+      } else {
+        HIP_TRY(hipEventRecord(d->e_near, d->stream));
+        near_done = d->e_near;
+      }
+      HIP_TRY(hipStreamWaitEvent(d->aux, near_done, 0));
+      if ((s = launch_sweep(d, d->bulk, far, LBM_KERNEL_STREAM_COLLIDE, d->aux, d->e_far, &far_done)) != LBM_OK)
+        return s;
       far_open = true;
     }
     for (int id = 0; id < LBM_MAX_BODIES; ++id) {
@@ -655,10 +665,10 @@ lbm_status lbm_step(lbm_domain d, int64_t nsteps) {
       if (b.mask_moves) b.bc_ready = true;
     }
     if (split) {
-      if ((s = launch_sweep(d, NEAR_CFG, near, LBM_KERNEL_NEAR_BOX)) != LBM_OK) return s;
-      HIP_TRY(hipEventRecord(d->e_near, d->stream));
+      if ((s = launch_sweep(d, NEAR_CFG, near, LBM_KERNEL_NEAR_BOX, d->stream, d->e_near, &near_done)) != LBM_OK)
+        return s;
     } else {
-      if ((s = launch_sweep(d, d->bulk, full, LBM_KERNEL_STREAM_COLLIDE)) != LBM_OK) return s;
+      if ((s = launch_sweep(d, d->bulk, full, LBM_KERNEL_STREAM_COLLIDE, d->stream)) != LBM_OK) return s;
     }
     std::swap(d->A, d->B);  // the advance works on the new state
     for (int id = 0; id < LBM_MAX_BODIES; ++id) {
@@ -671,7 +681,7 @@ lbm_status lbm_step(lbm_domain d, int64_t nsteps) {
     }
     d->t = t + 1;
   }
-  if (far_open) HIP_TRY(hipStreamWaitEvent(d->stream, d->e_far, 0));
+  if (far_open) HIP_TRY(hipStreamWaitEvent(d->stream, far_done, 0));
   return LBM_OK;
 }
 

@@ -84,22 +84,25 @@ struct Plan {
 
 // Near box of a member for the steps t0 .. t0+n-1 of a call: the node boxes
 // of every pose its bodies take (t0-1 .. t0+n for a body whose solid set
-// moves, t0 for the others) plus one layer, within the active nodes; empty
-// for a member without bodies. Every node the body work of the call reads or
-// writes lies inside it, one layer away from the far update.
+// moves, t0 for the others) plus one layer (two for a body with fixed links,
+// whose link rule of the next step reads nodes two away from its box), within
+// the active nodes; empty for a member without bodies. Every node the body
+// work of the call reads or writes lies inside it, one layer away from the
+// far update.
 void near_box_of(lbm_domain d, int64_t n, int hole[6]) {
   const Geom& g = d->g;
-  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
   bool any = false;
   for (const Body& b : d->body) {
     if (!b.active) continue;
     const Pose* P = reinterpret_cast<const Pose*>(b.pose_pinned);
     const int64_t k0 = (b.mask_moves && d->t - 1 >= b.pose_base) ? d->t - 1 : d->t;
     const int64_t k1 = b.mask_moves ? d->t + n : d->t;
+    const int m = b.mask_moves ? 1 : 2;
     for (int64_t k = k0; k <= k1; ++k)
       for (int a = 0; a < 3; ++a) {
-        lo[a] = std::min(lo[a], P[k - b.pose_base].lo[a]);
-        hi[a] = std::max(hi[a], P[k - b.pose_base].hi[a]);
+        lo[a] = std::min(lo[a], (int)P[k - b.pose_base].lo[a] - m);
+        hi[a] = std::max(hi[a], (int)P[k - b.pose_base].hi[a] + m);
       }
     any = true;
   }
@@ -109,8 +112,8 @@ void near_box_of(lbm_domain d, int64_t n, int hole[6]) {
     return;
   }
   for (int a = 0; a < 3; ++a) {
-    hole[2 * a] = std::max<int>(g.lo[a], (int)lo[a] - 1);
-    hole[2 * a + 1] = std::min<int>(g.hi[a], (int)hi[a] + 1);
+    hole[2 * a] = std::max<int>(g.lo[a], lo[a]);
+    hole[2 * a + 1] = std::min<int>(g.hi[a], hi[a]);
   }
 }
 
@@ -257,6 +260,10 @@ lbm_status batch_step(lbm_batch B, int64_t n, hipEvent_t e0, hipEvent_t e1) {
     HIP_TRY(hipEventCreateWithFlags(&B->e_near, hipEventDisableTiming | hipEventDisableSystemFence));
     HIP_TRY(hipEventCreateWithFlags(&B->e_far, hipEventDisableTiming | hipEventDisableSystemFence));
   }
+  // 2D: the link rule of the bodies with fixed links for step k+1 joins the
+  // advance launch of step k (at the call's first step it runs on its own;
+  // at its last, not at all: the next call starts with it)
+  const bool fuse = lat == 0 && !P.links.empty();
   for (int64_t k = 0; k < n; ++k) {
     if (split) {
       if (k > 0) HIP_TRY(hipStreamWaitEvent(B->stream, B->e_far, 0));
@@ -265,7 +272,7 @@ lbm_status batch_step(lbm_batch B, int64_t n, hipEvent_t e0, hipEvent_t e1) {
       // the launch records the completion event itself
       HIP_TRY(launch_batch_bulk(lat, st, eq, doms, tiles, (int)P.tiles.size(), bc, k, B->aux, 1, nullptr, B->e_far));
     }
-    if (!P.links.empty())
+    if (!P.links.empty() && (!fuse || k == 0))
       HIP_TRY(launch_batch_links(lat, st, eq, doms, links, (int)P.links.size(), P.link_grid, k, B->stream));
     if (split) {
       HIP_TRY(launch_batch_bulk(lat, st, eq, doms, near_tiles, (int)P.near_tiles.size(), nc, k, B->stream, 2, nullptr,
@@ -273,7 +280,10 @@ lbm_status batch_step(lbm_batch B, int64_t n, hipEvent_t e0, hipEvent_t e1) {
     } else {
       HIP_TRY(launch_batch_bulk(lat, st, eq, doms, tiles, (int)P.tiles.size(), bc, k, B->stream, 0));
     }
-    if (!P.moving.empty())
+    if (fuse && k + 1 < n)
+      HIP_TRY(launch_batch_body_links(lat, st, eq, doms, moving, (int)P.moving.size(), links, (int)P.links.size(),
+                                      P.max_cells, k, B->stream));
+    else if (!P.moving.empty())
       HIP_TRY(launch_batch_body_step(lat, st, eq, doms, moving, (int)P.moving.size(), P.max_cells, k, B->stream));
     for (const auto& f : P.fallback) {
       lbm_domain d = B->members[f.first];

@@ -1576,6 +1576,33 @@ __global__ __launch_bounds__(NT) void k_body_step_batch(const BatchDomain* __res
                                  batch_rec(b, t), batch_rec(b, t + 1), b.err, StepBox{});
 }
 
+// After batch step s's bulk update, one launch for all the body work that
+// follows it: blocks [0, n_moving) advance the moving bodies (as
+// k_body_step_batch), the others apply the link rule of step s+1 for the
+// bodies with fixed links (as k_links_batch, one workgroup per body). That
+// rule reads the new state only within two nodes of its body, inside the
+// body's near box, so it may run beside the far update of step s.
+template <class L, class S, int EQ, int NT>
+__global__ __launch_bounds__(NT) void k_body_links_batch(const BatchDomain* __restrict__ doms,
+                                                         const BatchBody* __restrict__ moving, int n_moving,
+                                                         const BatchBody* __restrict__ fixed, int64_t s) {
+  if ((int)blockIdx.x < n_moving) {
+    const BatchBody& b = moving[blockIdx.x];
+    const BatchDomain& D = doms[b.dom];
+    const int64_t t = b.t0 + s;
+    body_step<L, S, EQ, NT, false>((typename S::T*)D.buf[(s + 1) & 1], b.mask, b.links, b.n_links, b.cap,
+                                   b.pose + (t - b.pose_base) * POSE_DOUBLES, b.bs, b.bc, b.body, D.g, D.ph,
+                                   batch_rec(b, t), batch_rec(b, t + 1), b.err, StepBox{});
+    return;
+  }
+  const BatchBody& b = fixed[blockIdx.x - n_moving];
+  const BatchDomain& D = doms[b.dom];
+  const int64_t t = b.t0 + s + 1;
+  links_block<L, S, EQ, NT>((typename S::T*)D.buf[(s + 1) & 1], b.links, b.n_host,
+                            b.pose + (t - b.pose_base) * POSE_DOUBLES, b.bc, b.mask, D.g, D.ph, b.partials, b.counter,
+                            batch_rec(b, t), 0, 1);
+}
+
 // ---------------------------------------------------------------------------
 // steady-state check: relative change of the drag (x-force of the body's
 // momentum-exchange form) between steps t - 1 - window and t - 1, in FP64
@@ -1859,6 +1886,23 @@ hipError_t launch_batch_links(int lat, int st, int eq, const BatchDomain* doms, 
     else
       hipLaunchKernelGGL((k_links_batch<L, S, EQ, LINK_BLOCK>), dim3(grid, nbodies), dim3(LINK_BLOCK), 0, s, doms,
                          bodies, step);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_body_links(int lat, int st, int eq, const BatchDomain* doms, const BatchBody* moving,
+                                   int n_moving, const BatchBody* fixed, int n_fixed, int64_t max_region_cells,
+                                   int64_t step, hipStream_t s) {
+  if (lat != 0 || n_moving < 0 || n_fixed < 0 || n_moving + n_fixed <= 0) return hipErrorInvalidValue;
+  if (n_moving > 0 && (max_region_cells <= 0 || max_region_cells > STEP_CELLS)) return hipErrorInvalidValue;
+  const size_t lds = n_moving > 0 ? ((size_t)2 * max_region_cells + 15) / 16 * 16 : 0;
+  with_types(lat, st, eq, [&](auto Lt, auto St, auto E) {
+    using L = decltype(Lt);
+    using S = decltype(St);
+    constexpr int EQ = decltype(E)::value;
+    if constexpr (L::D == 2)
+      hipLaunchKernelGGL((k_body_links_batch<L, S, EQ, 1024>), dim3(n_moving + n_fixed), dim3(1024), lds, s, doms,
+                         moving, n_moving, fixed, step);
   });
   return hipGetLastError();
 }

@@ -125,6 +125,11 @@ hipError_t launch_batch_bulk(int lat, int st, int eq, const BatchDomain* doms, c
 int batch_link_grid(int lat, int max_links);
 hipError_t launch_batch_links(int lat, int st, int eq, const BatchDomain* doms, const BatchBody* bodies, int nbodies,
                               int grid, int64_t step, hipStream_t s);
+// 2D batches: the advance of the moving bodies after batch step `step` and
+// the link rule of step+1 for the bodies with fixed links, in one launch
+hipError_t launch_batch_body_links(int lat, int st, int eq, const BatchDomain* doms, const BatchBody* moving,
+                                   int n_moving, const BatchBody* fixed, int n_fixed, int64_t max_region_cells,
+                                   int64_t step, hipStream_t s);
 hipError_t launch_batch_body_step(int lat, int st, int eq, const BatchDomain* doms, const BatchBody* bodies,
                                   int nbodies, int64_t max_region_cells, int64_t step, hipStream_t s);
 

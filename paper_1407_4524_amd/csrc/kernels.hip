@@ -61,50 +61,72 @@ __device__ inline double inlet_speed(const Geom& g, const Phys& ph, double yB, d
   return u;
 }
 
-// Ghost values of the domain faces for the next step, written by the node
-// that owns them, from its post-collision deviations hout:
+// Density a face rule takes at a node: from the post-collision deviations
+// as stored (hs), summed in direction order, so that the rule gives the same
+// bits inside the stream-collide kernel and in k_faces.
+template <class L, class S>
+__device__ __forceinline__ typename S::C face_density(const typename S::C* hs, double rho0) {
+  typename S::C d = (typename S::C)rho0;
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) d += hs[i];
+  return d;
+}
+
+// The face rules of direction i at node (x, y, z) (cell c) for the next
+// step, from its post-collision deviations as stored: hopp (direction
+// opposite to i), hi (direction i), and the density rho_w (used by the
+// inlet rule only):
 //  * bounce rules (resting wall, inlet / velocity outlet at the half-way
-//    plane): the slot of source x - c_i gets hout[opp i] + 6 w_i rho_w c_i.u;
+//    plane): the slot of source x - c_i gets hopp + 6 w_i rho_w c_i.u;
 //  * copy rules (periodic images, zero-gradient outlet): the halo slot that a
-//    wrapped (or outlet-shifted) destination pulls from gets hout[i].
+//    wrapped (or outlet-shifted) destination pulls from gets hi.
+// st is source_type of x - c_i.
+template <class L, class S>
+__device__ __forceinline__ void face_rule(typename S::T* __restrict__ B, const Geom& g, const Phys& ph, int x, int y,
+                                          int z, int64_t c, int i, int st, typename S::C hopp, typename S::C hi,
+                                          typename S::C rho_w) {
+  using C = typename S::C;
+  const int cx = L::cx(i), cy = L::cy(i), cz = L::cz(i);
+  const int64_t off = cx + cy * g.sy + cz * g.sz;
+  if (st == SRC_WALL) {
+    S::store(B + i * g.S + c - off, hopp);
+  } else if (st == SRC_INLET || st == SRC_OUTVEL) {
+    double u = inlet_speed(g, ph, y - 0.5 * cy, z - 0.5 * cz);
+    C add = (C)(6.0 * L::w(i)) * rho_w * (C)(cx * u);
+    S::store(B + i * g.S + c - off, hopp + add);
+  }
+  int ex = x + cx, ey = y + cy, ez = z + cz;
+  bool sh = false;
+  if (g.face[1] == FACE_OUTLET && cx == -1 && x == g.nx - 1) {
+    ex += 1;
+    sh = true;
+  }
+  if (g.face[0] == FACE_PERIODIC && (ex < 0 || ex >= g.nx)) {
+    ex = ex < 0 ? ex + g.nx : ex - g.nx;
+    sh = true;
+  }
+  if (g.face[2] == FACE_PERIODIC && (ey < 0 || ey >= g.ny)) {
+    ey = ey < 0 ? ey + g.ny : ey - g.ny;
+    sh = true;
+  }
+  if (L::D == 3 && g.face[4] == FACE_PERIODIC && (ez < 0 || ez >= g.nz)) {
+    ez = ez < 0 ? ez + g.nz : ez - g.nz;
+    sh = true;
+  }
+  bool active = ex >= g.lo[0] && ex <= g.hi[0] && ey >= g.lo[1] && ey <= g.hi[1] &&
+                (L::D == 2 || (ez >= g.lo[2] && ez <= g.hi[2]));
+  if (sh && active) S::store(B + i * g.S + g.idx(ex - cx, ey - cy, ez - cz), hi);
+}
+
+// Every face rule of a node next to a face, from its post-collision
+// deviations as stored (hout), inside the kernel that computed them.
 template <class L, class S>
 __device__ void write_faces(typename S::T* __restrict__ B, const Geom& g, const Phys& ph, int x, int y, int z,
                             int64_t c, const typename S::C* hout, typename S::C rho_w) {
-  using C = typename S::C;
 #pragma unroll
-  for (int i = 1; i < L::Q; ++i) {
-    const int cx = L::cx(i), cy = L::cy(i), cz = L::cz(i);
-    const int64_t off = cx + cy * g.sy + cz * g.sz;
-    const int st = source_type(g, x - cx, y - cy, z - cz);
-    if (st == SRC_WALL) {
-      S::store(B + i * g.S + c - off, hout[L::opp(i)]);
-    } else if (st == SRC_INLET || st == SRC_OUTVEL) {
-      double u = inlet_speed(g, ph, y - 0.5 * cy, z - 0.5 * cz);
-      C add = (C)(6.0 * L::w(i)) * rho_w * (C)(cx * u);
-      S::store(B + i * g.S + c - off, hout[L::opp(i)] + add);
-    }
-    int ex = x + cx, ey = y + cy, ez = z + cz;
-    bool sh = false;
-    if (g.face[1] == FACE_OUTLET && cx == -1 && x == g.nx - 1) {
-      ex += 1;
-      sh = true;
-    }
-    if (g.face[0] == FACE_PERIODIC && (ex < 0 || ex >= g.nx)) {
-      ex = ex < 0 ? ex + g.nx : ex - g.nx;
-      sh = true;
-    }
-    if (g.face[2] == FACE_PERIODIC && (ey < 0 || ey >= g.ny)) {
-      ey = ey < 0 ? ey + g.ny : ey - g.ny;
-      sh = true;
-    }
-    if (L::D == 3 && g.face[4] == FACE_PERIODIC && (ez < 0 || ez >= g.nz)) {
-      ez = ez < 0 ? ez + g.nz : ez - g.nz;
-      sh = true;
-    }
-    bool active = ex >= g.lo[0] && ex <= g.hi[0] && ey >= g.lo[1] && ey <= g.hi[1] &&
-                  (L::D == 2 || (ez >= g.lo[2] && ez <= g.hi[2]));
-    if (sh && active) S::store(B + i * g.S + g.idx(ex - cx, ey - cy, ez - cz), hout[i]);
-  }
+  for (int i = 1; i < L::Q; ++i)
+    face_rule<L, S>(B, g, ph, x, y, z, c, i, source_type(g, x - L::cx(i), y - L::cy(i), z - L::cz(i)),
+                    hout[L::opp(i)], hout[i], rho_w);
 }
 
 // ---------------------------------------------------------------------------
@@ -155,7 +177,10 @@ __device__ inline int xcd_block(int hw, int nblocks) {
 // instruction of a wavefront covers 64 consecutive nodes. Nodes inside the
 // hole box (x0, x1, y0, y1, z0, z1; empty when x0 > x1) are left alone. All
 // CPT*Q loads are issued before any arithmetic.
-template <class L, class S, int EQ, int BX, int CPT, bool NT>
+// With FACES, a node next to a domain face also writes that face's ghost
+// values for the next step (write_faces); without, k_faces does it after the
+// launch (the face code then does not set the kernel's register budget).
+template <class L, class S, int EQ, int BX, int CPT, bool FACES>
 __device__ __forceinline__ void stream_collide_span(const typename S::T* __restrict__ A,
                                                     typename S::T* __restrict__ B, const Geom& g, const Phys& ph,
                                                     int x0, int y, int z, int xlast, const int* hole) {
@@ -198,13 +223,17 @@ __device__ __forceinline__ void stream_collide_span(const typename S::T* __restr
     C rho;
     collide<L, S, EQ>(h[k], (C)ph.rho0, (C)ph.omega, rho);
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) {
-      if (NT) S::store(B + i * g.S + c, h[k][i]);
-      else B[i * g.S + c] = (typename S::T)h[k][i];
-    }
+    for (int i = 0; i < L::Q; ++i) B[i * g.S + c] = (typename S::T)h[k][i];
+    (void)rho;
+    if (!FACES) continue;
     const bool near = x <= g.lo[0] || x >= g.hi[0] || y <= g.lo[1] || y >= g.hi[1] ||
                       (L::D == 3 && (z <= g.lo[2] || z >= g.hi[2]));
-    if (near) write_faces<L, S>(B, g, ph, x, y, z, c, h[k], EQ ? (C)ph.rho0 : rho);
+    if (near) {
+      C hs[L::Q];
+#pragma unroll
+      for (int i = 0; i < L::Q; ++i) hs[i] = S::stored(h[k][i]);
+      write_faces<L, S>(B, g, ph, x, y, z, c, hs, EQ ? (C)ph.rho0 : face_density<L, S>(hs, ph.rho0));
+    }
   }
 }
 
@@ -217,13 +246,67 @@ __device__ __forceinline__ void sweep_tile(const Sweep& sw, int k, int span, int
 }
 
 // one block per tile of the sweep
-template <class L, class S, int EQ, int BX, int CPT, bool NT>
+template <class L, class S, int EQ, int BX, int CPT, bool FACES>
 __global__ __launch_bounds__(BX) void k_stream_collide(const typename S::T* __restrict__ A,
                                                        typename S::T* __restrict__ B, Geom g, Phys ph, Sweep sw) {
   const int blk = sw.remap ? xcd_block(blockIdx.x, sw.ntiles) : blockIdx.x;
   int x, y, z;
   sweep_tile(sw, blk, BX * CPT, x, y, z);
-  stream_collide_span<L, S, EQ, BX, CPT, NT>(A, B, g, ph, x + threadIdx.x, y, z, sw.xlast, sw.hole);
+  stream_collide_span<L, S, EQ, BX, CPT, FACES>(A, B, g, ph, x + threadIdx.x, y, z, sw.xlast, sw.hole);
+}
+
+// The face rules of a whole-domain stream-collide launched without them:
+// one thread per (node next to a face, direction), the direction from the
+// grid's y index, so that a wavefront shares its direction and runs over
+// consecutive nodes (32-bit index arithmetic throughout). Face nodes are
+// enumerated slab by slab: x = lo, x = hi, y = lo, y = hi, then z = lo,
+// z = hi in 3D; a node in several slabs belongs to the first.
+__device__ __forceinline__ bool face_node(const Geom& g, int k, int& x, int& y, int& z) {
+  const int n0 = g.hi[0] - g.lo[0] + 1, n1 = g.hi[1] - g.lo[1] + 1, n2 = g.hi[2] - g.lo[2] + 1;
+  const int sx = n1 * n2, sy = n0 * n2, sz = n0 * n1;
+  if (k < 2 * sx) {
+    const int side = k >= sx, r = side ? k - sx : k;
+    x = side ? g.hi[0] : g.lo[0];
+    y = g.lo[1] + r % n1;
+    z = g.lo[2] + r / n1;
+    return !(side && n0 == 1);
+  }
+  k -= 2 * sx;
+  if (k < 2 * sy) {
+    const int side = k >= sy, r = side ? k - sy : k;
+    x = g.lo[0] + r % n0;
+    y = side ? g.hi[1] : g.lo[1];
+    z = g.lo[2] + r / n0;
+    return !(side && n1 == 1) && x != g.lo[0] && x != g.hi[0];
+  }
+  k -= 2 * sy;
+  if (g.D == 3 && k < 2 * sz) {
+    const int side = k >= sz, r = side ? k - sz : k;
+    x = g.lo[0] + r % n0;
+    y = g.lo[1] + r / n0;
+    z = side ? g.hi[2] : g.lo[2];
+    return !(side && n2 == 1) && x != g.lo[0] && x != g.hi[0] && y != g.lo[1] && y != g.hi[1];
+  }
+  return false;
+}
+
+template <class L, class S, int EQ>
+__global__ __launch_bounds__(256) void k_faces(typename S::T* __restrict__ B, Geom g, Phys ph, int nnodes) {
+  using C = typename S::C;
+  const int k = (int)blockIdx.x * 256 + (int)threadIdx.x;
+  const int i = (int)blockIdx.y + 1;
+  int x, y, z;
+  if (k >= nnodes || !face_node(g, k, x, y, z)) return;
+  const int64_t c = g.idx(x, y, z);
+  const int st = source_type(g, x - L::cx(i), y - L::cy(i), z - L::cz(i));
+  C rho_w = (C)ph.rho0;
+  if (!EQ && (st == SRC_INLET || st == SRC_OUTVEL)) {  // the inlet rule's density: all populations
+    C hs[L::Q];
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) hs[q] = S::load(B + q * g.S + c);
+    rho_w = face_density<L, S>(hs, ph.rho0);
+  }
+  face_rule<L, S>(B, g, ph, x, y, z, c, i, st, S::load(B + L::opp(i) * g.S + c), S::load(B + i * g.S + c), rho_w);
 }
 
 // initial state: equilibrium deviations at (rho, u) per node, the face ghosts
@@ -1540,14 +1623,14 @@ __global__ __launch_bounds__(BX) void k_stream_collide_batch(const BatchDomain* 
     const int nrows = D.hole[3] - D.hole[2] + 1;
     const int y = D.hole[2] + tl.row % nrows;
     const int z = D.hole[4] + tl.row / nrows;
-    stream_collide_span<L, S, EQ, BX, CPT, false>(A, B, g, ph, D.hole[0] + tl.bx * (BX * CPT) + threadIdx.x, y, z,
+    stream_collide_span<L, S, EQ, BX, CPT, true>(A, B, g, ph, D.hole[0] + tl.bx * (BX * CPT) + threadIdx.x, y, z,
                                                   D.hole[1], no_hole);
     return;
   }
   const int nrows = g.hi[1] - g.lo[1] + 1;
   const int y = g.lo[1] + tl.row % nrows;
   const int z = g.lo[2] + tl.row / nrows;
-  stream_collide_span<L, S, EQ, BX, CPT, false>(A, B, g, ph, g.lo[0] + tl.bx * (BX * CPT) + threadIdx.x, y, z,
+  stream_collide_span<L, S, EQ, BX, CPT, true>(A, B, g, ph, g.lo[0] + tl.bx * (BX * CPT) + threadIdx.x, y, z,
                                                 g.hi[0], part == 1 ? D.hole : no_hole);
 }
 
@@ -1669,29 +1752,33 @@ BulkConfig bulk_config(int lat, int st, size_t footprint) {
   return BulkConfig{256, 1, 0, 0};
 }
 
-template <class L, class S, int EQ, int BX, int CPT, bool NT>
+template <class L, class S, int EQ, int BX, int CPT, bool FACES>
 static void launch_bulk_variant(const void* A, void* B, const Geom& g, const Phys& ph, const Sweep& sw,
                                 hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-  auto kern = k_stream_collide<L, S, EQ, BX, CPT, NT>;
+  auto kern = k_stream_collide<L, S, EQ, BX, CPT, FACES>;
   const auto* a = (const typename S::T*)A;
   auto* o = (typename S::T*)B;
   if (e0 || e1) hipExtLaunchKernelGGL(kern, dim3(sw.ntiles), dim3(BX), 0, s, e0, e1, 0, a, o, g, ph, sw);
   else hipLaunchKernelGGL(kern, dim3(sw.ntiles), dim3(BX), 0, s, a, o, g, ph, sw);
 }
 
+// faces: the launch writes the face rules itself; without (3D only) the
+// caller follows it with k_faces
 template <class L, class S, int EQ>
 static void launch_bulk_cfg(const BulkConfig& c, const void* A, void* B, const Geom& g, const Phys& ph,
-                            const Sweep& sw, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-#define LBM_BULK_CASE(BX_, CPT_, NT_)                                                 \
-  if (c.block == BX_ && c.cells_per_thread == CPT_ && c.nontemporal == NT_) {         \
-    launch_bulk_variant<L, S, EQ, BX_, CPT_, (NT_ != 0)>(A, B, g, ph, sw, s, e0, e1); \
-    return;                                                                           \
+                            const Sweep& sw, hipStream_t s, hipEvent_t e0, hipEvent_t e1, bool faces) {
+#define LBM_BULK_CASE(BX_, CPT_)                                                          \
+  if (c.block == BX_ && c.cells_per_thread == CPT_) {                                     \
+    if constexpr (L::D == 3) {                                                            \
+      if (!faces) return launch_bulk_variant<L, S, EQ, BX_, CPT_, false>(A, B, g, ph, sw, s, e0, e1); \
+    }                                                                                     \
+    return launch_bulk_variant<L, S, EQ, BX_, CPT_, true>(A, B, g, ph, sw, s, e0, e1);    \
   }
-  LBM_BULK_CASE(256, 1, 0)
-  LBM_BULK_CASE(256, 2, 0)
-  LBM_BULK_CASE(512, 1, 0)
-  LBM_BULK_CASE(128, 2, 0)
-  LBM_BULK_CASE(128, 4, 0)
+  LBM_BULK_CASE(256, 1)
+  LBM_BULK_CASE(256, 2)
+  LBM_BULK_CASE(512, 1)
+  LBM_BULK_CASE(128, 2)
+  LBM_BULK_CASE(128, 4)
 #undef LBM_BULK_CASE
 }
 
@@ -1718,7 +1805,7 @@ Sweep make_sweep(const int lo[3], const int hi[3], int span, const int* hole, in
 
 hipError_t launch_stream_collide(int lat, int st, int eq, const void* A, void* B, const Geom& g, const Phys& ph,
                                  hipStream_t s, const BulkConfig& cfg, const Sweep& sw, hipEvent_t ev_start,
-                                 hipEvent_t ev_stop) {
+                                 hipEvent_t ev_stop, bool faces) {
   if (sw.ntiles <= 0 || !bulk_supported(cfg)) return hipErrorInvalidValue;
   if (sw.x0 < g.lo[0] || sw.xlast > g.hi[0] || sw.y0 < g.lo[1] || sw.z0 < g.lo[2]) return hipErrorInvalidValue;
   if (sw.y0 + sw.ny - 1 > g.hi[1] || sw.z0 + sw.ntiles / (sw.nbx * sw.ny) - 1 > g.hi[2])
@@ -1730,7 +1817,22 @@ hipError_t launch_stream_collide(int lat, int st, int eq, const void* A, void* B
     using L = decltype(Lt);
     using S = decltype(St);
     constexpr int EQ = decltype(E)::value;
-    launch_bulk_cfg<L, S, EQ>(cfg, A, B, g, ph, sw, s, ev_start, ev_stop);
+    launch_bulk_cfg<L, S, EQ>(cfg, A, B, g, ph, sw, s, ev_start, ev_stop, faces || L::D == 2);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_faces(int lat, int st, int eq, void* B, const Geom& g, const Phys& ph, hipStream_t s) {
+  const int64_t n[3] = {g.hi[0] - g.lo[0] + 1, g.hi[1] - g.lo[1] + 1, g.hi[2] - g.lo[2] + 1};
+  const int64_t nnodes = 2 * (n[1] * n[2] + n[0] * n[2] + (g.D == 3 ? n[0] * n[1] : 0));
+  if (nnodes <= 0) return hipSuccess;
+  if (nnodes > INT32_MAX - 256) return hipErrorInvalidValue;
+  with_types(lat, st, eq, [&](auto Lt, auto St, auto E) {
+    using L = decltype(Lt);
+    using S = decltype(St);
+    constexpr int EQ = decltype(E)::value;
+    hipLaunchKernelGGL((k_faces<L, S, EQ>), dim3((unsigned)((nnodes + 255) / 256), L::Q - 1), dim3(256), 0, s,
+                       (typename S::T*)B, g, ph, (int)nnodes);
   });
   return hipGetLastError();
 }

@@ -35,9 +35,13 @@ bool bulk_supported(const BulkConfig& c);
 // end of the kernel itself by the launch; a start event needs a stop event,
 // a stop event alone marks the kernel's completion (in place of a record
 // after the launch)
+// faces = false (3D): the face rules are left to launch_faces, which must
+// follow on the same stream before the next step
 hipError_t launch_stream_collide(int lat, int st, int eq, const void* A, void* B, const Geom& g, const Phys& ph,
                                  hipStream_t s, const BulkConfig& cfg, const Sweep& sw,
-                                 hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+                                 hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr, bool faces = true);
+// the face rules of the whole domain from the post-collision state B
+hipError_t launch_faces(int lat, int st, int eq, void* B, const Geom& g, const Phys& ph, hipStream_t s);
 
 hipError_t launch_init(int lat, int st, int eq, void* A, uint8_t* mask, const Geom& g, const Phys& ph,
                        const double* rho, const double* u, hipStream_t s);

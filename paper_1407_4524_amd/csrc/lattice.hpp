@@ -63,6 +63,8 @@ struct StoreF64 {
   __device__ static void store(T* p, C v) { __builtin_nontemporal_store(v, p); }
   __device__ static void store_plain(T* p, double v) { *p = v; }
   __device__ static double round_trip(double v) { return v; }
+  // the value a store keeps
+  __device__ static C stored(C v) { return v; }
 };
 
 struct StoreF32 {
@@ -75,6 +77,8 @@ struct StoreF32 {
   __device__ static void store(T* p, C v) { __builtin_nontemporal_store(v, p); }
   __device__ static void store_plain(T* p, double v) { *p = (float)v; }
   __device__ static double round_trip(double v) { return (double)(float)v; }
+  // the value a store keeps
+  __device__ static C stored(C v) { return v; }
 };
 
 // binary16 deviations, round-to-nearest-even on store, FP32 arithmetic
@@ -91,6 +95,8 @@ struct StoreF16 {
   __device__ static void store(T* p, C v) { *p = (_Float16)v; }
   __device__ static void store_plain(T* p, double v) { *p = (_Float16)(float)v; }
   __device__ static double round_trip(double v) { return (double)(float)(_Float16)(float)v; }
+  // the value a store keeps (rounded to binary16, to nearest even)
+  __device__ static C stored(C v) { return (float)(_Float16)v; }
 };
 
 }  // namespace lbm

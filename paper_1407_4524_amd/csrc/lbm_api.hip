@@ -371,14 +371,16 @@ static const BulkConfig NEAR_CFG{128, 2, 0, 0};
 // one stream-collide launch over a sweep of the current source buffer,
 // timed as `kind`, on stream s; *done (optional) becomes an event that
 // completes with the kernel (its timing stop event when timed, else
-// `marker`, recorded by the launch itself)
+// `marker`, recorded by the launch itself); faces = false leaves the face
+// rules to a launch_faces after it
 static lbm_status launch_sweep(lbm_domain d, const BulkConfig& cfg, const Sweep& sw, int kind, hipStream_t s,
-                               hipEvent_t marker = nullptr, hipEvent_t* done = nullptr) {
+                               hipEvent_t marker = nullptr, hipEvent_t* done = nullptr, bool faces = true) {
   hipEvent_t e0, e1;
   lbm_status st = timing_slot(d, kind, sweep_nodes(sw), e0, e1);
   if (st != LBM_OK) return st;
   if (done) *done = e1 ? e1 : marker;
-  HIP_TRY(launch_stream_collide(d->lat, d->st, d->eq, d->A, d->B, d->g, d->ph, s, cfg, sw, e0, e1 ? e1 : marker));
+  HIP_TRY(launch_stream_collide(d->lat, d->st, d->eq, d->A, d->B, d->g, d->ph, s, cfg, sw, e0, e1 ? e1 : marker,
+                                faces));
   return LBM_OK;
 }
 
@@ -668,7 +670,15 @@ lbm_status lbm_step(lbm_domain d, int64_t nsteps) {
       if ((s = launch_sweep(d, NEAR_CFG, near, LBM_KERNEL_NEAR_BOX, d->stream, d->e_near, &near_done)) != LBM_OK)
         return s;
     } else {
-      if ((s = launch_sweep(d, d->bulk, full, LBM_KERNEL_STREAM_COLLIDE, d->stream)) != LBM_OK) return s;
+      // 3D FP16: the face rules in a launch of their own. Inside the sweep
+      // they set its register budget (98 VGPRs against 47) and cost the FP16
+      // kernel 87 us of its 142; k_faces takes 56 us (its x-face nodes are
+      // strided in memory). For FP32 the trade goes the other way (24 us
+      // inside against 56), so FP32 keeps them inside.
+      const bool apart = d->D == 3 && d->st == LBM_F16_SHIFTED;
+      if ((s = launch_sweep(d, d->bulk, full, LBM_KERNEL_STREAM_COLLIDE, d->stream, nullptr, nullptr, !apart)) != LBM_OK)
+        return s;
+      if (apart) HIP_TRY(launch_faces(d->lat, d->st, d->eq, d->B, g, d->ph, d->stream));
     }
     std::swap(d->A, d->B);  // the advance works on the new state
     for (int id = 0; id < LBM_MAX_BODIES; ++id) {

@@ -34,6 +34,8 @@ struct Phys {
   int eq;  // 0 standard, 1 quasi-incompressible
   int inlet_profile;
   double inlet_u;
+  // parabolic inlet: 4 / (n - 2)^2 across the y and z wall pairs
+  double inlet_ky, inlet_kz;
 };
 
 // Pose of a body at one step: 16 doubles on the device.

@@ -46,17 +46,12 @@ __device__ inline int source_type(const Geom& g, int sx, int sy, int sz) {
 
 // inlet speed at the wall point (x = -1/2 or nx - 1/2) with transverse
 // coordinates yB, zB: uniform, or 4 u (p-1/2)(n-3/2-p)/(n-2)^2 per wall axis
+// (4/(n-2)^2 precomputed on the host)
 __device__ inline double inlet_speed(const Geom& g, const Phys& ph, double yB, double zB) {
   double u = ph.inlet_u;
   if (ph.inlet_profile == 1) {
-    if (g.face[2] == FACE_WALL) {
-      double H = g.ny - 2.0;
-      u *= 4.0 * (yB - 0.5) * (g.ny - 1.5 - yB) / (H * H);
-    }
-    if (g.D == 3 && g.face[4] == FACE_WALL) {
-      double H = g.nz - 2.0;
-      u *= 4.0 * (zB - 0.5) * (g.nz - 1.5 - zB) / (H * H);
-    }
+    if (g.face[2] == FACE_WALL) u *= ph.inlet_ky * ((yB - 0.5) * (g.ny - 1.5 - yB));
+    if (g.D == 3 && g.face[4] == FACE_WALL) u *= ph.inlet_kz * ((zB - 0.5) * (g.nz - 1.5 - zB));
   }
   return u;
 }
@@ -81,20 +76,11 @@ __device__ __forceinline__ typename S::C face_density(const typename S::C* hs, d
 //  * copy rules (periodic images, zero-gradient outlet): the halo slot that a
 //    wrapped (or outlet-shifted) destination pulls from gets hi.
 // st is source_type of x - c_i.
-template <class L, class S>
-__device__ __forceinline__ void face_rule(typename S::T* __restrict__ B, const Geom& g, const Phys& ph, int x, int y,
-                                          int z, int64_t c, int i, int st, typename S::C hopp, typename S::C hi,
-                                          typename S::C rho_w) {
-  using C = typename S::C;
+// The halo slot a copy rule of direction i at node (x, y, z) writes (cell
+// index, plane i), or -1 when no copy rule applies.
+template <class L>
+__device__ __forceinline__ int64_t face_copy_cell(const Geom& g, int x, int y, int z, int i) {
   const int cx = L::cx(i), cy = L::cy(i), cz = L::cz(i);
-  const int64_t off = cx + cy * g.sy + cz * g.sz;
-  if (st == SRC_WALL) {
-    S::store(B + i * g.S + c - off, hopp);
-  } else if (st == SRC_INLET || st == SRC_OUTVEL) {
-    double u = inlet_speed(g, ph, y - 0.5 * cy, z - 0.5 * cz);
-    C add = (C)(6.0 * L::w(i)) * rho_w * (C)(cx * u);
-    S::store(B + i * g.S + c - off, hopp + add);
-  }
   int ex = x + cx, ey = y + cy, ez = z + cz;
   bool sh = false;
   if (g.face[1] == FACE_OUTLET && cx == -1 && x == g.nx - 1) {
@@ -115,7 +101,25 @@ __device__ __forceinline__ void face_rule(typename S::T* __restrict__ B, const G
   }
   bool active = ex >= g.lo[0] && ex <= g.hi[0] && ey >= g.lo[1] && ey <= g.hi[1] &&
                 (L::D == 2 || (ez >= g.lo[2] && ez <= g.hi[2]));
-  if (sh && active) S::store(B + i * g.S + g.idx(ex - cx, ey - cy, ez - cz), hi);
+  return sh && active ? g.idx(ex - cx, ey - cy, ez - cz) : (int64_t)-1;
+}
+
+template <class L, class S>
+__device__ __forceinline__ void face_rule(typename S::T* __restrict__ B, const Geom& g, const Phys& ph, int x, int y,
+                                          int z, int64_t c, int i, int st, typename S::C hopp, typename S::C hi,
+                                          typename S::C rho_w) {
+  using C = typename S::C;
+  const int cx = L::cx(i), cy = L::cy(i), cz = L::cz(i);
+  const int64_t off = cx + cy * g.sy + cz * g.sz;
+  if (st == SRC_WALL) {
+    S::store(B + i * g.S + c - off, hopp);
+  } else if (st == SRC_INLET || st == SRC_OUTVEL) {
+    double u = inlet_speed(g, ph, y - 0.5 * cy, z - 0.5 * cz);
+    C add = (C)(6.0 * L::w(i)) * rho_w * (C)(cx * u);
+    S::store(B + i * g.S + c - off, hopp + add);
+  }
+  const int64_t dst = face_copy_cell<L>(g, x, y, z, i);
+  if (dst >= 0) S::store(B + i * g.S + dst, hi);
 }
 
 // Every face rule of a node next to a face, from its post-collision
@@ -255,23 +259,17 @@ __global__ __launch_bounds__(BX) void k_stream_collide(const typename S::T* __re
   stream_collide_span<L, S, EQ, BX, CPT, FACES>(A, B, g, ph, x + threadIdx.x, y, z, sw.xlast, sw.hole);
 }
 
-// The face rules of a whole-domain stream-collide launched without them:
-// one thread per (node next to a face, direction), the direction from the
-// grid's y index, so that a wavefront shares its direction and runs over
-// consecutive nodes (32-bit index arithmetic throughout). Face nodes are
-// enumerated slab by slab: x = lo, x = hi, y = lo, y = hi, then z = lo,
-// z = hi in 3D; a node in several slabs belongs to the first.
-__device__ __forceinline__ bool face_node(const Geom& g, int k, int& x, int& y, int& z) {
+// The face rules of a whole-domain stream-collide launched without them, in
+// two launches. The nodes of the x faces (a row pitch apart from one another)
+// take one thread each, which reads the node's populations once and applies
+// every rule (k_faces_x). The nodes of the other faces take one thread per
+// (node, direction), the direction from the grid's y index, so that a
+// wavefront shares its direction and runs over consecutive nodes
+// (k_faces_yz); a node of several faces belongs to the x faces, then the y
+// faces. 32-bit index arithmetic throughout.
+__device__ __forceinline__ bool face_node_yz(const Geom& g, int k, int& x, int& y, int& z) {
   const int n0 = g.hi[0] - g.lo[0] + 1, n1 = g.hi[1] - g.lo[1] + 1, n2 = g.hi[2] - g.lo[2] + 1;
-  const int sx = n1 * n2, sy = n0 * n2, sz = n0 * n1;
-  if (k < 2 * sx) {
-    const int side = k >= sx, r = side ? k - sx : k;
-    x = side ? g.hi[0] : g.lo[0];
-    y = g.lo[1] + r % n1;
-    z = g.lo[2] + r / n1;
-    return !(side && n0 == 1);
-  }
-  k -= 2 * sx;
+  const int sy = n0 * n2, sz = n0 * n1;
   if (k < 2 * sy) {
     const int side = k >= sy, r = side ? k - sy : k;
     x = g.lo[0] + r % n0;
@@ -291,14 +289,33 @@ __device__ __forceinline__ bool face_node(const Geom& g, int k, int& x, int& y, 
 }
 
 template <class L, class S, int EQ>
-__global__ __launch_bounds__(256) void k_faces(typename S::T* __restrict__ B, Geom g, Phys ph, int nnodes) {
+__global__ __launch_bounds__(256) void k_faces_x(typename S::T* __restrict__ B, Geom g, Phys ph) {
+  using C = typename S::C;
+  const int n0 = g.hi[0] - g.lo[0] + 1, n1 = g.hi[1] - g.lo[1] + 1, n2 = g.hi[2] - g.lo[2] + 1;
+  const int k = (int)blockIdx.x * 256 + (int)threadIdx.x;
+  if (k >= 2 * n1 * n2) return;
+  const int side = k >= n1 * n2, r = side ? k - n1 * n2 : k;
+  if (side && n0 == 1) return;
+  const int x = side ? g.hi[0] : g.lo[0], y = g.lo[1] + r % n1, z = g.lo[2] + r / n1;
+  const int64_t c = g.idx(x, y, z);
+  C hs[L::Q];
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) hs[q] = S::load(B + q * g.S + c);
+  write_faces<L, S>(B, g, ph, x, y, z, c, hs, EQ ? (C)ph.rho0 : face_density<L, S>(hs, ph.rho0));
+}
+
+template <class L, class S, int EQ>
+__global__ __launch_bounds__(256) void k_faces_yz(typename S::T* __restrict__ B, Geom g, Phys ph, int nnodes) {
   using C = typename S::C;
   const int k = (int)blockIdx.x * 256 + (int)threadIdx.x;
   const int i = (int)blockIdx.y + 1;
   int x, y, z;
-  if (k >= nnodes || !face_node(g, k, x, y, z)) return;
-  const int64_t c = g.idx(x, y, z);
+  if (k >= nnodes || !face_node_yz(g, k, x, y, z)) return;
   const int st = source_type(g, x - L::cx(i), y - L::cy(i), z - L::cz(i));
+  const int64_t dst = face_copy_cell<L>(g, x, y, z, i);
+  const bool bounce = st == SRC_WALL || st == SRC_INLET || st == SRC_OUTVEL;
+  if (!bounce && dst < 0) return;  // no rule for this direction: nothing to read
+  const int64_t c = g.idx(x, y, z);
   C rho_w = (C)ph.rho0;
   if (!EQ && (st == SRC_INLET || st == SRC_OUTVEL)) {  // the inlet rule's density: all populations
     C hs[L::Q];
@@ -306,7 +323,9 @@ __global__ __launch_bounds__(256) void k_faces(typename S::T* __restrict__ B, Ge
     for (int q = 0; q < L::Q; ++q) hs[q] = S::load(B + q * g.S + c);
     rho_w = face_density<L, S>(hs, ph.rho0);
   }
-  face_rule<L, S>(B, g, ph, x, y, z, c, i, st, S::load(B + L::opp(i) * g.S + c), S::load(B + i * g.S + c), rho_w);
+  const C hopp = bounce ? S::load(B + L::opp(i) * g.S + c) : (C)0;
+  const C hi = dst >= 0 ? S::load(B + i * g.S + c) : (C)0;
+  face_rule<L, S>(B, g, ph, x, y, z, c, i, st, hopp, hi, rho_w);
 }
 
 // initial state: equilibrium deviations at (rho, u) per node, the face ghosts
@@ -1824,15 +1843,19 @@ hipError_t launch_stream_collide(int lat, int st, int eq, const void* A, void* B
 
 hipError_t launch_faces(int lat, int st, int eq, void* B, const Geom& g, const Phys& ph, hipStream_t s) {
   const int64_t n[3] = {g.hi[0] - g.lo[0] + 1, g.hi[1] - g.lo[1] + 1, g.hi[2] - g.lo[2] + 1};
-  const int64_t nnodes = 2 * (n[1] * n[2] + n[0] * n[2] + (g.D == 3 ? n[0] * n[1] : 0));
-  if (nnodes <= 0) return hipSuccess;
-  if (nnodes > INT32_MAX - 256) return hipErrorInvalidValue;
+  const int64_t nx = 2 * n[1] * n[2];
+  const int64_t nyz = 2 * (n[0] * n[2] + (g.D == 3 ? n[0] * n[1] : 0));
+  if (nx + nyz > INT32_MAX - 256) return hipErrorInvalidValue;
   with_types(lat, st, eq, [&](auto Lt, auto St, auto E) {
     using L = decltype(Lt);
     using S = decltype(St);
     constexpr int EQ = decltype(E)::value;
-    hipLaunchKernelGGL((k_faces<L, S, EQ>), dim3((unsigned)((nnodes + 255) / 256), L::Q - 1), dim3(256), 0, s,
-                       (typename S::T*)B, g, ph, (int)nnodes);
+    if (nx > 0)
+      hipLaunchKernelGGL((k_faces_x<L, S, EQ>), dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, s,
+                         (typename S::T*)B, g, ph);
+    if (nyz > 0)
+      hipLaunchKernelGGL((k_faces_yz<L, S, EQ>), dim3((unsigned)((nyz + 255) / 256), L::Q - 1), dim3(256), 0, s,
+                         (typename S::T*)B, g, ph, (int)nyz);
   });
   return hipGetLastError();
 }

@@ -463,6 +463,8 @@ lbm_status lbm_create_domain(const lbm_domain_desc* desc, lbm_domain* out) {
   d->ph.eq = desc->eq_model;
   d->ph.inlet_profile = desc->inlet_profile;
   d->ph.inlet_u = desc->inlet_u;
+  d->ph.inlet_ky = 4.0 / ((desc->ny - 2.0) * (desc->ny - 2.0));
+  d->ph.inlet_kz = 4.0 / ((desc->nz - 2.0) * (desc->nz - 2.0));
   d->stream = (hipStream_t)desc->stream;
   d->own_stream = d->stream;
   d->rec_cap = L.rec_cap;

@@ -71,6 +71,8 @@ struct lbm_domain_s {
   // second stream: the far update of a split step; created on first use
   hipStream_t aux = nullptr;
   hipEvent_t e_near = nullptr, e_far = nullptr;
+  // x-face densities of a sweep without the face rules (see Sweep::face_rho)
+  void* face_rho = nullptr;
   // kernel timing ring, by kind (LBM_KERNEL_*), every timing_every-th launch
   // of each kind
   int timing_every = 0;

@@ -56,17 +56,6 @@ __device__ inline double inlet_speed(const Geom& g, const Phys& ph, double yB, d
   return u;
 }
 
-// Density a face rule takes at a node: from the post-collision deviations
-// as stored (hs), summed in direction order, so that the rule gives the same
-// bits inside the stream-collide kernel and in k_faces.
-template <class L, class S>
-__device__ __forceinline__ typename S::C face_density(const typename S::C* hs, double rho0) {
-  typename S::C d = (typename S::C)rho0;
-#pragma unroll
-  for (int i = 0; i < L::Q; ++i) d += hs[i];
-  return d;
-}
-
 // The face rules of direction i at node (x, y, z) (cell c) for the next
 // step, from its post-collision deviations as stored: hopp (direction
 // opposite to i), hi (direction i), and the density rho_w (used by the
@@ -182,12 +171,16 @@ __device__ inline int xcd_block(int hw, int nblocks) {
 // hole box (x0, x1, y0, y1, z0, z1; empty when x0 > x1) are left alone. All
 // CPT*Q loads are issued before any arithmetic.
 // With FACES, a node next to a domain face also writes that face's ghost
-// values for the next step (write_faces); without, k_faces does it after the
-// launch (the face code then does not set the kernel's register budget).
+// values for the next step (write_faces); without, the face kernels do it
+// after the launch (the face code then does not set the kernel's register
+// budget), and a node of an x face leaves its density (the one the inlet
+// rule takes) in face_rho, when given, so that they need not read all its
+// populations.
 template <class L, class S, int EQ, int BX, int CPT, bool FACES>
 __device__ __forceinline__ void stream_collide_span(const typename S::T* __restrict__ A,
                                                     typename S::T* __restrict__ B, const Geom& g, const Phys& ph,
-                                                    int x0, int y, int z, int xlast, const int* hole) {
+                                                    int x0, int y, int z, int xlast, const int* hole,
+                                                    typename S::C* face_rho = nullptr) {
   using C = typename S::C;
   const bool hole_row = y >= hole[2] && y <= hole[3] && z >= hole[4] && z <= hole[5];
   bool ok[CPT];
@@ -228,15 +221,20 @@ __device__ __forceinline__ void stream_collide_span(const typename S::T* __restr
     collide<L, S, EQ>(h[k], (C)ph.rho0, (C)ph.omega, rho);
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) B[i * g.S + c] = (typename S::T)h[k][i];
-    (void)rho;
-    if (!FACES) continue;
+    if (!FACES) {
+      if (face_rho && (x == g.lo[0] || x == g.hi[0])) {
+        const int n1 = g.hi[1] - g.lo[1] + 1, n2 = g.hi[2] - g.lo[2] + 1;
+        face_rho[(x == g.lo[0] ? 0 : n1 * n2) + (y - g.lo[1]) + n1 * (z - g.lo[2])] = rho;
+      }
+      continue;
+    }
     const bool near = x <= g.lo[0] || x >= g.hi[0] || y <= g.lo[1] || y >= g.hi[1] ||
                       (L::D == 3 && (z <= g.lo[2] || z >= g.hi[2]));
     if (near) {
       C hs[L::Q];
 #pragma unroll
       for (int i = 0; i < L::Q; ++i) hs[i] = S::stored(h[k][i]);
-      write_faces<L, S>(B, g, ph, x, y, z, c, hs, EQ ? (C)ph.rho0 : face_density<L, S>(hs, ph.rho0));
+      write_faces<L, S>(B, g, ph, x, y, z, c, hs, EQ ? (C)ph.rho0 : rho);
     }
   }
 }
@@ -256,20 +254,33 @@ __global__ __launch_bounds__(BX) void k_stream_collide(const typename S::T* __re
   const int blk = sw.remap ? xcd_block(blockIdx.x, sw.ntiles) : blockIdx.x;
   int x, y, z;
   sweep_tile(sw, blk, BX * CPT, x, y, z);
-  stream_collide_span<L, S, EQ, BX, CPT, FACES>(A, B, g, ph, x + threadIdx.x, y, z, sw.xlast, sw.hole);
+  stream_collide_span<L, S, EQ, BX, CPT, FACES>(A, B, g, ph, x + threadIdx.x, y, z, sw.xlast, sw.hole,
+                                                (typename S::C*)sw.face_rho);
 }
 
-// The face rules of a whole-domain stream-collide launched without them, in
-// two launches. The nodes of the x faces (a row pitch apart from one another)
-// take one thread each, which reads the node's populations once and applies
-// every rule (k_faces_x). The nodes of the other faces take one thread per
-// (node, direction), the direction from the grid's y index, so that a
-// wavefront shares its direction and runs over consecutive nodes
-// (k_faces_yz); a node of several faces belongs to the x faces, then the y
-// faces. 32-bit index arithmetic throughout.
-__device__ __forceinline__ bool face_node_yz(const Geom& g, int k, int& x, int& y, int& z) {
+// The face rules of a whole-domain stream-collide launched without them:
+// one thread per (node next to a face, direction), the direction from the
+// grid's y index, so that a wavefront shares its direction and runs over
+// consecutive nodes; a direction without a rule reads nothing. The inlet
+// rule's density (the node's density in the collision, which the sweep left
+// in face_rho) is read from there, so an x-face
+// node, whose populations lie a row pitch from its neighbours', is read only
+// where a rule needs it. Face nodes are enumerated slab by slab: x = lo,
+// x = hi, y = lo, y = hi, then z = lo, z = hi in 3D; a node in several slabs
+// belongs to the first. 32-bit index arithmetic throughout.
+__device__ __forceinline__ bool face_node(const Geom& g, int k, int& x, int& y, int& z, int& xrow) {
   const int n0 = g.hi[0] - g.lo[0] + 1, n1 = g.hi[1] - g.lo[1] + 1, n2 = g.hi[2] - g.lo[2] + 1;
-  const int sy = n0 * n2, sz = n0 * n1;
+  const int sx = n1 * n2, sy = n0 * n2, sz = n0 * n1;
+  xrow = -1;
+  if (k < 2 * sx) {
+    const int side = k >= sx, r = side ? k - sx : k;
+    x = side ? g.hi[0] : g.lo[0];
+    y = g.lo[1] + r % n1;
+    z = g.lo[2] + r / n1;
+    xrow = k;
+    return !(side && n0 == 1);
+  }
+  k -= 2 * sx;
   if (k < 2 * sy) {
     const int side = k >= sy, r = side ? k - sy : k;
     x = g.lo[0] + r % n0;
@@ -289,40 +300,21 @@ __device__ __forceinline__ bool face_node_yz(const Geom& g, int k, int& x, int& 
 }
 
 template <class L, class S, int EQ>
-__global__ __launch_bounds__(256) void k_faces_x(typename S::T* __restrict__ B, Geom g, Phys ph) {
-  using C = typename S::C;
-  const int n0 = g.hi[0] - g.lo[0] + 1, n1 = g.hi[1] - g.lo[1] + 1, n2 = g.hi[2] - g.lo[2] + 1;
-  const int k = (int)blockIdx.x * 256 + (int)threadIdx.x;
-  if (k >= 2 * n1 * n2) return;
-  const int side = k >= n1 * n2, r = side ? k - n1 * n2 : k;
-  if (side && n0 == 1) return;
-  const int x = side ? g.hi[0] : g.lo[0], y = g.lo[1] + r % n1, z = g.lo[2] + r / n1;
-  const int64_t c = g.idx(x, y, z);
-  C hs[L::Q];
-#pragma unroll
-  for (int q = 0; q < L::Q; ++q) hs[q] = S::load(B + q * g.S + c);
-  write_faces<L, S>(B, g, ph, x, y, z, c, hs, EQ ? (C)ph.rho0 : face_density<L, S>(hs, ph.rho0));
-}
-
-template <class L, class S, int EQ>
-__global__ __launch_bounds__(256) void k_faces_yz(typename S::T* __restrict__ B, Geom g, Phys ph, int nnodes) {
+__global__ __launch_bounds__(256) void k_faces(typename S::T* __restrict__ B, const typename S::C* __restrict__ face_rho,
+                                               Geom g, Phys ph, int nnodes) {
   using C = typename S::C;
   const int k = (int)blockIdx.x * 256 + (int)threadIdx.x;
   const int i = (int)blockIdx.y + 1;
-  int x, y, z;
-  if (k >= nnodes || !face_node_yz(g, k, x, y, z)) return;
+  int x, y, z, xrow;
+  if (k >= nnodes || !face_node(g, k, x, y, z, xrow)) return;
   const int st = source_type(g, x - L::cx(i), y - L::cy(i), z - L::cz(i));
   const int64_t dst = face_copy_cell<L>(g, x, y, z, i);
   const bool bounce = st == SRC_WALL || st == SRC_INLET || st == SRC_OUTVEL;
   if (!bounce && dst < 0) return;  // no rule for this direction: nothing to read
   const int64_t c = g.idx(x, y, z);
   C rho_w = (C)ph.rho0;
-  if (!EQ && (st == SRC_INLET || st == SRC_OUTVEL)) {  // the inlet rule's density: all populations
-    C hs[L::Q];
-#pragma unroll
-    for (int q = 0; q < L::Q; ++q) hs[q] = S::load(B + q * g.S + c);
-    rho_w = face_density<L, S>(hs, ph.rho0);
-  }
+  // only x-face nodes pull from an inlet or a velocity outlet
+  if (!EQ && (st == SRC_INLET || st == SRC_OUTVEL) && xrow >= 0) rho_w = face_rho[xrow];
   const C hopp = bounce ? S::load(B + L::opp(i) * g.S + c) : (C)0;
   const C hi = dst >= 0 ? S::load(B + i * g.S + c) : (C)0;
   face_rule<L, S>(B, g, ph, x, y, z, c, i, st, hopp, hi, rho_w);
@@ -1819,6 +1811,7 @@ Sweep make_sweep(const int lo[3], const int hi[3], int span, const int* hole, in
   sw.ntiles = sw.nbx * sw.ny * (hi[2] - lo[2] + 1);
   sw.remap = remap;
   for (int k = 0; k < 6; ++k) sw.hole[k] = hole ? hole[k] : (k & 1 ? 0 : 1);
+  sw.face_rho = nullptr;
   return sw;
 }
 
@@ -1841,21 +1834,18 @@ hipError_t launch_stream_collide(int lat, int st, int eq, const void* A, void* B
   return hipGetLastError();
 }
 
-hipError_t launch_faces(int lat, int st, int eq, void* B, const Geom& g, const Phys& ph, hipStream_t s) {
+hipError_t launch_faces(int lat, int st, int eq, void* B, const void* face_rho, const Geom& g, const Phys& ph,
+                        hipStream_t s) {
   const int64_t n[3] = {g.hi[0] - g.lo[0] + 1, g.hi[1] - g.lo[1] + 1, g.hi[2] - g.lo[2] + 1};
-  const int64_t nx = 2 * n[1] * n[2];
-  const int64_t nyz = 2 * (n[0] * n[2] + (g.D == 3 ? n[0] * n[1] : 0));
-  if (nx + nyz > INT32_MAX - 256) return hipErrorInvalidValue;
+  const int64_t nnodes = 2 * (n[1] * n[2] + n[0] * n[2] + (g.D == 3 ? n[0] * n[1] : 0));
+  if (nnodes <= 0) return hipSuccess;
+  if (nnodes > INT32_MAX - 256 || !face_rho) return hipErrorInvalidValue;
   with_types(lat, st, eq, [&](auto Lt, auto St, auto E) {
     using L = decltype(Lt);
     using S = decltype(St);
     constexpr int EQ = decltype(E)::value;
-    if (nx > 0)
-      hipLaunchKernelGGL((k_faces_x<L, S, EQ>), dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, s,
-                         (typename S::T*)B, g, ph);
-    if (nyz > 0)
-      hipLaunchKernelGGL((k_faces_yz<L, S, EQ>), dim3((unsigned)((nyz + 255) / 256), L::Q - 1), dim3(256), 0, s,
-                         (typename S::T*)B, g, ph, (int)nyz);
+    hipLaunchKernelGGL((k_faces<L, S, EQ>), dim3((unsigned)((nnodes + 255) / 256), L::Q - 1), dim3(256), 0, s,
+                       (typename S::T*)B, (const typename S::C*)face_rho, g, ph, (int)nnodes);
   });
   return hipGetLastError();
 }

@@ -27,6 +27,10 @@ BulkConfig bulk_config(int lat, int st, size_t footprint);
 struct Sweep {
   int x0, y0, z0, xlast, ny, nbx, ntiles, remap;
   int hole[6];
+  // sweeps without the face rules (3D): where the nodes of the faces x = lo
+  // (first half) and x = hi leave the density the inlet rule takes (row
+  // y + ny z of the active box), for launch_faces; null otherwise
+  void* face_rho;
 };
 Sweep make_sweep(const int lo[3], const int hi[3], int span, const int* hole, int remap);
 bool bulk_supported(const BulkConfig& c);
@@ -40,8 +44,11 @@ bool bulk_supported(const BulkConfig& c);
 hipError_t launch_stream_collide(int lat, int st, int eq, const void* A, void* B, const Geom& g, const Phys& ph,
                                  hipStream_t s, const BulkConfig& cfg, const Sweep& sw,
                                  hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr, bool faces = true);
-// the face rules of the whole domain from the post-collision state B
-hipError_t launch_faces(int lat, int st, int eq, void* B, const Geom& g, const Phys& ph, hipStream_t s);
+// the face rules of the whole domain from the post-collision state B and
+// the x-face densities the sweep left in face_rho (2 n_y n_z values of the
+// storage's compute type)
+hipError_t launch_faces(int lat, int st, int eq, void* B, const void* face_rho, const Geom& g, const Phys& ph,
+                        hipStream_t s);
 
 hipError_t launch_init(int lat, int st, int eq, void* A, uint8_t* mask, const Geom& g, const Phys& ph,
                        const double* rho, const double* u, hipStream_t s);

@@ -530,6 +530,7 @@ lbm_status lbm_destroy_domain(lbm_domain d) {
     (void)hipEventDestroy(d->e_near);
     (void)hipEventDestroy(d->e_far);
   }
+  if (d->face_rho) (void)hipFree(d->face_rho);
   if (d->steady_buf) (void)hipFree(d->steady_buf);
   if (d->owns_pool) (void)hipFree(d->pool);
   for (int k = 0; k < 64; ++k)
@@ -678,9 +679,17 @@ lbm_status lbm_step(lbm_domain d, int64_t nsteps) {
       // strided in memory). For FP32 the trade goes the other way (24 us
       // inside against 56), so FP32 keeps them inside.
       const bool apart = d->D == 3 && d->st == LBM_F16_SHIFTED;
-      if ((s = launch_sweep(d, d->bulk, full, LBM_KERNEL_STREAM_COLLIDE, d->stream, nullptr, nullptr, !apart)) != LBM_OK)
+      Sweep sw = full;
+      if (apart) {
+        if (!d->face_rho) {
+          const size_t n = 2 * (size_t)(g.hi[1] - g.lo[1] + 1) * (g.hi[2] - g.lo[2] + 1);
+          HIP_TRY(hipMalloc(&d->face_rho, n * (d->st == LBM_F64 ? sizeof(double) : sizeof(float))));
+        }
+        sw.face_rho = d->face_rho;
+      }
+      if ((s = launch_sweep(d, d->bulk, sw, LBM_KERNEL_STREAM_COLLIDE, d->stream, nullptr, nullptr, !apart)) != LBM_OK)
         return s;
-      if (apart) HIP_TRY(launch_faces(d->lat, d->st, d->eq, d->B, g, d->ph, d->stream));
+      if (apart) HIP_TRY(launch_faces(d->lat, d->st, d->eq, d->B, d->face_rho, g, d->ph, d->stream));
     }
     std::swap(d->A, d->B);  // the advance works on the new state
     for (int id = 0; id < LBM_MAX_BODIES; ++id) {

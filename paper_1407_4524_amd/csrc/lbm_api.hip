@@ -674,10 +674,11 @@ lbm_status lbm_step(lbm_domain d, int64_t nsteps) {
         return s;
     } else {
       // 3D FP16: the face rules in a launch of their own. Inside the sweep
-      // they set its register budget (98 VGPRs against 47) and cost the FP16
-      // kernel 87 us of its 142; k_faces takes 56 us (its x-face nodes are
-      // strided in memory). For FP32 the trade goes the other way (24 us
-      // inside against 56), so FP32 keeps them inside.
+      // they set its register budget (98 VGPRs against 48) and cost the FP16
+      // kernel 79 us of its 142; k_faces takes 19 us, reading the inlet
+      // density of each x-face node from the small array the sweep fills.
+      // For FP32 the trade is about even (24 us inside), so FP32 keeps them
+      // inside.
       const bool apart = d->D == 3 && d->st == LBM_F16_SHIFTED;
       Sweep sw = full;
       if (apart) {

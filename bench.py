@@ -294,9 +294,9 @@ def main():
                     help="run link rule, stream-collide and body advance one after another (no overlap)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
               "(a domain larger than one GPU would be split into x-slabs with a one-layer halo "
-              "exchange; that is described, not built).", file=sys.stderr)
+              "exchange; that is described, not implemented).", file=sys.stderr)
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
 

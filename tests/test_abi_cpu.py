@@ -55,3 +55,15 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(lbm, "_lib", None)
     with pytest.raises(ImportError):
         lbm.lib()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """the benchmark runs on one GPU only and says so, before touching any device"""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300, cwd=root)
+    assert r.returncode == 2
+    assert "exactly one GPU" in r.stderr
+    assert r.stdout.strip() == ""

@@ -195,6 +195,29 @@ def test_duct_sphere_64x32x32(storage, tol_ft, tol_u):
     assert eF < tol_ft and eT < tol_ft and du < tol_u
 
 
+@pytest.mark.parametrize("storage,tol_ft,tol_u", [("f32", 1e-4, 5e-6), ("f16", 1e-3, 3e-4)])
+def test_duct_sphere_full_size_first_steps(storage, tol_ft, tol_u):
+    """The full 256x128x128 duct with the sphere of radius 16 (the benchmarked
+    size and launch configuration: one sweep per step, the FP16 face rules in
+    a launch of their own), 3 steps against the oracle at full size: links,
+    force/torque and velocity. The fluid starts moving at the inlet speed
+    everywhere, so the sphere's force is the impulsive start's from the first
+    step rather than density noise."""
+    w = W.duct_sphere(scale=1, storage=storage)
+    n = w["nx"] * w["ny"] * w["nz"]
+    u0 = np.zeros((n, 3))
+    u0[:, 0] = w["inlet_u"]
+    print(f"full-size duct {storage}: {w['nx']}x{w['ny']}x{w['nz']}, 3 steps", flush=True)
+    g, o = run_pair(w, 3, init_u=u0)
+    same_links(g, o)
+    F, T = ora_series(o, 0, "static")
+    eF, eT = series_error(g.force_torque(0), F, T, 16.0, scale=np.abs(F).max())
+    du = velocity_error(g, o)
+    print(f"{storage}: F {eF:.2e} T {eT:.2e} u {du:.2e} (|F| max {np.abs(F).max():.3e})")
+    assert np.abs(F).max() > 1e-3
+    assert eF < tol_ft and eT < tol_ft and du < tol_u
+
+
 @pytest.mark.parametrize("lattice,storage,faces", [
     ("D2Q9", "f32", "ragged"), ("D2Q9", "f16", "ragged"), ("D3Q19", "f16", "ragged"), ("D2Q9", "f32", "wall_x"),
     ("D3Q19", "f32", "wall_x")])

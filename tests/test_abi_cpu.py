@@ -67,3 +67,46 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2
     assert "exactly one GPU" in r.stderr
     assert r.stdout.strip() == ""
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(nx=2), "each axis needs >= 3 nodes"),
+    (dict(lattice="D3Q19", nz=2), "each axis needs >= 3 nodes"),
+    (dict(ny=32001), "axis longer than 32000 nodes"),
+    (dict(tau=0.5), "tau must exceed 1/2"),
+    (dict(rho0=0.0), "rho0 must be positive"),
+    (dict(faces=("periodic", "wall", "wall", "wall", "periodic", "periodic")), "periodic faces come in pairs"),
+    (dict(faces=("outlet", "outlet", "wall", "wall", "periodic", "periodic")), "inlet only on -x"),
+    (dict(faces=("wall", "wall", "inlet", "wall", "periodic", "periodic")), "inlet/outlet faces only along x"),
+])
+def test_invalid_domain_rejected_on_the_host(kw, msg):
+    """The descriptor checks run before any HIP call: each invalid setting
+    gives LBM_E_INVAL and its message from lbm_create_domain and from
+    lbm_footprint_bytes, without a GPU."""
+    import ctypes as C
+    from paper_1407_4524_amd import Domain, lbm
+    with pytest.raises(lbm.LbmError) as e:
+        Domain(**kw)
+    assert e.value.status == -1 and msg in str(e.value)
+    d = lbm.domain_desc(**kw)
+    n = C.c_size_t(0)
+    assert lbm.lib().lbm_footprint_bytes(C.byref(d), C.byref(n)) == -1
+    assert msg in lbm.lib().lbm_last_error().decode()
+
+
+def test_footprint_follows_the_layout():
+    """lbm_footprint_bytes (host arithmetic only) grows with the storage
+    width and the lattice, and covers both population buffers."""
+    import ctypes as C
+    from paper_1407_4524_amd import lbm
+
+    def fp(**kw):
+        n = C.c_size_t(0)
+        assert lbm.lib().lbm_footprint_bytes(C.byref(lbm.domain_desc(**kw)), C.byref(n)) == 0
+        return n.value
+
+    nx, ny = 500, 300
+    f64, f32, f16 = (fp(nx=nx, ny=ny, storage=s) for s in ("f64", "f32", "f16"))
+    assert f64 > f32 > f16
+    assert f32 >= 2 * 9 * nx * ny * 4 and f16 >= 2 * 9 * nx * ny * 2
+    assert fp(lattice="D3Q19", nx=40, ny=30, nz=20) >= 2 * 19 * 40 * 30 * 20 * 4

@@ -75,10 +75,13 @@ def test_channel_cylinder_mls_f64_delta_bit_exact():
 
 
 @pytest.mark.parametrize("lat,eq,shape", [("D2Q9", "bgk", (37, 23, 1)), ("D2Q9", "heluo", (300, 5, 1)),
-                                          ("D3Q19", "bgk", (19, 13, 11)), ("D2Q9", "bgk", (3, 3, 1))])
+                                          ("D3Q19", "bgk", (19, 13, 11)), ("D2Q9", "bgk", (3, 3, 1)),
+                                          ("D3Q19", "bgk", (3, 3, 3)), ("D2Q9", "bgk", (32000, 3, 1)),
+                                          ("D3Q19", "bgk", (3, 3, 32000))])
 def test_periodic_box_f64(lat, eq, shape):
-    """Random density and velocity on a periodic box (ragged sizes, down to
-    3x3): fields after 150 steps equal the oracle's; mass is conserved."""
+    """Random density and velocity on a periodic box (ragged sizes, from the
+    smallest box of 3 nodes per axis to an axis of 32000, the longest one
+    allowed): fields after 150 steps equal the oracle's; mass is conserved."""
     w = box(lat, *shape, tau=0.7, eq=eq)
     rho, u = W.random_state(w, seed=21)
     g, o = run_pair(w, 150, init_rho=rho, init_u=u)

@@ -580,6 +580,7 @@ lbm_status lbm_set_body(lbm_domain d, int32_t id, const lbm_body_desc* bd) {
   if (s != LBM_OK) {
     (void)hipFree(b.links);
     (void)hipFree(b.n_links);
+    (void)hipFree(b.partials);
     b = Body();
     return s;
   }

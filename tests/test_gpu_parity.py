@@ -353,3 +353,44 @@ def test_rotating_ellipsoid_with_a_large_surface():
     assert eF < 1e-4 and eT < 1e-4
     g.close()
     o.close()
+
+
+# ---------------------------------------------------------------------------
+# error paths and calls that do nothing, on a live domain
+
+
+def test_domain_error_paths_and_empty_calls():
+    """step(0) changes nothing; a negative step count, a body id out of range
+    or in use, a body that would leave the interior and steps outside the
+    record ring each give their status, and the domain stays usable (the
+    failed body id is free again)."""
+    from paper_1407_4524_amd import LbmError
+    w = W.channel_cylinder_f64()
+    g = make_gpu(w, record_capacity=16)
+    print("error paths: channel 100x50, record ring of 16 steps", flush=True)
+    rho0, u0 = g.fields()
+    g.step(0)
+    assert g.t == 0
+    rho1, u1 = g.fields()
+    assert np.array_equal(rho0, rho1, equal_nan=True) and np.array_equal(u0, u1, equal_nan=True)
+
+    def status(fn, *a, **kw):
+        with pytest.raises(LbmError) as e:
+            fn(*a, **kw)
+        return e.value.status
+
+    assert status(g.step, -1) == -1
+    body = dict(w["bodies"][0])
+    assert status(g.set_body, 0, **body) == -6                      # id in use
+    assert status(g.set_body, 4, **body) == -1                      # id out of range
+    outside = dict(body, c0=(97.0, 25.0, 0.0))
+    assert status(g.set_body, 1, **outside) == -4                   # leaves the interior
+    assert status(g.force_torque, 0, 0, 1) == -4                    # no step taken yet
+    g.step(20)
+    assert g.t == 20
+    assert status(g.force_torque, 0, 0, 1) == -4                    # step 0 left the ring of 16
+    assert np.isfinite(g.force_torque(0, 4, 16)).all()              # the last 16 steps are there
+    g.set_body(1, **dict(body, c0=(70.2, 24.7, 0.0)))               # the failed id is free again
+    g.step(5)
+    assert np.isfinite(g.force_torque(1, 20, 5)).all()
+    g.close()

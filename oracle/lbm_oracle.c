@@ -764,6 +764,16 @@ int64_t ora_links(const ora_dom* d, int b, int64_t cap, int64_t* node, int32_t* 
   return k;
 }
 
+int ora_body_pose(const ora_dom* d, int b, int64_t t, double* out) {
+  if (!d || b < 0 || b >= ORA_MAX_BODIES || !d->body[b].active || t < 0) return -1;
+  pose_t p = body_pose(&d->body[b], t);
+  for (int a = 0; a < 3; ++a) out[a] = p.X[a];
+  out[3] = p.theta;
+  for (int a = 0; a < 3; ++a) out[4 + a] = p.V[a];
+  out[7] = p.Om;
+  return 0;
+}
+
 int ora_types(const ora_dom* d, int32_t* type) {
   memcpy(type, d->type, sizeof(int32_t) * d->N);
   return 0;

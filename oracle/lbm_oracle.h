@@ -85,6 +85,10 @@ int ora_face_records(const ora_dom* dom, int64_t first, int64_t count, double* r
    node index = x + nx*(y + ny*z). Returns the count; writes at most cap entries. */
 int64_t ora_links(const ora_dom* dom, int body_id, int64_t cap, int64_t* node, int32_t* dir, double* delta);
 
+/* prescribed pose of body `body_id` at step t (the one the step of time t
+   uses): out = X[3], theta, V[3], Omega_z */
+int ora_body_pose(const ora_dom* dom, int body_id, int64_t t, double* out);
+
 /* node type: 0 fluid, 1 wall layer, 2+b body b */
 int ora_types(const ora_dom* dom, int32_t* type);
 /* current populations f[node*Q + i] (pre-collision, time t); solid nodes hold NaN */

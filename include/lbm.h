@@ -237,6 +237,20 @@ lbm_status lbm_timing_enable(lbm_domain dom, int32_t every);
 lbm_status lbm_timing_read(lbm_domain dom, int32_t kernel, double* total_ms, int64_t* launches,
                            int64_t* nodes);
 
+/* Launch shape of a domain's stream-collide update: threads per workgroup x
+   nodes per thread, one of (256,1) (256,2) (128,2); memory: bit 0 = the new
+   state is written with non-temporal stores, bit 1 = the old state is read
+   with non-temporal loads (streaming hints for states larger than the
+   256 MB last-level cache); remap 1 = workgroups ordered so that each XCD
+   takes a contiguous run of rows. lbm_create_domain picks one from the
+   domain's footprint; every shape gives bitwise the same result.
+   LBM_E_INVAL for an unsupported shape. Takes effect at the next lbm_step. */
+typedef struct {
+  int32_t block, cells_per_thread, memory, remap;
+} lbm_sweep_config;
+lbm_status lbm_get_sweep_config(lbm_domain dom, lbm_sweep_config* cfg);
+lbm_status lbm_set_sweep_config(lbm_domain dom, const lbm_sweep_config* cfg);
+
 /* ---------------------------------------------------------------------------
    Batches: many independent domains of one lattice, storage and equilibrium
    advanced by the same launches every step -- one boundary-rule launch over
@@ -302,6 +316,18 @@ lbm_status lbm_batch_tune(lbm_batch batch, int32_t trial_steps, lbm_batch_config
    with too few steps gets steady = -1 and rel_change = NaN. Synchronises. */
 lbm_status lbm_batch_steady_state(lbm_batch batch, int64_t window, double tol, int32_t* steady,
                                   double* rel_change);
+
+/* Measurement: a plain device-to-device copy of `bytes` bytes (a multiple of
+   16; both addresses 16-byte aligned) by a hand-written kernel, enqueued on
+   `stream` (hipStream_t, borrowed). It is the copy ceiling the stream-collide
+   kernel is measured against and the reference whose exactly known bytes
+   calibrate the HBM traffic counters. variant: 0, 1, 2 = one, two or four
+   16-byte vectors per thread over a grid covering the array; 3 = four per
+   thread with non-temporal loads and stores; 4, 5 = four or two per thread
+   with a fixed grid of 2048 or 4096 workgroups striding over the array.
+   Enqueue only; LBM_E_INVAL for a size or alignment that is not a multiple
+   of 16 or an unknown variant. Not part of the method. */
+lbm_status lbm_copy(const void* src, void* dst, size_t bytes, int32_t variant, void* stream);
 
 /* Thread-local description of the last error. */
 const char* lbm_last_error(void);

@@ -1,33 +1,64 @@
-"""Build step of the HIP library: compiles csrc/*.hip for gfx950 with hipcc
-into ``liblbm.so`` next to this file (in-tree, so it travels with the
-source tree)."""
+"""Build step of the HIP library: compiles csrc/*.hip for gfx950 with hipcc,
+one object per source in parallel, and links them into ``liblbm.so`` next to
+this file (in-tree, so it travels with the source tree)."""
 from __future__ import annotations
 
+import glob
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "liblbm.so")
-SOURCES = ["kernels.hip", "lbm_api.hip", "batch_api.hip"]
+OBJ_DIR = os.path.join(ROOT, "_build")
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
+FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
+         # packed FP32 instructions are kept out of the generated code
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
-def compile_library(verbose: bool = False) -> str:
-    out = LIB + ".tmp"
-    cmd = ["hipcc", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
-           # packed FP32 instructions are kept out of the generated code
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
-           "-o", out] + [os.path.join(HERE, "csrc", s) for s in SOURCES]
+def sources():
+    return sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
+
+
+def _filtered(r):
+    return "\n".join(l for l in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops" not in l)
+
+
+def _compile(src, verbose):
+    obj = os.path.join(OBJ_DIR, os.path.basename(src)[:-4] + ".o")
+    cmd = ["hipcc"] + FLAGS + ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
+                               "-c", "-o", obj, src]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
-    msgs = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops" not in l)
-    if r.returncode != 0:
-        sys.stderr.write(msgs + "\n")
+    return obj, r
+
+
+def compile_library(verbose: bool = False, jobs: int | None = None) -> str:
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    srcs = sources()
+    jobs = jobs or min(len(srcs), max(1, min(8, os.cpu_count() or 1)))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        results = list(ex.map(lambda s: _compile(s, verbose), srcs))
+    failed = False
+    for obj, r in results:
+        msgs = _filtered(r)
+        if r.returncode != 0:
+            sys.stderr.write(msgs + "\n")
+            failed = True
+    if failed:
         raise RuntimeError("hipcc failed")
+    out = LIB + ".tmp"
+    cmd = ["hipcc", "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", out] + [o for o, _ in results]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(_filtered(r) + "\n")
+        raise RuntimeError("hipcc link failed")
     os.replace(out, LIB)
     return LIB
 

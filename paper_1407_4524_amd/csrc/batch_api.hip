@@ -162,7 +162,7 @@ lbm_status make_plan(lbm_batch B, int64_t n, Plan& P) {
   const int span = B->cfg.block * B->cfg.cells_per_thread;
   for (size_t i = 0; i < m.size(); ++i) {
     lbm_domain d = m[i];
-    BatchDomain bd{d->g, d->ph, {d->A, d->B}, {1, 0, 1, 0, 1, 0}};
+    BatchDomain bd{d->g, d->ph, {d->A, d->B}, {d->rhoA, d->rhoB}, {1, 0, 1, 0, 1, 0}};
     if (B->cfg.overlap) {
       near_box_of(d, n, bd.hole);
       if (bd.hole[0] <= bd.hole[1]) {
@@ -301,7 +301,10 @@ lbm_status batch_step(lbm_batch B, int64_t n, hipEvent_t e0, hipEvent_t e1) {
   if (e1) HIP_TRY(hipEventRecord(e1, B->stream));
   for (lbm_domain d : B->members) {
     d->t += n;
-    if (n & 1) std::swap(d->A, d->B);
+    if (n & 1) {
+      std::swap(d->A, d->B);
+      std::swap(d->rhoA, d->rhoB);
+    }
   }
   return LBM_OK;
 }

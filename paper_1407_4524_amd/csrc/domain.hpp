@@ -71,8 +71,10 @@ struct lbm_domain_s {
   // second stream: the far update of a split step; created on first use
   hipStream_t aux = nullptr;
   hipEvent_t e_near = nullptr, e_far = nullptr;
-  // x-face densities of a sweep without the face rules (see Sweep::face_rho)
-  void* face_rho = nullptr;
+  // densities of the x-face nodes of the states in A and B (see Sweep); null
+  // when no face rule needs them
+  void* rhoA = nullptr;
+  void* rhoB = nullptr;
   // kernel timing ring, by kind (LBM_KERNEL_*), every timing_every-th launch
   // of each kind
   int timing_every = 0;

@@ -8,16 +8,27 @@
 
 namespace lbm {
 
+// Sizes of the single-workgroup body kernels (status box in LDS, two bytes
+// per node): the host picks the kernel from them.
+constexpr int ADV_LDS_CELLS = 20480;  // 2 bytes each + the window table stay within 64 KB of LDS
+constexpr int STEP_ROWS = 1024;       // region rows covered by the window table
+constexpr int STEP_LIST = 2048;       // window nodes
+constexpr int STEP_CELLS = 20480;     // status box nodes (two bytes each)
+constexpr int STEP_LINKS = 8192;      // links held in LDS (the rest go through global memory)
+constexpr int LINK_BLOCK = 256;       // threads per block of the link-rule kernel
+
 struct BulkShape {
   int nbx, nrows, nplanes, nblocks;
 };
 BulkShape bulk_shape(const Geom& g, int span);
 
-// stream-collide launch shape: threads per block, nodes per thread,
-// non-temporal stores, XCD-aware block order
+// stream-collide launch shape: threads per block, nodes per thread, memory
+// mode (bit 0: non-temporal stores of the new state, bit 1: non-temporal
+// loads of the old one), XCD-aware block order
 struct BulkConfig {
   int block, cells_per_thread, nontemporal, remap;
 };
+enum { MEM_NT_STORE = 1, MEM_NT_LOAD = 2 };
 BulkConfig bulk_config(int lat, int st, size_t footprint);
 
 // Node box swept by one stream-collide launch, in tiles of `span`
@@ -27,10 +38,13 @@ BulkConfig bulk_config(int lat, int st, size_t footprint);
 struct Sweep {
   int x0, y0, z0, xlast, ny, nbx, ntiles, remap;
   int hole[6];
-  // sweeps without the face rules (3D): where the nodes of the faces x = lo
-  // (first half) and x = hi leave the density the inlet rule takes (row
-  // y + ny z of the active box), for launch_faces; null otherwise
-  void* face_rho;
+  // densities of the x-face nodes (x = lo: first half, x = hi: second half;
+  // row y + ny z of the active box) of the old state, read by the velocity
+  // bounce-back of the faces, and of the new state, written by the sweep;
+  // null when the domain has no inlet or velocity outlet (or the
+  // quasi-incompressible equilibrium, whose wall term takes rho0)
+  const void* rho_in;
+  void* rho_out;
 };
 Sweep make_sweep(const int lo[3], const int hi[3], int span, const int* hole, int remap);
 bool bulk_supported(const BulkConfig& c);
@@ -39,19 +53,13 @@ bool bulk_supported(const BulkConfig& c);
 // end of the kernel itself by the launch; a start event needs a stop event,
 // a stop event alone marks the kernel's completion (in place of a record
 // after the launch)
-// faces = false (3D): the face rules are left to launch_faces, which must
-// follow on the same stream before the next step
 hipError_t launch_stream_collide(int lat, int st, int eq, const void* A, void* B, const Geom& g, const Phys& ph,
                                  hipStream_t s, const BulkConfig& cfg, const Sweep& sw,
-                                 hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr, bool faces = true);
-// the face rules of the whole domain from the post-collision state B and
-// the x-face densities the sweep left in face_rho (2 n_y n_z values of the
-// storage's compute type)
-hipError_t launch_faces(int lat, int st, int eq, void* B, const void* face_rho, const Geom& g, const Phys& ph,
-                        hipStream_t s);
+                                 hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 
+// rho_out (optional): the x-face densities of the initial state (see Sweep)
 hipError_t launch_init(int lat, int st, int eq, void* A, uint8_t* mask, const Geom& g, const Phys& ph,
-                       const double* rho, const double* u, hipStream_t s);
+                       const double* rho, const double* u, void* rho_out, hipStream_t s);
 hipError_t launch_links(int lat, int st, int eq, void* A, const Link* links, int n_host, const int* n_dev,
                         int grid, const double* pose, int bc, const uint8_t* mask, const Geom& g, const Phys& ph,
                         double* partials, unsigned* counter, double* rec, hipStream_t s, hipEvent_t ev_start = nullptr,
@@ -95,6 +103,7 @@ struct BatchDomain {
   Geom g;
   Phys ph;
   void* buf[2];
+  void* rho[2];  // x-face densities of the state in buf[k] (see Sweep)
   int hole[6];
 };
 
@@ -143,5 +152,47 @@ hipError_t launch_batch_body_links(int lat, int st, int eq, const BatchDomain* d
                                    int64_t step, hipStream_t s);
 hipError_t launch_batch_body_step(int lat, int st, int eq, const BatchDomain* doms, const BatchBody* bodies,
                                   int nbodies, int64_t max_region_cells, int64_t step, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// The launches of one (lattice, storage, equilibrium) combination. Defined in
+// kernels_impl.hpp and instantiated once per lattice and storage (both
+// equilibria) in the inst_*.hip sources, so that the kernel templates compile
+// in parallel translation units; the launch_* functions above dispatch to
+// them after validating their arguments.
+template <class L, class S, int EQ>
+struct Ops {
+  static void stream_collide(const BulkConfig& c, const void* A, void* B, const Geom& g, const Phys& ph,
+                             const Sweep& sw, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+  static void init(void* A, uint8_t* mask, const Geom& g, const Phys& ph, const double* rho, const double* u,
+                   void* rho_out, hipStream_t s);
+  static void links(void* A, const Link* links, int n_host, const int* n_dev, int grid, const double* pose, int bc,
+                    const uint8_t* mask, const Geom& g, const Phys& ph, double* partials, unsigned* counter,
+                    double* rec, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+  static void body_advance(void* B, uint8_t* mask, uint8_t* mask_next, Link* links, int* n_links, int cap,
+                           const double* pose, const double* pose_host, const BodyShape& bs, int bc, int body,
+                           int mode, const Geom& g, const Phys& ph, double* rec_t, double* rec_t1, int* err,
+                           hipStream_t s, int64_t region_cells, int64_t region_rows, int64_t list_nodes,
+                           hipEvent_t e0, hipEvent_t e1);
+  static void batch_bulk(const BatchDomain* doms, const BatchTile* tiles, int ntiles, const BulkConfig& cfg,
+                         int64_t step, hipStream_t s, int part, hipEvent_t e0, hipEvent_t e1);
+  static void batch_links(const BatchDomain* doms, const BatchBody* bodies, int nbodies, int grid, int64_t step,
+                          hipStream_t s);
+  static void batch_body_links(const BatchDomain* doms, const BatchBody* moving, int n_moving,
+                               const BatchBody* fixed, int n_fixed, size_t lds, int64_t step, hipStream_t s);
+  static void batch_body_step(const BatchDomain* doms, const BatchBody* bodies, int nbodies, size_t lds,
+                              int64_t step, hipStream_t s);
+};
+
+#define LBM_OPS_FOR(MACRO, Lt, St) \
+  MACRO(Lt, St, 0)                 \
+  MACRO(Lt, St, 1)
+#define LBM_OPS_EXTERN(Lt, St, E) extern template struct Ops<Lt, St, E>;
+LBM_OPS_FOR(LBM_OPS_EXTERN, D2Q9, StoreF64)
+LBM_OPS_FOR(LBM_OPS_EXTERN, D2Q9, StoreF32)
+LBM_OPS_FOR(LBM_OPS_EXTERN, D2Q9, StoreF16)
+LBM_OPS_FOR(LBM_OPS_EXTERN, D3Q19, StoreF64)
+LBM_OPS_FOR(LBM_OPS_EXTERN, D3Q19, StoreF32)
+LBM_OPS_FOR(LBM_OPS_EXTERN, D3Q19, StoreF16)
+#undef LBM_OPS_EXTERN
 
 }  // namespace lbm

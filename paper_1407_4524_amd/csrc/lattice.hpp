@@ -58,9 +58,13 @@ struct StoreF64 {
   using C = double;
   using R = double;  // register form of a loaded element
   __device__ static R load_raw(const T* p) { return *p; }
+  template <bool NT>
+  __device__ static R load_raw_mem(const T* p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+  }
   __device__ static C from_raw(R r) { return r; }
   __device__ static C load(const T* p) { return *p; }
-  __device__ static void store(T* p, C v) { __builtin_nontemporal_store(v, p); }
   __device__ static void store_plain(T* p, double v) { *p = v; }
   __device__ static double round_trip(double v) { return v; }
   // the value a store keeps
@@ -72,9 +76,13 @@ struct StoreF32 {
   using C = float;
   using R = float;
   __device__ static R load_raw(const T* p) { return *p; }
+  template <bool NT>
+  __device__ static R load_raw_mem(const T* p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+  }
   __device__ static C from_raw(R r) { return r; }
   __device__ static C load(const T* p) { return *p; }
-  __device__ static void store(T* p, C v) { __builtin_nontemporal_store(v, p); }
   __device__ static void store_plain(T* p, double v) { *p = (float)v; }
   __device__ static double round_trip(double v) { return (double)(float)v; }
   // the value a store keeps
@@ -90,9 +98,14 @@ struct StoreF16 {
   // packed into one register would serialise them)
   using R = uint32_t;
   __device__ static R load_raw(const T* p) { return (uint32_t)*reinterpret_cast<const uint16_t*>(p); }
+  template <bool NT>
+  __device__ static R load_raw_mem(const T* p) {
+    const uint16_t* q = reinterpret_cast<const uint16_t*>(p);
+    if constexpr (NT) return (uint32_t)__builtin_nontemporal_load(q);
+    else return (uint32_t)*q;
+  }
   __device__ static C from_raw(R r) { return (float)__builtin_bit_cast(_Float16, (uint16_t)r); }
   __device__ static C load(const T* p) { return (float)*p; }
-  __device__ static void store(T* p, C v) { *p = (_Float16)v; }
   __device__ static void store_plain(T* p, double v) { *p = (_Float16)(float)v; }
   __device__ static double round_trip(double v) { return (double)(float)(_Float16)(float)v; }
   // the value a store keeps (rounded to binary16, to nearest even)

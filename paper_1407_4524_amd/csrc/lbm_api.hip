@@ -28,9 +28,15 @@ lbm_status lbm::host::fail(lbm_status code, const std::string& msg) {
 
 struct Layout {
   Geom g;
-  size_t pop_bytes, mask_bytes, rec_bytes, err_bytes, cnt_bytes, total;
+  size_t pop_bytes, mask_bytes, rec_bytes, err_bytes, cnt_bytes, rho_bytes, total;
   int64_t rec_cap;
 };
+
+// the velocity bounce-back of an inlet or velocity outlet takes rho(x_F) of
+// the standard equilibrium: the x-face densities are kept for it
+static bool needs_face_rho(const lbm_domain_desc* d) {
+  return d->eq_model == LBM_EQ_BGK && (d->face[0] == LBM_FACE_INLET || d->face[1] == LBM_FACE_OUTLET_VELOCITY);
+}
 
 // link capacity of a body: (Q-1) links per node of a shell two nodes thick
 // around the circumscribed circle/sphere, doubled
@@ -103,7 +109,13 @@ static Layout make_layout(const lbm_domain_desc* d) {
   L.rec_bytes = align_up((size_t)L.rec_cap * LBM_MAX_BODIES * LBM_REC_LEN * sizeof(double), 256);
   L.err_bytes = 256;
   L.cnt_bytes = 256;
-  L.total = 2 * L.pop_bytes + 2 * L.mask_bytes + L.rec_bytes + L.err_bytes + L.cnt_bytes;
+  // two arrays (the states in A and B) of 2 n_y n_z densities in the
+  // collision's type
+  L.rho_bytes = needs_face_rho(d) ? align_up((size_t)2 * (g.hi[1] - g.lo[1] + 1) * (g.hi[2] - g.lo[2] + 1) *
+                                                 (d->storage == LBM_F64 ? 8 : 4),
+                                             256)
+                                  : 0;
+  L.total = 2 * L.pop_bytes + 2 * L.mask_bytes + L.rec_bytes + L.err_bytes + L.cnt_bytes + 2 * L.rho_bytes;
   return L;
 }
 
@@ -311,7 +323,8 @@ static lbm_status init_state(lbm_domain d, const Layout& L, const lbm_domain_des
     e = hipMalloc(&u_dev, 3 * N * sizeof(double));
     if (e == hipSuccess) e = hipMemcpy(u_dev, desc->init_u, 3 * N * sizeof(double), hipMemcpyHostToDevice);
   }
-  if (e == hipSuccess) e = launch_init(d->lat, d->st, d->eq, d->A, d->mask, d->g, d->ph, rho_dev, u_dev, d->stream);
+  if (e == hipSuccess)
+    e = launch_init(d->lat, d->st, d->eq, d->A, d->mask, d->g, d->ph, rho_dev, u_dev, d->rhoA, d->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(d->stream);
   if (rho_dev) (void)hipFree(rho_dev);
   if (u_dev) (void)hipFree(u_dev);
@@ -371,16 +384,17 @@ static const BulkConfig NEAR_CFG{128, 2, 0, 0};
 // one stream-collide launch over a sweep of the current source buffer,
 // timed as `kind`, on stream s; *done (optional) becomes an event that
 // completes with the kernel (its timing stop event when timed, else
-// `marker`, recorded by the launch itself); faces = false leaves the face
-// rules to a launch_faces after it
-static lbm_status launch_sweep(lbm_domain d, const BulkConfig& cfg, const Sweep& sw, int kind, hipStream_t s,
-                               hipEvent_t marker = nullptr, hipEvent_t* done = nullptr, bool faces = true) {
+// `marker`, recorded by the launch itself). The sweep reads the x-face
+// densities of the current state and writes those of the new one.
+static lbm_status launch_sweep(lbm_domain d, const BulkConfig& cfg, Sweep sw, int kind, hipStream_t s,
+                               hipEvent_t marker = nullptr, hipEvent_t* done = nullptr) {
+  sw.rho_in = d->rhoA;
+  sw.rho_out = d->rhoB;
   hipEvent_t e0, e1;
   lbm_status st = timing_slot(d, kind, sweep_nodes(sw), e0, e1);
   if (st != LBM_OK) return st;
   if (done) *done = e1 ? e1 : marker;
-  HIP_TRY(launch_stream_collide(d->lat, d->st, d->eq, d->A, d->B, d->g, d->ph, s, cfg, sw, e0, e1 ? e1 : marker,
-                                faces));
+  HIP_TRY(launch_stream_collide(d->lat, d->st, d->eq, d->A, d->B, d->g, d->ph, s, cfg, sw, e0, e1 ? e1 : marker));
   return LBM_OK;
 }
 
@@ -499,6 +513,12 @@ lbm_status lbm_create_domain(const lbm_domain_desc* desc, lbm_domain* out) {
   p += L.err_bytes;
   d->counters = (unsigned*)p;
   p += L.cnt_bytes;
+  if (L.rho_bytes) {
+    d->rhoA = p;
+    p += L.rho_bytes;
+    d->rhoB = p;
+    p += L.rho_bytes;
+  }
   s = init_state(d, L, desc);
   if (s != LBM_OK) {
     std::string msg = g_last_error;
@@ -530,7 +550,6 @@ lbm_status lbm_destroy_domain(lbm_domain d) {
     (void)hipEventDestroy(d->e_near);
     (void)hipEventDestroy(d->e_far);
   }
-  if (d->face_rho) (void)hipFree(d->face_rho);
   if (d->steady_buf) (void)hipFree(d->steady_buf);
   if (d->owns_pool) (void)hipFree(d->pool);
   for (int k = 0; k < 64; ++k)
@@ -674,31 +693,16 @@ lbm_status lbm_step(lbm_domain d, int64_t nsteps) {
       if ((s = launch_sweep(d, NEAR_CFG, near, LBM_KERNEL_NEAR_BOX, d->stream, d->e_near, &near_done)) != LBM_OK)
         return s;
     } else {
-      // 3D FP16: the face rules in a launch of their own. Inside the sweep
-      // they set its register budget (98 VGPRs against 48) and cost the FP16
-      // kernel 79 us of its 142; k_faces takes 19 us, reading the inlet
-      // density of each x-face node from the small array the sweep fills.
-      // For FP32 the trade is about even (24 us inside), so FP32 keeps them
-      // inside.
-      const bool apart = d->D == 3 && d->st == LBM_F16_SHIFTED;
-      Sweep sw = full;
-      if (apart) {
-        if (!d->face_rho) {
-          const size_t n = 2 * (size_t)(g.hi[1] - g.lo[1] + 1) * (g.hi[2] - g.lo[2] + 1);
-          HIP_TRY(hipMalloc(&d->face_rho, n * (d->st == LBM_F64 ? sizeof(double) : sizeof(float))));
-        }
-        sw.face_rho = d->face_rho;
-      }
-      if ((s = launch_sweep(d, d->bulk, sw, LBM_KERNEL_STREAM_COLLIDE, d->stream, nullptr, nullptr, !apart)) != LBM_OK)
-        return s;
-      if (apart) HIP_TRY(launch_faces(d->lat, d->st, d->eq, d->B, d->face_rho, g, d->ph, d->stream));
+      if ((s = launch_sweep(d, d->bulk, full, LBM_KERNEL_STREAM_COLLIDE, d->stream)) != LBM_OK) return s;
     }
     std::swap(d->A, d->B);  // the advance works on the new state
+    std::swap(d->rhoA, d->rhoB);
     for (int id = 0; id < LBM_MAX_BODIES; ++id) {
       Body& b = d->body[id];
       if (!b.active || !b.mask_moves) continue;
       if ((s = launch_advance(d, id, t)) != LBM_OK) {
         std::swap(d->A, d->B);
+        std::swap(d->rhoA, d->rhoB);
         return s;
       }
     }
@@ -860,6 +864,23 @@ lbm_status lbm_get_fields(lbm_domain d, double* rho, double* u) {
         finite = finite && isfinite(r);
       }
   if (!finite) return fail(LBM_E_UNSTABLE, "non-finite density in the fluid");
+  return LBM_OK;
+}
+
+lbm_status lbm_get_sweep_config(lbm_domain d, lbm_sweep_config* cfg) {
+  if (!d || !cfg) return fail(LBM_E_INVAL, "null argument");
+  cfg->block = d->bulk.block;
+  cfg->cells_per_thread = d->bulk.cells_per_thread;
+  cfg->memory = d->bulk.nontemporal;
+  cfg->remap = d->bulk.remap;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_sweep_config(lbm_domain d, const lbm_sweep_config* cfg) {
+  if (!d || !cfg) return fail(LBM_E_INVAL, "null argument");
+  const BulkConfig c{cfg->block, cfg->cells_per_thread, cfg->memory, cfg->remap};
+  if (!bulk_supported(c)) return fail(LBM_E_INVAL, "unsupported stream-collide launch shape");
+  d->bulk = c;
   return LBM_OK;
 }
 

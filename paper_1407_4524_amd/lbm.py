@@ -37,7 +37,7 @@ EXPORTS = ["lbm_footprint_bytes", "lbm_body_footprint_bytes", "lbm_create_domain
            "lbm_get_fields", "lbm_get_types", "lbm_timing_enable", "lbm_timing_read", "lbm_last_error",
            "lbm_batch_create", "lbm_batch_destroy", "lbm_batch_add", "lbm_batch_remove", "lbm_batch_step",
            "lbm_batch_set_config", "lbm_batch_get_config", "lbm_batch_tune", "lbm_steady_state",
-           "lbm_batch_steady_state"]
+           "lbm_batch_steady_state", "lbm_copy", "lbm_get_sweep_config", "lbm_set_sweep_config"]
 
 
 class LbmError(RuntimeError):
@@ -53,6 +53,13 @@ class DomainDesc(C.Structure):
                 ("init_rho", C.POINTER(C.c_double)), ("init_u", C.POINTER(C.c_double)),
                 ("stream", C.c_void_p), ("device_buffer", C.c_void_p), ("device_buffer_bytes", C.c_size_t),
                 ("record_capacity", C.c_int64), ("plain_schedule", C.c_int32)]
+
+
+class SweepConfig(C.Structure):
+    _fields_ = [("block", C.c_int32), ("cells_per_thread", C.c_int32), ("memory", C.c_int32), ("remap", C.c_int32)]
+
+    def as_dict(self):
+        return {f[0]: getattr(self, f[0]) for f in self._fields_}
 
 
 class BatchConfig(C.Structure):
@@ -110,6 +117,9 @@ def lib():
         L.lbm_steady_state.argtypes = [C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.POINTER(C.c_int32),
                                        C.POINTER(C.c_double)]
         L.lbm_batch_steady_state.argtypes = [C.c_void_p, C.c_int64, C.c_double, C.c_void_p, C.c_void_p]
+        L.lbm_get_sweep_config.argtypes = [C.c_void_p, C.POINTER(SweepConfig)]
+        L.lbm_set_sweep_config.argtypes = [C.c_void_p, C.POINTER(SweepConfig)]
+        L.lbm_copy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int32, C.c_void_p]
         L.lbm_last_error.restype = C.c_char_p
         _lib = L
     return _lib
@@ -311,6 +321,18 @@ class Domain:
         _check(lib().lbm_get_fields(self._h, rho.ctypes.data, u.ctypes.data))
         return rho, u.reshape(self.N, 3)
 
+    @property
+    def sweep_config(self):
+        """launch shape of the stream-collide update (lbm_get_sweep_config)"""
+        c = SweepConfig()
+        _check(lib().lbm_get_sweep_config(self._h, C.byref(c)))
+        return c.as_dict()
+
+    @sweep_config.setter
+    def sweep_config(self, d):
+        c = SweepConfig(**d)
+        _check(lib().lbm_set_sweep_config(self._h, C.byref(c)))
+
     def timing_enable(self, every=1):
         """time every n-th launch of each kernel (True = 1, False/0 = off)"""
         _check(lib().lbm_timing_enable(self._h, int(every)))
@@ -337,6 +359,16 @@ class Domain:
         t = np.zeros(self.N, np.int32)
         _check(lib().lbm_get_types(self._h, t.ctypes.data))
         return t
+
+
+def copy(src, dst, nbytes, variant=2, stream=None):
+    """lbm_copy: the library's plain device copy (measurement only) of nbytes
+    from device address src to dst, enqueued on `stream` (default: torch's
+    current stream)."""
+    if stream is None:
+        torch = _torch_cuda()
+        stream = torch.cuda.current_stream().cuda_stream if torch is not None else 0
+    _check(lib().lbm_copy(C.c_void_p(src), C.c_void_p(dst), C.c_size_t(nbytes), int(variant), C.c_void_p(stream)))
 
 
 class Batch:

@@ -41,7 +41,8 @@ def test_library_exports_every_declared_function():
 
 
 @pytest.mark.parametrize("cname,pyname", [("lbm_domain_desc", "DomainDesc"), ("lbm_body_desc", "BodyDesc"),
-                                          ("lbm_batch_config", "BatchConfig")])
+                                          ("lbm_batch_config", "BatchConfig"),
+                                          ("lbm_sweep_config", "SweepConfig")])
 def test_ctypes_structs_follow_header(cname, pyname):
     from paper_1407_4524_amd import lbm
     py = [f[0] for f in getattr(lbm, pyname)._fields_]

@@ -317,6 +317,20 @@ lbm_status lbm_batch_tune(lbm_batch batch, int32_t trial_steps, lbm_batch_config
 lbm_status lbm_batch_steady_state(lbm_batch batch, int64_t window, double tol, int32_t* steady,
                                   double* rel_change);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): the same
+   checks and results as lbm_batch_steady_state, with the table of checks and
+   their results in a static device array of the library (one per GPU, kept
+   until the process ends, about 32 KB) instead of a buffer the batch grows
+   with hipMalloc. Host tables live on the caller's stack (about 34 KB). At
+   most LBM_STEADY_NOALLOC_MAX members (LBM_E_INVAL beyond). Call with the
+   batch's device current. Every call on a GPU shares that GPU's array: calls
+   that overlap on one GPU (from several threads) race; each call overwrites
+   every entry it reads back, so nothing needs clearing. Synchronises. */
+#define LBM_STEADY_NOALLOC_MAX 512
+lbm_status lbm_batch_steady_state_noalloc(lbm_batch batch, int64_t window, double tol, int32_t* steady,
+                                          double* rel_change);
+
 /* Measurement: a plain device-to-device copy of `bytes` bytes (a multiple of
    16; both addresses 16-byte aligned) by a hand-written kernel, enqueued on
    `stream` (hipStream_t, borrowed). It is the copy ceiling the stream-collide

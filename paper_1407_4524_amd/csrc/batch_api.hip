@@ -5,7 +5,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <numeric>
+#include <string>
 #include <vector>
 
 #include "domain.hpp"
@@ -378,35 +380,31 @@ lbm_status lbm_batch_step(lbm_batch B, int64_t nsteps) {
   return batch_step(B, nsteps, nullptr, nullptr);
 }
 
-lbm_status lbm_batch_steady_state(lbm_batch B, int64_t window, double tol, int32_t* steady, double* rel_change) {
-  if (!B || !steady) return fail(LBM_E_INVAL, "null argument");
+// The steady-state checks of a batch's members (see lbm_batch_steady_state):
+// the table of checks is built in `checks` (host, room for `cap`), uploaded
+// to `dev` (device, room for the table and 2 doubles per check after
+// align256 of the table), evaluated by one launch and read back into `out`
+// (host, 2 per check); slot[i] is member i's check or -1.
+static lbm_status batch_steady_into(lbm_batch B, int64_t window, double tol, int32_t* steady, double* rel_change,
+                                    SteadyCheck* checks, int* slot, double* out, size_t cap, char* dev) {
   const size_t n = B->members.size();
-  if (n == 0) return LBM_OK;
-  std::vector<SteadyCheck> checks;
-  std::vector<int> slot(n, -1);
+  size_t nc = 0;
   for (size_t i = 0; i < n; ++i) {
     lbm_domain d = B->members[i];
     SteadyCheck c{};
+    slot[i] = -1;
     if (d->body[0].active && steady_check(d, 0, window, c)) {
-      slot[i] = (int)checks.size();
-      checks.push_back(c);
+      if (nc >= cap) return fail(LBM_E_INVAL, "more steady-state checks than the table holds");
+      slot[i] = (int)nc;
+      checks[nc++] = c;
     }
   }
-  std::vector<double> out(2 * checks.size());
-  if (!checks.empty()) {
-    const size_t off = align256(checks.size() * sizeof(SteadyCheck));
-    const size_t need = off + out.size() * sizeof(double);
-    if (need > B->steady_cap) {
-      if (B->steady_dev) HIP_TRY(hipFree(B->steady_dev));
-      B->steady_dev = nullptr;
-      HIP_TRY(hipMalloc(&B->steady_dev, 2 * need));
-      B->steady_cap = 2 * need;
-    }
-    HIP_TRY(hipMemcpyAsync(B->steady_dev, checks.data(), checks.size() * sizeof(SteadyCheck), hipMemcpyHostToDevice,
-                           B->stream));
-    double* dout = reinterpret_cast<double*>(B->steady_dev + off);
-    HIP_TRY(launch_steady(reinterpret_cast<const SteadyCheck*>(B->steady_dev), (int)checks.size(), dout, B->stream));
-    HIP_TRY(hipMemcpyAsync(out.data(), dout, out.size() * sizeof(double), hipMemcpyDeviceToHost, B->stream));
+  if (nc > 0) {
+    const size_t off = align256(nc * sizeof(SteadyCheck));
+    HIP_TRY(hipMemcpyAsync(dev, checks, nc * sizeof(SteadyCheck), hipMemcpyHostToDevice, B->stream));
+    double* dout = reinterpret_cast<double*>(dev + off);
+    HIP_TRY(launch_steady(reinterpret_cast<const SteadyCheck*>(dev), (int)nc, dout, B->stream));
+    HIP_TRY(hipMemcpyAsync(out, dout, 2 * nc * sizeof(double), hipMemcpyDeviceToHost, B->stream));
     HIP_TRY(hipStreamSynchronize(B->stream));
   }
   for (size_t i = 0; i < n; ++i) {
@@ -424,6 +422,75 @@ lbm_status lbm_batch_steady_state(lbm_batch B, int64_t window, double tol, int32
     if (s != LBM_OK) return s;
   }
   return LBM_OK;
+}
+
+lbm_status lbm_batch_steady_state(lbm_batch B, int64_t window, double tol, int32_t* steady, double* rel_change) {
+  if (!B || !steady) return fail(LBM_E_INVAL, "null argument");
+  const size_t n = B->members.size();
+  if (n == 0) return LBM_OK;
+  std::vector<SteadyCheck> checks(n);
+  std::vector<int> slot(n, -1);
+  std::vector<double> out(2 * n);
+  const size_t need = align256(n * sizeof(SteadyCheck)) + out.size() * sizeof(double);
+  if (need > B->steady_cap) {
+    if (B->steady_dev) HIP_TRY(hipFree(B->steady_dev));
+    B->steady_dev = nullptr;
+    HIP_TRY(hipMalloc(&B->steady_dev, 2 * need));
+    B->steady_cap = 2 * need;
+  }
+  return batch_steady_into(B, window, tol, steady, rel_change, checks.data(), slot.data(), out.data(), n,
+                           B->steady_dev);
+}
+
+// Device memory of lbm_batch_steady_state_noalloc: the table of checks and
+// their results, in a static array each GPU holds until the process ends.
+// Host code never passes the array's name to a kernel or a copy (on the host
+// it is only a stand-in for the symbol): it uses the address that
+// hipGetSymbolAddress returns for the current device, looked up once per
+// device on the entry point's first call there.
+constexpr size_t STEADY_TABLE_BYTES = (LBM_STEADY_NOALLOC_MAX * sizeof(SteadyCheck) + 255) / 256 * 256;
+constexpr size_t STEADY_SCRATCH_BYTES = STEADY_TABLE_BYTES + 2 * LBM_STEADY_NOALLOC_MAX * sizeof(double);
+static __device__ __align__(256) char scratch[STEADY_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[MAX_DEVICES] = {};
+
+lbm_status scratch_for_current_device(char** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(LBM_E_INVAL, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(LBM_E_HIP, "hipGetSymbolAddress returned no address for the scratch array");
+    g_scratch_ptr[dev] = static_cast<char*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return LBM_OK;
+}
+}  // namespace
+
+lbm_status lbm_batch_steady_state_noalloc(lbm_batch B, int64_t window, double tol, int32_t* steady,
+                                          double* rel_change) {
+  if (!B || !steady) return fail(LBM_E_INVAL, "null argument");
+  const size_t n = B->members.size();
+  if (n == 0) return LBM_OK;
+  if (n > (size_t)LBM_STEADY_NOALLOC_MAX)
+    return fail(LBM_E_INVAL, "lbm_batch_steady_state_noalloc takes at most " +
+                                 std::to_string(LBM_STEADY_NOALLOC_MAX) + " members, the batch has " +
+                                 std::to_string(n));
+  char* dev = nullptr;
+  lbm_status st = scratch_for_current_device(&dev);
+  if (st != LBM_OK) return st;
+  // host tables on the stack: no allocation anywhere on this path
+  SteadyCheck checks[LBM_STEADY_NOALLOC_MAX];
+  int slot[LBM_STEADY_NOALLOC_MAX];
+  double out[2 * LBM_STEADY_NOALLOC_MAX];
+  static_assert(STEADY_TABLE_BYTES >= LBM_STEADY_NOALLOC_MAX * sizeof(SteadyCheck), "check table fits");
+  return batch_steady_into(B, window, tol, steady, rel_change, checks, slot, out, n, dev);
 }
 
 lbm_status lbm_batch_set_config(lbm_batch B, const lbm_batch_config* cfg) {

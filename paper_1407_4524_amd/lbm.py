@@ -31,13 +31,15 @@ STATUS = {0: "LBM_OK", -1: "LBM_E_INVAL", -2: "LBM_E_NOMEM", -3: "LBM_E_HIP", -4
           -5: "LBM_E_UNSTABLE", -6: "LBM_E_STATE"}
 REC_LEN = 20
 MAX_BODIES = 4
+MAX_STEADY_NOALLOC = 512  # LBM_STEADY_NOALLOC_MAX
 
 EXPORTS = ["lbm_footprint_bytes", "lbm_body_footprint_bytes", "lbm_create_domain", "lbm_destroy_domain", "lbm_set_body", "lbm_step",
            "lbm_synchronize", "lbm_time", "lbm_force_torque", "lbm_records", "lbm_get_links",
            "lbm_get_fields", "lbm_get_types", "lbm_timing_enable", "lbm_timing_read", "lbm_last_error",
            "lbm_batch_create", "lbm_batch_destroy", "lbm_batch_add", "lbm_batch_remove", "lbm_batch_step",
            "lbm_batch_set_config", "lbm_batch_get_config", "lbm_batch_tune", "lbm_steady_state",
-           "lbm_batch_steady_state", "lbm_copy", "lbm_get_sweep_config", "lbm_set_sweep_config"]
+           "lbm_batch_steady_state", "lbm_copy", "lbm_get_sweep_config", "lbm_set_sweep_config",
+           "lbm_batch_steady_state_noalloc"]
 
 
 class LbmError(RuntimeError):
@@ -117,6 +119,7 @@ def lib():
         L.lbm_steady_state.argtypes = [C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.POINTER(C.c_int32),
                                        C.POINTER(C.c_double)]
         L.lbm_batch_steady_state.argtypes = [C.c_void_p, C.c_int64, C.c_double, C.c_void_p, C.c_void_p]
+        L.lbm_batch_steady_state_noalloc.argtypes = [C.c_void_p, C.c_int64, C.c_double, C.c_void_p, C.c_void_p]
         L.lbm_get_sweep_config.argtypes = [C.c_void_p, C.POINTER(SweepConfig)]
         L.lbm_set_sweep_config.argtypes = [C.c_void_p, C.POINTER(SweepConfig)]
         L.lbm_copy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int32, C.c_void_p]
@@ -415,14 +418,17 @@ class Batch:
         _check(lib().lbm_batch_tune(self._h, int(trial_steps), C.byref(chosen), trials, 128, C.byref(n)))
         return chosen.as_dict(), [trials[i].as_dict() for i in range(n.value)]
 
-    def steady_state(self, window=500, tol=1e-6):
+    def steady_state(self, window=500, tol=1e-6, noalloc=False):
         """per member (in the order added): steady flag (1, 0, or -1 when it
-        cannot be evaluated yet) and relative drag change over `window` steps"""
+        cannot be evaluated yet) and relative drag change over `window` steps;
+        noalloc=True calls lbm_batch_steady_state_noalloc (no device
+        allocation, at most LBM_STEADY_NOALLOC_MAX members)"""
         n = len(self.members)
         st = np.zeros(n, np.int32)
         rel = np.zeros(n)
+        fn = lib().lbm_batch_steady_state_noalloc if noalloc else lib().lbm_batch_steady_state
         if n:
-            _check(lib().lbm_batch_steady_state(self._h, int(window), float(tol), st.ctypes.data, rel.ctypes.data))
+            _check(fn(self._h, int(window), float(tol), st.ctypes.data, rel.ctypes.data))
         return st, rel
 
     def close(self):

@@ -44,13 +44,14 @@ BulkShape bulk_shape(const Geom& g, int span) {
 
 // Launch configuration of the stream-collide kernel per (lattice, storage).
 // Measured on MI355X: while both population buffers fit the 256 MB MALL,
-// plain loads and stores in hardware block order are best; beyond it the
-// non-temporal hint pays on the loads of 4- and 8-byte storage (D3Q19 duct
-// 256x128x128 FP32: 120.7 -> 102.0 us) and on the stores of 2-byte storage
-// (FP16: 64.0 -> 63.1 us).
+// plain loads and stores in hardware block order are best (channel
+// 2000x800 FP32: 18.9 us); beyond it the non-temporal hint pays on the loads
+// of 4- and 8-byte storage (duct 256x128x128 FP32: 119.7 -> 101.3 us) and
+// costs on 2-byte storage (FP16: 57.7 us plain, 62.0 with non-temporal
+// stores, 68.4 with non-temporal loads).
 BulkConfig bulk_config(int lat, int st, size_t footprint) {
   if (footprint <= (size_t)192 << 20) return BulkConfig{256, 1, 0, 0};
-  const int mem = st == 2 ? MEM_NT_STORE : MEM_NT_LOAD;
+  const int mem = st == 2 ? 0 : MEM_NT_LOAD;
   return BulkConfig{256, lat == 0 ? 2 : 1, mem, 0};
 }
 

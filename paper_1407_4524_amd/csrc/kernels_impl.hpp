@@ -100,31 +100,50 @@ __device__ __forceinline__ int xface_index(const Geom& g, int x, int y, int z) {
 // ---------------------------------------------------------------------------
 // fused pull stream + collide
 
+// BGK collision (Eq. collision) of one node in deviation form, h_i = f_i -
+// w_i rho0, with the equilibrium of Eq. Fillipova_equilibrium (standard, or
+// the quasi-incompressible form when EQ: momentum terms carry rho0 and
+// u = j/rho0). Written over the opposite pairs (i, ibar): the moments from
+// pair sums and differences, and each pair's equilibria as a common even part
+// a and an odd part +-b, so that the arithmetic per node is about 5
+// operations per direction (it is what bounds the 2-byte storage sweep).
 template <class L, class S, int EQ>
 __device__ __forceinline__ void collide(typename S::C* h, typename S::C rho0, typename S::C omega,
                                         typename S::C& rho_out) {
   using C = typename S::C;
-  C drho = 0, jx = 0, jy = 0, jz = 0;
+  C drho = h[0], jx = 0, jy = 0, jz = 0;
 #pragma unroll
-  for (int i = 0; i < L::Q; ++i) {
-    drho += h[i];
-    if (L::cx(i)) jx += L::cx(i) > 0 ? h[i] : -h[i];
-    if (L::cy(i)) jy += L::cy(i) > 0 ? h[i] : -h[i];
-    if (L::D == 3 && L::cz(i)) jz += L::cz(i) > 0 ? h[i] : -h[i];
+  for (int i = 1; i < L::Q; ++i) {
+    const int o = L::opp(i);
+    if (o < i) continue;
+    const C sum = h[i] + h[o], dif = h[i] - h[o];
+    drho += sum;
+    if (L::cx(i)) jx += L::cx(i) > 0 ? dif : -dif;
+    if (L::cy(i)) jy += L::cy(i) > 0 ? dif : -dif;
+    if (L::D == 3 && L::cz(i)) jz += L::cz(i) > 0 ? dif : -dif;
   }
   const C rho = rho0 + drho;
   const C rhoU = EQ ? rho0 : rho;
   const C inv = (C)1 / rhoU;
   const C ux = jx * inv, uy = jy * inv, uz = jz * inv;
-  const C usq = (C)1.5 * (ux * ux + uy * uy + uz * uz);
+  // even part common to all directions: drho - rhoU 3/2 u.u
+  const C t = drho - rhoU * ((C)1.5 * (ux * ux + uy * uy + uz * uz));
+  const C keep = (C)1 - omega;
+  const C r45 = (C)4.5 * rhoU, r3 = (C)3 * rhoU;
+  h[0] = keep * h[0] + omega * ((C)L::w(0) * t);
 #pragma unroll
-  for (int i = 0; i < L::Q; ++i) {
+  for (int i = 1; i < L::Q; ++i) {
+    const int o = L::opp(i);
+    if (o < i) continue;
     C cu = 0;
     if (L::cx(i)) cu += L::cx(i) > 0 ? ux : -ux;
     if (L::cy(i)) cu += L::cy(i) > 0 ? uy : -uy;
     if (L::D == 3 && L::cz(i)) cu += L::cz(i) > 0 ? uz : -uz;
-    const C heq = (C)L::w(i) * (drho + rhoU * ((C)3 * cu + (C)4.5 * cu * cu - usq));
-    h[i] = h[i] + omega * (heq - h[i]);
+    const C wo = omega * (C)L::w(i);
+    const C a = wo * (t + r45 * (cu * cu));  // omega times the even part of f^eq_i - w_i rho0
+    const C b = wo * (r3 * cu);              // omega times the odd part
+    h[i] = keep * h[i] + (a + b);
+    h[o] = keep * h[o] + (a - b);
   }
   rho_out = rho;
 }
@@ -151,7 +170,7 @@ __device__ inline int xcd_block(int hw, int nblocks) {
 // per direction (xface_delta) selected per lane, so that the loads stay one
 // batch. rho_in / rho_out: densities of the x-face nodes of the old / new
 // state (the velocity bounce-back's rho(x_F)); null when no face needs them.
-template <class L, class S, int EQ, int BX, int CPT, int MEM, bool FACE_ROW>
+template <class L, class S, int EQ, int BX, int CPT, int MEM, bool FACE_ROW, bool BUF>
 __device__ __forceinline__ void stream_collide_row(const typename S::T* __restrict__ A,
                                                    typename S::T* __restrict__ B, const Geom& g, const Phys& ph,
                                                    int x0, int y, int z, int xlast, const int* hole,
@@ -175,6 +194,15 @@ __device__ __forceinline__ void stream_collide_row(const typename S::T* __restri
   // and lands in its own register before any conversion, so that all of them
   // are in flight together; a guarded load would sit in its own basic block
   // and be waited for at the block's end.
+  // BUF: raw buffer accesses with 32-bit byte offsets (the host picks this
+  // form when a population buffer is below 4 GiB): a plain pull is the
+  // node's offset plus a per-direction constant, so the address arithmetic
+  // is scalar except where a lane's pull is shifted by a face rule
+  constexpr uint32_t ESZ = sizeof(T);
+  constexpr int LAUX = (MEM & MEM_NT_LOAD) ? BUF_NT : 0;
+  constexpr int SAUX = (MEM & MEM_NT_STORE) ? BUF_NT : 0;
+  [[maybe_unused]] const Rsrc ra = make_rsrc(A, (uint64_t)L::Q * g.S * ESZ);
+  [[maybe_unused]] const Rsrc rb = make_rsrc(B, (uint64_t)L::Q * g.S * ESZ);
   typename S::R raw[CPT][L::Q];
   C rho_w[CPT];
 #pragma unroll
@@ -184,16 +212,25 @@ __device__ __forceinline__ void stream_collide_row(const typename S::T* __restri
     const bool xlo = x == g.lo[0], xhi = x == g.hi[0];
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
+      const int64_t plain = i * g.S - (L::cx(i) + L::cy(i) * g.sy + L::cz(i) * g.sz);  // uniform
       int64_t a;
       if constexpr (FACE_ROW) {
         int st;
         a = i == 0 ? ck : face_pull<L>(g, x, y, z, ck, i, st);
       } else {
-        a = i * g.S + ck - (L::cx(i) + L::cy(i) * g.sy + L::cz(i) * g.sz);
+        a = plain + ck;
         if (L::cx(i) == 1) a += xlo ? xface_delta<L>(g, i, true) : (int64_t)0;
         if (L::cx(i) == -1) a += xhi ? xface_delta<L>(g, i, false) : (int64_t)0;
       }
-      raw[k][i] = S::template load_raw_mem<(MEM & MEM_NT_LOAD) != 0>(A + a);
+      if constexpr (BUF) {
+        // 32-bit wrap-around arithmetic: the sum is the offset itself
+        if (!FACE_ROW && L::cx(i) == 0)
+          raw[k][i] = S::template load_buf<LAUX>(ra, (uint32_t)ck * ESZ, (uint32_t)plain * ESZ);
+        else
+          raw[k][i] = S::template load_buf<LAUX>(ra, (uint32_t)a * ESZ, 0u);
+      } else {
+        raw[k][i] = S::template load_raw_mem<(MEM & MEM_NT_LOAD) != 0>(A + a);
+      }
     }
     // the x-face density (every lane loads one; only x-face lanes use it)
     rho_w[k] = need_rho ? rho_in[xface_index(g, xhi ? g.hi[0] : g.lo[0], y, z)] : (C)ph.rho0;
@@ -238,14 +275,15 @@ __device__ __forceinline__ void stream_collide_row(const typename S::T* __restri
     collide<L, S, EQ>(h[k], (C)ph.rho0, (C)ph.omega, rho);
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
-      if constexpr ((MEM & MEM_NT_STORE) != 0) __builtin_nontemporal_store((T)h[k][i], B + i * g.S + c);
+      if constexpr (BUF) S::template store_buf<SAUX>(rb, (uint32_t)c * ESZ, (uint32_t)(i * g.S) * ESZ, h[k][i]);
+      else if constexpr ((MEM & MEM_NT_STORE) != 0) __builtin_nontemporal_store((T)h[k][i], B + i * g.S + c);
       else B[i * g.S + c] = (T)h[k][i];
     }
     if (rho_out && (x == g.lo[0] || x == g.hi[0])) rho_out[xface_index(g, x, y, z)] = rho;
   }
 }
 
-template <class L, class S, int EQ, int BX, int CPT, int MEM>
+template <class L, class S, int EQ, int BX, int CPT, int MEM, bool BUF = false>
 __device__ __forceinline__ void stream_collide_span(const typename S::T* __restrict__ A,
                                                     typename S::T* __restrict__ B, const Geom& g, const Phys& ph,
                                                     int x0, int y, int z, int xlast, const int* hole,
@@ -253,9 +291,9 @@ __device__ __forceinline__ void stream_collide_span(const typename S::T* __restr
                                                     typename S::C* __restrict__ rho_out) {
   const bool face_row = (y <= g.lo[1]) | (y >= g.hi[1]) | (L::D == 3 && ((z <= g.lo[2]) | (z >= g.hi[2])));
   if (face_row)
-    stream_collide_row<L, S, EQ, BX, CPT, MEM, true>(A, B, g, ph, x0, y, z, xlast, hole, rho_in, rho_out);
+    stream_collide_row<L, S, EQ, BX, CPT, MEM, true, BUF>(A, B, g, ph, x0, y, z, xlast, hole, rho_in, rho_out);
   else
-    stream_collide_row<L, S, EQ, BX, CPT, MEM, false>(A, B, g, ph, x0, y, z, xlast, hole, rho_in, rho_out);
+    stream_collide_row<L, S, EQ, BX, CPT, MEM, false, BUF>(A, B, g, ph, x0, y, z, xlast, hole, rho_in, rho_out);
 }
 // tile k of a sweep: the span of BX*CPT nodes at which thread 0 starts
 __device__ __forceinline__ void sweep_tile(const Sweep& sw, int k, int span, int& x, int& y, int& z) {
@@ -266,14 +304,14 @@ __device__ __forceinline__ void sweep_tile(const Sweep& sw, int k, int span, int
 }
 
 // one block per tile of the sweep
-template <class L, class S, int EQ, int BX, int CPT, int MEM>
+template <class L, class S, int EQ, int BX, int CPT, int MEM, bool BUF>
 __global__ __launch_bounds__(BX) void k_stream_collide(const typename S::T* __restrict__ A,
                                                        typename S::T* __restrict__ B, Geom g, Phys ph, Sweep sw) {
   const int blk = sw.remap ? xcd_block(blockIdx.x, sw.ntiles) : blockIdx.x;
   int x, y, z;
   sweep_tile(sw, blk, BX * CPT, x, y, z);
-  stream_collide_span<L, S, EQ, BX, CPT, MEM>(A, B, g, ph, x + threadIdx.x, y, z, sw.xlast, sw.hole,
-                                              (const typename S::C*)sw.rho_in, (typename S::C*)sw.rho_out);
+  stream_collide_span<L, S, EQ, BX, CPT, MEM, BUF>(A, B, g, ph, x + threadIdx.x, y, z, sw.xlast, sw.hole,
+                                                   (const typename S::C*)sw.rho_in, (typename S::C*)sw.rho_out);
 }
 
 // initial state: equilibrium deviations at (rho, u) per node, the densities
@@ -1576,10 +1614,14 @@ static void launch_timed(K kern, dim3 grid, dim3 block, size_t lds, hipStream_t 
 template <class L, class S, int EQ, int BX, int CPT, int MEM>
 static void launch_bulk_variant(const void* A, void* B, const Geom& g, const Phys& ph, const Sweep& sw,
                                 hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-  auto kern = k_stream_collide<L, S, EQ, BX, CPT, MEM>;
   const auto* a = (const typename S::T*)A;
   auto* o = (typename S::T*)B;
-  launch_timed(kern, dim3(sw.ntiles), dim3(BX), 0, s, e0, e1, a, o, g, ph, sw);
+  // raw buffer accesses whenever a population buffer is below 4 GiB
+  const bool buf = (uint64_t)L::Q * g.S * sizeof(typename S::T) < ((uint64_t)1 << 32);
+  if (buf) launch_timed(k_stream_collide<L, S, EQ, BX, CPT, MEM, true>, dim3(sw.ntiles), dim3(BX), 0, s, e0, e1, a, o,
+                        g, ph, sw);
+  else launch_timed(k_stream_collide<L, S, EQ, BX, CPT, MEM, false>, dim3(sw.ntiles), dim3(BX), 0, s, e0, e1, a, o,
+                    g, ph, sw);
 }
 
 template <class L, class S, int EQ>

@@ -9,6 +9,18 @@
 
 namespace lbm {
 
+// Raw buffer resource over `bytes` bytes at p (stride 0: byte offsets, a
+// per-lane one plus a uniform one; lanes whose offset reaches past the end
+// read zero and write nothing). Offsets are 32-bit, so a buffer addressed
+// this way holds less than 4 GiB.
+using Rsrc = __amdgpu_buffer_rsrc_t;
+__device__ __forceinline__ Rsrc make_rsrc(const void* p, uint64_t bytes) {
+  const uint32_t n = bytes > 0xffffffffull ? 0xffffffffu : (uint32_t)bytes;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, (int)n, 0x00020000);
+}
+// cache-policy bits of a buffer access: the non-temporal hint
+constexpr int BUF_NT = 2;
+
 struct D2Q9 {
   static constexpr int D = 2;
   static constexpr int Q = 9;
@@ -63,6 +75,15 @@ struct StoreF64 {
     if constexpr (NT) return __builtin_nontemporal_load(p);
     else return *p;
   }
+  template <int AUX>
+  __device__ static R load_buf(Rsrc r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, AUX));
+  }
+  template <int AUX>
+  __device__ static void store_buf(Rsrc r, uint32_t voff, uint32_t soff, C v) {
+    using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, (int)voff, (int)soff, AUX);
+  }
   __device__ static C from_raw(R r) { return r; }
   __device__ static C load(const T* p) { return *p; }
   __device__ static void store_plain(T* p, double v) { *p = v; }
@@ -80,6 +101,14 @@ struct StoreF32 {
   __device__ static R load_raw_mem(const T* p) {
     if constexpr (NT) return __builtin_nontemporal_load(p);
     else return *p;
+  }
+  template <int AUX>
+  __device__ static R load_buf(Rsrc r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, AUX));
+  }
+  template <int AUX>
+  __device__ static void store_buf(Rsrc r, uint32_t voff, uint32_t soff, C v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, (int)soff, AUX);
   }
   __device__ static C from_raw(R r) { return r; }
   __device__ static C load(const T* p) { return *p; }
@@ -103,6 +132,14 @@ struct StoreF16 {
     const uint16_t* q = reinterpret_cast<const uint16_t*>(p);
     if constexpr (NT) return (uint32_t)__builtin_nontemporal_load(q);
     else return (uint32_t)*q;
+  }
+  template <int AUX>
+  __device__ static R load_buf(Rsrc r, uint32_t voff, uint32_t soff) {
+    return (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, AUX);
+  }
+  template <int AUX>
+  __device__ static void store_buf(Rsrc r, uint32_t voff, uint32_t soff, C v) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, (_Float16)v), r, (int)voff, (int)soff, AUX);
   }
   __device__ static C from_raw(R r) { return (float)__builtin_bit_cast(_Float16, (uint16_t)r); }
   __device__ static C load(const T* p) { return (float)*p; }

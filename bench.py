@@ -1,19 +1,25 @@
 #!/usr/bin/env python3
 """Benchmark of the lattice-Boltzmann + momentum-exchange step on one MI355X.
 
-Default workload: the 2000x800 D2Q9 channel with an oscillating cylinder
-(R=40, y(t) = 400 + 20 sin(2 pi t/4000), interpolated bounce-back,
-lattice-frame moving-body force and torque every step), FP32 storage with
-FP64 force accumulation. A step is the whole hot path: boundary rule and
-momentum exchange at the body, fused stream-collide with the domain faces,
-covered/uncovered nodes with refill, and the link rebuild for the next pose.
+Headline workload: the D3Q19 duct 256x128x128 with a static sphere of
+radius 16 (interpolated bounce-back, force and torque on the sphere by
+momentum exchange every step), FP32 storage with FP64 force accumulation --
+the configuration whose two population buffers (2 x 411 MB) exceed the
+256 MB last-level cache, so that the stream-collide kernel is measured
+against HBM. A step is the whole hot path: the boundary rule and momentum
+exchange at the body, and the fused stream-collide with the domain faces.
 
 Prints ONE JSON line (rank 0). `value` = million lattice-node updates per
 second over the timed steps (every node of the box counts). `roofline` is
 the stream-collide kernel: algorithmic bytes (2 Q s per active node) over its
-average duration from HIP events around each launch in the timed region,
-against 8 TB/s. `cpu_baseline` is the FP64 CPU oracle on a bounded sample of
-the same workload.
+average duration from HIP events around its launches in the timed region
+(every launch while the window is short), against 8 TB/s, with the HBM
+traffic of its counter runs when they were taken on the current kernel
+source. `cpu_baseline` is the FP64 CPU oracle on a bounded sample of the same
+workload. Secondary lines: the same duct in FP16-shifted storage, the
+oscillating-cylinder channel 2000x800 (MALL-resident), a 4.8 GB channel
+(8192x8192), the 64-domain batch and the served request stream, each with its
+configuration stated.
 """
 import argparse
 import json
@@ -28,6 +34,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "MLUPS incl. ME force/torque; batched solves/s + p99 latency vs plain"
+HEADLINE = "duct_sphere_f32"
+MIN_TIMED = 20  # the roofline needs at least this many timed launches (or every launch of a shorter run)
 
 
 def workload(name):
@@ -40,6 +48,8 @@ def workload(name):
         return W.duct_sphere(scale=1, storage="f16")
     if name == "channel_cylinder_f64":
         return W.channel_cylinder_f64()
+    if name == "channel_large_f32":
+        return W.channel_large(storage="f32")
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -82,7 +92,10 @@ KERNEL_SYMBOLS = {"stream_collide": "k_stream_collide", "body": "k_links/k_body_
                   "near_box": "k_stream_collide (near box)"}
 
 
-TIMING_EVERY = 16  # every 16th launch of each kernel carries start/stop events
+def timing_period(steps):
+    """time every launch while the window is short; beyond 1024 steps about
+    512 launches of each kind, so that the events' host cost stays small"""
+    return 1 if steps <= 1024 else max(1, steps // 512)
 
 
 def run_gpu(name, steps, warmup, plain_schedule=False):
@@ -94,7 +107,8 @@ def run_gpu(name, steps, warmup, plain_schedule=False):
         dom = Domain.from_spec(w, plain_schedule=plain_schedule)
     dom.step(warmup)
     dom.synchronize()
-    dom.timing_enable(TIMING_EVERY)
+    every = timing_period(steps)
+    dom.timing_enable(every)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     dom.step(steps)
@@ -104,29 +118,69 @@ def run_gpu(name, steps, warmup, plain_schedule=False):
     sec = t1 - t0
     kernels = {}
     for k in ("stream_collide", "near_box", "body"):
-        kms, timed, nodes = dom.timing_read(k)
+        kms, timed, nodes, issued = dom.timing_read(k, issued=True)
         if not timed:
             continue
         avg_s = kms / timed / 1e3
-        per_step = timed * TIMING_EVERY / steps  # launches per step (timed ones are every 16th)
+        per_step = issued / steps
         entry = dict(symbol=KERNEL_SYMBOLS[k], launches_per_step=round(per_step, 3), avg_us=round(avg_s * 1e6, 3),
-                     share_of_step=round(avg_s * per_step / (sec / steps), 4), timed_launches=timed)
+                     share_of_step=round(avg_s * per_step / (sec / steps), 4), timed_launches=timed,
+                     timing_period=every)
         if nodes:
             algo = nodes * bytes_per_node(w) / timed  # algorithmic bytes per launch
             entry.update(algorithmic_bytes_per_launch=round(algo), achieved_gbs=round(algo / avg_s / 1e9, 1))
         kernels[k] = entry
     kd = kernels["stream_collide"]
-    ft = dom.force_torque(0, dom.t - 1, 1)[0]
+    need = min(MIN_TIMED, steps)
+    if kd["timed_launches"] >= need:
+        roofline = dict(bound="hbm", achieved=kd["achieved_gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
+                        frac=round(kd["achieved_gbs"] / HBM_PEAK_GBS, 4),
+                        traffic=measured_traffic(w["name"], kd["symbol"]), kernel=kd["symbol"],
+                        avg_us=kd["avg_us"], timed_launches=kd["timed_launches"],
+                        algorithmic_bytes_per_launch=kd["algorithmic_bytes_per_launch"])
+    else:
+        roofline = None  # too few timed launches to stand for the kernel
+    ft = dom.force_torque(0, dom.t - 1, 1)[0] if w["bodies"] else [0.0] * 6
     cells = w["nx"] * w["ny"] * (w["nz"] if w["lattice"] == "D3Q19" else 1)
-    out = dict(
-        w=w, cells=cells, seconds=sec, ms_per_step=sec / steps * 1e3, mlups=cells * steps / sec / 1e6,
-        kernels=kernels, roofline=dict(
-            bound="hbm", achieved=kd["achieved_gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
-            frac=round(kd["achieved_gbs"] / HBM_PEAK_GBS, 4), traffic=measured_traffic(name, kd["symbol"]),
-            kernel=kd["symbol"], avg_us=kd["avg_us"],
-            algorithmic_bytes_per_launch=kd["algorithmic_bytes_per_launch"]),
-        last_force_torque=[float(x) for x in ft])
+    footprint = dom.footprint()
     dom.close()
+    return dict(w=w, cells=cells, seconds=sec, ms_per_step=sec / steps * 1e3, mlups=cells * steps / sec / 1e6,
+                kernels=kernels, roofline=roofline, footprint_bytes=footprint,
+                last_force_torque=[float(x) for x in ft])
+
+
+def copy_ceiling(nbytes, reps=20, variant=0):
+    """The library's hand-written copy kernel (lbm_copy) moving nbytes per
+    launch (half read, half written), timed with HIP events on the current
+    stream: the copy ceiling at a kernel's footprint. Torch's own copy of the
+    same bytes is reported beside it."""
+    import torch
+    from paper_1407_4524_amd import lbm
+    half = max(16, nbytes // 2 // 16 * 16)
+    a = torch.empty(half, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3 / reps
+
+    sec = timed(lambda: lbm.copy(a.data_ptr(), b.data_ptr(), half, variant))
+    sec_t = timed(lambda: b.copy_(a))
+    moved = 2 * half
+    out = dict(bytes_per_copy=moved, kernel="lbm::k_copy", variant=variant, avg_us=round(sec * 1e6, 3),
+               gbs=round(moved / sec / 1e9, 1), frac_of_peak=round(moved / sec / 1e9 / HBM_PEAK_GBS, 4),
+               torch_copy_gbs=round(moved / sec_t / 1e9, 1))
+    del a, b
+    torch.cuda.empty_cache()
     return out
 
 
@@ -226,70 +280,73 @@ def run_serving(count, max_steps, seed=0, rate=200.0, budget_gb=64.0):
     same = all(r.force_torque == by_id[r.id].force_torque and r.steps == by_id[r.id].steps for r in res_b)
     load_rate = 0.7 * sat["solves_per_s"]
     loaded, _ = batched(W.serving_requests(count=count, seed=seed + 1, rate=load_rate, max_steps=max_steps))
-    return dict(workload=f"served_{count}_requests", max_steps=max_steps, offered_rate_per_s=rate,
-                batched=sat, plain=plain, speedup=round(plain["seconds"] / sat["seconds"], 2),
-                results_equal_alone=same, at_70pct_capacity=dict(offered_rate_per_s=round(load_rate, 3), **loaded))
+    note = ("the configured stream (256 requests, 50000-step cap)" if (count, max_steps) == (256, 50000) else
+            f"reduced from the configured 256 requests / 50000-step cap to {count} requests / {max_steps} steps")
+    return dict(workload=f"served_{count}_requests_cap{max_steps}", requests=count, max_steps=max_steps,
+                offered_rate_per_s=rate, note=note, batched=sat, plain=plain,
+                speedup=round(plain["seconds"] / sat["seconds"], 2), results_equal_alone=same,
+                at_70pct_capacity=dict(offered_rate_per_s=round(load_rate, 3), **loaded))
 
 
-def copy_ceiling(nbytes, reps=20):
-    """A plain device-to-device copy moving nbytes (half read, half written)
-    per launch, as torch issues it: the copy ceiling at the stream-collide
-    launch's footprint, and the reference kernel for scaling HBM counters."""
-    import torch
-    n = max(1, nbytes // 8)  # float32 elements per buffer
-    a = torch.rand(n, device="cuda")
-    b = torch.empty_like(a)
-    for _ in range(3):
-        b.copy_(a)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(reps):
-        b.copy_(a)
-    e1.record()
-    torch.cuda.synchronize()
-    sec = e0.elapsed_time(e1) / 1e3 / reps
-    moved = 2 * n * 4
-    return dict(bytes_per_copy=moved, avg_us=round(sec * 1e6, 3), gbs=round(moved / sec / 1e9, 1))
-
-
-def cpu_baseline(name, budget_s):
+def cpu_baseline(name, budget_s, single_thread_s):
     """The FP64 oracle (untuned, OpenMP on its bulk loops) on the first steps
-    of the same workload, until about budget_s seconds of CPU time."""
+    of the same workload, until about budget_s seconds of CPU time, then the
+    same at one thread for about single_thread_s seconds."""
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     import oracle
     from oracle_helpers import make_oracle
     w = workload(name)
+    cells = w["nx"] * w["ny"] * (w["nz"] if w["lattice"] == "D3Q19" else 1)
     o = make_oracle(w)
     o.step(1)
-    t0 = time.perf_counter()
-    n = 0
-    while time.perf_counter() - t0 < budget_s:
-        o.step(1)
-        n += 1
-    sec = time.perf_counter() - t0
-    cells = w["nx"] * w["ny"] * (w["nz"] if w["lattice"] == "D3Q19" else 1)
+
+    def sample(budget):
+        t0 = time.perf_counter()
+        n = 0
+        while time.perf_counter() - t0 < budget or n == 0:
+            o.step(1)
+            n += 1
+        return n, time.perf_counter() - t0
+
+    threads = oracle.nthreads()
+    n, sec = sample(budget_s)
+    out = dict(value=round(cells * n / sec / 1e6, 3), unit="MLUPS", cores=threads, kind="oracle",
+               sample=f"{w['name']}: steps 2..{n + 1} ({n} steps, {sec:.1f} s), FP64 oracle, {threads} threads")
+    if single_thread_s > 0:
+        oracle.set_threads(1)
+        n1, sec1 = sample(single_thread_s)
+        oracle.set_threads(threads)
+        out["single_thread"] = dict(value=round(cells * n1 / sec1 / 1e6, 3), unit="MLUPS", cores=1,
+                                    sample=f"the next {n1} steps ({sec1:.1f} s) at one thread")
     o.close()
-    return dict(value=round(cells * n / sec / 1e6, 3), unit="MLUPS", cores=oracle.nthreads(), kind="oracle",
-                sample=f"{w['name']}: steps 2..{n + 1} ({n} steps, {sec:.1f} s), FP64 oracle")
+    return out
+
+
+def secondary_line(r):
+    w = r["w"]
+    return dict(workload=w["name"], value=round(r["mlups"], 1), unit="MLUPS", storage=w["storage"],
+                ms_per_step=round(r["ms_per_step"], 5), footprint_bytes=r["footprint_bytes"],
+                roofline=r["roofline"], kernels=r["kernels"])
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20000)
-    ap.add_argument("--warmup", type=int, default=500)
-    ap.add_argument("--workload", default="channel_oscillating_f32")
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default=HEADLINE)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-single-seconds", type=float, default=6.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--no-large", action="store_true", help="skip the 4.8 GB channel line")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-domain batched line")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-requests line")
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--serve-max-steps", type=int, default=3000)
     ap.add_argument("--batch-steps", type=int, default=5000)
     ap.add_argument("--no-copy-ceiling", action="store_true",
-                    help="skip the plain-copy reference at the stream-collide footprint")
+                    help="skip the copy-kernel reference at the stream-collide footprint")
     ap.add_argument("--plain-schedule", action="store_true",
                     help="run link rule, stream-collide and body advance one after another (no overlap)")
     args = ap.parse_args()
@@ -319,26 +376,31 @@ def main():
                    "nz": w["nz"], "tau": w["tau"], "storage": w["storage"],
                    "force_accumulation": "f64", "bodies": len(w["bodies"]),
                    "me": w["bodies"][0]["me"] if w["bodies"] else None, "parallelism": "single-gpu",
+                   "footprint_bytes": main_run["footprint_bytes"],
                    "schedule": "plain" if args.plain_schedule else "overlapped"},
         "roofline": main_run["roofline"],
         "kernels": main_run["kernels"],
     }
-    if not args.no_copy_ceiling:
+    if not args.no_copy_ceiling and main_run["roofline"]:
         line["copy_ceiling"] = copy_ceiling(main_run["roofline"]["algorithmic_bytes_per_launch"])
-    if not args.no_secondary and args.workload == "channel_oscillating_f32":
+    if not args.no_secondary and args.workload == HEADLINE:
         sec = {}
-        for name in ("duct_sphere_f32", "duct_sphere_f16"):
-            r = run_gpu(name, 500, 50, args.plain_schedule)
-            sec[r["w"]["name"]] = dict(value=round(r["mlups"], 1), unit="MLUPS",
-                                       ms_per_step=round(r["ms_per_step"], 5), roofline=r["roofline"],
-                                       kernels=r["kernels"])
+        for name in ("duct_sphere_f16", "channel_oscillating_f32"):
+            r = run_gpu(name, args.steps, args.warmup, args.plain_schedule)
+            sec[r["w"]["name"]] = secondary_line(r)
+        if not args.no_large:
+            r = run_gpu("channel_large_f32", min(args.steps, 200), min(args.warmup, 10))
+            ent = secondary_line(r)
+            if r["roofline"] and not args.no_copy_ceiling:
+                ent["copy_ceiling"] = copy_ceiling(r["roofline"]["algorithmic_bytes_per_launch"], reps=10)
+            sec[r["w"]["name"]] = ent
         line["secondary"] = sec
-    if not args.no_batch and args.workload == "channel_oscillating_f32":
+    if not args.no_batch and args.workload == HEADLINE:
         line["batched"] = run_batch(args.batch_steps)
-    if not args.no_serve and args.workload == "channel_oscillating_f32":
+    if not args.no_serve and args.workload == HEADLINE:
         line["served"] = run_serving(args.serve_requests, args.serve_max_steps)
     if not args.no_cpu_baseline and rank == 0:
-        line["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)
+        line["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds, args.cpu_single_seconds)
     if rank == 0:
         print(json.dumps(line), flush=True)
 

@@ -230,12 +230,13 @@ lbm_status lbm_get_types(lbm_domain dom, int32_t* type);
    of a split step. Each call waits for the domain's work and restarts the
    totals. lbm_timing_read waits for the events and returns, for one kind and
    since the last enable, the summed duration of the timed launches in
-   milliseconds, their number and the node updates they made (zero for the
-   body kernels). */
+   milliseconds, their number, the node updates they made (zero for the
+   body kernels) and the number of launches of that kind issued, timed or
+   not (issued may be NULL). */
 enum { LBM_KERNEL_STREAM_COLLIDE = 0, LBM_KERNEL_BODY = 1, LBM_KERNEL_NEAR_BOX = 2 };
 lbm_status lbm_timing_enable(lbm_domain dom, int32_t every);
 lbm_status lbm_timing_read(lbm_domain dom, int32_t kernel, double* total_ms, int64_t* launches,
-                           int64_t* nodes);
+                           int64_t* nodes, int64_t* issued);
 
 /* Launch shape of a domain's stream-collide update: threads per workgroup x
    nodes per thread, one of (256,1) (256,2) (128,2); memory: bit 0 = the new

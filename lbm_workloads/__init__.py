@@ -68,6 +68,19 @@ def duct_sphere(scale: int = 1, storage: str = "f32"):
                      c0=(64.0 / s, 64.0 / s, 64.0 / s))])
 
 
+def channel_large(storage: str = "f32", n: int = 8192):
+    """D2Q9 channel n x n (8192 x 8192: 4.8 GB of FP32 populations, well past
+    the 256 MB last-level cache), static cylinder R=40 at (n/5, n/2) with the
+    interpolated rule and static momentum exchange; a footprint point for the
+    stream-collide kernel beyond 1 GB."""
+    return dict(
+        name=f"channel_large_{storage}_{n}x{n}", lattice="D2Q9", nx=n, ny=n, nz=1, tau=0.6, rho0=1.0, eq="bgk",
+        faces=CHANNEL_FACES, inlet_profile="parabolic", inlet_u=0.04, storage=storage, rho_noise=0.0, seed=0,
+        steps=200,
+        bodies=[dict(shape="circle", axes=(40.0,), bc="mls", me="static", motion="static",
+                     c0=(n / 5.0, n / 2.0 + 0.3, 0.0))])
+
+
 def with_changes(w, **kw):
     w = copy.deepcopy(w)
     w.update(kw)

@@ -94,6 +94,7 @@ def load(path):
     L.ora_fields.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
     L.ora_lattice.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
     L.ora_body_pose.argtypes = [C.c_void_p, C.c_int, C.c_int64, C.c_void_p]
+    L.ora_set_threads.argtypes = [C.c_int]
     return L
 
 
@@ -108,6 +109,11 @@ def lattice(kind: int):
 
 def nthreads() -> int:
     return lib().ora_nthreads()
+
+
+def set_threads(n: int) -> int:
+    """threads of the oracle's bulk loops from now on; returns the count"""
+    return lib().ora_set_threads(int(n))
 
 
 def _dptr(a):

@@ -381,6 +381,16 @@ int ora_nthreads(void) {
 #endif
 }
 
+int ora_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
+}
+
 static int ensure_records(ora_dom* d, int64_t upto) {
   if (upto <= d->rec_cap) return 0;
   int64_t cap = d->rec_cap ? d->rec_cap : 1024;

@@ -76,6 +76,8 @@ int ora_set_body(ora_dom* dom, int body_id, const ora_body_desc* b);
 int ora_step(ora_dom* dom, int64_t nsteps);
 int64_t ora_time(const ora_dom* dom);
 int ora_nthreads(void);
+/* threads of the bulk loops from now on (n > 0); returns the new count */
+int ora_set_threads(int n);
 
 /* records: rec[(step - first)*ORA_REC_LEN ...] for steps first..first+count-1 */
 int ora_body_records(const ora_dom* dom, int body_id, int64_t first, int64_t count, double* rec);

@@ -902,7 +902,8 @@ lbm_status lbm_timing_enable(lbm_domain d, int32_t every) {
   return LBM_OK;
 }
 
-lbm_status lbm_timing_read(lbm_domain d, int32_t kernel, double* total_ms, int64_t* launches, int64_t* nodes) {
+lbm_status lbm_timing_read(lbm_domain d, int32_t kernel, double* total_ms, int64_t* launches, int64_t* nodes,
+                           int64_t* issued) {
   if (!d || !total_ms || !launches || !nodes) return fail(LBM_E_INVAL, "null argument");
   if (kernel < LBM_KERNEL_STREAM_COLLIDE || kernel > LBM_KERNEL_NEAR_BOX) return fail(LBM_E_INVAL, "unknown kernel");
   lbm_status s = fold_timing(d, 0);
@@ -910,6 +911,7 @@ lbm_status lbm_timing_read(lbm_domain d, int32_t kernel, double* total_ms, int64
   *total_ms = d->kind_ms[kernel];
   *launches = d->kind_launches[kernel];
   *nodes = d->kind_nodes[kernel];
+  if (issued) *issued = d->kind_count[kernel];
   return LBM_OK;
 }
 

@@ -6,13 +6,16 @@ Usage:
 
 FETCH.csv and WRITE.csv are the ``*_counter_collection.csv`` files of two
 ``rocprofv3 --pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE`` runs of the same command
-(counters in KiB per dispatch). That command must also launch a plain
-device-to-device copy (``__amd_rocclr_copyBuffer``) moving COPY_BYTES in
-total, half read and half written: each counter is scaled by what it reads
-for that copy against the bytes the copy is known to move, which calibrates
-away what the counter does not see (reads served by the L2, channels it does
-not cover). The kernel is the one whose name starts with KERNEL_PREFIX and
-whose grid is the most frequent among its dispatches.
+(counters in KiB per dispatch). That command must also launch the library's
+plain copy kernel (``lbm::k_copy``, see lbm_copy) moving COPY_BYTES in total,
+half read and half written: each counter is scaled by what it reads for that
+copy against the bytes the copy is known to move. On gfx950 the write
+counter reads the copy's bytes exactly (scale 1.000) and the fetch counter
+half of them (0.500): FETCH_SIZE prices every read request that is not a
+32-byte one at 64 bytes, while the L2 fetches whole 128-byte lines per
+request (TCC_EA0_RDREQ_sum x 128 equals the copy's source bytes). The
+kernel is the one whose name starts with KERNEL_PREFIX and whose grid is the
+most frequent among its dispatches.
 """
 import argparse
 import collections
@@ -21,15 +24,16 @@ import hashlib
 import json
 import os
 
-COPY_KERNEL = "__amd_rocclr_copyBuffer"
+COPY_KERNEL = "void lbm::k_copy"
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
 def kernel_source_hash():
-    """Hash of the sources the HIP kernels are built from (a summary is only
-    valid for the kernels it was taken on)."""
+    """Hash of the sources of the stream-collide kernel (sweep.hpp and the
+    layout headers it reads): a summary is only valid for the kernel it was
+    taken on."""
     h = hashlib.sha256()
-    for f in ("kernels.hip", "lattice.hpp", "geom.hpp"):
+    for f in ("sweep.hpp", "lattice.hpp", "geom.hpp"):
         with open(os.path.join(HERE, "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

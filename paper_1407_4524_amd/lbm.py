@@ -106,7 +106,7 @@ def lib():
         L.lbm_get_types.argtypes = [C.c_void_p, C.c_void_p]
         L.lbm_timing_enable.argtypes = [C.c_void_p, C.c_int32]
         L.lbm_timing_read.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64),
-                                      C.POINTER(C.c_int64)]
+                                      C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.lbm_batch_create.argtypes = [C.c_void_p, C.POINTER(C.c_void_p)]
         L.lbm_batch_destroy.argtypes = [C.c_void_p]
         L.lbm_batch_add.argtypes = [C.c_void_p, C.c_void_p]
@@ -340,14 +340,19 @@ class Domain:
         """time every n-th launch of each kernel (True = 1, False/0 = off)"""
         _check(lib().lbm_timing_enable(self._h, int(every)))
 
-    def timing_read(self, kernel="stream_collide"):
-        """(summed kernel time in ms, number of launches, node updates made
-        by them) of the kernels "stream_collide", "body" or "near_box" since
-        the last timing_enable"""
+    def timing_read(self, kernel="stream_collide", issued=False):
+        """(summed kernel time in ms, number of timed launches, node updates
+        made by them) of the kernels "stream_collide", "body" or "near_box"
+        since the last timing_enable; with issued=True a fourth entry, the
+        number of launches of that kind issued (timed or not)"""
         ms = C.c_double(0)
         n = C.c_int64(0)
         nodes = C.c_int64(0)
-        _check(lib().lbm_timing_read(self._h, _enum(KERNEL, kernel), C.byref(ms), C.byref(n), C.byref(nodes)))
+        iss = C.c_int64(0)
+        _check(lib().lbm_timing_read(self._h, _enum(KERNEL, kernel), C.byref(ms), C.byref(n), C.byref(nodes),
+                                     C.byref(iss)))
+        if issued:
+            return ms.value, n.value, nodes.value, iss.value
         return ms.value, n.value, nodes.value
 
     def steady_state(self, window=500, tol=1e-6, body_id=0):

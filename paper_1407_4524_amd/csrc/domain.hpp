@@ -23,6 +23,7 @@ constexpr double PI = 3.14159265358979323846;
 constexpr int POSE_LEN = 16;  // doubles per Pose record
 constexpr int LINK_GRID_MAX = 64;
 constexpr int64_t POSE_WINDOW = 8192;
+constexpr int PART_RING = 64;  // steps of link-rule chunk sums a body keeps before they are folded into records
 
 struct Body {
   bool active = false;
@@ -38,6 +39,11 @@ struct Body {
   double* pose_dev = nullptr;
   double* pose_pinned = nullptr;
   int64_t pose_base = 0, pose_cap = 0, pose_valid = 0;
+  // ring of the link rule's chunk sums (PART_RING steps of ring_chunks x 12
+  // doubles) and the steps [part_t0, part_t0 + part_n) not yet folded
+  double* ring = nullptr;
+  int ring_chunks = 0;
+  int64_t part_t0 = 0, part_n = 0;
   bool bc_ready = false;
 };
 

@@ -3,6 +3,7 @@
 // instantiation that holds its kernels (inst_*.hip), plus the steady-state
 // kernel, which does not depend on the lattice.
 #include "kernels.hpp"
+#include "reduce.hpp"
 #include "rows.hpp"
 
 #include <hip/hip_ext.h>
@@ -114,6 +115,53 @@ hipError_t launch_links(int lat, int st, int eq, void* A, const Link* links, int
     LBM_TYPES
     O::links(A, links, n_host, n_dev, grid, pose, bc, mask, g, ph, partials, counter, rec, s, e0, e1);
   });
+  return hipGetLastError();
+}
+
+hipError_t launch_links_part(int lat, int st, int eq, void* A, const Link* links, int n, const double* pose, int bc,
+                             const uint8_t* mask, const Geom& g, const Phys& ph, double* part, hipStream_t s,
+                             hipEvent_t e0, hipEvent_t e1) {
+  if (n < 0) return hipErrorInvalidValue;
+  with_types(lat, st, eq, [&](auto Lt, auto St, auto E) {
+    LBM_TYPES
+    O::links_part(A, links, n, pose, bc, mask, g, ph, part, s, e0, e1);
+  });
+  return hipGetLastError();
+}
+
+// The records of steps t0 .. t0 + gridDim.x - 1 from their chunk sums in the
+// ring (nchunks chunks of 12 per step, ring_steps steps): lane l adds chunks
+// l, l + 64, ... in order, then the lanes are summed by the fixed shuffle
+// tree -- the order of the single-launch link kernel's final sum, so the
+// records are the same bits. Static and comoving sums go to record entries
+// 0..5 and 12..17; with zero_nodes the node terms and counts (6..11, 18, 19)
+// are zeroed (a body whose solid set does not move has none).
+__global__ __launch_bounds__(64) void k_fold(const double* __restrict__ ring, int nchunks, int ring_steps, int64_t t0,
+                                             double* rec, int64_t rec_cap, int64_t rec_stride, int zero_nodes) {
+  const int64_t t = t0 + blockIdx.x;
+  const int lane = threadIdx.x;
+  const double* part = ring + (t % ring_steps) * (int64_t)nchunks * 12;
+  double* r = rec + (t % rec_cap) * rec_stride;
+  double acc[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int c = lane; c < nchunks; c += 64)
+#pragma unroll
+    for (int j = 0; j < 12; ++j) acc[j] += part[c * 12 + j];
+#pragma unroll
+  for (int j = 0; j < 12; ++j) {
+    const double v = wave_sum(acc[j]);
+    if (lane == j) r[j < 6 ? j : j + 6] = v;
+  }
+  if (zero_nodes) {
+    if (lane >= 12 && lane < 18) r[lane - 6] = 0.0;
+    if (lane >= 18 && lane < 20) r[lane] = 0.0;
+  }
+}
+
+hipError_t launch_fold(const double* ring, int nchunks, int ring_steps, int64_t t0, int64_t nsteps, double* rec,
+                       int64_t rec_cap, int64_t rec_stride, bool zero_nodes, hipStream_t s) {
+  if (nsteps <= 0 || nsteps > ring_steps || nchunks <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_fold, dim3((unsigned)nsteps), dim3(64), 0, s, ring, nchunks, ring_steps, t0, rec, rec_cap,
+                     rec_stride, zero_nodes ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -64,6 +64,16 @@ hipError_t launch_links(int lat, int st, int eq, void* A, const Link* links, int
                         int grid, const double* pose, int bc, const uint8_t* mask, const Geom& g, const Phys& ph,
                         double* partials, unsigned* counter, double* rec, hipStream_t s, hipEvent_t ev_start = nullptr,
                         hipEvent_t ev_stop = nullptr);
+// The link rule + momentum exchange of a body at one step with its chunk
+// sums (12 per chunk of 64 links) written to `part`, the step's slot of the
+// body's ring; launch_fold later turns the slots of steps t0..t0+nsteps-1
+// into records (rec: the body's record of ring slot 0; rec_stride doubles
+// between steps). n >= 0 links (none: zero sums).
+hipError_t launch_links_part(int lat, int st, int eq, void* A, const Link* links, int n, const double* pose, int bc,
+                             const uint8_t* mask, const Geom& g, const Phys& ph, double* part, hipStream_t s,
+                             hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+hipError_t launch_fold(const double* ring, int nchunks, int ring_steps, int64_t t0, int64_t nsteps, double* rec,
+                       int64_t rec_cap, int64_t rec_stride, bool zero_nodes, hipStream_t s);
 // pose: the poses of t and t+1 on the device; pose_host: the same two on the
 // host (read at the call)
 hipError_t launch_body_advance(int lat, int st, int eq, void* B, uint8_t* mask, uint8_t* mask_next, Link* links,
@@ -168,6 +178,8 @@ struct Ops {
   static void links(void* A, const Link* links, int n_host, const int* n_dev, int grid, const double* pose, int bc,
                     const uint8_t* mask, const Geom& g, const Phys& ph, double* partials, unsigned* counter,
                     double* rec, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+  static void links_part(void* A, const Link* links, int n, const double* pose, int bc, const uint8_t* mask,
+                         const Geom& g, const Phys& ph, double* part, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
   static void body_advance(void* B, uint8_t* mask, uint8_t* mask_next, Link* links, int* n_links, int cap,
                            const double* pose, const double* pose_host, const BodyShape& bs, int bc, int body,
                            int mode, const Geom& g, const Phys& ph, double* rec_t, double* rec_t1, int* err,

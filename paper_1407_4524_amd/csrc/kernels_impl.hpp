@@ -19,6 +19,7 @@
 // structure-of-arrays layout; momentum exchange accumulates in FP64.
 #include "kernels.hpp"
 #include "rows.hpp"
+#include "reduce.hpp"
 #include "sweep.hpp"
 
 #include <hip/hip_ext.h>
@@ -234,45 +235,10 @@ __device__ __forceinline__ void block_sum(double v[N], double* out /* shared or 
   __syncthreads();
 }
 
-
-
 // Boundary rule + momentum exchange over a body's link list at step t. The
 // last block to finish sums the per-block partials in block order and writes
-// the step's record (static and comoving sums; node terms zero).
-// Lane 15 of every row of 16 lanes gets the row's total: DPP row shifts,
-// without the LDS crossbar, in a fixed order.
-__device__ __forceinline__ double row_sum16(double v) {
-  int lo = __double2loint(v), hi = __double2hiint(v);
-#define WAVE_SUM_STEP(CTRL)                                                              \
-  {                                                                                      \
-    const int l2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xf, 0xf, false);            \
-    const int h2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xf, 0xf, false);            \
-    const double t = __hiloint2double(h2, l2) + __hiloint2double(hi, lo);                \
-    lo = __double2loint(t);                                                              \
-    hi = __double2hiint(t);                                                              \
-  }
-  WAVE_SUM_STEP(0x111)  // row_shr:1
-  WAVE_SUM_STEP(0x112)  // row_shr:2
-  WAVE_SUM_STEP(0x114)  // row_shr:4
-  WAVE_SUM_STEP(0x118)  // row_shr:8
-#undef WAVE_SUM_STEP
-  return __hiloint2double(hi, lo);
-}
-
-// Sum of a double over the 64 lanes of a wavefront: the four row totals of
-// row_sum16 read out and added in a fixed order (deterministic). Every lane
-// returns the wavefront total.
-__device__ __forceinline__ double wave_sum(double v) {
-  const double rs = row_sum16(v);
-  const int lo = __double2loint(rs), hi = __double2hiint(rs);
-  double tot = 0.0;
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-    tot += __hiloint2double(__builtin_amdgcn_readlane(hi, 16 * r + 15), __builtin_amdgcn_readlane(lo, 16 * r + 15));
-  return tot;
-}
-
-// block blk of nblk (NTL threads each) working on one body's links. Wave w
+// the step's record (static and comoving sums; node terms zero): block blk
+// of nblk (NTL threads each) working on one body's links. Wave w
 // of the grid takes the chunks of 64 consecutive links c = w, w + waves, ...
 // and sums each chunk with a fixed shuffle tree into partials[c]; the first
 // wave of the last block to finish adds the chunk sums, lane l over chunks
@@ -332,6 +298,31 @@ __global__ __launch_bounds__(LINK_BLOCK) void k_links(typename S::T* A, const Li
                                                       double* partials, unsigned* counter, double* rec) {
   const int n = n_dev ? *n_dev : n_host;
   links_block<L, S, EQ, LINK_BLOCK>(A, links, n, pose, bc, mask, g, ph, partials, counter, rec, blockIdx.x, gridDim.x);
+}
+
+// The boundary rule + momentum exchange over a body's link list at step t,
+// without the final sum: wave w of the grid takes chunk w of 64 consecutive
+// links and writes the chunk's 12 sums (fixed shuffle tree) to part[12 w ..],
+// the step's slot of the body's ring of partial sums; k_fold adds the chunks
+// later, for many steps in one launch. Two dependent memory round trips per
+// step (link record, then the populations) and no grid-wide handshake.
+template <class L, class S, int EQ>
+__global__ __launch_bounds__(LINK_BLOCK) void k_links_part(typename S::T* A, const Link* __restrict__ links, int n,
+                                                           const double* __restrict__ pose, int bc,
+                                                           const uint8_t* __restrict__ mask, Geom g, Phys ph,
+                                                           double* __restrict__ part) {
+  const int lane = threadIdx.x & 63;
+  const int c = (int)blockIdx.x * (LINK_BLOCK / 64) + (int)(threadIdx.x >> 6);
+  if (c > 0 && c * 64 >= n) return;  // wave-uniform; chunk 0 is written even without links (zero sums)
+  const Pose P = *reinterpret_cast<const Pose*>(pose);
+  double acc[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  const int k = c * 64 + lane;
+  if (k < n) link_rule_m<L, S, EQ>(A, links[k], P, bc, mask, g, ph, acc);
+#pragma unroll
+  for (int j = 0; j < 12; ++j) {
+    const double v = wave_sum(acc[j]);
+    if (lane == j) part[c * 12 + j] = v;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1370,6 +1361,16 @@ void Ops<L, S, EQ>::links(void* A, const Link* links, int n_host, const int* n_d
                           unsigned* counter, double* rec, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   launch_timed(k_links<L, S, EQ>, dim3(grid), dim3(LINK_BLOCK), 0, s, e0, e1, (typename S::T*)A, links, n_host,
                n_dev, pose, bc, mask, g, ph, partials, counter, rec);
+}
+
+template <class L, class S, int EQ>
+void Ops<L, S, EQ>::links_part(void* A, const Link* links, int n, const double* pose, int bc, const uint8_t* mask,
+                               const Geom& g, const Phys& ph, double* part, hipStream_t s, hipEvent_t e0,
+                               hipEvent_t e1) {
+  const int chunks = n > 0 ? (n + 63) / 64 : 1;
+  const int grid = (chunks + LINK_BLOCK / 64 - 1) / (LINK_BLOCK / 64);
+  launch_timed(k_links_part<L, S, EQ>, dim3(grid), dim3(LINK_BLOCK), 0, s, e0, e1, (typename S::T*)A, links, n, pose,
+               bc, mask, g, ph, part);
 }
 
 template <class L, class S, int EQ>

@@ -431,6 +431,39 @@ static void near_box(lbm_domain d, const Body& b, int64_t t0, int64_t t1, int lo
 
 static_assert(sizeof(Pose) == POSE_LEN * sizeof(double), "pose record layout");
 
+// Undoes a placement of body `id` that the device reported as failed: every
+// node marked as the body's becomes fluid again (placement touches nothing
+// but the node status and the body's own link list), the device error flags
+// are cleared and the body's memory is released.
+static lbm_status undo_placement(lbm_domain d, int id) {
+  Body& b = d->body[id];
+  std::vector<uint8_t> m((size_t)d->g.S);
+  HIP_TRY(hipMemcpy(m.data(), d->mask, m.size(), hipMemcpyDeviceToHost));
+  const uint8_t self = (uint8_t)(MASK_BODY0 + id);
+  for (auto& v : m)
+    if (v == self) v = MASK_FLUID;
+  HIP_TRY(hipMemcpy(d->mask, m.data(), m.size(), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemset(d->err, 0, 4 * sizeof(int)));
+  if (b.links) (void)hipFree(b.links);
+  if (b.n_links) (void)hipFree(b.n_links);
+  if (b.partials) (void)hipFree(b.partials);
+  if (b.pose_dev) (void)hipFree(b.pose_dev);
+  if (b.pose_pinned) (void)hipHostFree(b.pose_pinned);
+  b = Body();
+  return LBM_OK;
+}
+
+// Folds the pending chunk sums of body b (steps part_t0 .. part_t0 +
+// part_n - 1) into its records, on the domain's stream.
+static lbm_status fold_pending(lbm_domain d, int id) {
+  Body& b = d->body[id];
+  if (b.part_n == 0) return LBM_OK;
+  HIP_TRY(launch_fold(b.ring, b.ring_chunks, PART_RING, b.part_t0, b.part_n, d->rec + id * LBM_REC_LEN, d->rec_cap,
+                      (int64_t)LBM_MAX_BODIES * LBM_REC_LEN, !b.mask_moves, d->stream));
+  b.part_n = 0;
+  return LBM_OK;
+}
+
 
 extern "C" {
 
@@ -540,6 +573,7 @@ lbm_status lbm_destroy_domain(lbm_domain d) {
     if (b.links) (void)hipFree(b.links);
     if (b.n_links) (void)hipFree(b.n_links);
     if (b.partials) (void)hipFree(b.partials);
+    if (b.ring) (void)hipFree(b.ring);
     if (b.pose_dev) (void)hipFree(b.pose_dev);
     if (b.pose_pinned) (void)hipHostFree(b.pose_pinned);
   }
@@ -609,9 +643,21 @@ lbm_status lbm_set_body(lbm_domain d, int32_t id, const lbm_body_desc* bd) {
                               d->stream, region_cells(b, d->D, d->t, 0), region_rows(b, d->t, 0), 0));
   HIP_TRY(hipMemcpyAsync(&b.n_host, b.n_links, sizeof(int), hipMemcpyDeviceToHost, d->stream));
   HIP_TRY(hipStreamSynchronize(d->stream));
+  s = check_device_errors(d);
+  if (s != LBM_OK) {
+    // a failed placement is undone: the body's nodes become fluid again (the
+    // placement changed nothing else), the error flags are cleared and the id
+    // is free
+    const std::string msg = g_last_error;
+    lbm_status su = undo_placement(d, id);
+    return su != LBM_OK ? su : fail(s, msg);
+  }
+  b.ring_chunks = std::max(1, (b.n_host + 63) / 64);
+  HIP_TRY(hipMalloc(&b.ring, (size_t)PART_RING * b.ring_chunks * 12 * sizeof(double)));
+  b.part_n = 0;
   b.active = true;
   b.bc_ready = false;
-  return check_device_errors(d);
+  return LBM_OK;
 }
 
 // One step is, in order: the boundary rule + momentum exchange of bodies
@@ -682,11 +728,11 @@ lbm_status lbm_step(lbm_domain d, int64_t nsteps) {
     for (int id = 0; id < LBM_MAX_BODIES; ++id) {
       Body& b = d->body[id];
       if (!b.active || (b.mask_moves && b.bc_ready)) continue;
-      int grid = std::max(1, std::min(LINK_GRID_MAX, (b.n_host + 255) / 256));
       if ((s = timing_slot(d, LBM_KERNEL_BODY, 0, e0, e1)) != LBM_OK) return s;
-      HIP_TRY(launch_links(d->lat, d->st, d->eq, d->A, b.links, b.n_host, b.mask_moves ? b.n_links : nullptr, grid,
-                           pose_at(b, t), b.desc.bc, d->mask, g, d->ph, b.partials, d->counters + id,
-                           rec_slot(d, t, id), d->stream, e0, e1));
+      if (b.part_n == 0) b.part_t0 = t;
+      HIP_TRY(launch_links_part(d->lat, d->st, d->eq, d->A, b.links, b.n_host, pose_at(b, t), b.desc.bc, d->mask, g,
+                                d->ph, b.ring + (t % PART_RING) * (int64_t)b.ring_chunks * 12, d->stream, e0, e1));
+      if (++b.part_n == PART_RING && (s = fold_pending(d, id)) != LBM_OK) return s;
       if (b.mask_moves) b.bc_ready = true;
     }
     if (split) {
@@ -709,6 +755,11 @@ lbm_status lbm_step(lbm_domain d, int64_t nsteps) {
     d->t = t + 1;
   }
   if (far_open) HIP_TRY(hipStreamWaitEvent(d->stream, far_done, 0));
+  for (int id = 0; id < LBM_MAX_BODIES; ++id)
+    if (d->body[id].active) {
+      lbm_status s = fold_pending(d, id);
+      if (s != LBM_OK) return s;
+    }
   return LBM_OK;
 }
 

@@ -65,7 +65,12 @@
  * caller enqueues on the stream after lbm_step sees the whole step (see
  * plain_schedule for the second stream a domain may use).
  * No exception crosses this interface; every call returns lbm_status and
- * lbm_last_error() gives a thread-local message.
+ * lbm_last_error() gives a thread-local message. An error a kernel reports
+ * (instability, an overflowed link or node list, a body meeting a wall or
+ * another body while it moves) is sticky: the results from then on are not
+ * valid and every later call that synchronises reports it again; destroy the
+ * domain. A placement that lbm_set_body finds invalid is undone instead (the
+ * body id stays free, the domain usable).
  */
 #ifndef LBM_H
 #define LBM_H
@@ -82,7 +87,8 @@ typedef enum {
   LBM_E_NOMEM = -2,    /* device allocation failed or caller buffer too small */
   LBM_E_HIP = -3,      /* HIP runtime error */
   LBM_E_RANGE = -4,    /* body not strictly inside the domain, or record out of the ring */
-  LBM_E_UNSTABLE = -5, /* non-finite force/torque or field (checked when results are read) */
+  LBM_E_UNSTABLE = -5, /* a fluid node's |u| > 0.4 or not a number (flagged on the device by the
+                          stream-collide update), or a non-finite force/torque or field */
   LBM_E_STATE = -6     /* call not valid in the current state (e.g. body id in use) */
 } lbm_status;
 
@@ -135,6 +141,13 @@ typedef struct {
                                runs on a second stream the domain owns (default priority),
                                overlapping the body's advance, and every call leaves
                                `stream` waiting for it. Results are bitwise the same */
+  int32_t face_records;     /* 1: the momentum exchange of the domain faces is recorded every
+                               step (lbm_face_records, lbm_force_torque with LBM_WALLS); one
+                               small kernel per step over the face nodes. 0: not recorded */
+  int32_t debug_poison;     /* 1: every population slot of a non-fluid node (wall layers, halo,
+                               the solid nodes of a body placed by lbm_set_body) starts as NaN,
+                               so a pull that reads a slot no boundary rule wrote shows up as
+                               LBM_E_UNSTABLE; results are otherwise unchanged. 0: zeros */
 } lbm_domain_desc;
 
 typedef struct {
@@ -191,6 +204,8 @@ int64_t lbm_time(lbm_domain dom);
 
 /* Force and torque on body `body_id` in its me_mode, for steps
    first_step..first_step+count-1: ft[6*k..6*k+5] = Fx,Fy,Fz,Tx,Ty,Tz.
+   body_id LBM_WALLS: the force and torque (about the origin) on the wall
+   layers of a domain with face_records (see lbm_face_records).
    Synchronises. LBM_E_RANGE if a step is not in the record ring. */
 lbm_status lbm_force_torque(lbm_domain dom, int32_t body_id, int64_t first_step, int64_t count,
                             double* ft);
@@ -198,6 +213,29 @@ lbm_status lbm_force_torque(lbm_domain dom, int32_t body_id, int64_t first_step,
 /* Full per-step records (LBM_REC_LEN doubles each, layout LBM_REC_*). */
 lbm_status lbm_records(lbm_domain dom, int32_t body_id, int64_t first_step, int64_t count,
                        double* rec);
+
+/* The covered (A+, fluid at t and solid at t+1) and uncovered (A-, solid at t
+   and fluid at t+1) node counts of body `body_id` between steps `step` and
+   step+1 (Sec. III.B.3, the sets of Eqs. ForceInMovement, TorqueInMovement),
+   taken forward in time; zero for a body whose solid set does not move.
+   The same numbers as LBM_REC_N_COVERED / LBM_REC_N_UNCOVERED of the step's
+   record. Synchronises; LBM_E_RANGE if the step is not in the record ring. */
+lbm_status lbm_get_moving_sets(lbm_domain dom, int32_t body_id, int64_t step, int64_t* n_plus,
+                               int64_t* n_minus);
+
+/* The momentum exchange of the domain faces per step, when the domain was
+   created with face_records = 1: rec[18*k ...] = F (3), T (3) of the wall
+   layers, then of the inlet, then of the outlet(s), for steps
+   first_step..first_step+count-1, T about the origin (node (0,0,0)); the
+   force on the faces by the flow, -c_i (f_out + f_in) over every population
+   that a face rule supplies (the closed-channel budget behind Eq.
+   flow_force_2: at steady state the wall force balances the pressure drop).
+   LBM_E_STATE if the domain does not record them; LBM_E_RANGE outside the
+   ring. Synchronises. lbm_force_torque with body_id LBM_WALLS returns the
+   wall part. */
+#define LBM_WALLS (-1)
+#define LBM_FACE_REC_LEN 18
+lbm_status lbm_face_records(lbm_domain dom, int64_t first_step, int64_t count, double* rec);
 
 /* Boundary links of a body at the current step, canonical order (node index
    x + nx*(y + ny*z) ascending, then direction ascending). Writes at most cap

@@ -164,7 +164,7 @@ lbm_status make_plan(lbm_batch B, int64_t n, Plan& P) {
   const int span = B->cfg.block * B->cfg.cells_per_thread;
   for (size_t i = 0; i < m.size(); ++i) {
     lbm_domain d = m[i];
-    BatchDomain bd{d->g, d->ph, {d->A, d->B}, {d->rhoA, d->rhoB}, {1, 0, 1, 0, 1, 0}};
+    BatchDomain bd{d->g, d->ph, {d->A, d->B}, {d->rhoA, d->rhoB}, d->mask, d->err + 1, {1, 0, 1, 0, 1, 0}};
     if (B->cfg.overlap) {
       near_box_of(d, n, bd.hole);
       if (bd.hole[0] <= bd.hole[1]) {
@@ -348,6 +348,7 @@ lbm_status lbm_batch_add(lbm_batch B, lbm_domain d) {
   if (!B || !d) return fail(LBM_E_INVAL, "null argument");
   if (d->batch) return fail(LBM_E_STATE, "the domain already belongs to a batch");
   if (B->members.size() >= 65535) return fail(LBM_E_INVAL, "a batch holds at most 65535 domains");
+  if (d->face_rec) return fail(LBM_E_INVAL, "a domain that records its faces is stepped alone, not in a batch");
   if (!B->members.empty()) {
     const lbm_domain f = B->members[0];
     if (f->lat != d->lat || f->st != d->st || f->eq != d->eq)

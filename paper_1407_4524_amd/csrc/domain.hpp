@@ -77,6 +77,12 @@ struct lbm_domain_s {
   // second stream: the far update of a split step; created on first use
   hipStream_t aux = nullptr;
   hipEvent_t e_near = nullptr, e_far = nullptr;
+  // face records (face_records): ring of 18 doubles per step, and the ring of
+  // the face kernel's chunk sums with its pending steps
+  double* face_rec = nullptr;
+  double* face_ring = nullptr;
+  int face_chunks = 0;
+  int64_t face_part_t0 = 0, face_part_n = 0;
   // densities of the x-face nodes of the states in A and B (see Sweep); null
   // when no face rule needs them
   void* rhoA = nullptr;

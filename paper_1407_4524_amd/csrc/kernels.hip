@@ -78,6 +78,8 @@ Sweep make_sweep(const int lo[3], const int hi[3], int span, const int* hole, in
   for (int k = 0; k < 6; ++k) sw.hole[k] = hole ? hole[k] : (k & 1 ? 0 : 1);
   sw.rho_in = nullptr;
   sw.rho_out = nullptr;
+  sw.mask = nullptr;
+  sw.unstable = nullptr;
   return sw;
 }
 
@@ -155,6 +157,59 @@ __global__ __launch_bounds__(64) void k_fold(const double* __restrict__ ring, in
     if (lane >= 12 && lane < 18) r[lane - 6] = 0.0;
     if (lane >= 18 && lane < 20) r[lane] = 0.0;
   }
+}
+
+// records of 18 doubles (walls, inlet, outlet) of steps t0 .. from the face
+// ring, in the fixed order of k_fold
+__global__ __launch_bounds__(64) void k_fold_faces(const double* __restrict__ ring, int nchunks, int ring_steps,
+                                                   int64_t t0, double* rec, int64_t rec_cap) {
+  const int64_t t = t0 + blockIdx.x;
+  const int lane = threadIdx.x;
+  const double* part = ring + (t % ring_steps) * (int64_t)nchunks * 18;
+  double* r = rec + (t % rec_cap) * 18;
+  double acc[18];
+#pragma unroll
+  for (int j = 0; j < 18; ++j) acc[j] = 0.0;
+  for (int c = lane; c < nchunks; c += 64)
+#pragma unroll
+    for (int j = 0; j < 18; ++j) acc[j] += part[c * 18 + j];
+#pragma unroll
+  for (int j = 0; j < 18; ++j) {
+    const double v = wave_sum(acc[j]);
+    if (lane == j) r[j] = v;
+  }
+}
+
+int face_nodes(const Geom& g) {
+  const int64_t n[3] = {g.hi[0] - g.lo[0] + 1, g.hi[1] - g.lo[1] + 1, g.hi[2] - g.lo[2] + 1};
+  return (int)(2 * (n[1] * n[2] + n[0] * n[2] + (g.D == 3 ? n[0] * n[1] : 0)));
+}
+
+hipError_t launch_face_part(int lat, int st, int eq, const void* A, const Geom& g, const Phys& ph, const void* rho_in,
+                            double* part, hipStream_t s) {
+  const int n = face_nodes(g);
+  if (n <= 0) return hipErrorInvalidValue;
+  with_types(lat, st, eq, [&](auto Lt, auto St, auto E) {
+    LBM_TYPES
+    O::face_part(A, g, ph, rho_in, n, part, s);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_fold_faces(const double* ring, int nchunks, int ring_steps, int64_t t0, int64_t nsteps, double* rec,
+                             int64_t rec_cap, hipStream_t s) {
+  if (nsteps <= 0 || nsteps > ring_steps || nchunks <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_fold_faces, dim3((unsigned)nsteps), dim3(64), 0, s, ring, nchunks, ring_steps, t0, rec, rec_cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_poison_body(int lat, int st, int eq, void* A, void* B, const uint8_t* mask, const Geom& g,
+                              const int lo[3], const int hi[3], int body, hipStream_t s) {
+  with_types(lat, st, eq, [&](auto Lt, auto St, auto E) {
+    LBM_TYPES
+    O::poison_body(A, B, mask, g, lo, hi, body, s);
+  });
+  return hipGetLastError();
 }
 
 hipError_t launch_fold(const double* ring, int nchunks, int ring_steps, int64_t t0, int64_t nsteps, double* rec,

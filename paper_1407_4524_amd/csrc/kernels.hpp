@@ -45,6 +45,11 @@ struct Sweep {
   // quasi-incompressible equilibrium, whose wall term takes rho0)
   const void* rho_in;
   void* rho_out;
+  // node status (read only for a node whose speed is out of range) and the
+  // word the sweep sets to 1 when a fluid node's |u| exceeds 0.4 or is not a
+  // number; null: no check
+  const uint8_t* mask;
+  int* unstable;
 };
 Sweep make_sweep(const int lo[3], const int hi[3], int span, const int* hole, int remap);
 bool bulk_supported(const BulkConfig& c);
@@ -72,6 +77,20 @@ hipError_t launch_links(int lat, int st, int eq, void* A, const Link* links, int
 hipError_t launch_links_part(int lat, int st, int eq, void* A, const Link* links, int n, const double* pose, int bc,
                              const uint8_t* mask, const Geom& g, const Phys& ph, double* part, hipStream_t s,
                              hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+// The momentum exchange of the domain faces at one step from the state A
+// (post-collision values of the step), one thread per face node: 18 sums
+// (walls, inlet, outlet: F and T about the origin) per wavefront into
+// `part`, the step's slot of the face ring (face_chunks(g) chunks);
+// launch_fold_faces turns slots into records of 18 doubles.
+int face_nodes(const Geom& g);
+inline int face_chunks(const Geom& g) { return (face_nodes(g) + 63) / 64; }
+hipError_t launch_face_part(int lat, int st, int eq, const void* A, const Geom& g, const Phys& ph, const void* rho_in,
+                            double* part, hipStream_t s);
+hipError_t launch_fold_faces(const double* ring, int nchunks, int ring_steps, int64_t t0, int64_t nsteps, double* rec,
+                             int64_t rec_cap, hipStream_t s);
+// NaN into both buffers' slots of the nodes of `body` inside the node box
+hipError_t launch_poison_body(int lat, int st, int eq, void* A, void* B, const uint8_t* mask, const Geom& g,
+                              const int lo[3], const int hi[3], int body, hipStream_t s);
 hipError_t launch_fold(const double* ring, int nchunks, int ring_steps, int64_t t0, int64_t nsteps, double* rec,
                        int64_t rec_cap, int64_t rec_stride, bool zero_nodes, hipStream_t s);
 // pose: the poses of t and t+1 on the device; pose_host: the same two on the
@@ -114,6 +133,8 @@ struct BatchDomain {
   Phys ph;
   void* buf[2];
   void* rho[2];  // x-face densities of the state in buf[k] (see Sweep)
+  const uint8_t* mask;  // node status and instability word (see Sweep)
+  int* unstable;
   int hole[6];
 };
 
@@ -180,6 +201,10 @@ struct Ops {
                     double* rec, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
   static void links_part(void* A, const Link* links, int n, const double* pose, int bc, const uint8_t* mask,
                          const Geom& g, const Phys& ph, double* part, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+  static void face_part(const void* A, const Geom& g, const Phys& ph, const void* rho_in, int nnodes, double* part,
+                        hipStream_t s);
+  static void poison_body(void* A, void* B, const uint8_t* mask, const Geom& g, const int lo[3], const int hi[3],
+                          int body, hipStream_t s);
   static void body_advance(void* B, uint8_t* mask, uint8_t* mask_next, Link* links, int* n_links, int cap,
                            const double* pose, const double* pose_host, const BodyShape& bs, int bc, int body,
                            int mode, const Geom& g, const Phys& ph, double* rec_t, double* rec_t1, int* err,

@@ -326,6 +326,118 @@ __global__ __launch_bounds__(LINK_BLOCK) void k_links_part(typename S::T* A, con
 }
 
 // ---------------------------------------------------------------------------
+// momentum exchange of the domain faces (the channel budget behind Eq.
+// flow_force_2), and the NaN fill of a debug domain's solid nodes
+
+// Node k of the enumeration of the active nodes next to a face, slab by
+// slab: x = lo, x = hi, y = lo, y = hi, then z = lo, z = hi in 3D; a node in
+// several slabs belongs to the first. 32-bit index arithmetic.
+__device__ __forceinline__ bool face_node(const Geom& g, int k, int& x, int& y, int& z) {
+  const int n0 = g.hi[0] - g.lo[0] + 1, n1 = g.hi[1] - g.lo[1] + 1, n2 = g.hi[2] - g.lo[2] + 1;
+  const int sx = n1 * n2, sy = n0 * n2, sz = n0 * n1;
+  if (k < 2 * sx) {
+    const int side = k >= sx, r = side ? k - sx : k;
+    x = side ? g.hi[0] : g.lo[0];
+    y = g.lo[1] + r % n1;
+    z = g.lo[2] + r / n1;
+    return !(side && n0 == 1);
+  }
+  k -= 2 * sx;
+  if (k < 2 * sy) {
+    const int side = k >= sy, r = side ? k - sy : k;
+    x = g.lo[0] + r % n0;
+    y = side ? g.hi[1] : g.lo[1];
+    z = g.lo[2] + r / n0;
+    return !(side && n1 == 1) && x != g.lo[0] && x != g.hi[0];
+  }
+  k -= 2 * sy;
+  if (g.D == 3 && k < 2 * sz) {
+    const int side = k >= sz, r = side ? k - sz : k;
+    x = g.lo[0] + r % n0;
+    y = g.lo[1] + r / n0;
+    z = side ? g.hi[2] : g.lo[2];
+    return !(side && n2 == 1) && x != g.lo[0] && x != g.hi[0] && y != g.lo[1] && y != g.hi[1];
+  }
+  return false;
+}
+
+// Per face node (one per thread) and direction whose pull crosses a face:
+// the value leaving the face is the face rule's (see face_pull; the velocity
+// bounce-back term in the collision's type, as in the sweep) and the
+// momentum exchanged is -c_i (f_out + f_in) with f = h + w_i rho0, torque
+// about the origin. Walls, inlet and outlet(s) are summed apart (18 values)
+// and every wavefront writes its 18 sums (fixed shuffle tree) to part, the
+// step's slot of the domain's face ring; k_fold_faces adds them later.
+template <class L, class S, int EQ>
+__global__ __launch_bounds__(256) void k_face_part(const typename S::T* __restrict__ A, Geom g, Phys ph,
+                                                   const typename S::C* __restrict__ rho_in, int nnodes,
+                                                   double* __restrict__ part) {
+  using C = typename S::C;
+  const int k = (int)blockIdx.x * 256 + (int)threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int chunk = k >> 6;  // one per wavefront: face_chunks = ceil(nnodes / 64) of them
+  if (chunk * 64 >= nnodes) return;  // wave-uniform
+  double acc[18];
+#pragma unroll
+  for (int j = 0; j < 18; ++j) acc[j] = 0.0;
+  int x, y, z;
+  if (k < nnodes && face_node(g, k, x, y, z)) {
+    const int64_t c = g.idx(x, y, z);
+    C rho_w = (C)ph.rho0;
+    if (!EQ && rho_in && (x == g.lo[0] || x == g.hi[0])) rho_w = rho_in[xface_index(g, x, y, z)];
+#pragma unroll
+    for (int i = 1; i < L::Q; ++i) {
+      int st;
+      const int64_t off = face_pull<L>(g, x, y, z, c, i, st);
+      if (st == SRC_NONE) continue;
+      const C fin = S::load(A + L::opp(i) * g.S + c);
+      C fbc = st == SRC_OUTLET ? S::load(A + off) : fin;
+      if (st == SRC_INLET || st == SRC_OUTVEL)
+        fbc += (C)(6.0 * L::w(i) * L::cx(i)) * rho_w *
+               inlet_speed<C>(g, ph, (C)y - (C)(0.5 * L::cy(i)), (C)z - (C)(0.5 * L::cz(i)));
+      const double sum = (double)fbc + (double)fin + 2.0 * L::w(i) * ph.rho0;
+      const double m[3] = {-L::cx(i) * sum, -L::cy(i) * sum, -L::cz(i) * sum};
+      const double t[3] = {y * m[2] - z * m[1], z * m[0] - x * m[2], x * m[1] - y * m[0]};
+      const double sw = st == SRC_WALL ? 1.0 : 0.0, si = st == SRC_INLET ? 1.0 : 0.0;
+      const double so = (st == SRC_OUTLET || st == SRC_OUTVEL) ? 1.0 : 0.0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        acc[a] += sw * m[a];
+        acc[3 + a] += sw * t[a];
+        acc[6 + a] += si * m[a];
+        acc[9 + a] += si * t[a];
+        acc[12 + a] += so * m[a];
+        acc[15 + a] += so * t[a];
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 18; ++j) {
+    const double v = wave_sum(acc[j]);
+    if (lane == j) part[chunk * 18 + j] = v;
+  }
+}
+
+// NaN in every population slot (both buffers) of the nodes of body `self`
+// inside the node box lo..hi (debug domains: a pull that reads a solid
+// node's slot that no link rule wrote then shows)
+template <class L, class S>
+__global__ __launch_bounds__(256) void k_poison_body(typename S::T* A, typename S::T* B, const uint8_t* mask, Geom g,
+                                                     int lo0, int lo1, int lo2, int n0, int n1, int64_t total,
+                                                     uint8_t self) {
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k >= total) return;
+  const int x = lo0 + (int)(k % n0), y = lo1 + (int)((k / n0) % n1), z = lo2 + (int)(k / ((int64_t)n0 * n1));
+  const int64_t c = g.idx(x, y, z);
+  if (mask[c] != self) return;
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) {
+    S::store_plain(A + i * g.S + c, __builtin_nan(""));
+    S::store_plain(B + i * g.S + c, __builtin_nan(""));
+  }
+}
+
+// ---------------------------------------------------------------------------
 // body placement and advance (one workgroup per body)
 
 constexpr int ADV_BLOCK = 1024;
@@ -1243,14 +1355,14 @@ __global__ __launch_bounds__(BX) void k_stream_collide_batch(const BatchDomain* 
     const int y = D.hole[2] + tl.row % nrows;
     const int z = D.hole[4] + tl.row / nrows;
     stream_collide_span<L, S, EQ, BX, CPT, 0>(A, B, g, ph, D.hole[0] + tl.bx * (BX * CPT) + threadIdx.x, y, z,
-                                              D.hole[1], no_hole, rin, rout);
+                                              D.hole[1], no_hole, rin, rout, D.mask, D.unstable);
     return;
   }
   const int nrows = g.hi[1] - g.lo[1] + 1;
   const int y = g.lo[1] + tl.row % nrows;
   const int z = g.lo[2] + tl.row / nrows;
   stream_collide_span<L, S, EQ, BX, CPT, 0>(A, B, g, ph, g.lo[0] + tl.bx * (BX * CPT) + threadIdx.x, y, z,
-                                            g.hi[0], part == 1 ? D.hole : no_hole, rin, rout);
+                                            g.hi[0], part == 1 ? D.hole : no_hole, rin, rout, D.mask, D.unstable);
 }
 
 // grid (blocks per body, bodies), NTL threads per block: the boundary rule +
@@ -1371,6 +1483,24 @@ void Ops<L, S, EQ>::links_part(void* A, const Link* links, int n, const double* 
   const int grid = (chunks + LINK_BLOCK / 64 - 1) / (LINK_BLOCK / 64);
   launch_timed(k_links_part<L, S, EQ>, dim3(grid), dim3(LINK_BLOCK), 0, s, e0, e1, (typename S::T*)A, links, n, pose,
                bc, mask, g, ph, part);
+}
+
+template <class L, class S, int EQ>
+void Ops<L, S, EQ>::face_part(const void* A, const Geom& g, const Phys& ph, const void* rho_in, int nnodes,
+                              double* part, hipStream_t s) {
+  hipLaunchKernelGGL((k_face_part<L, S, EQ>), dim3((unsigned)((nnodes + 255) / 256)), dim3(256), 0, s,
+                     (const typename S::T*)A, g, ph, (const typename S::C*)rho_in, nnodes, part);
+}
+
+template <class L, class S, int EQ>
+void Ops<L, S, EQ>::poison_body(void* A, void* B, const uint8_t* mask, const Geom& g, const int lo[3], const int hi[3],
+                                int body, hipStream_t s) {
+  const int n0 = hi[0] - lo[0] + 1, n1 = hi[1] - lo[1] + 1, n2 = hi[2] - lo[2] + 1;
+  const int64_t total = (int64_t)n0 * n1 * n2;
+  if (total <= 0) return;
+  hipLaunchKernelGGL((k_poison_body<L, S>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
+                     (typename S::T*)A, (typename S::T*)B, mask, g, lo[0], lo[1], lo[2], n0, n1, total,
+                     (uint8_t)(MASK_BODY0 + body));
 }
 
 template <class L, class S, int EQ>

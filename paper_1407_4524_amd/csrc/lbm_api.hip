@@ -28,7 +28,7 @@ lbm_status lbm::host::fail(lbm_status code, const std::string& msg) {
 
 struct Layout {
   Geom g;
-  size_t pop_bytes, mask_bytes, rec_bytes, err_bytes, cnt_bytes, rho_bytes, total;
+  size_t pop_bytes, mask_bytes, rec_bytes, err_bytes, cnt_bytes, rho_bytes, face_rec_bytes, face_ring_bytes, total;
   int64_t rec_cap;
 };
 
@@ -71,6 +71,8 @@ static lbm_status check_desc(const lbm_domain_desc* d) {
   if (d->inlet_profile != LBM_PROFILE_UNIFORM && d->inlet_profile != LBM_PROFILE_PARABOLIC)
     return fail(LBM_E_INVAL, "unknown inlet profile");
   if (d->record_capacity < 0) return fail(LBM_E_INVAL, "negative record capacity");
+  if ((d->face_records != 0 && d->face_records != 1) || (d->debug_poison != 0 && d->debug_poison != 1))
+    return fail(LBM_E_INVAL, "face_records and debug_poison are 0 or 1");
   return LBM_OK;
 }
 
@@ -115,7 +117,11 @@ static Layout make_layout(const lbm_domain_desc* d) {
                                                  (d->storage == LBM_F64 ? 8 : 4),
                                              256)
                                   : 0;
-  L.total = 2 * L.pop_bytes + 2 * L.mask_bytes + L.rec_bytes + L.err_bytes + L.cnt_bytes + 2 * L.rho_bytes;
+  L.face_rec_bytes = d->face_records ? align_up((size_t)L.rec_cap * LBM_FACE_REC_LEN * sizeof(double), 256) : 0;
+  L.face_ring_bytes =
+      d->face_records ? align_up((size_t)PART_RING * face_chunks(g) * LBM_FACE_REC_LEN * sizeof(double), 256) : 0;
+  L.total = 2 * L.pop_bytes + 2 * L.mask_bytes + L.rec_bytes + L.err_bytes + L.cnt_bytes + 2 * L.rho_bytes +
+            L.face_rec_bytes + L.face_ring_bytes;
   return L;
 }
 
@@ -302,15 +308,17 @@ lbm_status lbm::host::check_device_errors(lbm_domain d) {
   if (e[0] & 1) return fail(LBM_E_NOMEM, "boundary-link list overflowed its capacity");
   if (e[0] & 2) return fail(LBM_E_RANGE, "a body overlaps a wall layer or another body");
   if (e[0] & 4) return fail(LBM_E_NOMEM, "the surface-node list of a moving body overflowed");
+  if (e[1]) return fail(LBM_E_UNSTABLE, "a fluid node's speed exceeded 0.4 lattice units or is not a number");
   return LBM_OK;
 }
 
 // rest state everywhere (deviation 0), every node non-fluid until k_init
 // marks the active ones, then the equilibrium of the initial fields
 static lbm_status init_state(lbm_domain d, const Layout& L, const lbm_domain_desc* desc) {
-  HIP_TRY(hipMemsetAsync(d->A, 0, 2 * L.pop_bytes, d->stream));
+  HIP_TRY(hipMemsetAsync(d->A, desc->debug_poison ? 0xff : 0, 2 * L.pop_bytes, d->stream));  // 0xff..: NaN
   HIP_TRY(hipMemsetAsync(d->mask, MASK_WALL, 2 * L.mask_bytes, d->stream));
   HIP_TRY(hipMemsetAsync(d->rec, 0, L.rec_bytes + L.err_bytes + L.cnt_bytes, d->stream));
+  if (L.face_rec_bytes) HIP_TRY(hipMemsetAsync(d->face_rec, 0, L.face_rec_bytes, d->stream));
   const int64_t N = (int64_t)d->g.nx * d->g.ny * d->g.nz;
   double* rho_dev = nullptr;
   double* u_dev = nullptr;
@@ -390,6 +398,8 @@ static lbm_status launch_sweep(lbm_domain d, const BulkConfig& cfg, Sweep sw, in
                                hipEvent_t marker = nullptr, hipEvent_t* done = nullptr) {
   sw.rho_in = d->rhoA;
   sw.rho_out = d->rhoB;
+  sw.mask = d->mask;
+  sw.unstable = d->err + 1;
   hipEvent_t e0, e1;
   lbm_status st = timing_slot(d, kind, sweep_nodes(sw), e0, e1);
   if (st != LBM_OK) return st;
@@ -450,6 +460,15 @@ static lbm_status undo_placement(lbm_domain d, int id) {
   if (b.pose_dev) (void)hipFree(b.pose_dev);
   if (b.pose_pinned) (void)hipHostFree(b.pose_pinned);
   b = Body();
+  return LBM_OK;
+}
+
+// Folds the pending face chunk sums into the face records.
+static lbm_status fold_faces(lbm_domain d) {
+  if (d->face_part_n == 0) return LBM_OK;
+  HIP_TRY(launch_fold_faces(d->face_ring, d->face_chunks, PART_RING, d->face_part_t0, d->face_part_n, d->face_rec,
+                            d->rec_cap, d->stream));
+  d->face_part_n = 0;
   return LBM_OK;
 }
 
@@ -552,6 +571,13 @@ lbm_status lbm_create_domain(const lbm_domain_desc* desc, lbm_domain* out) {
     d->rhoB = p;
     p += L.rho_bytes;
   }
+  if (L.face_rec_bytes) {
+    d->face_rec = (double*)p;
+    p += L.face_rec_bytes;
+    d->face_ring = (double*)p;
+    p += L.face_ring_bytes;
+    d->face_chunks = face_chunks(L.g);
+  }
   s = init_state(d, L, desc);
   if (s != LBM_OK) {
     std::string msg = g_last_error;
@@ -641,6 +667,12 @@ lbm_status lbm_set_body(lbm_domain d, int32_t id, const lbm_body_desc* bd) {
                               pose_at(b, d->t), pose_host_at(b, d->t), b.shape, bd->bc, id, 0, d->g, d->ph, nullptr,
                               nullptr, d->err,
                               d->stream, region_cells(b, d->D, d->t, 0), region_rows(b, d->t, 0), 0));
+  if (d->desc.debug_poison) {
+    const Pose* P = reinterpret_cast<const Pose*>(pose_host_at(b, d->t));
+    const int lo[3] = {(int)P->lo[0], (int)P->lo[1], (int)P->lo[2]}, hi[3] = {(int)P->hi[0], (int)P->hi[1],
+                                                                            (int)P->hi[2]};
+    HIP_TRY(launch_poison_body(d->lat, d->st, d->eq, d->A, d->B, d->mask, d->g, lo, hi, id, d->stream));
+  }
   HIP_TRY(hipMemcpyAsync(&b.n_host, b.n_links, sizeof(int), hipMemcpyDeviceToHost, d->stream));
   HIP_TRY(hipStreamSynchronize(d->stream));
   s = check_device_errors(d);
@@ -735,6 +767,13 @@ lbm_status lbm_step(lbm_domain d, int64_t nsteps) {
       if (++b.part_n == PART_RING && (s = fold_pending(d, id)) != LBM_OK) return s;
       if (b.mask_moves) b.bc_ready = true;
     }
+    if (d->face_rec) {  // the faces' momentum exchange of step t, from the state of t
+      if (d->face_part_n == 0) d->face_part_t0 = t;
+      HIP_TRY(launch_face_part(d->lat, d->st, d->eq, d->A, g, d->ph, d->rhoA,
+                               d->face_ring + (t % PART_RING) * (int64_t)d->face_chunks * LBM_FACE_REC_LEN,
+                               d->stream));
+      if (++d->face_part_n == PART_RING && (s = fold_faces(d)) != LBM_OK) return s;
+    }
     if (split) {
       if ((s = launch_sweep(d, NEAR_CFG, near, LBM_KERNEL_NEAR_BOX, d->stream, d->e_near, &near_done)) != LBM_OK)
         return s;
@@ -760,7 +799,7 @@ lbm_status lbm_step(lbm_domain d, int64_t nsteps) {
       lbm_status s = fold_pending(d, id);
       if (s != LBM_OK) return s;
     }
-  return LBM_OK;
+  return fold_faces(d);
 }
 
 lbm_status lbm_synchronize(lbm_domain d) {
@@ -776,8 +815,11 @@ lbm_status lbm_records(lbm_domain d, int32_t id, int64_t first, int64_t count, d
   if (id < 0 || id >= LBM_MAX_BODIES || !d->body[id].active) return fail(LBM_E_INVAL, "no such body");
   if (count < 0 || first < 0 || first + count > d->t || first < d->t - d->rec_cap)
     return fail(LBM_E_RANGE, "steps outside the record ring");
+  // an instability flag still lets the records be read (they show where it
+  // began); the status is returned after the copy
   lbm_status s = lbm_synchronize(d);
-  if (s != LBM_OK) return s;
+  if (s != LBM_OK && s != LBM_E_UNSTABLE) return s;
+  const std::string dev_msg = s == LBM_E_UNSTABLE ? g_last_error : std::string();
   std::vector<double> buf;
   int64_t k = 0;
   while (k < count) {
@@ -791,13 +833,52 @@ lbm_status lbm_records(lbm_domain d, int32_t id, int64_t first, int64_t count, d
              LBM_REC_LEN * sizeof(double));
     k += run;
   }
+  if (s == LBM_E_UNSTABLE) return fail(s, dev_msg);
   for (int64_t j = 0; j < count * LBM_REC_LEN; ++j)
     if (!isfinite(rec[j])) return fail(LBM_E_UNSTABLE, "non-finite force or torque");
   return LBM_OK;
 }
 
+lbm_status lbm_face_records(lbm_domain d, int64_t first, int64_t count, double* rec) {
+  if (!d || !rec) return fail(LBM_E_INVAL, "null argument");
+  if (!d->face_rec) return fail(LBM_E_STATE, "the domain does not record its faces (face_records = 0)");
+  if (count < 0 || first < 0 || first + count > d->t || first < d->t - d->rec_cap)
+    return fail(LBM_E_RANGE, "steps outside the record ring");
+  lbm_status s = lbm_synchronize(d);
+  if (s != LBM_OK && s != LBM_E_UNSTABLE) return s;
+  const std::string dev_msg = s == LBM_E_UNSTABLE ? g_last_error : std::string();
+  int64_t k = 0;
+  while (k < count) {
+    const int64_t slot = (first + k) % d->rec_cap;
+    const int64_t run = std::min(count - k, d->rec_cap - slot);
+    HIP_TRY(hipMemcpy(rec + k * LBM_FACE_REC_LEN, d->face_rec + slot * LBM_FACE_REC_LEN,
+                      run * LBM_FACE_REC_LEN * sizeof(double), hipMemcpyDeviceToHost));
+    k += run;
+  }
+  if (s == LBM_E_UNSTABLE) return fail(s, dev_msg);
+  return LBM_OK;
+}
+
+lbm_status lbm_get_moving_sets(lbm_domain d, int32_t id, int64_t step, int64_t* n_plus, int64_t* n_minus) {
+  if (!d || !n_plus || !n_minus) return fail(LBM_E_INVAL, "null argument");
+  double r[LBM_REC_LEN];
+  lbm_status s = lbm_records(d, id, step, 1, r);
+  if (s != LBM_OK) return s;
+  *n_plus = (int64_t)r[LBM_REC_N_COVERED];
+  *n_minus = (int64_t)r[LBM_REC_N_UNCOVERED];
+  return LBM_OK;
+}
+
 lbm_status lbm_force_torque(lbm_domain d, int32_t id, int64_t first, int64_t count, double* ft) {
   if (!d || !ft) return fail(LBM_E_INVAL, "null argument");
+  if (id == LBM_WALLS) {
+    std::vector<double> rec((size_t)std::max<int64_t>(count, 0) * LBM_FACE_REC_LEN);
+    lbm_status s = lbm_face_records(d, first, count, rec.data());
+    if (s != LBM_OK && s != LBM_E_UNSTABLE) return s;
+    for (int64_t k = 0; k < count; ++k)
+      for (int a = 0; a < 6; ++a) ft[6 * k + a] = rec[k * LBM_FACE_REC_LEN + a];
+    return s;
+  }
   std::vector<double> rec((size_t)std::max<int64_t>(count, 0) * LBM_REC_LEN);
   lbm_status s = lbm_records(d, id, first, count, rec.data());
   if (s != LBM_OK && s != LBM_E_UNSTABLE) return s;

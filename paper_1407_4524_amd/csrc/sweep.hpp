@@ -91,7 +91,7 @@ __device__ __forceinline__ int xface_index(const Geom& g, int x, int y, int z) {
 // operations per direction (it is what bounds the 2-byte storage sweep).
 template <class L, class S, int EQ>
 __device__ __forceinline__ void collide(typename S::C* h, typename S::C rho0, typename S::C omega,
-                                        typename S::C& rho_out) {
+                                        typename S::C& rho_out, typename S::C& uu_out) {
   using C = typename S::C;
   C drho = h[0], jx = 0, jy = 0, jz = 0;
 #pragma unroll
@@ -108,8 +108,10 @@ __device__ __forceinline__ void collide(typename S::C* h, typename S::C rho0, ty
   const C rhoU = EQ ? rho0 : rho;
   const C inv = (C)1 / rhoU;
   const C ux = jx * inv, uy = jy * inv, uz = jz * inv;
+  const C uu = ux * ux + uy * uy + uz * uz;
+  uu_out = uu;
   // even part common to all directions: drho - rhoU 3/2 u.u
-  const C t = drho - rhoU * ((C)1.5 * (ux * ux + uy * uy + uz * uz));
+  const C t = drho - rhoU * ((C)1.5 * uu);
   const C keep = (C)1 - omega;
   const C r45 = (C)4.5 * rhoU, r3 = (C)3 * rhoU;
   h[0] = keep * h[0] + omega * ((C)L::w(0) * t);
@@ -157,7 +159,8 @@ __device__ __forceinline__ void stream_collide_row(const typename S::T* __restri
                                                    typename S::T* __restrict__ B, const Geom& g, const Phys& ph,
                                                    int x0, int y, int z, int xlast, const int* hole,
                                                    const typename S::C* __restrict__ rho_in,
-                                                   typename S::C* __restrict__ rho_out) {
+                                                   typename S::C* __restrict__ rho_out,
+                                                   const uint8_t* __restrict__ mask, int* unstable) {
   using C = typename S::C;
   using T = typename S::T;
   const bool hole_row = y >= hole[2] && y <= hole[3] && z >= hole[4] && z <= hole[5];
@@ -253,8 +256,12 @@ __device__ __forceinline__ void stream_collide_row(const typename S::T* __restri
     if (!ok[k]) continue;
     const int x = x0 + k * BX;
     const int64_t c = c0 + k * BX;
-    C rho;
-    collide<L, S, EQ>(h[k], (C)ph.rho0, (C)ph.omega, rho);
+    C rho, uu;
+    collide<L, S, EQ>(h[k], (C)ph.rho0, (C)ph.omega, rho, uu);
+    // instability: a fluid node whose speed exceeds 0.4 or is not a number
+    // (the mask is read only for such a node; solid nodes are swept too but
+    // their values are never used)
+    if (!(uu <= (C)0.16) && unstable && mask[c] == MASK_FLUID) *unstable = 1;
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
       if constexpr (BUF) S::template store_buf<SAUX>(rb, (uint32_t)c * ESZ, (uint32_t)(i * g.S) * ESZ, h[k][i]);
@@ -270,12 +277,15 @@ __device__ __forceinline__ void stream_collide_span(const typename S::T* __restr
                                                     typename S::T* __restrict__ B, const Geom& g, const Phys& ph,
                                                     int x0, int y, int z, int xlast, const int* hole,
                                                     const typename S::C* __restrict__ rho_in,
-                                                    typename S::C* __restrict__ rho_out) {
+                                                    typename S::C* __restrict__ rho_out,
+                                                    const uint8_t* __restrict__ mask, int* unstable) {
   const bool face_row = (y <= g.lo[1]) | (y >= g.hi[1]) | (L::D == 3 && ((z <= g.lo[2]) | (z >= g.hi[2])));
   if (face_row)
-    stream_collide_row<L, S, EQ, BX, CPT, MEM, true, BUF>(A, B, g, ph, x0, y, z, xlast, hole, rho_in, rho_out);
+    stream_collide_row<L, S, EQ, BX, CPT, MEM, true, BUF>(A, B, g, ph, x0, y, z, xlast, hole, rho_in, rho_out, mask,
+                                                          unstable);
   else
-    stream_collide_row<L, S, EQ, BX, CPT, MEM, false, BUF>(A, B, g, ph, x0, y, z, xlast, hole, rho_in, rho_out);
+    stream_collide_row<L, S, EQ, BX, CPT, MEM, false, BUF>(A, B, g, ph, x0, y, z, xlast, hole, rho_in, rho_out, mask,
+                                                           unstable);
 }
 // tile k of a sweep: the span of BX*CPT nodes at which thread 0 starts
 __device__ __forceinline__ void sweep_tile(const Sweep& sw, int k, int span, int& x, int& y, int& z) {
@@ -293,7 +303,8 @@ __global__ __launch_bounds__(BX) void k_stream_collide(const typename S::T* __re
   int x, y, z;
   sweep_tile(sw, blk, BX * CPT, x, y, z);
   stream_collide_span<L, S, EQ, BX, CPT, MEM, BUF>(A, B, g, ph, x + threadIdx.x, y, z, sw.xlast, sw.hole,
-                                                   (const typename S::C*)sw.rho_in, (typename S::C*)sw.rho_out);
+                                                   (const typename S::C*)sw.rho_in, (typename S::C*)sw.rho_out,
+                                                   sw.mask, sw.unstable);
 }
 
 }  // namespace lbm

@@ -30,6 +30,8 @@ KERNEL = {"stream_collide": 0, "body": 1, "near_box": 2}
 STATUS = {0: "LBM_OK", -1: "LBM_E_INVAL", -2: "LBM_E_NOMEM", -3: "LBM_E_HIP", -4: "LBM_E_RANGE",
           -5: "LBM_E_UNSTABLE", -6: "LBM_E_STATE"}
 REC_LEN = 20
+FACE_REC_LEN = 18
+WALLS = -1  # LBM_WALLS
 MAX_BODIES = 4
 MAX_STEADY_NOALLOC = 512  # LBM_STEADY_NOALLOC_MAX
 
@@ -39,7 +41,7 @@ EXPORTS = ["lbm_footprint_bytes", "lbm_body_footprint_bytes", "lbm_create_domain
            "lbm_batch_create", "lbm_batch_destroy", "lbm_batch_add", "lbm_batch_remove", "lbm_batch_step",
            "lbm_batch_set_config", "lbm_batch_get_config", "lbm_batch_tune", "lbm_steady_state",
            "lbm_batch_steady_state", "lbm_copy", "lbm_get_sweep_config", "lbm_set_sweep_config",
-           "lbm_batch_steady_state_noalloc"]
+           "lbm_batch_steady_state_noalloc", "lbm_get_moving_sets", "lbm_face_records"]
 
 
 class LbmError(RuntimeError):
@@ -54,7 +56,8 @@ class DomainDesc(C.Structure):
                 ("face", C.c_int32 * 6), ("inlet_profile", C.c_int32), ("inlet_u", C.c_double),
                 ("init_rho", C.POINTER(C.c_double)), ("init_u", C.POINTER(C.c_double)),
                 ("stream", C.c_void_p), ("device_buffer", C.c_void_p), ("device_buffer_bytes", C.c_size_t),
-                ("record_capacity", C.c_int64), ("plain_schedule", C.c_int32)]
+                ("record_capacity", C.c_int64), ("plain_schedule", C.c_int32), ("face_records", C.c_int32),
+                ("debug_poison", C.c_int32)]
 
 
 class SweepConfig(C.Structure):
@@ -122,6 +125,9 @@ def lib():
         L.lbm_batch_steady_state_noalloc.argtypes = [C.c_void_p, C.c_int64, C.c_double, C.c_void_p, C.c_void_p]
         L.lbm_get_sweep_config.argtypes = [C.c_void_p, C.POINTER(SweepConfig)]
         L.lbm_set_sweep_config.argtypes = [C.c_void_p, C.POINTER(SweepConfig)]
+        L.lbm_get_moving_sets.argtypes = [C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_int64),
+                                          C.POINTER(C.c_int64)]
+        L.lbm_face_records.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_void_p]
         L.lbm_copy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int32, C.c_void_p]
         L.lbm_last_error.restype = C.c_char_p
         _lib = L
@@ -151,7 +157,7 @@ def _enum(table, v):
 
 def domain_desc(lattice="D2Q9", nx=64, ny=64, nz=1, tau=0.8, rho0=1.0, storage="f32", eq="bgk",
                 faces=("periodic",) * 6, inlet_profile="uniform", inlet_u=0.0, record_capacity=0,
-                plain_schedule=False):
+                plain_schedule=False, face_records=False, debug_poison=False):
     """lbm_domain_desc of these settings (no initial fields, stream or buffer)"""
     d = DomainDesc()
     d.lattice = _enum(LATTICE, lattice)
@@ -165,6 +171,8 @@ def domain_desc(lattice="D2Q9", nx=64, ny=64, nz=1, tau=0.8, rho0=1.0, storage="
     d.inlet_u = inlet_u
     d.record_capacity = record_capacity
     d.plain_schedule = 1 if plain_schedule else 0
+    d.face_records = 1 if face_records else 0
+    d.debug_poison = 1 if debug_poison else 0
     return d
 
 
@@ -216,9 +224,10 @@ class Domain:
 
     def __init__(self, lattice="D2Q9", nx=64, ny=64, nz=1, tau=0.8, rho0=1.0, storage="f32", eq="bgk",
                  faces=("periodic",) * 6, inlet_profile="uniform", inlet_u=0.0, init_rho=None, init_u=None,
-                 record_capacity=0, stream=None, torch_buffer=True, plain_schedule=False):
+                 record_capacity=0, stream=None, torch_buffer=True, plain_schedule=False, face_records=False,
+                 debug_poison=False):
         d = domain_desc(lattice, nx, ny, nz, tau, rho0, storage, eq, faces, inlet_profile, inlet_u,
-                        record_capacity, plain_schedule)
+                        record_capacity, plain_schedule, face_records, debug_poison)
         self.nx, self.ny, self.nz = nx, ny, (nz if d.lattice == 1 else 1)
         self.N = self.nx * self.ny * self.nz
         keep = []
@@ -307,6 +316,22 @@ class Domain:
         out = np.zeros((count, REC_LEN))
         _check(lib().lbm_records(self._h, body_id, first, count, out.ctypes.data))
         return out
+
+    def face_records(self, first=0, count=None):
+        """per step: F, T of the wall layers, the inlet and the outlet (18
+        values, T about the origin); the domain must record its faces"""
+        if count is None:
+            count = self.t - first
+        out = np.zeros((count, FACE_REC_LEN))
+        _check(lib().lbm_face_records(self._h, first, count, out.ctypes.data))
+        return out
+
+    def moving_sets(self, body_id, step):
+        """(n_plus, n_minus): covered and uncovered node counts between step
+        and step + 1"""
+        a, b = C.c_int64(0), C.c_int64(0)
+        _check(lib().lbm_get_moving_sets(self._h, body_id, step, C.byref(a), C.byref(b)))
+        return a.value, b.value
 
     def links(self, body_id=0):
         n = C.c_int64(0)

@@ -15,6 +15,10 @@ less than ``tol`` (relative) over ``window`` steps, or at ``max_steps``
 (checked at epoch boundaries); it then leaves, and its memory admits the
 next waiting request at once. The batched arithmetic is that of a domain
 stepped alone, so a result does not depend on the mix it was served in.
+A request the library refuses (a body that does not fit its domain) or
+whose domain reports an error (LBM_E_UNSTABLE and the like) finishes as a
+failed result with the error's text; its memory is released and the others
+carry on.
 
 ``serve_plain`` serves the same stream one request at a time with one
 domain per launch, the reference the batched loop is measured against.
@@ -38,6 +42,8 @@ class Result:
     arrival: float
     admitted: float
     finished: float
+    failed: bool = False
+    error: str = ""
 
     @property
     def latency(self):
@@ -81,21 +87,41 @@ class GpuEngine:
         return h
 
     def step(self, n):
-        """every resident request advances n steps (enqueued on each group's stream)"""
+        """every resident request advances n steps (enqueued on each group's
+        stream); {handle: error text} of the requests whose step failed"""
+        failed = {}
+        by_dom = {id(dom): h for h, (_, dom) in self.handles.items()}
         for batch, _ in self.groups.values():
-            if batch.members:
+            if not batch.members:
+                continue
+            try:
                 batch.step(n)
+            except self.lbm.LbmError as e:
+                for dom in batch.members:
+                    failed[by_dom[id(dom)]] = str(e)
+        return failed
 
     def poll(self, window, tol):
-        """{handle: (steady flag, relative change, step)} for every resident request"""
+        """{handle: (steady flag, relative change, step, error text)} for every
+        resident request; a request whose domain reports an error gets flag -2
+        (the others of its group are checked one by one)"""
         out = {}
         by_dom = {id(dom): h for h, (_, dom) in self.handles.items()}
         for batch, _ in self.groups.values():
             if not batch.members:
                 continue
-            st, rel = batch.steady_state(window, tol)
+            try:
+                st, rel = batch.steady_state(window, tol)
+            except self.lbm.LbmError:
+                for dom in batch.members:
+                    try:
+                        s, r = dom.steady_state(window, tol) if dom.t - 1 - window >= 0 else (False, float("nan"))
+                        out[by_dom[id(dom)]] = (1 if s else 0, float(r), dom.t, "")
+                    except self.lbm.LbmError as e:
+                        out[by_dom[id(dom)]] = (-2, float("nan"), dom.t, str(e))
+                continue
             for dom, s, r in zip(batch.members, st, rel):
-                out[by_dom[id(dom)]] = (int(s), float(r), dom.t)
+                out[by_dom[id(dom)]] = (int(s), float(r), dom.t, "")
         return out
 
     def finish(self, h):
@@ -104,6 +130,18 @@ class GpuEngine:
         self.groups[k][0].remove(dom)
         dom.close()
         return ft
+
+    def drop(self, h):
+        """releases a failed request's domain without reading its results"""
+        k, dom = self.handles.pop(h)
+        try:
+            self.groups[k][0].remove(dom)
+        except self.lbm.LbmError:
+            pass
+        try:
+            dom.close()
+        except self.lbm.LbmError:
+            pass
 
     def close(self):
         for h in list(self.handles):
@@ -151,23 +189,35 @@ class Server:
                     continue
                 if used + fp > self.budget or len(active) >= self.max_active:
                     break  # the head waits; no later request overtakes it
-                h = self.engine.start(r["spec"])
+                pending.popleft()
+                try:
+                    h = self.engine.start(r["spec"])
+                except Exception as e:  # refused by the library: a failed result, nothing held
+                    results.append(Result(r["id"], 0, False, float("nan"), (float("nan"),) * 6, r["arrival"], now,
+                                          self.clock() - t0, failed=True, error=str(e)))
+                    continue
                 active[h] = (r, fp, now)
                 used += fp
-                pending.popleft()
             self.peak_memory = max(self.peak_memory, used)
             self.peak_active = max(self.peak_active, len(active))
             if not active:
                 if pending:
                     self.sleep(max(0.0, pending[0]["arrival"] - (self.clock() - t0)))
                 continue
-            self.engine.step(self.epoch)
+            step_failed = self.engine.step(self.epoch) or {}
             state = self.engine.poll(self.window, self.tol)
             done_at = self.clock() - t0
             for h in list(active):
                 r, fp, adm = active[h]
-                steady, rel, t = state[h]
-                if steady == 1 or t >= r["max_steps"]:
+                steady, rel, t, err = state[h] if len(state[h]) == 4 else (*state[h], "")
+                err = step_failed.get(h, err)
+                if err or steady == -2:
+                    self.engine.drop(h)
+                    results.append(Result(r["id"], t, False, rel, (float("nan"),) * 6, r["arrival"], adm, done_at,
+                                          failed=True, error=err))
+                    used -= fp
+                    del active[h]
+                elif steady == 1 or t >= r["max_steps"]:
                     ft = self.engine.finish(h)
                     results.append(Result(r["id"], t, steady == 1, rel, ft, r["arrival"], adm, done_at))
                     used -= fp
@@ -210,4 +260,5 @@ def summary(results, wall=None):
     return dict(requests=len(results), seconds=round(wall, 4), solves_per_s=round(len(results) / wall, 3),
                 p50_latency_s=round(float(np.percentile(lat, 50)), 4),
                 p99_latency_s=round(float(np.percentile(lat, 99)), 4),
-                converged=int(sum(r.converged for r in results)))
+                converged=int(sum(r.converged for r in results)),
+                failed=int(sum(r.failed for r in results)))

@@ -124,3 +124,48 @@ def test_result_is_the_same_alone_and_in_the_mix():
         _, _, alone = serve([dict(r, arrival=0.0)], 10 ** 9)
         assert alone[r["id"]].steps == mix[r["id"]].steps
         assert alone[r["id"]].force_torque == mix[r["id"]].force_torque
+
+
+class FailingEngine(FakeEngine):
+    """start refuses a spec marked 'refuse'; a spec with 'breaks' reports an
+    error (flag -2) once it has run that many steps"""
+
+    def start(self, spec):
+        if spec.get("refuse"):
+            raise RuntimeError("LBM_E_RANGE: body leaves the interior")
+        return super().start(spec)
+
+    def poll(self, window, tol):
+        out = {}
+        for h, (spec, t) in self.active.items():
+            if spec.get("breaks") and t >= spec["breaks"]:
+                out[h] = (-2, float("nan"), t, "LBM_E_UNSTABLE: speed out of range")
+                continue
+            ok = t - 1 - window >= 0
+            out[h] = ((1 if t >= spec["conv"] else 0) if ok else -1, 0.0, t, "")
+        return out
+
+    def drop(self, h):
+        spec, t = self.active.pop(h)
+        self.used -= spec["fp"]
+
+
+def test_failed_requests_finish_as_failed_and_release_memory():
+    """a request the library refuses and one whose domain turns unstable end
+    as failed results with the error's text; their memory goes back to the
+    budget and every other request is served as usual"""
+    reqs = requests(10, seed=4)
+    reqs[1]["spec"]["refuse"] = True
+    reqs[4]["spec"]["breaks"] = 1000
+    clock = FakeClock()
+    eng = FailingEngine(clock)
+    budget = 2000
+    srv = Server(eng, budget, epoch=500, window=500, clock=clock, sleep=clock.sleep)
+    res = {r.id: r for r in srv.run(reqs)}
+    assert sorted(res) == [r["id"] for r in reqs]
+    assert res[1].failed and "LBM_E_RANGE" in res[1].error and res[1].steps == 0
+    assert res[4].failed and "UNSTABLE" in res[4].error and res[4].steps == 1000
+    for k, r in res.items():
+        if k not in (1, 4):
+            assert not r.failed and r.converged
+    assert eng.used == 0 and not eng.active and eng.peak_used <= budget

@@ -307,9 +307,13 @@ typedef struct lbm_batch_s* lbm_batch;
    poses of the call plus one layer) are updated on the batch's stream
    together with the body work, the rest on a second stream the batch owns
    (default priority), so that the body work overlaps it. us_per_step is
-   filled in by lbm_batch_tune. Every shape gives bitwise the same result. */
+   filled in by lbm_batch_tune. graph 1 = a call of at least 64 steps
+   captures 32 steps once into a HIP graph (its kernels take their step from
+   a device counter) and replays it, instead of enqueueing every launch from
+   the host (not for members with a body too large for the batched advance).
+   Every shape gives bitwise the same result. */
 typedef struct {
-  int32_t block, cells_per_thread, remap, order, overlap;
+  int32_t block, cells_per_thread, remap, order, overlap, graph;
   double us_per_step;
 } lbm_batch_config;
 
@@ -342,10 +346,11 @@ lbm_status lbm_batch_set_config(lbm_batch batch, const lbm_batch_config* cfg);
 lbm_status lbm_batch_get_config(lbm_batch batch, lbm_batch_config* cfg);
 
 /* Autotuner: runs trial_steps real steps of the batch under every candidate
-   launch shape (the members advance by ntrials x trial_steps steps), times
-   each on the batch's stream with HIP events, keeps the fastest and returns
-   it in *chosen; up to trial_cap trials are written to `trials` (host, may
-   be NULL) and their number to *ntrials. */
+   launch shape (the members advance by the sum of the trials' steps), times
+   each on the batch's stream with HIP events, then times the best shape in
+   ordinary and in graph mode (overlap off and on) over 64-step calls, keeps
+   the fastest and returns it in *chosen; up to trial_cap trials are written
+   to `trials` (host, may be NULL) and their number to *ntrials. */
 lbm_status lbm_batch_tune(lbm_batch batch, int32_t trial_steps, lbm_batch_config* chosen,
                           lbm_batch_config* trials, int32_t trial_cap, int32_t* ntrials);
 

@@ -18,7 +18,7 @@ using namespace lbm::host;
 struct lbm_batch_s {
   hipStream_t stream = nullptr;
   std::vector<lbm_domain> members;
-  lbm_batch_config cfg{256, 1, 1, 0, 1, 0.0};
+  lbm_batch_config cfg{256, 1, 1, 0, 1, 0, 0.0};
   // second stream of the overlapped step; created on first use
   hipStream_t aux = nullptr;
   hipEvent_t e_near = nullptr, e_far = nullptr;
@@ -30,6 +30,13 @@ struct lbm_batch_s {
   // steady-state checks of the members: device checks + results
   char* steady_dev = nullptr;
   size_t steady_cap = 0;
+  // graph mode: the device step counter the captured kernels add to their
+  // step, and the last executable graph (destroyed at the next call or with
+  // the batch, after the stream has drained it)
+  int64_t* step_dev = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  hipStream_t cap = nullptr;  // the stream sequences are captured on (the batch's may be the null stream)
 };
 
 namespace {
@@ -38,8 +45,12 @@ size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
 bool config_ok(const lbm_batch_config& c) {
   return batch_bulk_supported(c.block, c.cells_per_thread) && (c.remap == 0 || c.remap == 1) && c.order >= 0 &&
-         c.order <= 2 && (c.overlap == 0 || c.overlap == 1);
+         c.order <= 2 && (c.overlap == 0 || c.overlap == 1) && (c.graph == 0 || c.graph == 1);
 }
+
+// steps per captured sequence of a graph-mode call (even: the buffer parity
+// of every replay is the same)
+constexpr int64_t GRAPH_STEPS = 32;
 
 int64_t active_nodes(const Geom& g) {
   return (int64_t)(g.hi[0] - g.lo[0] + 1) * (g.hi[1] - g.lo[1] + 1) * (g.hi[2] - g.lo[2] + 1);
@@ -233,15 +244,14 @@ lbm_status upload(lbm_batch B, const Plan& P) {
 
 // n steps of every member; e0 (optional) is recorded once the tables are on
 // their way and e1 after the last launch
-lbm_status batch_step(lbm_batch B, int64_t n, hipEvent_t e0, hipEvent_t e1) {
-  if (n <= 0 || B->members.empty()) return LBM_OK;
+// Enqueues batch steps k0 .. k1-1 of a call on stream `main` (the batch's
+// stream, or the stream a sequence is captured on) and the batch's second
+// stream when split: the step index k goes to the kernels, plus *sbase when
+// given (captured sequences). `capture`: completion events are recorded by
+// separate calls, not by the launches.
+static lbm_status enqueue_steps(lbm_batch B, const Plan& P, int64_t k0, int64_t k1, const int64_t* sbase, bool split,
+                                bool capture, hipStream_t main) {
   const lbm_domain first = B->members[0];
-  Plan P;
-  lbm_status s = make_plan(B, n, P);
-  if (s != LBM_OK) return s;
-  s = upload(B, P);
-  if (s != LBM_OK) return s;
-  if (e0) HIP_TRY(hipEventRecord(e0, B->stream));
   const auto* doms = reinterpret_cast<const BatchDomain*>(B->dev);
   const auto* tiles = reinterpret_cast<const BatchTile*>(B->dev + P.off_tiles);
   const auto* near_tiles = reinterpret_cast<const BatchTile*>(B->dev + P.off_near);
@@ -250,6 +260,68 @@ lbm_status batch_step(lbm_batch B, int64_t n, hipEvent_t e0, hipEvent_t e1) {
   const BulkConfig bc{B->cfg.block, B->cfg.cells_per_thread, 0, B->cfg.remap};
   const BulkConfig nc{B->cfg.block, B->cfg.cells_per_thread, 0, 0};
   const int lat = first->lat, st = first->st, eq = first->eq;
+  // 2D: the link rule of the bodies with fixed links for step k+1 joins the
+  // advance launch of step k (at the first step of a sequence it runs on its
+  // own; at its last, not at all: the next sequence starts with it)
+  const bool fuse = lat == 0 && !P.links.empty();
+  for (int64_t k = k0; k < k1; ++k) {
+    if (split) {
+      if (k > k0) HIP_TRY(hipStreamWaitEvent(main, B->e_far, 0));
+      else HIP_TRY(hipEventRecord(B->e_near, main));
+      HIP_TRY(hipStreamWaitEvent(B->aux, B->e_near, 0));
+      HIP_TRY(launch_batch_bulk(lat, st, eq, doms, tiles, (int)P.tiles.size(), bc, k, B->aux, 1, nullptr,
+                                capture ? nullptr : B->e_far, sbase));
+      if (capture) HIP_TRY(hipEventRecord(B->e_far, B->aux));
+    }
+    if (!P.links.empty() && (!fuse || k == k0))
+      HIP_TRY(launch_batch_links(lat, st, eq, doms, links, (int)P.links.size(), P.link_grid, k, main, sbase));
+    if (split) {
+      HIP_TRY(launch_batch_bulk(lat, st, eq, doms, near_tiles, (int)P.near_tiles.size(), nc, k, main, 2, nullptr,
+                                capture ? nullptr : B->e_near, sbase));
+      if (capture) HIP_TRY(hipEventRecord(B->e_near, main));
+    } else {
+      HIP_TRY(launch_batch_bulk(lat, st, eq, doms, tiles, (int)P.tiles.size(), bc, k, main, 0, nullptr, nullptr,
+                                sbase));
+    }
+    if (fuse && k + 1 < k1)
+      HIP_TRY(launch_batch_body_links(lat, st, eq, doms, moving, (int)P.moving.size(), links, (int)P.links.size(),
+                                      P.max_cells, k, main, sbase));
+    else if (!P.moving.empty())
+      HIP_TRY(launch_batch_body_step(lat, st, eq, doms, moving, (int)P.moving.size(), P.max_cells, k, main,
+                                     sbase));
+    for (const auto& f : P.fallback) {  // never in a captured sequence
+      lbm_domain d = B->members[f.first];
+      Body& b = d->body[f.second];
+      const int64_t t = d->t + k;
+      void* cur = (k & 1) ? d->A : d->B;  // the state of t+1
+      HIP_TRY(launch_body_advance(d->lat, d->st, d->eq, cur, d->mask, d->mask_next, b.links, b.n_links, b.cap,
+                                  pose_at(b, t), pose_host_at(b, t), b.shape, b.desc.bc, f.second, 1, d->g, d->ph,
+                                  rec_slot(d, t, f.second),
+                                  rec_slot(d, t + 1, f.second), d->err, main, region_cells(b, d->D, t, 1),
+                                  region_rows(b, t, 1), list_bound(b, d->D, t)));
+    }
+  }
+  if (split) HIP_TRY(hipStreamWaitEvent(main, B->e_far, 0));
+  return LBM_OK;
+}
+
+// frees the last executable graph (its launches have completed: called
+// after the stream was synchronised)
+static void drop_graph(lbm_batch B) {
+  if (B->exec) (void)hipGraphExecDestroy(B->exec);
+  if (B->graph) (void)hipGraphDestroy(B->graph);
+  B->exec = nullptr;
+  B->graph = nullptr;
+}
+
+lbm_status batch_step(lbm_batch B, int64_t n, hipEvent_t e0, hipEvent_t e1) {
+  if (n <= 0 || B->members.empty()) return LBM_OK;
+  Plan P;
+  lbm_status s = make_plan(B, n, P);  // synchronises the stream (table upload): the last graph is done
+  if (s != LBM_OK) return s;
+  s = upload(B, P);
+  if (s != LBM_OK) return s;
+  drop_graph(B);
   // Overlapped step (as the single-domain split of lbm_step): the far update
   // of step k, on the second stream, waits for the near update of step k-1;
   // the near update of step k waits for the far update of step k-1; the body
@@ -262,44 +334,41 @@ lbm_status batch_step(lbm_batch B, int64_t n, hipEvent_t e0, hipEvent_t e1) {
     HIP_TRY(hipEventCreateWithFlags(&B->e_near, hipEventDisableTiming | hipEventDisableSystemFence));
     HIP_TRY(hipEventCreateWithFlags(&B->e_far, hipEventDisableTiming | hipEventDisableSystemFence));
   }
-  // 2D: the link rule of the bodies with fixed links for step k+1 joins the
-  // advance launch of step k (at the call's first step it runs on its own;
-  // at its last, not at all: the next call starts with it)
-  const bool fuse = lat == 0 && !P.links.empty();
-  for (int64_t k = 0; k < n; ++k) {
-    if (split) {
-      if (k > 0) HIP_TRY(hipStreamWaitEvent(B->stream, B->e_far, 0));
-      else HIP_TRY(hipEventRecord(B->e_near, B->stream));
-      HIP_TRY(hipStreamWaitEvent(B->aux, B->e_near, 0));
-      // the launch records the completion event itself
-      HIP_TRY(launch_batch_bulk(lat, st, eq, doms, tiles, (int)P.tiles.size(), bc, k, B->aux, 1, nullptr, B->e_far));
+  if (e0) HIP_TRY(hipEventRecord(e0, B->stream));
+  // Graph mode: GRAPH_STEPS steps are captured once into a HIP graph whose
+  // kernels take their step from a device counter (the last node adds
+  // GRAPH_STEPS to it), and the graph is replayed; the steps left over run
+  // as ordinary launches. The launches are the same as in ordinary mode, so
+  // the results are the same bits. Bodies advanced by their own per-step
+  // launches (too large for the batched kernels) keep ordinary mode.
+  int64_t done = 0;
+  if (B->cfg.graph && P.fallback.empty() && n >= 2 * GRAPH_STEPS) {
+    if (!B->step_dev) HIP_TRY(hipMalloc(&B->step_dev, sizeof(int64_t)));
+    if (!B->cap) HIP_TRY(hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));
+    HIP_TRY(launch_set_step(B->step_dev, 0, B->stream));
+    HIP_TRY(hipStreamBeginCapture(B->cap, hipStreamCaptureModeRelaxed));
+    lbm_status sc = enqueue_steps(B, P, 0, GRAPH_STEPS, B->step_dev, split, true, B->cap);
+    if (sc == LBM_OK) {
+      hipError_t e = launch_add_step(B->step_dev, GRAPH_STEPS, B->cap);
+      if (e != hipSuccess) sc = fail(LBM_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
     }
-    if (!P.links.empty() && (!fuse || k == 0))
-      HIP_TRY(launch_batch_links(lat, st, eq, doms, links, (int)P.links.size(), P.link_grid, k, B->stream));
-    if (split) {
-      HIP_TRY(launch_batch_bulk(lat, st, eq, doms, near_tiles, (int)P.near_tiles.size(), nc, k, B->stream, 2, nullptr,
-                                B->e_near));
-    } else {
-      HIP_TRY(launch_batch_bulk(lat, st, eq, doms, tiles, (int)P.tiles.size(), bc, k, B->stream, 0));
+    hipGraph_t graph = nullptr;
+    const hipError_t ee = hipStreamEndCapture(B->cap, &graph);
+    if (sc != LBM_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return sc;
     }
-    if (fuse && k + 1 < n)
-      HIP_TRY(launch_batch_body_links(lat, st, eq, doms, moving, (int)P.moving.size(), links, (int)P.links.size(),
-                                      P.max_cells, k, B->stream));
-    else if (!P.moving.empty())
-      HIP_TRY(launch_batch_body_step(lat, st, eq, doms, moving, (int)P.moving.size(), P.max_cells, k, B->stream));
-    for (const auto& f : P.fallback) {
-      lbm_domain d = B->members[f.first];
-      Body& b = d->body[f.second];
-      const int64_t t = d->t + k;
-      void* cur = (k & 1) ? d->A : d->B;  // the state of t+1
-      HIP_TRY(launch_body_advance(d->lat, d->st, d->eq, cur, d->mask, d->mask_next, b.links, b.n_links, b.cap,
-                                  pose_at(b, t), pose_host_at(b, t), b.shape, b.desc.bc, f.second, 1, d->g, d->ph,
-                                  rec_slot(d, t, f.second),
-                                  rec_slot(d, t + 1, f.second), d->err, B->stream, region_cells(b, d->D, t, 1),
-                                  region_rows(b, t, 1), list_bound(b, d->D, t)));
-    }
+    if (ee != hipSuccess) return fail(LBM_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ee));
+    B->graph = graph;
+    HIP_TRY(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
+    const int64_t reps = n / GRAPH_STEPS;
+    for (int64_t r = 0; r < reps; ++r) HIP_TRY(hipGraphLaunch(B->exec, B->stream));
+    done = reps * GRAPH_STEPS;
   }
-  if (split) HIP_TRY(hipStreamWaitEvent(B->stream, B->e_far, 0));
+  if (done < n) {
+    s = enqueue_steps(B, P, done, n, nullptr, split, false, B->stream);
+    if (s != LBM_OK) return s;
+  }
   if (e1) HIP_TRY(hipEventRecord(e1, B->stream));
   for (lbm_domain d : B->members) {
     d->t += n;
@@ -336,9 +405,12 @@ lbm_status lbm_batch_destroy(lbm_batch B) {
     (void)hipEventDestroy(B->e_near);
     (void)hipEventDestroy(B->e_far);
   }
+  drop_graph(B);
   if (B->dev) (void)hipFree(B->dev);
   if (B->pinned) (void)hipHostFree(B->pinned);
   if (B->steady_dev) (void)hipFree(B->steady_dev);
+  if (B->step_dev) (void)hipFree(B->step_dev);
+  if (B->cap) (void)hipStreamDestroy(B->cap);
   delete B;
   if (e != hipSuccess) return fail(LBM_E_HIP, hipGetErrorString(e));
   return LBM_OK;
@@ -523,7 +595,7 @@ lbm_status lbm_batch_tune(lbm_batch B, int32_t trial_steps, lbm_batch_config* ch
   for (const auto& v : BATCH_BULK_VARIANTS)
     for (int remap = 0; remap <= 1 && s == LBM_OK; ++remap)
       for (int order = 0; order <= 2 && s == LBM_OK; ++order) {
-        B->cfg = lbm_batch_config{v[0], v[1], remap, order, overlap, 0.0};
+        B->cfg = lbm_batch_config{v[0], v[1], remap, order, overlap, 0, 0.0};
         s = batch_step(B, trial_steps, e0, e1);
         if (s != LBM_OK) break;
         hipError_t e = hipEventSynchronize(e1);
@@ -538,6 +610,39 @@ lbm_status lbm_batch_tune(lbm_batch B, int32_t trial_steps, lbm_batch_config* ch
         count++;
         if (B->cfg.us_per_step < best.us_per_step) best = B->cfg;
       }
+  // graph mode: the best shape of each overlap setting replayed from a
+  // captured sequence, against the best ordinary configuration, over a call
+  // long enough to replay the graph (2 GRAPH_STEPS steps)
+  if (s == LBM_OK) {
+    lbm_batch_config cand[3];
+    int nc = 0;
+    cand[nc++] = best;
+    for (int overlap = 0; overlap <= 1; ++overlap) {
+      lbm_batch_config c = best;
+      c.overlap = overlap;
+      c.graph = 1;
+      cand[nc++] = c;
+    }
+    lbm_batch_config best_long{};
+    best_long.us_per_step = 1e300;
+    for (int k = 0; k < nc && s == LBM_OK; ++k) {
+      B->cfg = cand[k];
+      s = batch_step(B, 2 * GRAPH_STEPS, e0, e1);
+      if (s != LBM_OK) break;
+      hipError_t e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        s = fail(LBM_E_HIP, std::string("autotuner timing: ") + hipGetErrorString(e));
+        break;
+      }
+      B->cfg.us_per_step = ms * 1e3 / (2 * GRAPH_STEPS);
+      if (trials && count < trial_cap) trials[count] = B->cfg;
+      count++;
+      if (B->cfg.us_per_step < best_long.us_per_step) best_long = B->cfg;
+    }
+    best = best_long;
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (s != LBM_OK) return s;

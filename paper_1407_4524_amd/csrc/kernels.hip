@@ -294,13 +294,13 @@ bool batch_bulk_supported(int block, int cells_per_thread) {
 
 hipError_t launch_batch_bulk(int lat, int st, int eq, const BatchDomain* doms, const BatchTile* tiles, int ntiles,
                              const BulkConfig& cfg, int64_t step, hipStream_t s, int part, hipEvent_t ev_start,
-                             hipEvent_t ev_stop) {
+                             hipEvent_t ev_stop, const int64_t* sbase) {
   if (ntiles <= 0 || !batch_bulk_supported(cfg.block, cfg.cells_per_thread) || part < 0 || part > 2)
     return hipErrorInvalidValue;
   if (ev_start != nullptr && ev_stop == nullptr) return hipErrorInvalidValue;
   with_types(lat, st, eq, [&](auto Lt, auto St, auto E) {
     LBM_TYPES
-    O::batch_bulk(doms, tiles, ntiles, cfg, step, s, part, ev_start, ev_stop);
+    O::batch_bulk(doms, tiles, ntiles, cfg, step, s, part, ev_start, ev_stop, sbase);
   });
   return hipGetLastError();
 }
@@ -311,36 +311,55 @@ int batch_link_grid(int lat, int max_links) {
 }
 
 hipError_t launch_batch_links(int lat, int st, int eq, const BatchDomain* doms, const BatchBody* bodies, int nbodies,
-                              int grid, int64_t step, hipStream_t s) {
+                              int grid, int64_t step, hipStream_t s, const int64_t* sbase) {
   if (nbodies <= 0 || grid <= 0 || grid > 64 || (lat == 0 && grid != 1)) return hipErrorInvalidValue;
   with_types(lat, st, eq, [&](auto Lt, auto St, auto E) {
     LBM_TYPES
-    O::batch_links(doms, bodies, nbodies, grid, step, s);
+    O::batch_links(doms, bodies, nbodies, grid, step, s, sbase);
   });
   return hipGetLastError();
 }
 
 hipError_t launch_batch_body_links(int lat, int st, int eq, const BatchDomain* doms, const BatchBody* moving,
                                    int n_moving, const BatchBody* fixed, int n_fixed, int64_t max_region_cells,
-                                   int64_t step, hipStream_t s) {
+                                   int64_t step, hipStream_t s, const int64_t* sbase) {
   if (lat != 0 || n_moving < 0 || n_fixed < 0 || n_moving + n_fixed <= 0) return hipErrorInvalidValue;
   if (n_moving > 0 && (max_region_cells <= 0 || max_region_cells > STEP_CELLS)) return hipErrorInvalidValue;
   const size_t lds = n_moving > 0 ? ((size_t)2 * max_region_cells + 15) / 16 * 16 : 0;
   with_types(lat, st, eq, [&](auto Lt, auto St, auto E) {
     LBM_TYPES
-    O::batch_body_links(doms, moving, n_moving, fixed, n_fixed, lds, step, s);
+    O::batch_body_links(doms, moving, n_moving, fixed, n_fixed, lds, step, s, sbase);
   });
   return hipGetLastError();
 }
 
 hipError_t launch_batch_body_step(int lat, int st, int eq, const BatchDomain* doms, const BatchBody* bodies,
-                                  int nbodies, int64_t max_region_cells, int64_t step, hipStream_t s) {
+                                  int nbodies, int64_t max_region_cells, int64_t step, hipStream_t s,
+                                  const int64_t* sbase) {
   if (nbodies <= 0 || max_region_cells <= 0 || max_region_cells > STEP_CELLS) return hipErrorInvalidValue;
   const size_t lds = ((size_t)2 * max_region_cells + 15) / 16 * 16;
   with_types(lat, st, eq, [&](auto Lt, auto St, auto E) {
     LBM_TYPES
-    O::batch_body_step(doms, bodies, nbodies, lds, step, s);
+    O::batch_body_step(doms, bodies, nbodies, lds, step, s, sbase);
   });
+  return hipGetLastError();
+}
+
+__global__ void k_add_step(int64_t* counter, int64_t k) {
+  if (threadIdx.x == 0) *counter += k;
+}
+
+hipError_t launch_add_step(int64_t* counter, int64_t k, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_step, dim3(1), dim3(64), 0, s, counter, k);
+  return hipGetLastError();
+}
+
+__global__ void k_set_step(int64_t* counter, int64_t v) {
+  if (threadIdx.x == 0) *counter = v;
+}
+
+hipError_t launch_set_step(int64_t* counter, int64_t v, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_step, dim3(1), dim3(64), 0, s, counter, v);
   return hipGetLastError();
 }
 

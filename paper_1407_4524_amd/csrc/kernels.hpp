@@ -168,21 +168,28 @@ bool batch_bulk_supported(int block, int cells_per_thread);
 
 // part: 0 every node of the tiles' rows, 1 the same but the members' near
 // boxes, 2 near-box tiles (rows numbered within the box)
+// sbase (optional, device): added to `step` by the kernels, for step
+// sequences captured once and replayed
 hipError_t launch_batch_bulk(int lat, int st, int eq, const BatchDomain* doms, const BatchTile* tiles, int ntiles,
                              const BulkConfig& cfg, int64_t step, hipStream_t s, int part = 0,
-                             hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+                             hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr,
+                             const int64_t* sbase = nullptr);
 // blocks per body of the batched link-rule launch for bodies of up to
 // max_links links
 int batch_link_grid(int lat, int max_links);
 hipError_t launch_batch_links(int lat, int st, int eq, const BatchDomain* doms, const BatchBody* bodies, int nbodies,
-                              int grid, int64_t step, hipStream_t s);
+                              int grid, int64_t step, hipStream_t s, const int64_t* sbase = nullptr);
 // 2D batches: the advance of the moving bodies after batch step `step` and
 // the link rule of step+1 for the bodies with fixed links, in one launch
 hipError_t launch_batch_body_links(int lat, int st, int eq, const BatchDomain* doms, const BatchBody* moving,
                                    int n_moving, const BatchBody* fixed, int n_fixed, int64_t max_region_cells,
-                                   int64_t step, hipStream_t s);
+                                   int64_t step, hipStream_t s, const int64_t* sbase = nullptr);
 hipError_t launch_batch_body_step(int lat, int st, int eq, const BatchDomain* doms, const BatchBody* bodies,
-                                  int nbodies, int64_t max_region_cells, int64_t step, hipStream_t s);
+                                  int nbodies, int64_t max_region_cells, int64_t step, hipStream_t s,
+                                  const int64_t* sbase = nullptr);
+// *counter += k, one thread (closes a captured step sequence); *counter = v
+hipError_t launch_add_step(int64_t* counter, int64_t k, hipStream_t s);
+hipError_t launch_set_step(int64_t* counter, int64_t v, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // The launches of one (lattice, storage, equilibrium) combination. Defined in
@@ -211,13 +218,14 @@ struct Ops {
                            hipStream_t s, int64_t region_cells, int64_t region_rows, int64_t list_nodes,
                            hipEvent_t e0, hipEvent_t e1);
   static void batch_bulk(const BatchDomain* doms, const BatchTile* tiles, int ntiles, const BulkConfig& cfg,
-                         int64_t step, hipStream_t s, int part, hipEvent_t e0, hipEvent_t e1);
+                         int64_t step, hipStream_t s, int part, hipEvent_t e0, hipEvent_t e1, const int64_t* sbase);
   static void batch_links(const BatchDomain* doms, const BatchBody* bodies, int nbodies, int grid, int64_t step,
-                          hipStream_t s);
+                          hipStream_t s, const int64_t* sbase);
   static void batch_body_links(const BatchDomain* doms, const BatchBody* moving, int n_moving,
-                               const BatchBody* fixed, int n_fixed, size_t lds, int64_t step, hipStream_t s);
+                               const BatchBody* fixed, int n_fixed, size_t lds, int64_t step, hipStream_t s,
+                               const int64_t* sbase);
   static void batch_body_step(const BatchDomain* doms, const BatchBody* bodies, int nbodies, size_t lds,
-                              int64_t step, hipStream_t s);
+                              int64_t step, hipStream_t s, const int64_t* sbase);
 };
 
 #define LBM_OPS_FOR(MACRO, Lt, St) \

@@ -1338,7 +1338,9 @@ __device__ __forceinline__ double* batch_rec(const BatchBody& b, int64_t t) {
 template <class L, class S, int EQ, int BX, int CPT>
 __global__ __launch_bounds__(BX) void k_stream_collide_batch(const BatchDomain* __restrict__ doms,
                                                              const BatchTile* __restrict__ tiles, int ntiles,
-                                                             int remap, int64_t s, int part) {
+                                                             int remap, int64_t s, int part,
+                                                             const int64_t* __restrict__ sbase) {
+  s += sbase ? *sbase : 0;  // a captured step sequence takes its first step from the device
   const int blk = remap ? xcd_block(blockIdx.x, ntiles) : blockIdx.x;
   const BatchTile tl = tiles[blk];
   const BatchDomain& D = doms[tl.dom];
@@ -1370,7 +1372,9 @@ __global__ __launch_bounds__(BX) void k_stream_collide_batch(const BatchDomain* 
 // buffer
 template <class L, class S, int EQ, int NTL>
 __global__ __launch_bounds__(NTL) void k_links_batch(const BatchDomain* __restrict__ doms,
-                                                     const BatchBody* __restrict__ bodies, int64_t s) {
+                                                     const BatchBody* __restrict__ bodies, int64_t s,
+                                                     const int64_t* __restrict__ sbase) {
+  s += sbase ? *sbase : 0;
   const BatchBody& b = bodies[blockIdx.y];
   const BatchDomain& D = doms[b.dom];
   const int64_t t = b.t0 + s;
@@ -1381,7 +1385,9 @@ __global__ __launch_bounds__(NTL) void k_links_batch(const BatchDomain* __restri
 // one workgroup per moving body: its advance after batch step s's bulk update
 template <class L, class S, int EQ, int NT>
 __global__ __launch_bounds__(NT) void k_body_step_batch(const BatchDomain* __restrict__ doms,
-                                                        const BatchBody* __restrict__ bodies, int64_t s) {
+                                                        const BatchBody* __restrict__ bodies, int64_t s,
+                                                        const int64_t* __restrict__ sbase) {
+  s += sbase ? *sbase : 0;
   const BatchBody& b = bodies[blockIdx.x];
   const BatchDomain& D = doms[b.dom];
   const int64_t t = b.t0 + s;
@@ -1399,7 +1405,9 @@ __global__ __launch_bounds__(NT) void k_body_step_batch(const BatchDomain* __res
 template <class L, class S, int EQ, int NT>
 __global__ __launch_bounds__(NT) void k_body_links_batch(const BatchDomain* __restrict__ doms,
                                                          const BatchBody* __restrict__ moving, int n_moving,
-                                                         const BatchBody* __restrict__ fixed, int64_t s) {
+                                                         const BatchBody* __restrict__ fixed, int64_t s,
+                                                         const int64_t* __restrict__ sbase) {
+  s += sbase ? *sbase : 0;
   if ((int)blockIdx.x < n_moving) {
     const BatchBody& b = moving[blockIdx.x];
     const BatchDomain& D = doms[b.dom];
@@ -1534,11 +1542,12 @@ void Ops<L, S, EQ>::body_advance(void* B, uint8_t* mask, uint8_t* mask_next, Lin
 
 template <class L, class S, int EQ>
 void Ops<L, S, EQ>::batch_bulk(const BatchDomain* doms, const BatchTile* tiles, int ntiles, const BulkConfig& cfg,
-                               int64_t step, hipStream_t s, int part, hipEvent_t e0, hipEvent_t e1) {
+                               int64_t step, hipStream_t s, int part, hipEvent_t e0, hipEvent_t e1,
+                               const int64_t* sbase) {
 #define LBM_BATCH_CASE(BX_, CPT_)                                                                          \
   if (cfg.block == BX_ && cfg.cells_per_thread == CPT_) {                                                  \
     launch_timed(k_stream_collide_batch<L, S, EQ, BX_, CPT_>, dim3(ntiles), dim3(BX_), 0, s, e0, e1, doms, tiles, \
-                 ntiles, cfg.remap, step, part);                                                           \
+                 ntiles, cfg.remap, step, part, sbase);                                                    \
     return;                                                                                                \
   }
   LBM_BATCH_CASE(64, 1)
@@ -1551,27 +1560,28 @@ void Ops<L, S, EQ>::batch_bulk(const BatchDomain* doms, const BatchTile* tiles, 
 
 template <class L, class S, int EQ>
 void Ops<L, S, EQ>::batch_links(const BatchDomain* doms, const BatchBody* bodies, int nbodies, int grid, int64_t step,
-                                hipStream_t s) {
+                                hipStream_t s, const int64_t* sbase) {
   if constexpr (L::D == 2)
-    hipLaunchKernelGGL((k_links_batch<L, S, EQ, 1024>), dim3(1, nbodies), dim3(1024), 0, s, doms, bodies, step);
+    hipLaunchKernelGGL((k_links_batch<L, S, EQ, 1024>), dim3(1, nbodies), dim3(1024), 0, s, doms, bodies, step, sbase);
   else
     hipLaunchKernelGGL((k_links_batch<L, S, EQ, LINK_BLOCK>), dim3(grid, nbodies), dim3(LINK_BLOCK), 0, s, doms,
-                       bodies, step);
+                       bodies, step, sbase);
 }
 
 template <class L, class S, int EQ>
 void Ops<L, S, EQ>::batch_body_links(const BatchDomain* doms, const BatchBody* moving, int n_moving,
-                                     const BatchBody* fixed, int n_fixed, size_t lds, int64_t step, hipStream_t s) {
+                                     const BatchBody* fixed, int n_fixed, size_t lds, int64_t step, hipStream_t s,
+                                     const int64_t* sbase) {
   if constexpr (L::D == 2)
     hipLaunchKernelGGL((k_body_links_batch<L, S, EQ, 1024>), dim3(n_moving + n_fixed), dim3(1024), lds, s, doms,
-                       moving, n_moving, fixed, step);
+                       moving, n_moving, fixed, step, sbase);
 }
 
 template <class L, class S, int EQ>
 void Ops<L, S, EQ>::batch_body_step(const BatchDomain* doms, const BatchBody* bodies, int nbodies, size_t lds,
-                                    int64_t step, hipStream_t s) {
+                                    int64_t step, hipStream_t s, const int64_t* sbase) {
   constexpr int NT = L::D == 2 ? 1024 : 512;
-  hipLaunchKernelGGL((k_body_step_batch<L, S, EQ, NT>), dim3(nbodies), dim3(NT), lds, s, doms, bodies, step);
+  hipLaunchKernelGGL((k_body_step_batch<L, S, EQ, NT>), dim3(nbodies), dim3(NT), lds, s, doms, bodies, step, sbase);
 }
 
 }  // namespace lbm

@@ -69,7 +69,7 @@ class SweepConfig(C.Structure):
 
 class BatchConfig(C.Structure):
     _fields_ = [("block", C.c_int32), ("cells_per_thread", C.c_int32), ("remap", C.c_int32), ("order", C.c_int32),
-                ("overlap", C.c_int32), ("us_per_step", C.c_double)]
+                ("overlap", C.c_int32), ("graph", C.c_int32), ("us_per_step", C.c_double)]
 
     def as_dict(self):
         return {f[0]: getattr(self, f[0]) for f in self._fields_}

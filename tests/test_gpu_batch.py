@@ -43,10 +43,12 @@ def assert_same(a, b):
     assert np.array_equal(ra, rb, equal_nan=True) and np.array_equal(ua, ub, equal_nan=True)
 
 
-@pytest.mark.parametrize("overlap,own_stream", [(1, True), (1, False), (0, False)])
-def test_batch_equals_each_domain_alone(overlap, own_stream):
+@pytest.mark.parametrize("overlap,own_stream,graph", [(1, True, 0), (1, False, 0), (0, False, 0), (0, True, 1),
+                                                      (1, True, 1)])
+def test_batch_equals_each_domain_alone(overlap, own_stream, graph):
     """overlap on a stream of the batch's own uses the CU-masked second
-    stream, on the default stream a plain one"""
+    stream, on the default stream a plain one; graph mode replays a captured
+    32-step sequence in the 100-step call (3 replays and 4 ordinary steps)"""
     import torch
     from paper_1407_4524_amd import Batch
     ws = small_batch()
@@ -59,7 +61,7 @@ def test_batch_equals_each_domain_alone(overlap, own_stream):
         d.step(150)
     s = torch.cuda.Stream() if own_stream else torch.cuda.current_stream()
     batch = Batch(stream=s.cuda_stream)
-    batch.config = dict(batch.config, overlap=overlap)
+    batch.config = dict(batch.config, overlap=overlap, graph=graph)
     with torch.cuda.stream(s):
         members = [make_gpu(w) for w in ws]
     for d in members:
@@ -105,10 +107,12 @@ def test_batch_members_at_different_steps_and_tuning():
     for d in members:
         batch.add(d)
     chosen, trials = batch.tune(trial_steps=3)
-    assert len(trials) == 60 and chosen["us_per_step"] == min(t["us_per_step"] for t in trials)
+    # 60 shapes of 3 steps, then the best shape in ordinary and graph mode over 64 steps each
+    assert len(trials) == 63 and chosen["us_per_step"] == min(t["us_per_step"] for t in trials[60:])
+    assert {t["graph"] for t in trials[60:]} == {0, 1}
     batch.step(20)
     for a in alone:
-        a.step(60 * 3 + 20)
+        a.step(60 * 3 + 3 * 64 + 20)
     for a, m in zip(alone, members):
         assert_same(m, a)
     # a member can still be stepped on its own while it belongs to the batch

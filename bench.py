@@ -98,13 +98,13 @@ def timing_period(steps):
     return 1 if steps <= 1024 else max(1, steps // 512)
 
 
-def run_gpu(name, steps, warmup, plain_schedule=False):
+def run_gpu(name, steps, warmup, split_schedule=False):
     import torch
     from paper_1407_4524_amd import Domain
     w = workload(name)
     stream = torch.cuda.Stream()  # the domain's own stream, as a serving process would give it
     with torch.cuda.stream(stream):
-        dom = Domain.from_spec(w, plain_schedule=plain_schedule)
+        dom = Domain.from_spec(w, split_schedule=split_schedule)
     dom.step(warmup)
     dom.synchronize()
     every = timing_period(steps)
@@ -354,8 +354,9 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=5000)
     ap.add_argument("--no-copy-ceiling", action="store_true",
                     help="skip the copy-kernel reference at the stream-collide footprint")
-    ap.add_argument("--plain-schedule", action="store_true",
-                    help="run link rule, stream-collide and body advance one after another (no overlap)")
+    ap.add_argument("--split-schedule", action="store_true",
+                    help="with a single moving body, update the nodes away from it on a second stream, "
+                         "overlapping the body's advance")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
@@ -364,7 +365,7 @@ def main():
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
 
-    main_run = run_gpu(args.workload, args.steps, args.warmup, args.plain_schedule)
+    main_run = run_gpu(args.workload, args.steps, args.warmup, args.split_schedule)
     w = main_run["w"]
     line = {
         "metric": METRIC,
@@ -384,7 +385,7 @@ def main():
                    "force_accumulation": "f64", "bodies": len(w["bodies"]),
                    "me": w["bodies"][0]["me"] if w["bodies"] else None, "parallelism": "single-gpu",
                    "footprint_bytes": main_run["footprint_bytes"],
-                   "schedule": "plain" if args.plain_schedule else "overlapped"},
+                   "schedule": "split" if args.split_schedule else "plain"},
         "roofline": main_run["roofline"],
         "kernels": main_run["kernels"],
     }
@@ -393,7 +394,7 @@ def main():
     if not args.no_secondary and args.workload == HEADLINE:
         sec = {}
         for name in ("duct_sphere_f16", "channel_oscillating_f32"):
-            r = run_gpu(name, args.steps, args.warmup, args.plain_schedule)
+            r = run_gpu(name, args.steps, args.warmup, args.split_schedule)
             sec[r["w"]["name"]] = secondary_line(r)
         if not args.no_large:
             r = run_gpu("channel_large_f32", min(args.steps, 200), min(args.warmup, 10))

@@ -47,14 +47,41 @@
  *              row holds after the table ends)
  * The wall velocity at a point x is V + Omega e_z x (x - X).
  *
+ * Free bodies (FREE; the sedimentation tests of Sec. IV): the flow force of
+ * step t, in the form me_mode selects, plus ext_force and ext_torque, moves
+ * the body by Newton-Euler about z: a = (F + ext_force)/mass (a_z = 0 in
+ * 2D), alpha = (T_z + ext_torque)/inertia; EULER: dv = a, AB2: dv =
+ * 1.5 a - 0.5 a_prev after the first step; V += dv, X += V (the new V),
+ * Omega += dalpha, theta += Omega, each operation in that order in IEEE
+ * double without fused multiply-add. With LBM_ME_LATTICE (or _BACKWARD) the
+ * covered/uncovered terms come from the step before (the approximation of
+ * Aidun et al. that Sec. III.B.3 describes, which keeps the step explicit).
+ * cos/sin of theta are not libm's: k = rint(theta * 0.63661977236758134),
+ * r = (theta - k*1.5707963267948966) - k*6.123233995736766e-17, z = r*r,
+ * then Horner through 1/17! (sin r = r + (r*z)*p(z)) and 1/18! (cos r =
+ * 1 - z*q(z)), quadrant k mod 4. The node box of the new pose must stay
+ * inside the interior and |V| below 0.5 (a sticky error otherwise; the body
+ * then stops).
+ *
  * Faces: -x,+x,-y,+y,-z,+z each PERIODIC (in pairs), WALL (the boundary
  * layer of nodes is solid; halfway bounce-back puts the no-slip plane half
  * way into it), INLET (-x only: velocity bounce-back at x = -1/2 with the
  * inlet profile), OUTLET (+x only: zero gradient, the incoming populations of
  * the last column copied from the column's own outgoing ones shifted along
  * the link) or OUTLET_VELOCITY (+x only: velocity bounce-back at
- * x = nx - 1/2). A parabolic profile is 4 u (p - 1/2)(n - 3/2 - p)/(n-2)^2
- * along every WALL axis transverse to x.
+ * x = nx - 1/2), or, on either x face, ZOUHE_VELOCITY / ZOUHE_PRESSURE (the
+ * face nodes x = 0 or nx - 1 are boundary nodes of Zou & He, the reference
+ * the paper's Sec. IV set-up uses for its faces: after the pull, the
+ * populations entering through the face are rebuilt from the node's others
+ * by bounce-back of their non-equilibrium part with the transverse
+ * correction, so that the node carries the inlet profile as velocity along x
+ * (VELOCITY) or rho0 as density (PRESSURE), with no transverse velocity; on
+ * an edge with a WALL face the wall's bounce-back supplies the populations
+ * that cross only the wall). A parabolic profile is
+ * 4 u (p - 1/2)(n - 3/2 - p)/(n-2)^2 along every WALL axis transverse to x,
+ * taken at the wall point of a velocity bounce-back link, at the node itself
+ * on a Zou-He face. Face records (face_records = 1) are not kept with a
+ * Zou-He face.
  *
  * Ownership and threading: a domain owns its device arrays unless the caller
  * passes device_buffer, which then must outlive the domain. The caller owns
@@ -63,7 +90,7 @@
  * never synchronises; errors raised on the device surface at the next call
  * that reads results (lbm_force_torque, lbm_records, lbm_get_*). Work the
  * caller enqueues on the stream after lbm_step sees the whole step (see
- * plain_schedule for the second stream a domain may use).
+ * split_schedule for the second stream a domain may use).
  * No exception crosses this interface; every call returns lbm_status and
  * lbm_last_error() gives a thread-local message. An error a kernel reports
  * (instability, an overflowed link or node list, a body meeting a wall or
@@ -96,15 +123,17 @@ enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1 };
 enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16_SHIFTED = 2 };
 enum { LBM_EQ_BGK = 0, LBM_EQ_HELUO = 1 };
 enum { LBM_FACE_PERIODIC = 0, LBM_FACE_WALL = 1, LBM_FACE_INLET = 2, LBM_FACE_OUTLET = 3,
-       LBM_FACE_OUTLET_VELOCITY = 4 };
+       LBM_FACE_OUTLET_VELOCITY = 4, LBM_FACE_ZOUHE_VELOCITY = 5, LBM_FACE_ZOUHE_PRESSURE = 6 };
 enum { LBM_PROFILE_UNIFORM = 0, LBM_PROFILE_PARABOLIC = 1 };
 enum { LBM_SHAPE_CIRCLE = 0, LBM_SHAPE_ELLIPSE = 1, LBM_SHAPE_OUTER_CIRCLE = 2 };
 enum { LBM_BC_HALFWAY = 0, LBM_BC_MLS = 1 };
-enum { LBM_ME_STATIC = 0, LBM_ME_LATTICE = 1, LBM_ME_COMOVING = 2 };
+enum { LBM_ME_STATIC = 0, LBM_ME_LATTICE = 1, LBM_ME_COMOVING = 2, LBM_ME_LATTICE_BACKWARD = 3 };
 enum { LBM_MOTION_STATIC = 0, LBM_MOTION_CONST_VEL = 1, LBM_MOTION_ROTATE = 2,
-       LBM_MOTION_OSCILLATE = 3, LBM_MOTION_TABLE = 4 };
+       LBM_MOTION_OSCILLATE = 3, LBM_MOTION_TABLE = 4, LBM_MOTION_FREE = 5 };
+enum { LBM_INTEGRATOR_EULER = 0, LBM_INTEGRATOR_AB2 = 1 };
+enum { LBM_REFILL_MEAN = 0, LBM_REFILL_AIDUN = 1, LBM_REFILL_EXTRAPOLATE = 2 };
 
-#define LBM_MAX_BODIES 4
+#define LBM_MAX_BODIES 64
 /* one per-step record of a body: 20 doubles */
 #define LBM_REC_LEN 20
 #define LBM_REC_F_STATIC 0 /* Fx,Fy,Fz of Eq. flow_force_2 */
@@ -135,12 +164,14 @@ typedef struct {
   void* device_buffer;      /* optional caller-owned device memory; NULL = library allocates */
   size_t device_buffer_bytes;
   int64_t record_capacity;  /* steps kept in each body's record ring; 0 = 65536 */
-  int32_t plain_schedule;   /* 1: each step runs the link rule, the stream-collide update and
-                               the body advance one after another on `stream`; 0: with a
-                               single moving body, the update of the nodes away from it
-                               runs on a second stream the domain owns (default priority),
-                               overlapping the body's advance, and every call leaves
-                               `stream` waiting for it. Results are bitwise the same */
+  int32_t split_schedule;   /* 0 (default): each step runs the link rule, the stream-collide
+                               update and the body advance one after another on `stream`;
+                               1: with a single moving body, the update of the nodes away
+                               from it runs on a second stream the domain owns (default
+                               priority), overlapping the body's advance, and every call
+                               leaves `stream` waiting for it. Results are bitwise the same.
+                               The split costs two cross-stream waits per step on the host,
+                               which on small domains outweighs the overlap */
   int32_t face_records;     /* 1: the momentum exchange of the domain faces is recorded every
                                step (lbm_face_records, lbm_force_torque with LBM_WALLS); one
                                small kernel per step over the face nodes. 0: not recorded */
@@ -148,20 +179,41 @@ typedef struct {
                                the solid nodes of a body placed by lbm_set_body) starts as NaN,
                                so a pull that reads a slot no boundary rule wrote shows up as
                                LBM_E_UNSTABLE; results are otherwise unchanged. 0: zeros */
+  int32_t max_bodies;       /* body slots: ids 0 .. max_bodies-1 (0 = 4; at most
+                               LBM_MAX_BODIES); the record ring keeps one record per slot
+                               and step (max_bodies * 160 bytes per step of record_capacity) */
 } lbm_domain_desc;
 
 typedef struct {
   int32_t shape;            /* LBM_SHAPE_* */
   double axes[3];           /* radius, or semi-axes a, b (, c) */
   int32_t bc;               /* LBM_BC_HALFWAY | LBM_BC_MLS */
-  int32_t me_mode;          /* which form lbm_force_torque returns */
+  int32_t me_mode;          /* which form lbm_force_torque returns (LBM_ME_*), and for a FREE
+                               body the flow force that moves it */
   int32_t motion;           /* LBM_MOTION_* */
   double c0[3], theta0;
-  double vel[3];
-  double omega;
+  double vel[3];            /* CONST_VEL velocity; FREE: initial velocity */
+  double omega;             /* ROTATE angular speed; FREE: initial angular speed */
   double amp[3], period;
   const double* pose_table; /* TABLE: host rows of 8 doubles, copied */
   int64_t pose_count;
+  /* FREE: mass, moment of inertia about z through X, and a constant external
+     force and torque (weight minus buoyancy); see "Free bodies" above */
+  double mass, inertia;
+  double ext_force[3], ext_torque;
+  int32_t integrator;       /* FREE: LBM_INTEGRATOR_EULER | LBM_INTEGRATOR_AB2 */
+  int32_t refill;           /* moving bodies: LBM_REFILL_*, the value given to a node the body
+                               uncovers (Sec. III.B.3): MEAN, the equilibrium at the mean density
+                               and velocity of its neighbours fluid at t and t+1 (rho0 and the
+                               wall velocity when there are none); AIDUN, the equilibrium at that
+                               mean density and the wall velocity at the node; EXTRAPOLATE,
+                               every population extrapolated quadratically, 3 f(x+c) - 3 f(x+2c)
+                               + f(x+3c), along the lattice direction c that maximises
+                               (n.c)/|c| for the outward normal n of the body at the node (the
+                               gradient of phi, pose t+1: (dx,dy,dz) for a circle/sphere,
+                               (xi ct ia2 - eta st ib2, xi st ia2 + eta ct ib2, dz ic2) for an
+                               ellipse/ellipsoid, each left to right; ties to the smallest
+                               (cx,cy,cz)), from nodes fluid at t and t+1, else MEAN */
 } lbm_body_desc;
 
 /* Device bytes a domain with this descriptor needs (for admission by HBM
@@ -184,13 +236,19 @@ lbm_status lbm_create_domain(const lbm_domain_desc* desc, lbm_domain* out);
 /* Waits for the domain's stream and frees what the library allocated. */
 lbm_status lbm_destroy_domain(lbm_domain dom);
 
-/* Places body `body_id` (0..LBM_MAX_BODIES-1) at its pose of the current
-   step: marks its nodes solid and builds its boundary-link list, the gained
-   sets G_i of Sec. III.B (x_F fluid with x_F - c_i inside the body), with
-   Delta per link (Sec. II.A). Its bounding box plus two nodes must stay
+/* Places body `body_id` (0..max_bodies-1 of the domain) at its pose of the
+   current step: marks its nodes solid and builds its boundary-link list, the
+   gained sets G_i of Sec. III.B (x_F fluid with x_F - c_i inside the body),
+   with Delta per link (Sec. II.A). Its bounding box plus two nodes must stay
    inside the non-wall interior at every step that lbm_step reaches
-   (LBM_E_RANGE otherwise), except for a static OUTER_CIRCLE. Synchronises
-   the stream once. */
+   (LBM_E_RANGE otherwise), except for a static OUTER_CIRCLE. Several bodies
+   of one domain (a suspension) are independent: each keeps its own links,
+   records and advance. They must stay at least four nodes apart at every
+   step (the interpolated rule reads two nodes out from the wall, the refill
+   one node around a node that leaves a body, and bodies closer than that
+   would make the result depend on the order in which their advances run);
+   a body whose nodes meet another body's while it moves is reported as a
+   sticky error. Synchronises the stream once. */
 lbm_status lbm_set_body(lbm_domain dom, int32_t body_id, const lbm_body_desc* body);
 
 /* Advances nsteps time steps. Enqueue only. */
@@ -204,11 +262,23 @@ int64_t lbm_time(lbm_domain dom);
 
 /* Force and torque on body `body_id` in its me_mode, for steps
    first_step..first_step+count-1: ft[6*k..6*k+5] = Fx,Fy,Fz,Tx,Ty,Tz.
+   LBM_ME_LATTICE_BACKWARD: the static terms of step t plus the covered/
+   uncovered terms of step t-1 (nodes that changed between t-1 and t, the
+   sets of Aidun et al. and Wen et al. that Sec. III.B.3 contrasts with its
+   own forward-in-time sets; zero before the first step).
    body_id LBM_WALLS: the force and torque (about the origin) on the wall
    layers of a domain with face_records (see lbm_face_records).
    Synchronises. LBM_E_RANGE if a step is not in the record ring. */
 lbm_status lbm_force_torque(lbm_domain dom, int32_t body_id, int64_t first_step, int64_t count,
                             double* ft);
+
+/* Pose of body `body_id` at steps first_step..first_step+count-1:
+   out[8*k ...] = X[3], theta, V[3], Omega_z, for a FREE body from the ring
+   its integration fills (steps within record_capacity of the current one,
+   up to the current step), for a prescribed motion from its definition.
+   Synchronises. LBM_E_RANGE outside that span. */
+lbm_status lbm_body_trajectory(lbm_domain dom, int32_t body_id, int64_t first_step, int64_t count,
+                               double* out);
 
 /* Full per-step records (LBM_REC_LEN doubles each, layout LBM_REC_*). */
 lbm_status lbm_records(lbm_domain dom, int32_t body_id, int64_t first_step, int64_t count,

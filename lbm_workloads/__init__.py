@@ -28,6 +28,7 @@ import math
 import numpy as np
 
 PERIODIC, WALL, INLET, OUTLET, OUTLET_VELOCITY = 0, 1, 2, 3, 4
+ZOUHE_VELOCITY, ZOUHE_PRESSURE = 5, 6
 
 CHANNEL_FACES = (INLET, OUTLET, WALL, WALL, PERIODIC, PERIODIC)
 DUCT_FACES = (INLET, OUTLET, WALL, WALL, WALL, WALL)
@@ -79,6 +80,128 @@ def channel_large(storage: str = "f32", n: int = 8192):
         steps=200,
         bodies=[dict(shape="circle", axes=(40.0,), bc="mls", me="static", motion="static",
                      c0=(n / 5.0, n / 2.0 + 0.3, 0.0))])
+
+
+def channel_zouhe(lattice: str = "D2Q9", storage: str = "f64", eq: str = "heluo", scale: int = 1, body: bool = True):
+    """Channel (D2Q9 400x160, or D3Q19 duct 128x48x48) with the face method
+    of the paper's Sec. IV set-up: Zou-He velocity inlet (parabolic, u_max
+    0.04) and Zou-He pressure outlet (rho0), halfway walls, the
+    quasi-incompressible equilibrium by default, tau 0.6, and a static
+    circle/sphere (R 16, interpolated rule) a quarter of the way in.
+    ``scale`` divides the sizes."""
+    s = scale
+    if lattice == "D2Q9":
+        nx, ny, nz, r = 400 // s, 160 // s, 1, 16.0 / s
+        faces, c0 = (ZOUHE_VELOCITY, ZOUHE_PRESSURE, WALL, WALL, PERIODIC, PERIODIC), (nx / 4, ny / 2 + 0.3, 0.0)
+    else:
+        nx, ny, nz, r = 128 // s, 48 // s, 48 // s, 8.0 / s
+        faces, c0 = (ZOUHE_VELOCITY, ZOUHE_PRESSURE, WALL, WALL, WALL, WALL), (nx / 4, ny / 2 + 0.3, nz / 2 - 0.2)
+    return dict(
+        name=f"channel_zouhe_{lattice.lower()}_{eq}_{storage}_{nx}x{ny}" + (f"x{nz}" if nz > 1 else ""),
+        lattice=lattice, nx=nx, ny=ny, nz=nz, tau=0.6, rho0=1.0, eq=eq, faces=faces, inlet_profile="parabolic",
+        inlet_u=0.04, storage=storage, rho_noise=0.0, seed=0, steps=4000 // s,
+        bodies=[dict(shape="circle", axes=(r,), bc="mls", me="static", motion="static", c0=c0)] if body else [])
+
+
+def suspension(storage: str = "f32", nx: int = 2048, ny: int = 1024, rows: int = 4, cols: int = 8, seed: int = 0,
+               radius=(12.0, 24.0), lattice: str = "D2Q9", nz: int = 1):
+    """Many bodies in one channel (a fixed suspension): rows x cols cells,
+    one body per cell at a seeded jittered position, radius (or semi-axes)
+    drawn from `radius`. Cell k takes, by k % 4: a static circle (interpolated
+    rule, static ME), a static circle with halfway bounce-back, an ellipse
+    rotating in place at Omega in [2e-4, 1e-3] rad/step (lattice-frame ME),
+    a circle oscillating across the channel with amplitude 2 and period
+    U[300, 600] (lattice-frame ME). Parabolic inflow u_max = 0.04, tau = 0.6,
+    zero-gradient outlet; every body stays at least 8 nodes from its cell's
+    edges, so bodies keep far apart. D3Q19 gives spheres/ellipsoids in a
+    duct (rows along y, cols along x, one layer in z)."""
+    rng = np.random.default_rng(seed)
+    cw, ch = nx / (cols + 1), ny / rows
+    bodies = []
+    for r in range(rows):
+        for c in range(cols):
+            k = r * cols + c
+            a = float(rng.uniform(*radius))
+            kind = k % 4
+            b = float(rng.uniform(0.5 * a, a)) if kind == 2 else a
+            slack = max(0.0, min(cw, ch) / 2 - a - 8.0 - (2.0 if kind == 3 else 0.0))
+            cx = cw * (c + 0.5) + float(rng.uniform(-slack, slack))
+            cy = ch * (r + 0.5) + float(rng.uniform(-slack, slack))
+            cz = nz / 2 + float(rng.uniform(-0.5, 0.5)) if lattice == "D3Q19" else 0.0
+            theta0 = float(rng.uniform(0.0, math.pi))
+            if kind == 0:
+                bd = dict(shape="circle", axes=(a,), bc="mls", me="static", motion="static", c0=(cx, cy, cz))
+            elif kind == 1:
+                bd = dict(shape="circle", axes=(a,), bc="halfway", me="static", motion="static", c0=(cx, cy, cz))
+            elif kind == 2:
+                bd = dict(shape="ellipse", axes=(a, b, b), bc="mls", me="lattice", motion="rotate", c0=(cx, cy, cz),
+                          theta0=theta0, omega=float(rng.uniform(2e-4, 1e-3)))
+            else:
+                bd = dict(shape="circle", axes=(a,), bc="mls", me="lattice", motion="oscillate", c0=(cx, cy, cz),
+                          amp=(0.0, 2.0, 0.0), period=float(rng.uniform(300.0, 600.0)))
+            bodies.append(bd)
+    faces = CHANNEL_FACES if lattice == "D2Q9" else DUCT_FACES
+    name = f"suspension{len(bodies)}_{lattice.lower()}_{storage}_{nx}x{ny}" + (f"x{nz}" if lattice == "D3Q19" else "")
+    return dict(name=name, lattice=lattice, nx=nx, ny=ny, nz=nz if lattice == "D3Q19" else 1, tau=0.6, rho0=1.0,
+                eq="bgk", faces=faces, inlet_profile="parabolic", inlet_u=0.04, storage=storage, rho_noise=0.0,
+                seed=seed, steps=2000, bodies=bodies)
+
+
+def sedimenting(nx, ny, shape, axes, c0, ratio, g, storage="f64", tau=0.6, theta0=0.0, me="lattice",
+                integrator="euler", refill="mean", eq="bgk", bc="mls"):
+    """A free body released from rest in a closed vertical channel of fluid at
+    rest (the set-up of the paper's Sec. IV sedimentation tests): halfway
+    walls on every face, gravity g along -y; mass ratio*rho0*area (per unit
+    depth), inertia of a uniform disc/ellipse, external force weight minus
+    buoyancy, (ratio - 1) rho0 area g."""
+    a = axes[0]
+    b = axes[1] if shape == "ellipse" else a
+    area = math.pi * a * b
+    M = ratio * area
+    inertia = M * (a * a + b * b) / 4.0
+    return dict(name=f"sedimenting_{shape}_{storage}_{nx}x{ny}", lattice="D2Q9", nx=nx, ny=ny, nz=1, tau=tau, rho0=1.0,
+                eq=eq, faces=CLOSED_FACES, inlet_profile="uniform", inlet_u=0.0, storage=storage, rho_noise=0.0,
+                seed=0, steps=20000,
+                bodies=[dict(shape=shape, axes=tuple(axes), bc=bc, me=me, motion="free", c0=tuple(c0), theta0=theta0,
+                             mass=M, inertia=inertia, ext_force=(0.0, -(ratio - 1.0) * area * g, 0.0),
+                             integrator=integrator, refill=refill)])
+
+
+def _paper_units(width_m, nx, tau=0.6, nu=1e-6, gravity=9.81):
+    """lattice spacing, time step and gravity of a channel of width_m metres
+    resolved by nx nodes (walls half way out of the first and last), at the
+    given tau and kinematic viscosity"""
+    dx = width_m / (nx - 1)
+    dt = ((tau - 0.5) / 3.0) * dx * dx / nu
+    return dx, dt, gravity * dt * dt / dx
+
+
+def sedimenting_disc(ratio=1.01, storage="f32", me="lattice", integrator="euler", refill="mean"):
+    """The paper's sedimenting disc: d = 1e-3 m, W = 4d, H = 8W on 135 x 1073
+    nodes (dx = W/134), tau = 0.6, water (nu = 1e-6 m^2/s), released from rest
+    at x = 7.6e-4 m from the left wall (reading of the printed position),
+    2.5e-2 m above the bottom; density ratio 1.01 or 1.03."""
+    dx, dt, g = _paper_units(4e-3, 135)
+    R = 0.5e-3 / dx
+    w = sedimenting(135, 1073, "circle", (R,), (7.6e-4 / dx, 2.5e-2 / dx, 0.0), ratio, g, storage=storage, me=me,
+                    integrator=integrator, refill=refill)
+    w["name"] = f"sedimenting_disc_r{ratio}_{storage}_135x1073"
+    w["dt_s"], w["dx_m"] = dt, dx
+    return w
+
+
+def sedimenting_ellipse(ratio=1.1, storage="f32", me="lattice", integrator="euler", refill="mean"):
+    """The paper's sedimenting ellipse: major axis a = 1e-3 m, aspect ratio 2,
+    W = 4a, H = 50a on 135 x 1676 nodes, tau = 0.6, water, released from rest
+    at the channel centre 4.8e-2 m above the bottom at theta0 = pi/4, density
+    ratio 1.1 (semi-axes a/2 and a/4)."""
+    dx, dt, g = _paper_units(4e-3, 135)
+    A = 0.5e-3 / dx
+    w = sedimenting(135, 1676, "ellipse", (A, A / 2.0), (2e-3 / dx, 4.8e-2 / dx, 0.0), ratio, g, storage=storage,
+                    theta0=math.pi / 4, me=me, integrator=integrator, refill=refill)
+    w["name"] = f"sedimenting_ellipse_r{ratio}_{storage}_135x1676"
+    w["dt_s"], w["dx_m"] = dt, dx
+    return w
 
 
 def with_changes(w, **kw):

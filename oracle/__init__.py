@@ -21,13 +21,17 @@ SOURCES = [os.path.join(HERE, "lbm_oracle.c")]
 D2Q9, D3Q19 = 0, 1
 EQ_BGK, EQ_HELUO = 0, 1
 FACE_PERIODIC, FACE_WALL, FACE_INLET, FACE_OUTLET, FACE_OUTLET_VELOCITY = 0, 1, 2, 3, 4
+FACE_ZOUHE_VELOCITY, FACE_ZOUHE_PRESSURE = 5, 6
 PROFILE_UNIFORM, PROFILE_PARABOLIC = 0, 1
 SHAPE_CIRCLE, SHAPE_ELLIPSE, SHAPE_OUTER_CIRCLE = 0, 1, 2
 BC_HALFWAY, BC_MLS = 0, 1
-MOTION_STATIC, MOTION_CONST_VEL, MOTION_ROTATE, MOTION_OSCILLATE, MOTION_TABLE = 0, 1, 2, 3, 4
+MOTION_STATIC, MOTION_CONST_VEL, MOTION_ROTATE, MOTION_OSCILLATE, MOTION_TABLE, MOTION_FREE = 0, 1, 2, 3, 4, 5
+DRIVE_STATIC, DRIVE_LATTICE, DRIVE_COMOVING = 0, 1, 2
+INTEGRATOR_EULER, INTEGRATOR_AB2 = 0, 1
+REFILL_MEAN, REFILL_AIDUN, REFILL_EXTRAPOLATE = 0, 1, 2
 REC_LEN = 20
 FACE_REC_LEN = 18
-MAX_BODIES = 4
+MAX_BODIES = 64
 
 
 def compile_c(sources, out_path) -> str:
@@ -59,7 +63,9 @@ class _Body(C.Structure):
                 ("motion", C.c_int32), ("c0", C.c_double * 3), ("theta0", C.c_double),
                 ("vel", C.c_double * 3), ("omega", C.c_double), ("amp", C.c_double * 3),
                 ("period", C.c_double), ("table", C.POINTER(C.c_double)),
-                ("table_count", C.c_int64)]
+                ("table_count", C.c_int64), ("mass", C.c_double), ("inertia", C.c_double),
+                ("ext_force", C.c_double * 3), ("ext_torque", C.c_double), ("drive", C.c_int32),
+                ("integrator", C.c_int32), ("refill", C.c_int32)]
 
 
 _lib = None
@@ -167,8 +173,14 @@ class OracleDomain:
             pass
 
     def set_body(self, body_id, shape, axes, bc=BC_HALFWAY, motion=MOTION_STATIC, c0=(0, 0, 0),
-                 theta0=0.0, vel=(0, 0, 0), omega=0.0, amp=(0, 0, 0), period=1.0, table=None):
+                 theta0=0.0, vel=(0, 0, 0), omega=0.0, amp=(0, 0, 0), period=1.0, table=None,
+                 mass=0.0, inertia=0.0, ext_force=(0, 0, 0), ext_torque=0.0, drive=DRIVE_STATIC,
+                 integrator=INTEGRATOR_EULER, refill=REFILL_MEAN):
         b = _Body()
+        b.mass, b.inertia, b.ext_torque = mass, inertia, ext_torque
+        for a in range(3):
+            b.ext_force[a] = ext_force[a] if a < len(ext_force) else 0.0
+        b.drive, b.integrator, b.refill = drive, integrator, refill
         b.shape = shape
         ax = list(axes) + [0.0] * (3 - len(axes))
         for a in range(3):

@@ -90,12 +90,60 @@ typedef struct {
   ora_body_desc d;
   double* table; /* owned copy of a TABLE motion */
   double ia2, ib2, ic2;
+  /* FREE motion: poses of steps traj_t0 .. traj_t0 + traj_n - 1, and the
+     previous step's accelerations (linear, angular) for Adams-Bashforth */
+  pose_t* traj;
+  int64_t traj_t0, traj_n, traj_cap;
+  double a_prev[4];
+  int have_prev;
 } body_t;
+
+/* cos and sin of theta for FREE bodies, whose angle the simulation
+ * produces: Cody-Waite reduction by pi/2 (the double nearest pi/2 plus its
+ * remainder) to |r| <= pi/4, then the Taylor series of sin and cos through
+ * r^17 / 17! and r^18 / 18! (truncation below 1e-19 there) in Horner form.
+ * Every operation is a plain IEEE double operation in a fixed order, so the
+ * GPU library, which evaluates the same steps, gets the same bits. */
+static void free_trig(double theta, double* c, double* s) {
+  const double k = nearbyint(theta * 0.63661977236758134);
+  const double r = (theta - k * 1.5707963267948966) - k * 6.123233995736766e-17;
+  const double z = r * r;
+  double ps = 1.0 / 355687428096000.0;
+  ps = -1.0 / 1307674368000.0 + z * ps;
+  ps = 1.0 / 6227020800.0 + z * ps;
+  ps = -1.0 / 39916800.0 + z * ps;
+  ps = 1.0 / 362880.0 + z * ps;
+  ps = -1.0 / 5040.0 + z * ps;
+  ps = 1.0 / 120.0 + z * ps;
+  ps = -1.0 / 6.0 + z * ps;
+  const double sr = r + (r * z) * ps;
+  double pc = 1.0 / 6402373705728000.0;
+  pc = -1.0 / 20922789888000.0 + z * pc;
+  pc = 1.0 / 87178291200.0 + z * pc;
+  pc = -1.0 / 479001600.0 + z * pc;
+  pc = 1.0 / 3628800.0 + z * pc;
+  pc = -1.0 / 40320.0 + z * pc;
+  pc = 1.0 / 720.0 + z * pc;
+  pc = -1.0 / 24.0 + z * pc;
+  pc = 0.5 + z * pc;
+  const double cr = 1.0 - z * pc;
+  const long q = ((long)k) & 3;
+  if (q == 0) { *c = cr; *s = sr; }
+  else if (q == 1) { *c = -sr; *s = cr; }
+  else if (q == 2) { *c = -cr; *s = -sr; }
+  else { *c = sr; *s = -cr; }
+}
 
 static pose_t body_pose(const body_t* b, int64_t t) {
   pose_t p;
   memset(&p, 0, sizeof(p));
   const ora_body_desc* d = &b->d;
+  if (d->motion == ORA_MOTION_FREE) {
+    int64_t k = t - b->traj_t0;
+    if (k < 0) k = 0;
+    if (k >= b->traj_n) k = b->traj_n - 1;
+    return b->traj[k];
+  }
   for (int a = 0; a < 3; ++a) p.X[a] = d->c0[a];
   p.theta = d->theta0;
   switch (d->motion) {
@@ -209,7 +257,7 @@ static void surface_velocity(const pose_t* p, const double x[3], double u[3]) {
 /* Domain */
 
 enum { T_FLUID = 0, T_WALL = 1, T_BODY0 = 2 };
-enum { S_INLET = -2, S_OUTLET = -3, S_OUTLET_VEL = -4 };
+enum { S_INLET = -2, S_OUTLET = -3, S_OUTLET_VEL = -4, S_ZOUHE = -5 };
 
 struct ora_dom {
   lattice_t L;
@@ -252,8 +300,11 @@ static int classify(const ora_dom* d, int q[3], int64_t* n) {
     if (d->face[2 * a] == ORA_FACE_WALL && q[a] <= 0) return T_WALL;
     if (d->face[2 * a + 1] == ORA_FACE_WALL && q[a] >= dims[a] - 1) return T_WALL;
   }
-  if (q[0] < 0) return S_INLET;
-  if (q[0] >= d->nx) return d->face[1] == ORA_FACE_OUTLET_VELOCITY ? S_OUTLET_VEL : S_OUTLET;
+  if (q[0] < 0) return d->face[0] >= ORA_FACE_ZOUHE_VELOCITY ? S_ZOUHE : S_INLET;
+  if (q[0] >= d->nx) {
+    if (d->face[1] >= ORA_FACE_ZOUHE_VELOCITY) return S_ZOUHE;
+    return d->face[1] == ORA_FACE_OUTLET_VELOCITY ? S_OUTLET_VEL : S_OUTLET;
+  }
   *n = node_index(d, q[0], q[1], q[2]);
   return d->type[*n];
 }
@@ -296,7 +347,9 @@ static int check_faces(const ora_desc* ds) {
   for (int a = 0; a < 3; ++a) {
     int lo = ds->face[2 * a], hi = ds->face[2 * a + 1];
     if (a >= D) continue;
+    if (lo < 0 || lo > ORA_FACE_ZOUHE_PRESSURE || hi < 0 || hi > ORA_FACE_ZOUHE_PRESSURE) return -1;
     if ((lo == ORA_FACE_PERIODIC) != (hi == ORA_FACE_PERIODIC)) return -1;
+    if (a > 0 && (lo >= ORA_FACE_ZOUHE_VELOCITY || hi >= ORA_FACE_ZOUHE_VELOCITY)) return -1;
     if (lo == ORA_FACE_OUTLET || lo == ORA_FACE_OUTLET_VELOCITY || hi == ORA_FACE_INLET) return -1;
     if (a > 0 && (lo == ORA_FACE_INLET || hi == ORA_FACE_OUTLET || hi == ORA_FACE_OUTLET_VELOCITY)) return -1;
   }
@@ -365,6 +418,7 @@ void ora_destroy(ora_dom* d) {
   free(d->solid_new);
   for (int b = 0; b < ORA_MAX_BODIES; ++b) {
     free(d->body[b].table);
+    free(d->body[b].traj);
     free(d->rec[b]);
   }
   free(d->face_rec);
@@ -396,6 +450,7 @@ static int ensure_records(ora_dom* d, int64_t upto) {
   int64_t cap = d->rec_cap ? d->rec_cap : 1024;
   while (cap < upto) cap *= 2;
   for (int b = 0; b < ORA_MAX_BODIES; ++b) {
+    if (!d->body[b].active) continue; /* allocated when the body is placed */
     double* r = (double*)realloc(d->rec[b], sizeof(double) * ORA_REC_LEN * cap);
     if (!r) return -1;
     memset(r + ORA_REC_LEN * d->rec_cap, 0, sizeof(double) * ORA_REC_LEN * (cap - d->rec_cap));
@@ -421,10 +476,34 @@ int ora_set_body(ora_dom* d, int id, const ora_body_desc* bd) {
     memcpy(b->table, bd->table, sizeof(double) * 8 * bd->table_count);
   }
   b->d.table = NULL;
+  b->traj = NULL;
+  b->traj_n = b->traj_cap = 0;
+  b->have_prev = 0;
+  if (bd->motion == ORA_MOTION_FREE) {
+    if (!(bd->mass > 0.0) || !(bd->inertia > 0.0)) return -1;
+    b->traj_cap = 1024;
+    b->traj = (pose_t*)calloc((size_t)b->traj_cap, sizeof(pose_t));
+    if (!b->traj) return -1;
+    pose_t* p0 = &b->traj[0];
+    for (int a = 0; a < 3; ++a) {
+      p0->X[a] = bd->c0[a];
+      p0->V[a] = bd->vel[a];
+    }
+    if (d->L.D == 2) p0->X[2] = p0->V[2] = 0.0;
+    p0->theta = bd->theta0;
+    p0->Om = bd->omega;
+    free_trig(p0->theta, &p0->ct, &p0->st);
+    b->traj_t0 = d->t;
+    b->traj_n = 1;
+  }
   b->ia2 = 1.0 / (bd->axes[0] * bd->axes[0]);
   b->ib2 = 1.0 / (bd->axes[1] * bd->axes[1]);
   b->ic2 = (d->L.D == 3) ? 1.0 / (bd->axes[2] * bd->axes[2]) : 0.0;
   b->active = 1;
+  if (d->rec_cap > 0) {
+    d->rec[id] = (double*)calloc((size_t)ORA_REC_LEN * d->rec_cap, sizeof(double));
+    if (!d->rec[id]) return -1;
+  }
   pose_t p = body_pose(b, d->t);
   for (int64_t n = 0; n < d->N; ++n) {
     if (d->type[n] != T_FLUID) continue;
@@ -512,6 +591,94 @@ static double body_link_value(const ora_dom* d, const body_t* b, const pose_t* p
   return (1.0 - chi) * fin + chi * g + wall;
 }
 
+/* The refill of Lallemand & Luo for a node x that a moving body uncovers:
+ * every population by quadratic extrapolation along the lattice direction c
+ * closest to the body's outward normal at x, f_i(x) = 3 f_i(x + c) -
+ * 3 f_i(x + 2c) + f_i(x + 3c), from nodes fluid at t and at t+1 (values of
+ * t+1 after streaming). The normal is the gradient of the shape function
+ * phi at x (pose t+1), n = (dx, dy, dz) for a circle/sphere, (xi ct ia2 -
+ * eta st ib2, xi st ia2 + eta ct ib2, dz ic2) for an ellipse/ellipsoid; the
+ * direction maximises (n . c) / |c| (ties: the smallest (cx, cy, cz) in
+ * lexicographic order). Returns 0, leaving x alone, when one of the three
+ * nodes is not fluid at both times or lies outside the box (the caller then
+ * applies the mean rule). */
+static int refill_extrapolate(ora_dom* d, const body_t* b, const pose_t* P, const int p[3], int64_t n) {
+  const lattice_t* L = &d->L;
+  const int Q = L->Q, D = L->D;
+  const double dx = p[0] - P->X[0], dy = p[1] - P->X[1], dz = D == 3 ? p[2] - P->X[2] : 0.0;
+  double nv[3];
+  if (b->d.shape == ORA_SHAPE_ELLIPSE) {
+    const double xi = P->ct * dx + P->st * dy, eta = P->ct * dy - P->st * dx;
+    nv[0] = xi * P->ct * b->ia2 - eta * P->st * b->ib2;
+    nv[1] = xi * P->st * b->ia2 + eta * P->ct * b->ib2;
+    nv[2] = dz * b->ic2;
+  } else {
+    const double sgn = b->d.shape == ORA_SHAPE_OUTER_CIRCLE ? -1.0 : 1.0;
+    nv[0] = sgn * dx;
+    nv[1] = sgn * dy;
+    nv[2] = sgn * dz;
+  }
+  int best = -1;
+  double best_s = 0.0;
+  for (int i = 1; i < Q; ++i) {
+    const int* c = L->c[i];
+    const int diag = c[0] * c[0] + c[1] * c[1] + c[2] * c[2] == 2;
+    const double sc = (nv[0] * c[0] + nv[1] * c[1] + nv[2] * c[2]) * (diag ? 0.70710678118654757 : 1.0);
+    if (best < 0 || sc > best_s) {
+      best = i;
+      best_s = sc;
+    } else if (sc == best_s) {
+      const int* cb = L->c[best];
+      if (c[0] < cb[0] || (c[0] == cb[0] && (c[1] < cb[1] || (c[1] == cb[1] && c[2] < cb[2])))) best = i;
+    }
+  }
+  int64_t m[3];
+  const int dims[3] = {d->nx, d->ny, d->nz};
+  for (int k = 1; k <= 3; ++k) {
+    int q[3] = {p[0] + k * L->c[best][0], p[1] + k * L->c[best][1], p[2] + k * L->c[best][2]};
+    /* reading: the three nodes lie in the box itself (no periodic wrap) */
+    for (int a = 0; a < D; ++a)
+      if (q[a] < 0 || q[a] >= dims[a]) return 0;
+    if (classify(d, q, &m[k - 1]) != T_FLUID || d->solid_new[m[k - 1]] != 0) return 0;
+  }
+  for (int i = 0; i < Q; ++i)
+    d->fnew[n * Q + i] = (3.0 * d->fnew[m[0] * Q + i] - 3.0 * d->fnew[m[1] * Q + i]) + d->fnew[m[2] * Q + i];
+  return 1;
+}
+
+/* Newton-Euler step of a FREE body (Sec. IV: the flow force plus weight and
+ * buoyancy move the body; forward Euler, or two-step Adams-Bashforth):
+ * a = (F + F_ext) / M and alpha = (T_z + T_ext) / I from the flow force
+ * and torque of step t, then V(t+1) = V(t) + a (AB2: + 3/2 a(t) - 1/2 a(t-1),
+ * the first step Euler), X(t+1) = X(t) + V(t+1), and likewise Omega and
+ * theta about z (reading: the position takes the new velocity, which makes
+ * the covered/uncovered sets of step t depend on the force of step t, the
+ * implicit case of Sec. III.B.3; the lattice-frame drive then takes the
+ * approximation of Aidun et al., the sets of the previous step, i.e.
+ * F(t) = F_static(t) + [covered/uncovered terms of step t-1]). Lattice
+ * units: dt = 1. */
+static pose_t integrate_free(body_t* b, const pose_t* P, const double F[3], double Tz, int D) {
+  const ora_body_desc* bd = &b->d;
+  double a[4];
+  for (int k = 0; k < 3; ++k) a[k] = (F[k] + bd->ext_force[k]) / bd->mass;
+  a[3] = (Tz + bd->ext_torque) / bd->inertia;
+  if (D == 2) a[2] = 0.0;
+  double dv[4];
+  for (int k = 0; k < 4; ++k)
+    dv[k] = (bd->integrator == ORA_INTEGRATOR_AB2 && b->have_prev) ? 1.5 * a[k] - 0.5 * b->a_prev[k] : a[k];
+  pose_t q = *P;
+  for (int k = 0; k < 3; ++k) {
+    q.V[k] = P->V[k] + dv[k];
+    q.X[k] = P->X[k] + q.V[k];
+  }
+  q.Om = P->Om + dv[3];
+  q.theta = P->theta + q.Om;
+  free_trig(q.theta, &q.ct, &q.st);
+  for (int k = 0; k < 4; ++k) b->a_prev[k] = a[k];
+  b->have_prev = 1;
+  return q;
+}
+
 static void one_step(ora_dom* d) {
   const lattice_t* L = &d->L;
   const int Q = L->Q, D = L->D;
@@ -524,7 +691,7 @@ static void one_step(ora_dom* d) {
       P1[b] = body_pose(&d->body[b], t + 1);
     }
   double* rec[ORA_MAX_BODIES];
-  for (int b = 0; b < ORA_MAX_BODIES; ++b) rec[b] = d->rec[b] + ORA_REC_LEN * t;
+  for (int b = 0; b < ORA_MAX_BODIES; ++b) rec[b] = d->body[b].active ? d->rec[b] + ORA_REC_LEN * t : NULL;
   double* frec = d->face_rec + ORA_FACE_REC_LEN * t;
 
   /* 1. moments and collision on fluid nodes, Eq. collision */
@@ -575,7 +742,7 @@ static void one_step(ora_dom* d) {
       int q[3] = {p[0] - ci[0], p[1] - ci[1], p[2] - ci[2]};
       int64_t m = -1;
       int s = classify(d, q, &m);
-      if (s == T_FLUID) continue;
+      if (s == T_FLUID || s == S_ZOUHE) continue; /* Zou-He: supplied in step 3b */
       double fin = d->fpost[n * Q + L->opp[i]]; /* post-collision population heading across the link */
       double fbc;
       double xF[3] = {p[0], p[1], p[2]};
@@ -624,14 +791,108 @@ static void one_step(ora_dom* d) {
     }
   }
 
+  /* 3b. Zou-He faces (the boundary method the paper's Sec. IV names for its
+   *     faces): at a fluid node of the x = 0 (x = nx-1) plane, every
+   *     population with c_ix = +1 (-1) enters through the face and is
+   *     rebuilt from the node's other populations, replacing what step 3 put
+   *     there. The node is given u = (u_in, 0, 0) (velocity face; u_in the
+   *     inlet profile at the node) or rho = rho0 with u_y = u_z = 0
+   *     (pressure face); mass and x-momentum give the missing one. The
+   *     normal population takes the bounce-back of its non-equilibrium part,
+   *     f_i = f_ibar + f^eq_i - f^eq_ibar; each other unknown additionally
+   *     takes -c_ia N_a per transverse axis a, with N_a solved from the
+   *     node's a-momentum being rho_u u_a. Face momentum exchange is not
+   *     recorded for these faces. */
+  for (int side = 0; side < 2; ++side) {
+    if (d->face[side] < ORA_FACE_ZOUHE_VELOCITY) continue;
+    const int sgn = side == 0 ? 1 : -1, x = side == 0 ? 0 : d->nx - 1;
+    for (int z = 0; z < d->nz; ++z)
+      for (int y = 0; y < d->ny; ++y) {
+        int64_t n = node_index(d, x, y, z);
+        if (d->type[n] != T_FLUID) continue;
+        double* fn = d->fnew + n * Q;
+        int known[32];
+        for (int i = 0; i < Q; ++i) known[i] = L->c[i][0] != sgn;
+        /* sums over the known populations */
+        double K = 0.0, Kx = 0.0;
+        for (int i = 0; i < Q; ++i)
+          if (known[i]) {
+            K += fn[i];
+            Kx += L->c[i][0] * fn[i];
+          }
+        /* rho = K + U and j_x = Kx + sgn U, U the sum of the unknowns */
+        double rho, u[3] = {0.0, 0.0, 0.0};
+        if (d->face[side] == ORA_FACE_ZOUHE_VELOCITY) {
+          double xn[3] = {x, y, z};
+          u[0] = inlet_speed(d, xn);
+          if (d->eq == ORA_EQ_HELUO) rho = K + sgn * (d->rho0 * u[0] - Kx);  /* j_x = rho0 u_x */
+          else rho = (K - sgn * Kx) / (1.0 - sgn * u[0]);                    /* j_x = rho u_x */
+        } else {
+          rho = d->rho0;
+          double jx = Kx + sgn * (rho - K);
+          u[0] = jx / (d->eq == ORA_EQ_HELUO ? d->rho0 : rho);
+        }
+        for (int i = 0; i < Q; ++i)
+          if (!known[i]) {
+            int ib = L->opp[i];
+            fn[i] = fn[ib] + feq_i(d, i, rho, u) - feq_i(d, ib, rho, u);
+          }
+        const double rho_u = d->eq == ORA_EQ_HELUO ? d->rho0 : rho;
+        for (int a = 1; a < D; ++a) {
+          double ja = 0.0, cc = 0.0;
+          for (int i = 0; i < Q; ++i) {
+            ja += L->c[i][a] * fn[i];
+            if (!known[i]) cc += L->c[i][a] * L->c[i][a];
+          }
+          double N = (ja - rho_u * u[a]) / cc;
+          for (int i = 0; i < Q; ++i)
+            if (!known[i]) fn[i] -= L->c[i][a] * N;
+        }
+      }
+  }
+
+  /* 3c. FREE bodies: the pose of t+1 from the flow force of step t */
+  for (int b = 0; b < ORA_MAX_BODIES; ++b) {
+    body_t* B = &d->body[b];
+    if (!B->active || B->d.motion != ORA_MOTION_FREE) continue;
+    double F[3], Tz;
+    if (B->d.drive == ORA_DRIVE_COMOVING) {
+      for (int a = 0; a < 3; ++a) F[a] = rec[b][ORA_REC_F_COM + a];
+      Tz = rec[b][ORA_REC_T_COM + 2];
+    } else {
+      for (int a = 0; a < 3; ++a) F[a] = rec[b][ORA_REC_F_STATIC + a];
+      Tz = rec[b][ORA_REC_T_STATIC + 2];
+      if (B->d.drive == ORA_DRIVE_LATTICE && t - 1 >= B->traj_t0) {
+        const double* prev = d->rec[b] + ORA_REC_LEN * (t - 1);
+        for (int a = 0; a < 3; ++a) F[a] += prev[ORA_REC_F_IMP + a];
+        Tz += prev[ORA_REC_T_IMP + 2];
+      }
+    }
+    if (B->traj_n == B->traj_cap) {
+      pose_t* nt = (pose_t*)realloc(B->traj, sizeof(pose_t) * (size_t)(2 * B->traj_cap));
+      if (!nt) {
+        d->error = 5;
+        return;
+      }
+      B->traj = nt;
+      B->traj_cap *= 2;
+    }
+    P1[b] = integrate_free(B, &P0[b], F, Tz, D);
+    B->traj[B->traj_n++] = P1[b];
+  }
+
   /* 4. moving bodies: covered nodes A+ (fluid at t, solid at t+1) and
    *    uncovered nodes A- (solid at t, fluid at t+1), Sec. III.B.3, taken
    *    forward in time (pose t -> pose t+1; explicit for prescribed motion).
-   *    Uncovered nodes are refilled with the equilibrium at the mean density
-   *    and mean velocity of their lattice neighbours that are fluid at both
-   *    t and t+1 (the paper's third refill rule; reading: unweighted means of
-   *    their t+1 moments; with no such neighbour, rho0 and the surface
-   *    velocity). The impulsive terms of Eqs. ForceInMovement and
+   *    Uncovered nodes are refilled by the body's rule (Sec. III.B.3 names
+   *    three): MEAN, the equilibrium at the mean density and mean velocity
+   *    of their lattice neighbours that are fluid at both t and t+1 (the
+   *    paper's own rule; reading: unweighted means of their t+1 moments;
+   *    with no such neighbour, rho0 and the surface velocity); AIDUN, the
+   *    equilibrium at that mean density and the surface velocity at the node
+   *    (reading of Aidun et al.'s rule); EXTRAPOLATE, Lallemand & Luo's
+   *    extrapolation (refill_extrapolate; MEAN where it cannot apply). The
+   *    impulsive terms of Eqs. ForceInMovement and
    *    TorqueInMovement are + sum_{A+} c_i f_i(t+1) - sum_{A-} c_i f_i(t+1),
    *    with the lever arm about the body centre X_c(t). */
   memset(d->solid_new, 0, (size_t)N);
@@ -680,17 +941,21 @@ static void one_step(ora_dom* d) {
             for (int a = 0; a < 3; ++a) us[a] += u[a];
             cnt++;
           }
-          double rb, ub[3];
-          if (cnt > 0) {
-            rb = rs / cnt;
-            for (int a = 0; a < 3; ++a) ub[a] = us[a] / cnt;
-          } else {
+          const int rule = d->body[b].d.refill;
+          if (rule != ORA_REFILL_EXTRAPOLATE || !refill_extrapolate(d, &d->body[b], &P1[b], p, n)) {
+            double rb, ub[3];
             double x[3] = {p[0], p[1], p[2]};
-            rb = d->rho0;
-            surface_velocity(&P1[b], x, ub);
+            if (cnt > 0) {
+              rb = rs / cnt;
+              for (int a = 0; a < 3; ++a) ub[a] = us[a] / cnt;
+            } else {
+              rb = d->rho0;
+              surface_velocity(&P1[b], x, ub);
+            }
+            if (rule == ORA_REFILL_AIDUN) surface_velocity(&P1[b], x, ub);
+            if (D == 2) ub[2] = 0.0;
+            for (int i = 0; i < Q; ++i) d->fnew[n * Q + i] = feq_i(d, i, rb, ub);
           }
-          if (D == 2) ub[2] = 0.0;
-          for (int i = 0; i < Q; ++i) d->fnew[n * Q + i] = feq_i(d, i, rb, ub);
           double r[3] = {p[0] - P0[b].X[0], p[1] - P0[b].X[1], p[2] - P0[b].X[2]};
           double mom[3] = {0, 0, 0}, tq[3];
           for (int i = 0; i < Q; ++i)
@@ -738,7 +1003,8 @@ int ora_step(ora_dom* d, int64_t nsteps) {
 }
 
 int ora_body_records(const ora_dom* d, int b, int64_t first, int64_t count, double* out) {
-  if (!d || b < 0 || b >= ORA_MAX_BODIES || first < 0 || first + count > d->t) return -1;
+  if (!d || b < 0 || b >= ORA_MAX_BODIES || !d->body[b].active || first < 0 || first + count > d->t) return -1;
+  if (count == 0) return 0;
   memcpy(out, d->rec[b] + ORA_REC_LEN * first, sizeof(double) * ORA_REC_LEN * count);
   return 0;
 }
@@ -776,6 +1042,8 @@ int64_t ora_links(const ora_dom* d, int b, int64_t cap, int64_t* node, int32_t* 
 
 int ora_body_pose(const ora_dom* d, int b, int64_t t, double* out) {
   if (!d || b < 0 || b >= ORA_MAX_BODIES || !d->body[b].active || t < 0) return -1;
+  const body_t* B = &d->body[b];
+  if (B->d.motion == ORA_MOTION_FREE && (t < B->traj_t0 || t >= B->traj_t0 + B->traj_n)) return -1;
   pose_t p = body_pose(&d->body[b], t);
   for (int a = 0; a < 3; ++a) out[a] = p.X[a];
   out[3] = p.theta;

@@ -22,14 +22,20 @@ extern "C" {
 enum { ORA_D2Q9 = 0, ORA_D3Q19 = 1 };
 enum { ORA_EQ_BGK = 0, ORA_EQ_HELUO = 1 };
 enum { ORA_FACE_PERIODIC = 0, ORA_FACE_WALL = 1, ORA_FACE_INLET = 2, ORA_FACE_OUTLET = 3,
-       ORA_FACE_OUTLET_VELOCITY = 4 };
+       ORA_FACE_OUTLET_VELOCITY = 4, ORA_FACE_ZOUHE_VELOCITY = 5, ORA_FACE_ZOUHE_PRESSURE = 6 };
 enum { ORA_PROFILE_UNIFORM = 0, ORA_PROFILE_PARABOLIC = 1 };
 enum { ORA_SHAPE_CIRCLE = 0, ORA_SHAPE_ELLIPSE = 1, ORA_SHAPE_OUTER_CIRCLE = 2 };
 enum { ORA_BC_HALFWAY = 0, ORA_BC_MLS = 1 };
 enum { ORA_MOTION_STATIC = 0, ORA_MOTION_CONST_VEL = 1, ORA_MOTION_ROTATE = 2,
-       ORA_MOTION_OSCILLATE = 3, ORA_MOTION_TABLE = 4 };
+       ORA_MOTION_OSCILLATE = 3, ORA_MOTION_TABLE = 4, ORA_MOTION_FREE = 5 };
+/* which flow force moves a FREE body (the ME forms the paper compares in
+   its Sec. IV sedimentation tests) */
+enum { ORA_DRIVE_STATIC = 0, ORA_DRIVE_LATTICE = 1, ORA_DRIVE_COMOVING = 2 };
+enum { ORA_INTEGRATOR_EULER = 0, ORA_INTEGRATOR_AB2 = 1 };
+/* value given to the nodes a moving body uncovers */
+enum { ORA_REFILL_MEAN = 0, ORA_REFILL_AIDUN = 1, ORA_REFILL_EXTRAPOLATE = 2 };
 
-#define ORA_MAX_BODIES 4
+#define ORA_MAX_BODIES 64
 /* per-step record of one body: see ORA_REC_* offsets */
 #define ORA_REC_LEN 20
 #define ORA_REC_F_STATIC 0   /* Eq. flow_force_2 */
@@ -66,6 +72,13 @@ typedef struct {
   double amp[3], period;    /* OSCILLATE: X(t) = c0 + amp*sin(2*pi*t/period) */
   const double* table;      /* TABLE: 8 doubles per step: X[3], theta, V[3], Omega_z */
   int64_t table_count;
+  /* FREE: Newton-Euler motion under the flow force plus a constant external
+     force/torque, from X = c0, theta = theta0, V = vel, Omega = omega */
+  double mass, inertia;     /* inertia about the z axis through X */
+  double ext_force[3], ext_torque;
+  int32_t drive;            /* ORA_DRIVE_* */
+  int32_t integrator;       /* ORA_INTEGRATOR_* */
+  int32_t refill;           /* ORA_REFILL_* (every moving body) */
 } ora_body_desc;
 
 typedef struct ora_dom ora_dom;
@@ -87,8 +100,9 @@ int ora_face_records(const ora_dom* dom, int64_t first, int64_t count, double* r
    node index = x + nx*(y + ny*z). Returns the count; writes at most cap entries. */
 int64_t ora_links(const ora_dom* dom, int body_id, int64_t cap, int64_t* node, int32_t* dir, double* delta);
 
-/* prescribed pose of body `body_id` at step t (the one the step of time t
-   uses): out = X[3], theta, V[3], Omega_z */
+/* pose of body `body_id` at step t (the one the step of time t uses; for a
+   FREE body t <= the current step + 1 once that step ran): out = X[3],
+   theta, V[3], Omega_z */
 int ora_body_pose(const ora_dom* dom, int body_id, int64_t t, double* out);
 
 /* node type: 0 fluid, 1 wall layer, 2+b body b */

@@ -146,7 +146,7 @@ BatchBody batch_body(lbm_domain d, int member, int id) {
   bb.mask = d->mask;
   bb.rec = d->rec + id * LBM_REC_LEN;
   bb.rec_cap = d->rec_cap;
-  bb.rec_stride = LBM_MAX_BODIES * LBM_REC_LEN;
+  bb.rec_stride = (int64_t)d->nslots * LBM_REC_LEN;
   bb.partials = b.partials;
   bb.counter = d->counters + id;
   bb.err = d->err;
@@ -159,7 +159,7 @@ BatchBody batch_body(lbm_domain d, int member, int id) {
 lbm_status make_plan(lbm_batch B, int64_t n, Plan& P) {
   const auto& m = B->members;
   for (lbm_domain d : m)
-    for (int id = 0; id < LBM_MAX_BODIES; ++id) {
+    for (int id = 0; id < d->nslots; ++id) {
       Body& b = d->body[id];
       if (!b.active) continue;
       lbm_status s = ensure_poses(d, b, d->t, d->t + n);
@@ -186,7 +186,7 @@ lbm_status make_plan(lbm_batch B, int64_t n, Plan& P) {
       }
     }
     P.doms.push_back(bd);
-    for (int id = 0; id < LBM_MAX_BODIES; ++id) {
+    for (int id = 0; id < d->nslots; ++id) {
       Body& b = d->body[id];
       if (!b.active) continue;
       BatchBody bb = batch_body(d, (int)i, id);

@@ -45,6 +45,13 @@ struct Body {
   int ring_chunks = 0;
   int64_t part_t0 = 0, part_n = 0;
   bool bc_ready = false;
+  // FREE motion: the device fills the pose window step by step; traj is a
+  // ring of 8 doubles (X, theta, V, Omega) per step of the record ring, dyn
+  // the previous accelerations and their flag (Adams-Bashforth)
+  bool free_motion = false;
+  double* traj = nullptr;
+  double* dyn = nullptr;
+  int64_t t_placed = 0;
 };
 
 }  // namespace host
@@ -69,6 +76,7 @@ struct lbm_domain_s {
   uint8_t* mask_next = nullptr;
   double* rec = nullptr;
   int64_t rec_cap = 0;
+  int nslots = 4;  // body slots (ids 0 .. nslots-1); records per ring step
   int* err = nullptr;
   unsigned* counters = nullptr;
   int64_t t = 0;

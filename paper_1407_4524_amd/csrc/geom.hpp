@@ -10,7 +10,8 @@
 
 namespace lbm {
 
-enum { FACE_PERIODIC = 0, FACE_WALL = 1, FACE_INLET = 2, FACE_OUTLET = 3, FACE_OUTLET_VELOCITY = 4 };
+enum { FACE_PERIODIC = 0, FACE_WALL = 1, FACE_INLET = 2, FACE_OUTLET = 3, FACE_OUTLET_VELOCITY = 4,
+       FACE_ZOUHE_VELOCITY = 5, FACE_ZOUHE_PRESSURE = 6 };
 enum { SRC_NONE = 0, SRC_WALL = 1, SRC_INLET = 2, SRC_OUTLET = 3, SRC_OUTVEL = 4 };
 enum { SHAPE_CIRCLE = 0, SHAPE_ELLIPSE = 1, SHAPE_OUTER_CIRCLE = 2 };
 enum { MASK_FLUID = 0, MASK_WALL = 1, MASK_BODY0 = 2 };
@@ -52,7 +53,94 @@ struct BodyShape {
   int shape, D;
   double R;              // radius (circle/sphere, outer circle)
   double ia2, ib2, ic2;  // 1/(a*a), 1/(b*b), 1/(c*c)
+  int refill;            // REFILL_* rule for the nodes the body uncovers
 };
+
+enum { REFILL_MEAN = 0, REFILL_AIDUN = 1, REFILL_EXTRAPOLATE = 2 };
+
+// cos and sin of the angle of a body whose motion the simulation computes
+// (include/lbm.h fixes the steps so that every evaluation gives the same
+// bits): reduction by pi/2 in two parts (Cody-Waite), then the Taylor series
+// of sin through r^17/17! and of cos through r^18/18! in Horner form.
+__host__ __device__ inline void free_trig(double theta, double& c, double& s) {
+#pragma clang fp contract(off)
+  const double k = rint(theta * 0.63661977236758134);
+  const double r = (theta - k * 1.5707963267948966) - k * 6.123233995736766e-17;
+  const double z = r * r;
+  double ps = 1.0 / 355687428096000.0;
+  ps = -1.0 / 1307674368000.0 + z * ps;
+  ps = 1.0 / 6227020800.0 + z * ps;
+  ps = -1.0 / 39916800.0 + z * ps;
+  ps = 1.0 / 362880.0 + z * ps;
+  ps = -1.0 / 5040.0 + z * ps;
+  ps = 1.0 / 120.0 + z * ps;
+  ps = -1.0 / 6.0 + z * ps;
+  const double sr = r + (r * z) * ps;
+  double pc = 1.0 / 6402373705728000.0;
+  pc = -1.0 / 20922789888000.0 + z * pc;
+  pc = 1.0 / 87178291200.0 + z * pc;
+  pc = -1.0 / 479001600.0 + z * pc;
+  pc = 1.0 / 3628800.0 + z * pc;
+  pc = -1.0 / 40320.0 + z * pc;
+  pc = 1.0 / 720.0 + z * pc;
+  pc = -1.0 / 24.0 + z * pc;
+  pc = 0.5 + z * pc;
+  const double cr = 1.0 - z * pc;
+  const long long q = ((long long)k) & 3;
+  c = q == 0 ? cr : (q == 1 ? -sr : (q == 2 ? -cr : sr));
+  s = q == 0 ? sr : (q == 1 ? cr : (q == 2 ? -sr : -cr));
+}
+
+// Outward normal (gradient of phi up to a factor 2) of the body at node
+// (x, y, z), the direction Lallemand & Luo's refill extrapolates along
+__host__ __device__ inline void shape_normal(const BodyShape& b, const Pose& p, double x, double y, double z,
+                                             double n[3]) {
+#pragma clang fp contract(off)
+  const double dx = x - p.X[0], dy = y - p.X[1], dz = b.D == 3 ? z - p.X[2] : 0.0;
+  if (b.shape == SHAPE_ELLIPSE) {
+    const double xi = p.ct * dx + p.st * dy, eta = p.ct * dy - p.st * dx;
+    n[0] = xi * p.ct * b.ia2 - eta * p.st * b.ib2;
+    n[1] = xi * p.st * b.ia2 + eta * p.ct * b.ib2;
+    n[2] = b.D == 3 ? dz * b.ic2 : 0.0;
+  } else {
+    const double sg = b.shape == SHAPE_OUTER_CIRCLE ? -1.0 : 1.0;
+    n[0] = sg * dx;
+    n[1] = sg * dy;
+    n[2] = sg * dz;
+  }
+}
+
+// Node box of a pose: the body plus two layers (links and their
+// neighbours); the whole active box for an outer circle. axes: radius or
+// semi-axes; lo, hi: the active index ranges of the domain.
+__host__ __device__ inline void pose_box(int shape, const double* axes, int D, const int* glo, const int* ghi,
+                                         Pose& p) {
+#pragma clang fp contract(off)
+  if (shape == SHAPE_OUTER_CIRCLE) {
+    for (int a = 0; a < 3; ++a) {
+      p.lo[a] = glo[a];
+      p.hi[a] = ghi[a];
+    }
+    return;
+  }
+  double h[3];
+  if (shape == SHAPE_CIRCLE) {
+    h[0] = h[1] = h[2] = axes[0];
+  } else {
+    const double a = axes[0], bb = axes[1];
+    h[0] = sqrt(a * a * p.ct * p.ct + bb * bb * p.st * p.st);
+    h[1] = sqrt(a * a * p.st * p.st + bb * bb * p.ct * p.ct);
+    h[2] = axes[2];
+  }
+  for (int a = 0; a < 3; ++a) {
+    if (a >= D) {
+      p.lo[a] = p.hi[a] = 0;
+      continue;
+    }
+    p.lo[a] = floor(p.X[a] - h[a]) - 2.0;
+    p.hi[a] = ceil(p.X[a] + h[a]) + 2.0;
+  }
+}
 
 __host__ __device__ inline double shape_phi(const BodyShape& b, const Pose& p, double x, double y, double z) {
 #pragma clang fp contract(off)

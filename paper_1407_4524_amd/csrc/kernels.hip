@@ -233,6 +233,63 @@ hipError_t launch_body_advance(int lat, int st, int eq, void* B, uint8_t* mask, 
   return hipGetLastError();
 }
 
+__global__ __launch_bounds__(64) void k_body_integrate(const double* __restrict__ rec_t,
+                                                       const double* __restrict__ rec_tm1, double* pose,
+                                                       double* traj, double* dyn, FreeBody fb, int* err) {
+#pragma clang fp contract(off)
+  if (threadIdx.x != 0) return;
+  const Pose P = reinterpret_cast<const Pose*>(pose)[0];
+  double F[3], Tz;
+  if (fb.drive == 2) {  // comoving frame
+    for (int a = 0; a < 3; ++a) F[a] = rec_t[12 + a];
+    Tz = rec_t[17];
+  } else {  // static terms, plus the node terms of the step before (lattice frame)
+    for (int a = 0; a < 3; ++a) F[a] = rec_t[a];
+    Tz = rec_t[5];
+    if ((fb.drive == 1 || fb.drive == 3) && rec_tm1) {
+      for (int a = 0; a < 3; ++a) F[a] += rec_tm1[6 + a];
+      Tz += rec_tm1[11];
+    }
+  }
+  double acc[4];
+  for (int a = 0; a < 3; ++a) acc[a] = (F[a] + fb.ext_force[a]) / fb.mass;
+  acc[3] = (Tz + fb.ext_torque) / fb.inertia;
+  if (fb.D == 2) acc[2] = 0.0;
+  const bool ab2 = fb.integrator == 1 && dyn[4] != 0.0;
+  double dv[4];
+  for (int a = 0; a < 4; ++a) dv[a] = ab2 ? 1.5 * acc[a] - 0.5 * dyn[a] : acc[a];
+  Pose Q = P;
+  for (int a = 0; a < 3; ++a) {
+    Q.V[a] = P.V[a] + dv[a];
+    Q.X[a] = P.X[a] + Q.V[a];
+  }
+  Q.Om = P.Om + dv[3];
+  Q.theta = P.theta + Q.Om;
+  free_trig(Q.theta, Q.ct, Q.st);
+  pose_box(fb.shape, fb.axes, fb.D, fb.glo, fb.ghi, Q);
+  bool ok = Q.V[0] * Q.V[0] + Q.V[1] * Q.V[1] + Q.V[2] * Q.V[2] < 0.25;
+  for (int a = 0; a < fb.D; ++a) ok = ok && Q.lo[a] >= fb.glo[a] && Q.hi[a] <= fb.ghi[a];
+  if (!ok) {  // the body stops where it is; the error is sticky
+    atomicOr(err, 8);
+    Q = P;
+    for (int a = 0; a < 3; ++a) Q.V[a] = 0.0;
+    Q.Om = 0.0;
+  }
+  reinterpret_cast<Pose*>(pose)[1] = Q;
+  for (int a = 0; a < 3; ++a) traj[a] = Q.X[a];
+  traj[3] = Q.theta;
+  for (int a = 0; a < 3; ++a) traj[4 + a] = Q.V[a];
+  traj[7] = Q.Om;
+  for (int a = 0; a < 4; ++a) dyn[a] = acc[a];
+  dyn[4] = 1.0;
+}
+
+hipError_t launch_body_integrate(const double* rec_t, const double* rec_tm1, double* pose, double* traj, double* dyn,
+                                 const FreeBody& fb, int* err, hipStream_t s) {
+  hipLaunchKernelGGL(k_body_integrate, dim3(1), dim3(64), 0, s, rec_t, rec_tm1, pose, traj, dyn, fb, err);
+  return hipGetLastError();
+}
+
 // steady-state check: relative change of the drag (x-force of the body's
 // momentum-exchange form) between steps t - 1 - window and t - 1, in FP64
 // from the record rings, one thread per check

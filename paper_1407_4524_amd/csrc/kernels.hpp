@@ -187,6 +187,19 @@ hipError_t launch_batch_body_links(int lat, int st, int eq, const BatchDomain* d
 hipError_t launch_batch_body_step(int lat, int st, int eq, const BatchDomain* doms, const BatchBody* bodies,
                                   int nbodies, int64_t max_region_cells, int64_t step, hipStream_t s,
                                   const int64_t* sbase = nullptr);
+// Newton-Euler step of a FREE body (include/lbm.h): from the flow force of
+// the record rec_t (and the node terms of rec_tm1, optional) and the pose in
+// pose[0..15], the pose of the next step into pose[16..31] and traj[0..7];
+// dyn holds the previous accelerations and their flag. One thread.
+struct FreeBody {
+  double mass, inertia, ext_force[3], ext_torque;
+  int integrator, drive, shape, D;
+  double axes[3];
+  int glo[3], ghi[3];
+};
+hipError_t launch_body_integrate(const double* rec_t, const double* rec_tm1, double* pose, double* traj, double* dyn,
+                                 const FreeBody& fb, int* err, hipStream_t s);
+
 // *counter += k, one thread (closes a captured step sequence); *counter = v
 hipError_t launch_add_step(int64_t* counter, int64_t k, hipStream_t s);
 hipError_t launch_set_step(int64_t* counter, int64_t v, hipStream_t s);

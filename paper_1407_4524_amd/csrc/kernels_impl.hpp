@@ -123,6 +123,104 @@ __device__ __forceinline__ void moments_c(const typename S::T* A, const Geom& g,
   u[2] = jz / rhoU;
 }
 
+// Lattice direction of Lallemand & Luo's extrapolation at node (x, y, z):
+// the one that maximises (n . c) / |c| for the outward normal n of pose P
+// (ties: the smallest (cx, cy, cz) in lexicographic order).
+template <class L>
+__device__ __forceinline__ int extrap_dir(const BodyShape& bs, const Pose& P, int x, int y, int z) {
+#pragma clang fp contract(off)
+  double n[3];
+  shape_normal(bs, P, (double)x, (double)y, (double)z, n);
+  int best = 1;
+  double best_s = 0.0;
+#pragma unroll
+  for (int i = 1; i < L::Q; ++i) {
+    const int cx = L::cx(i), cy = L::cy(i), cz = L::cz(i);
+    const bool diag = cx * cx + cy * cy + cz * cz == 2;
+    const double sc = (n[0] * (double)cx + n[1] * (double)cy + n[2] * (double)cz) * (diag ? 0.70710678118654757 : 1.0);
+    const int bx = L::cx(best), by = L::cy(best), bz = L::cz(best);
+    const bool less = cx < bx || (cx == bx && (cy < by || (cy == by && cz < bz)));
+    if (i == 1 || sc > best_s || (sc == best_s && less)) {
+      best = i;
+      best_s = sc;
+    }
+  }
+  return best;
+}
+
+// Refill of node (x, y, z), which the body uncovers between poses P0 and P1
+// (Sec. III.B.3), by the body's rule (bs.refill): MEAN, the equilibrium at
+// the mean density and velocity of its neighbours fluid at t and t+1 (sums
+// rs, us over cnt of them; rho0 and the wall velocity when cnt = 0); AIDUN,
+// the equilibrium at that mean density and the wall velocity at the node;
+// EXTRAPOLATE, h_i = (3 h_i(x+c) - 3 h_i(x+2c)) + h_i(x+3c) along extrap_dir
+// when fluid_both says the three nodes are fluid at t and t+1 (MEAN
+// otherwise). Writes the node's populations (the state of t+1) and takes
+// their momentum off the node terms imp, about X_c(t).
+template <class L, class S, int EQ, class FluidBoth>
+__device__ __forceinline__ void refill_node(typename S::T* B, const Geom& g, const Phys& ph, const Pose& P0,
+                                            const Pose& P1, const BodyShape& bs, int x, int y, int z, double rs,
+                                            const double us[3], double cnt, FluidBoth fluid_both, double imp[8]) {
+  const int64_t c = g.idx(x, y, z);
+  double hv[L::Q];
+  bool done = false;
+  if (bs.refill == REFILL_EXTRAPOLATE) {
+    const int i = extrap_dir<L>(bs, P1, x, y, z);
+    const int dx = L::cx(i), dy = L::cy(i), dz = L::cz(i);
+    if (fluid_both(x + dx, y + dy, z + dz) && fluid_both(x + 2 * dx, y + 2 * dy, z + 2 * dz) &&
+        fluid_both(x + 3 * dx, y + 3 * dy, z + 3 * dz)) {
+      const int64_t c1 = g.idx(x + dx, y + dy, z + dz), c2 = g.idx(x + 2 * dx, y + 2 * dy, z + 2 * dz),
+                    c3 = g.idx(x + 3 * dx, y + 3 * dy, z + 3 * dz);
+#pragma unroll
+      for (int q = 0; q < L::Q; ++q) {
+        const double h1 = (double)S::load(B + q * g.S + c1), h2 = (double)S::load(B + q * g.S + c2),
+                     h3 = (double)S::load(B + q * g.S + c3);
+        hv[q] = (3.0 * h1 - 3.0 * h2) + h3;
+      }
+      done = true;
+    }
+  }
+  if (!done) {
+    double rb, ub[3];
+    const double wall[3] = {P1.V[0] - P1.Om * (y - P1.X[1]), P1.V[1] + P1.Om * (x - P1.X[0]), P1.V[2]};
+    if (cnt > 0.0) {
+      rb = rs / cnt;
+      for (int a = 0; a < 3; ++a) ub[a] = us[a] / cnt;
+    } else {
+      rb = ph.rho0;
+      for (int a = 0; a < 3; ++a) ub[a] = wall[a];
+    }
+    if (bs.refill == REFILL_AIDUN)
+      for (int a = 0; a < 3; ++a) ub[a] = wall[a];
+    if (L::D == 2) ub[2] = 0.0;
+    const double drb = rb - ph.rho0;
+    const double rhoU = EQ ? ph.rho0 : rb;
+    const double usq = 1.5 * (ub[0] * ub[0] + ub[1] * ub[1] + ub[2] * ub[2]);
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) {
+      const double cu = L::cx(q) * ub[0] + L::cy(q) * ub[1] + L::cz(q) * ub[2];
+      hv[q] = L::w(q) * (drb + rhoU * (3.0 * cu + 4.5 * cu * cu - usq));
+    }
+  }
+  double m[3] = {0, 0, 0};
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) {
+    S::store_plain(B + q * g.S + c, hv[q]);
+    const double v = S::round_trip(hv[q]);
+    m[0] += L::cx(q) * v;
+    m[1] += L::cy(q) * v;
+    m[2] += L::cz(q) * v;
+  }
+  const double r[3] = {x - P0.X[0], y - P0.X[1], z - P0.X[2]};
+  imp[0] -= m[0];
+  imp[1] -= m[1];
+  imp[2] -= m[2];
+  imp[3] -= r[1] * m[2] - r[2] * m[1];
+  imp[4] -= r[2] * m[0] - r[0] * m[2];
+  imp[5] -= r[0] * m[1] - r[1] * m[0];
+  imp[7] += 1.0;
+}
+
 // The interpolated boundary rule (Eq. Fillipova_interpolation with the
 // Mei-Luo-Shyy u_bf and chi; halfway bounce-back when bc == 0) for one link,
 // in deviation form, written to the solid node's slot; then the link's
@@ -580,39 +678,12 @@ __global__ __launch_bounds__(ADV_BLOCK) void k_body_advance(typename S::T* B, ui
         us[2] += un[2];
         cnt++;
       }
-      double rb, ub[3];
-      if (cnt > 0) {
-        rb = rs / cnt;
-        for (int a = 0; a < 3; ++a) ub[a] = us[a] / cnt;
-      } else {
-        rb = ph.rho0;
-        ub[0] = P1.V[0] - P1.Om * (y - P1.X[1]);
-        ub[1] = P1.V[1] + P1.Om * (x - P1.X[0]);
-        ub[2] = P1.V[2];
-      }
-      if (L::D == 2) ub[2] = 0.0;
-      const double drb = rb - ph.rho0;
-      const double rhoU = EQ ? ph.rho0 : rb;
-      const double usq = 1.5 * (ub[0] * ub[0] + ub[1] * ub[1] + ub[2] * ub[2]);
-      double m[3] = {0, 0, 0};
-#pragma unroll
-      for (int q = 0; q < L::Q; ++q) {
-        const double cu = L::cx(q) * ub[0] + L::cy(q) * ub[1] + L::cz(q) * ub[2];
-        const double heq = L::w(q) * (drb + rhoU * (3.0 * cu + 4.5 * cu * cu - usq));
-        S::store_plain(B + q * g.S + c, heq);
-        const double v = S::round_trip(heq);
-        m[0] += L::cx(q) * v;
-        m[1] += L::cy(q) * v;
-        m[2] += L::cz(q) * v;
-      }
-      const double r[3] = {x - P0.X[0], y - P0.X[1], z - P0.X[2]};
-      imp[0] -= m[0];
-      imp[1] -= m[1];
-      imp[2] -= m[2];
-      imp[3] -= r[1] * m[2] - r[2] * m[1];
-      imp[4] -= r[2] * m[0] - r[0] * m[2];
-      imp[5] -= r[0] * m[1] - r[1] * m[0];
-      imp[7] += 1.0;
+      auto fluid_both = [&](int xa, int ya, int za) {
+        const int64_t ca = g.idx(xa, ya, za);
+        const uint8_t na = R.contains(xa, ya, za) ? mask_next[ca] : mask[ca];
+        return mask[ca] == MASK_FLUID && na == MASK_FLUID;
+      };
+      refill_node<L, S, EQ>(B, g, ph, P0, P1, bs, x, y, z, rs, us, (double)cnt, fluid_both, imp);
     }
 #pragma unroll
     for (int q = 1; q < L::Q; ++q) {
@@ -797,7 +868,6 @@ __global__ __launch_bounds__(ADV_BLOCK) void k_body_advance_lds(typename S::T* B
     E.at(k, x, y, z);
     if (!R.contains(x, y, z) || !in_window(x, y, z)) continue;
     if (mode == 1 && lds[k] == self) {
-      const int64_t c = g.idx(x, y, z);
       double rs = 0, us[3] = {0, 0, 0};
       int cnt = 0;
 #pragma unroll
@@ -812,39 +882,12 @@ __global__ __launch_bounds__(ADV_BLOCK) void k_body_advance_lds(typename S::T* B
         us[2] += un[2];
         cnt++;
       }
-      double rb, ub[3];
-      if (cnt > 0) {
-        rb = rs / cnt;
-        for (int a = 0; a < 3; ++a) ub[a] = us[a] / cnt;
-      } else {
-        rb = ph.rho0;
-        ub[0] = P1.V[0] - P1.Om * (y - P1.X[1]);
-        ub[1] = P1.V[1] + P1.Om * (x - P1.X[0]);
-        ub[2] = P1.V[2];
-      }
-      if (L::D == 2) ub[2] = 0.0;
-      const double drb = rb - ph.rho0;
-      const double rhoU = EQ ? ph.rho0 : rb;
-      const double usq = 1.5 * (ub[0] * ub[0] + ub[1] * ub[1] + ub[2] * ub[2]);
-      double m[3] = {0, 0, 0};
-#pragma unroll
-      for (int q = 0; q < L::Q; ++q) {
-        const double cu = L::cx(q) * ub[0] + L::cy(q) * ub[1] + L::cz(q) * ub[2];
-        const double heq = L::w(q) * (drb + rhoU * (3.0 * cu + 4.5 * cu * cu - usq));
-        S::store_plain(B + q * g.S + c, heq);
-        const double v = S::round_trip(heq);
-        m[0] += L::cx(q) * v;
-        m[1] += L::cy(q) * v;
-        m[2] += L::cz(q) * v;
-      }
-      const double r[3] = {x - P0.X[0], y - P0.X[1], z - P0.X[2]};
-      imp[0] -= m[0];
-      imp[1] -= m[1];
-      imp[2] -= m[2];
-      imp[3] -= r[1] * m[2] - r[2] * m[1];
-      imp[4] -= r[2] * m[0] - r[0] * m[2];
-      imp[5] -= r[0] * m[1] - r[1] * m[0];
-      imp[7] += 1.0;
+      // beyond the status box a node keeps its status (the global mask)
+      auto fluid_both = [&](int xa, int ya, int za) {
+        if (!E.contains(xa, ya, za)) return mask[g.idx(xa, ya, za)] == MASK_FLUID;
+        return ADV_STATUS(xa, ya, za, 0) == MASK_FLUID && ADV_STATUS(xa, ya, za, 1) == MASK_FLUID;
+      };
+      refill_node<L, S, EQ>(B, g, ph, P0, P1, bs, x, y, z, rs, us, (double)cnt, fluid_both, imp);
     }
 #pragma unroll
     for (int q = 1; q < L::Q; ++q)
@@ -1236,40 +1279,13 @@ __device__ __forceinline__ void body_step(typename S::T* B, uint8_t* mask, Link*
 #pragma unroll
         for (int q = 0; q < 5; ++q) v[q] += __shfl_xor(v[q], o, G);
       if (j != 0) continue;
-      const int64_t c = g.idx(x, y, z);
-      double rb, ub[3];
-      if (v[4] > 0.0) {
-        rb = v[0] / v[4];
-        for (int a = 0; a < 3; ++a) ub[a] = v[1 + a] / v[4];
-      } else {
-        rb = ph.rho0;
-        ub[0] = P1.V[0] - P1.Om * (y - P1.X[1]);
-        ub[1] = P1.V[1] + P1.Om * (x - P1.X[0]);
-        ub[2] = P1.V[2];
-      }
-      if (L::D == 2) ub[2] = 0.0;
-      const double drb = rb - ph.rho0;
-      const double rhoU = EQ ? ph.rho0 : rb;
-      const double usq = 1.5 * (ub[0] * ub[0] + ub[1] * ub[1] + ub[2] * ub[2]);
-      double m[3] = {0, 0, 0};
-#pragma unroll
-      for (int i = 0; i < L::Q; ++i) {
-        const double cu = L::cx(i) * ub[0] + L::cy(i) * ub[1] + L::cz(i) * ub[2];
-        const double heq = L::w(i) * (drb + rhoU * (3.0 * cu + 4.5 * cu * cu - usq));
-        S::store_plain(B + i * g.S + c, heq);
-        const double hv = S::round_trip(heq);
-        m[0] += L::cx(i) * hv;
-        m[1] += L::cy(i) * hv;
-        m[2] += L::cz(i) * hv;
-      }
-      const double rr[3] = {x - P0.X[0], y - P0.X[1], z - P0.X[2]};
-      imp[0] -= m[0];
-      imp[1] -= m[1];
-      imp[2] -= m[2];
-      imp[3] -= rr[1] * m[2] - rr[2] * m[1];
-      imp[4] -= rr[2] * m[0] - rr[0] * m[2];
-      imp[5] -= rr[0] * m[1] - rr[1] * m[0];
-      imp[7] += 1.0;
+      // beyond the status box a node keeps its status (the global mask)
+      auto fluid_both = [&](int xa, int ya, int za) {
+        if (!E.contains(xa, ya, za)) return mask[g.idx(xa, ya, za)] == MASK_FLUID;
+        return STEP_STATUS(xa, ya, za, 0) == MASK_FLUID && STEP_STATUS(xa, ya, za, 1) == MASK_FLUID;
+      };
+      const double us[3] = {v[1], v[2], v[3]};
+      refill_node<L, S, EQ>(B, g, ph, P0, P1, bs, x, y, z, v[0], us, v[4], fluid_both, imp);
     }
   }
   __syncthreads();
@@ -1323,6 +1339,16 @@ __global__ __launch_bounds__(NT) void k_body_step(typename S::T* B, uint8_t* mas
                                                   Geom g, Phys ph, double* rec_t, double* rec_t1, int* err,
                                                   StepBox box) {
   body_step<L, S, EQ, NT, true>(B, mask, links, n_links, cap, pose, bs, bc, body, g, ph, rec_t, rec_t1, err, box);
+}
+
+// the same for a body whose poses only the device knows (FREE motion): the
+// region comes from the two poses
+template <class L, class S, int EQ, int NT>
+__global__ __launch_bounds__(NT) void k_body_step_free(typename S::T* B, uint8_t* mask, Link* links, int* n_links,
+                                                       int cap, const double* pose, BodyShape bs, int bc, int body,
+                                                       Geom g, Phys ph, double* rec_t, double* rec_t1, int* err) {
+  body_step<L, S, EQ, NT, false>(B, mask, links, n_links, cap, pose, bs, bc, body, g, ph, rec_t, rec_t1, err,
+                                 StepBox{});
 }
 
 // ---------------------------------------------------------------------------
@@ -1519,7 +1545,12 @@ void Ops<L, S, EQ>::body_advance(void* B, uint8_t* mask, uint8_t* mask_next, Lin
                                  hipEvent_t e0, hipEvent_t e1) {
   auto* b = (typename S::T*)B;
   const size_t lds = ((size_t)2 * region_cells + 15) / 16 * 16;
-  if (mode == 1 && bs.shape != SHAPE_OUTER_CIRCLE && body_step_fits(region_cells, region_rows, list_nodes)) {
+  if (mode == 1 && !pose_host && bs.shape != SHAPE_OUTER_CIRCLE &&
+      body_step_fits(region_cells, region_rows, list_nodes)) {
+    constexpr int NT = L::D == 2 ? 1024 : 512;
+    launch_timed(k_body_step_free<L, S, EQ, NT>, dim3(1), dim3(NT), lds, s, e0, e1, b, mask, links, n_links, cap,
+                 pose, bs, bc, body, g, ph, rec_t, rec_t1, err);
+  } else if (mode == 1 && bs.shape != SHAPE_OUTER_CIRCLE && body_step_fits(region_cells, region_rows, list_nodes)) {
     constexpr int NT = L::D == 2 ? 1024 : 512;  // 2D fits the 128 VGPRs of 1024-thread blocks
     const Pose* P = reinterpret_cast<const Pose*>(pose_host);  // the same two poses, host copy
     StepBox box;

@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <string>
 #include <vector>
 
@@ -61,7 +62,10 @@ static lbm_status check_desc(const lbm_domain_desc* d) {
   if (d->eq_model != LBM_EQ_BGK && d->eq_model != LBM_EQ_HELUO) return fail(LBM_E_INVAL, "unknown eq_model");
   for (int a = 0; a < D; ++a) {
     int lo = d->face[2 * a], hi = d->face[2 * a + 1];
-    if (lo < 0 || lo > 4 || hi < 0 || hi > 4) return fail(LBM_E_INVAL, "unknown face type");
+    if (lo < 0 || lo > 6 || hi < 0 || hi > 6) return fail(LBM_E_INVAL, "unknown face type");
+    const bool zh = lo >= LBM_FACE_ZOUHE_VELOCITY || hi >= LBM_FACE_ZOUHE_VELOCITY;
+    if (zh && a > 0) return fail(LBM_E_INVAL, "Zou-He faces only along x");
+    if (zh && d->face_records) return fail(LBM_E_INVAL, "face records are not kept for Zou-He faces");
     if ((lo == LBM_FACE_PERIODIC) != (hi == LBM_FACE_PERIODIC)) return fail(LBM_E_INVAL, "periodic faces come in pairs");
     if (lo == LBM_FACE_OUTLET || lo == LBM_FACE_OUTLET_VELOCITY || hi == LBM_FACE_INLET)
       return fail(LBM_E_INVAL, "inlet only on -x, outlets only on +x");
@@ -71,10 +75,14 @@ static lbm_status check_desc(const lbm_domain_desc* d) {
   if (d->inlet_profile != LBM_PROFILE_UNIFORM && d->inlet_profile != LBM_PROFILE_PARABOLIC)
     return fail(LBM_E_INVAL, "unknown inlet profile");
   if (d->record_capacity < 0) return fail(LBM_E_INVAL, "negative record capacity");
+  if (d->max_bodies < 0 || d->max_bodies > LBM_MAX_BODIES) return fail(LBM_E_INVAL, "max_bodies out of range");
   if ((d->face_records != 0 && d->face_records != 1) || (d->debug_poison != 0 && d->debug_poison != 1))
     return fail(LBM_E_INVAL, "face_records and debug_poison are 0 or 1");
   return LBM_OK;
 }
+
+// body slots of a domain (the record ring holds one record per slot and step)
+static int body_slots(const lbm_domain_desc* d) { return d->max_bodies ? d->max_bodies : 4; }
 
 static Layout make_layout(const lbm_domain_desc* d) {
   Layout L{};
@@ -108,7 +116,7 @@ static Layout make_layout(const lbm_domain_desc* d) {
   L.rec_cap = d->record_capacity ? d->record_capacity : 65536;
   L.pop_bytes = align_up((size_t)Q * g.S * elem, 256);
   L.mask_bytes = align_up((size_t)g.S, 256);
-  L.rec_bytes = align_up((size_t)L.rec_cap * LBM_MAX_BODIES * LBM_REC_LEN * sizeof(double), 256);
+  L.rec_bytes = align_up((size_t)L.rec_cap * body_slots(d) * LBM_REC_LEN * sizeof(double), 256);
   L.err_bytes = 256;
   L.cnt_bytes = 256;
   // two arrays (the states in A and B) of 2 n_y n_z densities in the
@@ -169,33 +177,15 @@ static Pose body_pose(const Body& b, const Geom& g, int64_t t) {
     p.X[2] = 0.0;
     p.V[2] = 0.0;
   }
-  p.ct = cos(p.theta);
-  p.st = sin(p.theta);
-  // node box holding the body plus two layers (links and their neighbours)
-  if (d.shape == LBM_SHAPE_OUTER_CIRCLE) {
-    for (int a = 0; a < 3; ++a) {
-      p.lo[a] = g.lo[a];
-      p.hi[a] = g.hi[a];
-    }
+  if (d.motion == LBM_MOTION_FREE) {  // the start of a computed motion
+    for (int a = 0; a < 3; ++a) p.V[a] = g.D == 2 && a == 2 ? 0.0 : d.vel[a];
+    p.Om = d.omega;
+    free_trig(p.theta, p.ct, p.st);
   } else {
-    double h[3];
-    if (d.shape == LBM_SHAPE_CIRCLE) {
-      h[0] = h[1] = h[2] = d.axes[0];
-    } else {
-      double a = d.axes[0], bb = d.axes[1];
-      h[0] = sqrt(a * a * p.ct * p.ct + bb * bb * p.st * p.st);
-      h[1] = sqrt(a * a * p.st * p.st + bb * bb * p.ct * p.ct);
-      h[2] = d.axes[2];
-    }
-    for (int a = 0; a < 3; ++a) {
-      if (a >= g.D) {
-        p.lo[a] = p.hi[a] = 0;
-        continue;
-      }
-      p.lo[a] = floor(p.X[a] - h[a]) - 2.0;
-      p.hi[a] = ceil(p.X[a] + h[a]) + 2.0;
-    }
+    p.ct = cos(p.theta);
+    p.st = sin(p.theta);
   }
+  pose_box(d.shape, d.axes, g.D, g.lo, g.hi, p);
   return p;
 }
 
@@ -224,19 +214,31 @@ bool lbm::host::steady_check(lbm_domain d, int id, int64_t window, SteadyCheck& 
   if (window < 0 || d->t - 1 - window < 0 || window >= d->rec_cap) return false;
   c.rec = d->rec + id * LBM_REC_LEN;
   c.rec_cap = d->rec_cap;
-  c.rec_stride = LBM_MAX_BODIES * LBM_REC_LEN;
+  c.rec_stride = (int64_t)d->nslots * LBM_REC_LEN;
   c.t = d->t;
   c.window = window;
-  c.me_mode = d->body[id].desc.me_mode;
+  const int mode = d->body[id].desc.me_mode;
+  c.me_mode = mode == LBM_ME_LATTICE_BACKWARD ? LBM_ME_LATTICE : mode;
   return true;
 }
 
 double* lbm::host::rec_slot(lbm_domain d, int64_t t, int b) {
-  return d->rec + ((t % d->rec_cap) * LBM_MAX_BODIES + b) * LBM_REC_LEN;
+  return d->rec + ((t % d->rec_cap) * d->nslots + b) * LBM_REC_LEN;
 }
 
-// make sure the device pose table of body b covers steps [t0, t1]
+// make sure the device pose table of body b covers steps [t0, t1]; for a
+// FREE body, whose poses the device computes one step ahead, that the
+// window has room for step t0 + 1 (the window restarts at t0 otherwise,
+// from the device's pose of t0)
 lbm_status lbm::host::ensure_poses(lbm_domain d, Body& b, int64_t t0, int64_t t1) {
+  if (b.free_motion) {
+    if (t0 < b.pose_base) return fail(LBM_E_STATE, "pose window of a free body behind its step");
+    if (t0 + 1 - b.pose_base < b.pose_cap) return LBM_OK;
+    HIP_TRY(hipMemcpyAsync(b.pose_dev, b.pose_dev + (t0 - b.pose_base) * POSE_LEN, sizeof(Pose),
+                           hipMemcpyDeviceToDevice, d->stream));
+    b.pose_base = t0;
+    return LBM_OK;
+  }
   if (t0 >= b.pose_base && t1 < b.pose_base + b.pose_valid) return LBM_OK;
   int64_t need = t1 - t0 + 1;
   int64_t cap = std::max<int64_t>(need, POSE_WINDOW);
@@ -308,6 +310,7 @@ lbm_status lbm::host::check_device_errors(lbm_domain d) {
   if (e[0] & 1) return fail(LBM_E_NOMEM, "boundary-link list overflowed its capacity");
   if (e[0] & 2) return fail(LBM_E_RANGE, "a body overlaps a wall layer or another body");
   if (e[0] & 4) return fail(LBM_E_NOMEM, "the surface-node list of a moving body overflowed");
+  if (e[0] & 8) return fail(LBM_E_RANGE, "a free body left the interior or reached speed 0.5; it was stopped");
   if (e[1]) return fail(LBM_E_UNSTABLE, "a fluid node's speed exceeded 0.4 lattice units or is not a number");
   return LBM_OK;
 }
@@ -408,18 +411,101 @@ static lbm_status launch_sweep(lbm_domain d, const BulkConfig& cfg, Sweep sw, in
   return LBM_OK;
 }
 
+// The pose window, trajectory ring and integrator state of a FREE body,
+// holding its pose at the current step (the rest comes from the device).
+static lbm_status start_free_motion(lbm_domain d, Body& b) {
+  const Pose p0 = body_pose(b, d->g, d->t);
+  if (!pose_inside(p0, d->g)) return fail(LBM_E_RANGE, "body not inside the interior (bounding box plus two nodes)");
+  b.pose_cap = POSE_WINDOW;
+  HIP_TRY(hipMalloc(&b.pose_dev, b.pose_cap * POSE_LEN * sizeof(double)));
+  HIP_TRY(hipHostMalloc(&b.pose_pinned, POSE_LEN * sizeof(double), hipHostMallocDefault));
+  HIP_TRY(hipMalloc(&b.traj, (size_t)d->rec_cap * 8 * sizeof(double)));
+  HIP_TRY(hipMalloc(&b.dyn, 8 * sizeof(double)));
+  HIP_TRY(hipMemsetAsync(b.dyn, 0, 8 * sizeof(double), d->stream));
+  memcpy(b.pose_pinned, &p0, sizeof(Pose));
+  HIP_TRY(hipMemcpyAsync(b.pose_dev, b.pose_pinned, sizeof(Pose), hipMemcpyHostToDevice, d->stream));
+  const double row[8] = {p0.X[0], p0.X[1], p0.X[2], p0.theta, p0.V[0], p0.V[1], p0.V[2], p0.Om};
+  HIP_TRY(hipMemcpy(b.traj + (d->t % d->rec_cap) * 8, row, sizeof(row), hipMemcpyHostToDevice));
+  HIP_TRY(hipStreamSynchronize(d->stream));
+  b.pose_base = d->t;
+  b.pose_valid = 1;
+  return LBM_OK;
+}
+
+// Sizes of a FREE body's advance that hold at any pose (the host does not
+// know the pose): per axis the region spans at most 2h + 8 nodes for the
+// half-width h of the body (two poses less than one node apart, two
+// layers each side), the status box two more.
+static void free_bounds(const Body& b, int D, int64_t& cells, int64_t& rows, int64_t& list) {
+  const lbm_body_desc& bd = b.desc;
+  double h[3];
+  if (bd.shape == LBM_SHAPE_ELLIPSE) {
+    h[0] = h[1] = std::max(bd.axes[0], bd.axes[1]);
+    h[2] = bd.axes[2];
+  } else {
+    h[0] = h[1] = h[2] = bd.axes[0];
+  }
+  cells = 1;
+  rows = 1;
+  for (int a = 0; a < D; ++a) {
+    const int64_t n = (int64_t)std::ceil(2.0 * h[a]) + 8;
+    cells *= n + 2;
+    if (a > 0) rows *= n;
+  }
+  list = cells <= STEP_LIST ? cells : (int64_t)STEP_LIST + 1;  // larger bodies take the box-scan advance
+}
+
+// The Newton-Euler step of a FREE body from the records of step t: the pose
+// of t+1 into the pose window and the trajectory ring.
+static lbm_status launch_integrate(lbm_domain d, int id, int64_t t) {
+  Body& b = d->body[id];
+  lbm_status s = ensure_poses(d, b, t, t + 1);
+  if (s != LBM_OK) return s;
+  const lbm_body_desc& bd = b.desc;
+  FreeBody fb{};
+  fb.mass = bd.mass;
+  fb.inertia = bd.inertia;
+  for (int a = 0; a < 3; ++a) {
+    fb.ext_force[a] = bd.ext_force[a];
+    fb.axes[a] = bd.axes[a];
+    fb.glo[a] = d->g.lo[a];
+    fb.ghi[a] = d->g.hi[a];
+  }
+  fb.ext_torque = bd.ext_torque;
+  fb.integrator = bd.integrator;
+  fb.drive = bd.me_mode;
+  fb.shape = bd.shape;
+  fb.D = d->D;
+  const double* rec_tm1 = t > b.t_placed ? rec_slot(d, t - 1, id) : nullptr;
+  HIP_TRY(launch_body_integrate(rec_slot(d, t, id), rec_tm1, const_cast<double*>(pose_at(b, t)),
+                                b.traj + ((t + 1) % d->rec_cap) * 8, b.dyn, fb, d->err, d->stream));
+  return LBM_OK;
+}
+
 // The advance of body `id` from step t to t+1 on the current source buffer
-// (which holds the state of t+1), as its own launch.
+// (which holds the state of t+1), as its own launch; a FREE body's, after
+// its integration.
 lbm_status lbm::host::launch_advance(lbm_domain d, int id, int64_t t) {
   Body& b = d->body[id];
+  if (b.free_motion) {
+    lbm_status si = launch_integrate(d, id, t);
+    if (si != LBM_OK) return si;
+  }
   hipEvent_t e0, e1;
   lbm_status s = timing_slot(d, LBM_KERNEL_BODY, 0, e0, e1);
   if (s != LBM_OK) return s;
+  int64_t cells, rows, list;
+  if (b.free_motion) {
+    free_bounds(b, d->D, cells, rows, list);
+  } else {
+    cells = region_cells(b, d->D, t, 1);
+    rows = region_rows(b, t, 1);
+    list = list_bound(b, d->D, t);
+  }
   HIP_TRY(launch_body_advance(d->lat, d->st, d->eq, d->A, d->mask, d->mask_next, b.links, b.n_links, b.cap,
-                              pose_at(b, t), pose_host_at(b, t), b.shape, b.desc.bc, id, 1, d->g, d->ph,
-                              rec_slot(d, t, id),
-                              rec_slot(d, t + 1, id), d->err, d->stream, region_cells(b, d->D, t, 1),
-                              region_rows(b, t, 1), list_bound(b, d->D, t), e0, e1));
+                              pose_at(b, t), b.free_motion ? nullptr : pose_host_at(b, t), b.shape, b.desc.bc, id,
+                              1, d->g, d->ph, rec_slot(d, t, id), rec_slot(d, t + 1, id), d->err, d->stream, cells,
+                              rows, list, e0, e1));
   return LBM_OK;
 }
 
@@ -459,6 +545,8 @@ static lbm_status undo_placement(lbm_domain d, int id) {
   if (b.partials) (void)hipFree(b.partials);
   if (b.pose_dev) (void)hipFree(b.pose_dev);
   if (b.pose_pinned) (void)hipHostFree(b.pose_pinned);
+  if (b.traj) (void)hipFree(b.traj);
+  if (b.dyn) (void)hipFree(b.dyn);
   b = Body();
   return LBM_OK;
 }
@@ -478,7 +566,7 @@ static lbm_status fold_pending(lbm_domain d, int id) {
   Body& b = d->body[id];
   if (b.part_n == 0) return LBM_OK;
   HIP_TRY(launch_fold(b.ring, b.ring_chunks, PART_RING, b.part_t0, b.part_n, d->rec + id * LBM_REC_LEN, d->rec_cap,
-                      (int64_t)LBM_MAX_BODIES * LBM_REC_LEN, !b.mask_moves, d->stream));
+                      (int64_t)d->nslots * LBM_REC_LEN, !b.mask_moves, d->stream));
   b.part_n = 0;
   return LBM_OK;
 }
@@ -534,6 +622,7 @@ lbm_status lbm_create_domain(const lbm_domain_desc* desc, lbm_domain* out) {
   d->stream = (hipStream_t)desc->stream;
   d->own_stream = d->stream;
   d->rec_cap = L.rec_cap;
+  d->nslots = body_slots(desc);
   d->bulk = bulk_config(d->lat, d->st, 2 * L.pop_bytes);
   if (desc->device_buffer) {
     if (desc->device_buffer_bytes < L.total) {
@@ -600,6 +689,8 @@ lbm_status lbm_destroy_domain(lbm_domain d) {
     if (b.n_links) (void)hipFree(b.n_links);
     if (b.partials) (void)hipFree(b.partials);
     if (b.ring) (void)hipFree(b.ring);
+    if (b.traj) (void)hipFree(b.traj);
+    if (b.dyn) (void)hipFree(b.dyn);
     if (b.pose_dev) (void)hipFree(b.pose_dev);
     if (b.pose_pinned) (void)hipHostFree(b.pose_pinned);
   }
@@ -622,13 +713,20 @@ lbm_status lbm_destroy_domain(lbm_domain d) {
 
 lbm_status lbm_set_body(lbm_domain d, int32_t id, const lbm_body_desc* bd) {
   if (!d || !bd) return fail(LBM_E_INVAL, "null argument");
-  if (id < 0 || id >= LBM_MAX_BODIES) return fail(LBM_E_INVAL, "body id out of range");
+  if (id < 0 || id >= d->nslots) return fail(LBM_E_INVAL, "body id out of range");
   Body& b = d->body[id];
   if (b.active) return fail(LBM_E_STATE, "body id already in use");
   if (bd->shape < 0 || bd->shape > 2) return fail(LBM_E_INVAL, "unknown shape");
   if (bd->bc != LBM_BC_HALFWAY && bd->bc != LBM_BC_MLS) return fail(LBM_E_INVAL, "unknown boundary rule");
-  if (bd->me_mode < 0 || bd->me_mode > 2) return fail(LBM_E_INVAL, "unknown me_mode");
-  if (bd->motion < 0 || bd->motion > 4) return fail(LBM_E_INVAL, "unknown motion");
+  if (bd->me_mode < 0 || bd->me_mode > 3) return fail(LBM_E_INVAL, "unknown me_mode");
+  if (bd->motion < 0 || bd->motion > 5) return fail(LBM_E_INVAL, "unknown motion");
+  if (bd->refill < 0 || bd->refill > 2) return fail(LBM_E_INVAL, "unknown refill rule");
+  if (bd->motion == LBM_MOTION_FREE) {
+    if (!(bd->mass > 0) || !(bd->inertia > 0)) return fail(LBM_E_INVAL, "a free body needs positive mass and inertia");
+    if (bd->integrator != LBM_INTEGRATOR_EULER && bd->integrator != LBM_INTEGRATOR_AB2)
+      return fail(LBM_E_INVAL, "unknown integrator");
+    if (d->batch) return fail(LBM_E_STATE, "a free body is stepped alone, not in a batch");
+  }
   const int na = bd->shape == LBM_SHAPE_ELLIPSE ? d->D : 1;
   for (int a = 0; a < na; ++a)
     if (!(bd->axes[a] > 0)) return fail(LBM_E_INVAL, "axes must be positive");
@@ -647,19 +745,24 @@ lbm_status lbm_set_body(lbm_domain d, int32_t id, const lbm_body_desc* bd) {
   nb.shape.ia2 = 1.0 / (bd->axes[0] * bd->axes[0]);
   nb.shape.ib2 = bd->shape == LBM_SHAPE_ELLIPSE ? 1.0 / (bd->axes[1] * bd->axes[1]) : 0.0;
   nb.shape.ic2 = (bd->shape == LBM_SHAPE_ELLIPSE && d->D == 3) ? 1.0 / (bd->axes[2] * bd->axes[2]) : 0.0;
+  nb.shape.refill = bd->refill;
   const bool round = bd->shape != LBM_SHAPE_ELLIPSE;
   nb.mask_moves = !(bd->motion == LBM_MOTION_STATIC || (round && bd->motion == LBM_MOTION_ROTATE));
+  nb.free_motion = bd->motion == LBM_MOTION_FREE;
+  nb.t_placed = d->t;
   nb.cap = link_capacity(d->D, bd);
   b = std::move(nb);
   HIP_TRY(hipMalloc(&b.links, (size_t)b.cap * sizeof(Link)));
   HIP_TRY(hipMalloc(&b.n_links, sizeof(int)));
   HIP_TRY(hipMalloc(&b.partials, (size_t)((b.cap + 63) / 64) * 12 * sizeof(double)));
   HIP_TRY(hipMemsetAsync(b.n_links, 0, sizeof(int), d->stream));
-  lbm_status s = ensure_poses(d, b, d->t, d->t + 1);
+  lbm_status s = b.free_motion ? start_free_motion(d, b) : ensure_poses(d, b, d->t, d->t + 1);
   if (s != LBM_OK) {
     (void)hipFree(b.links);
     (void)hipFree(b.n_links);
     (void)hipFree(b.partials);
+    if (b.traj) (void)hipFree(b.traj);
+    if (b.dyn) (void)hipFree(b.dyn);
     b = Body();
     return s;
   }
@@ -695,8 +798,8 @@ lbm_status lbm_set_body(lbm_domain d, int32_t id, const lbm_body_desc* bd) {
 // One step is, in order: the boundary rule + momentum exchange of bodies
 // whose links are fixed (k_links, on the source buffer), the stream-collide
 // update of every node, and the advance of bodies whose solid set moves (on
-// the new state). With a single body whose solid set moves (and no plain
-// schedule asked for) the update is split in two: the nodes of a near box
+// the new state). With a single body whose solid set moves and the split
+// schedule asked for, the update is split in two: the nodes of a near box
 // around the body are updated on the domain's stream, followed there by the
 // body's advance, while every other node is updated on the domain's second
 // stream. The far update of step t waits for the near update of step t-1,
@@ -710,15 +813,15 @@ lbm_status lbm_step(lbm_domain d, int64_t nsteps) {
   if (nsteps < 0) return fail(LBM_E_INVAL, "negative step count");
   if (nsteps == 0) return LBM_OK;
   int only = -1, nactive = 0;
-  for (int id = 0; id < LBM_MAX_BODIES; ++id)
+  for (int id = 0; id < d->nslots; ++id)
     if (d->body[id].active) {
       lbm_status s = ensure_poses(d, d->body[id], d->t, d->t + nsteps);
       if (s != LBM_OK) return s;
       only = id;
       nactive++;
     }
-  const bool split = !d->desc.plain_schedule && nactive == 1 && d->body[only].mask_moves &&
-                     d->body[only].desc.shape != LBM_SHAPE_OUTER_CIRCLE;
+  const bool split = d->desc.split_schedule && nactive == 1 && d->body[only].mask_moves &&
+                     d->body[only].desc.shape != LBM_SHAPE_OUTER_CIRCLE && !d->body[only].free_motion;
   if (split && !d->aux) {
     lbm_status sa = create_far_stream(d->stream, &d->aux, FAR_CU_EVERY);
     if (sa != LBM_OK) return sa;
@@ -757,14 +860,15 @@ lbm_status lbm_step(lbm_domain d, int64_t nsteps) {
         return s;
       far_open = true;
     }
-    for (int id = 0; id < LBM_MAX_BODIES; ++id) {
+    for (int id = 0; id < d->nslots; ++id) {
       Body& b = d->body[id];
       if (!b.active || (b.mask_moves && b.bc_ready)) continue;
       if ((s = timing_slot(d, LBM_KERNEL_BODY, 0, e0, e1)) != LBM_OK) return s;
       if (b.part_n == 0) b.part_t0 = t;
       HIP_TRY(launch_links_part(d->lat, d->st, d->eq, d->A, b.links, b.n_host, pose_at(b, t), b.desc.bc, d->mask, g,
                                 d->ph, b.ring + (t % PART_RING) * (int64_t)b.ring_chunks * 12, d->stream, e0, e1));
-      if (++b.part_n == PART_RING && (s = fold_pending(d, id)) != LBM_OK) return s;
+      // (a free body's integration reads the record of this step at once)
+      if ((++b.part_n == PART_RING || b.free_motion) && (s = fold_pending(d, id)) != LBM_OK) return s;
       if (b.mask_moves) b.bc_ready = true;
     }
     if (d->face_rec) {  // the faces' momentum exchange of step t, from the state of t
@@ -782,7 +886,7 @@ lbm_status lbm_step(lbm_domain d, int64_t nsteps) {
     }
     std::swap(d->A, d->B);  // the advance works on the new state
     std::swap(d->rhoA, d->rhoB);
-    for (int id = 0; id < LBM_MAX_BODIES; ++id) {
+    for (int id = 0; id < d->nslots; ++id) {
       Body& b = d->body[id];
       if (!b.active || !b.mask_moves) continue;
       if ((s = launch_advance(d, id, t)) != LBM_OK) {
@@ -794,7 +898,7 @@ lbm_status lbm_step(lbm_domain d, int64_t nsteps) {
     d->t = t + 1;
   }
   if (far_open) HIP_TRY(hipStreamWaitEvent(d->stream, far_done, 0));
-  for (int id = 0; id < LBM_MAX_BODIES; ++id)
+  for (int id = 0; id < d->nslots; ++id)
     if (d->body[id].active) {
       lbm_status s = fold_pending(d, id);
       if (s != LBM_OK) return s;
@@ -812,7 +916,7 @@ int64_t lbm_time(lbm_domain d) { return d ? d->t : -1; }
 
 lbm_status lbm_records(lbm_domain d, int32_t id, int64_t first, int64_t count, double* rec) {
   if (!d || !rec) return fail(LBM_E_INVAL, "null argument");
-  if (id < 0 || id >= LBM_MAX_BODIES || !d->body[id].active) return fail(LBM_E_INVAL, "no such body");
+  if (id < 0 || id >= d->nslots || !d->body[id].active) return fail(LBM_E_INVAL, "no such body");
   if (count < 0 || first < 0 || first + count > d->t || first < d->t - d->rec_cap)
     return fail(LBM_E_RANGE, "steps outside the record ring");
   // an instability flag still lets the records be read (they show where it
@@ -825,11 +929,11 @@ lbm_status lbm_records(lbm_domain d, int32_t id, int64_t first, int64_t count, d
   while (k < count) {
     int64_t slot = (first + k) % d->rec_cap;
     int64_t run = std::min(count - k, d->rec_cap - slot);
-    buf.resize((size_t)run * LBM_MAX_BODIES * LBM_REC_LEN);
-    HIP_TRY(hipMemcpy(buf.data(), d->rec + slot * LBM_MAX_BODIES * LBM_REC_LEN, buf.size() * sizeof(double),
+    buf.resize((size_t)run * d->nslots * LBM_REC_LEN);
+    HIP_TRY(hipMemcpy(buf.data(), d->rec + slot * d->nslots * LBM_REC_LEN, buf.size() * sizeof(double),
                       hipMemcpyDeviceToHost));
     for (int64_t j = 0; j < run; ++j)
-      memcpy(rec + (k + j) * LBM_REC_LEN, buf.data() + (j * LBM_MAX_BODIES + id) * LBM_REC_LEN,
+      memcpy(rec + (k + j) * LBM_REC_LEN, buf.data() + (j * d->nslots + id) * LBM_REC_LEN,
              LBM_REC_LEN * sizeof(double));
     k += run;
   }
@@ -879,16 +983,21 @@ lbm_status lbm_force_torque(lbm_domain d, int32_t id, int64_t first, int64_t cou
       for (int a = 0; a < 6; ++a) ft[6 * k + a] = rec[k * LBM_FACE_REC_LEN + a];
     return s;
   }
-  std::vector<double> rec((size_t)std::max<int64_t>(count, 0) * LBM_REC_LEN);
-  lbm_status s = lbm_records(d, id, first, count, rec.data());
-  if (s != LBM_OK && s != LBM_E_UNSTABLE) return s;
+  if (id < 0 || id >= d->nslots || !d->body[id].active) return fail(LBM_E_INVAL, "no such body");
   const int mode = d->body[id].desc.me_mode;
+  // the backward form also takes the node terms of the step before the first
+  const int64_t pre = (mode == LBM_ME_LATTICE_BACKWARD && first > 0 && count > 0) ? 1 : 0;
+  std::vector<double> rec((size_t)std::max<int64_t>(count + pre, 0) * LBM_REC_LEN);
+  lbm_status s = lbm_records(d, id, first - pre, count + pre, rec.data());
+  if (s != LBM_OK && s != LBM_E_UNSTABLE) return s;
   for (int64_t k = 0; k < count; ++k) {
-    const double* r = rec.data() + k * LBM_REC_LEN;
+    const double* r = rec.data() + (k + pre) * LBM_REC_LEN;
+    const double* rp = (k + pre > 0) ? r - LBM_REC_LEN : nullptr;  // step t - 1 (none before step 0)
     for (int a = 0; a < 6; ++a) {
       double v;
       if (mode == LBM_ME_STATIC) v = r[LBM_REC_F_STATIC + a];
       else if (mode == LBM_ME_LATTICE) v = r[LBM_REC_F_STATIC + a] + r[LBM_REC_F_NODES + a];
+      else if (mode == LBM_ME_LATTICE_BACKWARD) v = r[LBM_REC_F_STATIC + a] + (rp ? rp[LBM_REC_F_NODES + a] : 0.0);
       else v = r[LBM_REC_F_COMOVING + a];
       ft[6 * k + a] = v;
     }
@@ -896,10 +1005,36 @@ lbm_status lbm_force_torque(lbm_domain d, int32_t id, int64_t first, int64_t cou
   return s;
 }
 
+lbm_status lbm_body_trajectory(lbm_domain d, int32_t id, int64_t first, int64_t count, double* out) {
+  if (!d || (!out && count > 0)) return fail(LBM_E_INVAL, "null argument");
+  if (id < 0 || id >= d->nslots || !d->body[id].active) return fail(LBM_E_INVAL, "no such body");
+  if (count < 0 || first < 0) return fail(LBM_E_RANGE, "negative step or count");
+  Body& b = d->body[id];
+  if (!b.free_motion) {
+    for (int64_t k = 0; k < count; ++k) {
+      const Pose p = body_pose(b, d->g, first + k);
+      const double row[8] = {p.X[0], p.X[1], p.X[2], p.theta, p.V[0], p.V[1], p.V[2], p.Om};
+      memcpy(out + 8 * k, row, sizeof(row));
+    }
+    return LBM_OK;
+  }
+  if (first < b.t_placed || first + count - 1 > d->t || first <= d->t - d->rec_cap)
+    return fail(LBM_E_RANGE, "steps outside the trajectory ring");
+  lbm_status s = lbm_synchronize(d);
+  if (s != LBM_OK && s != LBM_E_UNSTABLE) return s;
+  for (int64_t k = 0; k < count;) {  // at most two contiguous runs of the ring
+    const int64_t slot = (first + k) % d->rec_cap;
+    const int64_t run = std::min(count - k, d->rec_cap - slot);
+    HIP_TRY(hipMemcpy(out + 8 * k, b.traj + slot * 8, (size_t)run * 8 * sizeof(double), hipMemcpyDeviceToHost));
+    k += run;
+  }
+  return s;
+}
+
 lbm_status lbm_get_links(lbm_domain d, int32_t id, int64_t cap, int64_t* node, int32_t* dir, double* delta,
                          int64_t* n) {
   if (!d || !n) return fail(LBM_E_INVAL, "null argument");
-  if (id < 0 || id >= LBM_MAX_BODIES || !d->body[id].active) return fail(LBM_E_INVAL, "no such body");
+  if (id < 0 || id >= d->nslots || !d->body[id].active) return fail(LBM_E_INVAL, "no such body");
   lbm_status s = lbm_synchronize(d);
   if (s != LBM_OK) return s;
   Body& b = d->body[id];
@@ -921,7 +1056,7 @@ lbm_status lbm_get_links(lbm_domain d, int32_t id, int64_t cap, int64_t* node, i
 lbm_status lbm_steady_state(lbm_domain d, int32_t id, int64_t window, double tol, int32_t* steady,
                             double* rel_change) {
   if (!d || !steady) return fail(LBM_E_INVAL, "null argument");
-  if (id < 0 || id >= LBM_MAX_BODIES || !d->body[id].active) return fail(LBM_E_INVAL, "no such body");
+  if (id < 0 || id >= d->nslots || !d->body[id].active) return fail(LBM_E_INVAL, "no such body");
   SteadyCheck c{};
   if (!steady_check(d, id, window, c)) return fail(LBM_E_RANGE, "the record ring does not hold both steps");
   if (!d->steady_buf) HIP_TRY(hipMalloc(&d->steady_buf, 256));

@@ -19,7 +19,8 @@ namespace lbm {
 //    opposite direction (halfway bounce-back at a resting wall);
 //  * SRC_INLET beyond -x, SRC_OUTVEL beyond a velocity outlet: the same (the
 //    wall term 6 w_i rho c_i.u_in is added by the caller: velocity
-//    bounce-back at x = -1/2 or nx - 1/2);
+//    bounce-back at x = -1/2 or nx - 1/2); beyond a Zou-He face the same
+//    placeholder, which the caller replaces (zou_he);
 //  * SRC_OUTLET beyond a zero-gradient outlet: direction i at the last
 //    column, one link back along the transverse axes;
 //  * SRC_NONE: the source x - c_i itself, wrapped across periodic faces.
@@ -36,7 +37,7 @@ __device__ __forceinline__ int64_t face_pull(const Geom& g, int x, int y, int z,
   bool wall = ((g.face[0] == FACE_WALL) & (sx <= 0)) | ((g.face[1] == FACE_WALL) & (sx >= g.nx - 1)) |
               ((g.face[2] == FACE_WALL) & (sy <= 0)) | ((g.face[3] == FACE_WALL) & (sy >= g.ny - 1));
   if (L::D == 3) wall = wall | ((g.face[4] == FACE_WALL) & (sz <= 0)) | ((g.face[5] == FACE_WALL) & (sz >= g.nz - 1));
-  const int beyond = sx >= g.nx ? (g.face[1] == FACE_OUTLET_VELOCITY ? SRC_OUTVEL : SRC_OUTLET) : SRC_NONE;
+  const int beyond = sx >= g.nx ? (g.face[1] == FACE_OUTLET ? SRC_OUTLET : SRC_OUTVEL) : SRC_NONE;
   st = wall ? SRC_WALL : (sx < 0 ? SRC_INLET : beyond);
   const bool own = st == SRC_WALL || st == SRC_INLET || st == SRC_OUTVEL;
   const int64_t src = g.idx(st == SRC_OUTLET ? g.nx - 1 : sx, sy, sz);
@@ -69,6 +70,46 @@ __device__ __forceinline__ C inlet_speed(const Geom& g, const Phys& ph, C yB, C 
     if (g.D == 3 && g.face[4] == FACE_WALL) u *= (C)ph.inlet_kz * ((zB - (C)0.5) * ((C)(g.nz - 1.5) - zB));
   }
   return u;
+}
+
+// Zou-He face at x = lo (SIDE = +1: the populations with c_ix = +1 are
+// unknown) or x = hi (SIDE = -1), on the deviations h of one node after the
+// pull (the unknown slots hold placeholders). The node is given either its
+// velocity (ux along x, no transverse velocity) or its density (rho0, no
+// transverse velocity); mass and x-momentum fix the other one:
+//   rho (1 - SIDE ux) = rho0 + K0 + 2 Kb   (standard equilibrium: j = rho u)
+//   j_x = rho0 ux                            (quasi-incompressible)
+//   j_x = -SIDE (K0 + 2 Kb)                  (given density rho0)
+// with K0 the sum over c_ix = 0 and Kb over c_ix = -SIDE. Each unknown i is
+// its opposite plus the odd part of the equilibrium difference, 6 w_i c_i.j,
+// minus the transverse corrections c_ia N_a, N_a = (1/2) sum_{c_ix=0} c_ia h,
+// which give the node zero tangential momentum.
+template <class L, int EQ, int SIDE, class C>
+__device__ __forceinline__ void zou_he(C* h, bool velocity, C ux, C rho0) {
+  C k0 = 0, kb = 0, ty = 0, tz = 0;
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) {
+    if (L::cx(i) == 0) {
+      k0 += h[i];
+      if (L::cy(i)) ty += L::cy(i) > 0 ? h[i] : -h[i];
+      if (L::D == 3 && L::cz(i)) tz += L::cz(i) > 0 ? h[i] : -h[i];
+    } else if (L::cx(i) == -SIDE) {
+      kb += h[i];
+    }
+  }
+  const C known = k0 + (C)2 * kb;
+  C jx;
+  if (velocity) jx = EQ ? rho0 * ux : (rho0 + known) / ((C)1 - (C)SIDE * ux) * ux;
+  else jx = -(C)SIDE * known;
+  const C ny = (C)0.5 * ty, nz = (C)0.5 * tz;
+#pragma unroll
+  for (int i = 1; i < L::Q; ++i) {
+    if (L::cx(i) != SIDE) continue;
+    C v = h[L::opp(i)] + (C)(6.0 * L::w(i) * SIDE) * jx;
+    if (L::cy(i)) v += L::cy(i) > 0 ? -ny : ny;
+    if (L::D == 3 && L::cz(i)) v += L::cz(i) > 0 ? -nz : nz;
+    h[i] = v;
+  }
 }
 
 // index of an x-face node (x = lo or x = hi) in the arrays of x-face
@@ -249,6 +290,18 @@ __device__ __forceinline__ void stream_collide_row(const typename S::T* __restri
       if (apply)
         h[k][i] += (C)(6.0 * L::w(i) * L::cx(i)) * rho_w[k] *
                    inlet_speed<C>(g, ph, (C)y - (C)(0.5 * L::cy(i)), (C)z - (C)(0.5 * L::cz(i)));
+    }
+  }
+  // Zou-He faces: the entering populations of the x-face nodes rebuilt
+  const bool zlo = g.face[0] >= FACE_ZOUHE_VELOCITY, zhi = g.face[1] >= FACE_ZOUHE_VELOCITY;
+  if (zlo | zhi) {
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      const int x = x0 + k * BX;
+      if (zlo & (x == g.lo[0]))
+        zou_he<L, EQ, 1>(h[k], g.face[0] == FACE_ZOUHE_VELOCITY, inlet_speed<C>(g, ph, (C)y, (C)z), (C)ph.rho0);
+      else if (zhi & (x == g.hi[0]))
+        zou_he<L, EQ, -1>(h[k], g.face[1] == FACE_ZOUHE_VELOCITY, inlet_speed<C>(g, ph, (C)y, (C)z), (C)ph.rho0);
     }
   }
 #pragma unroll

@@ -20,19 +20,22 @@ LIB_PATH = os.path.join(HERE, "liblbm.so")
 LATTICE = {"D2Q9": 0, "D3Q19": 1}
 STORAGE = {"f64": 0, "f32": 1, "f16": 2, "f16_shifted": 2}
 EQ = {"bgk": 0, "heluo": 1}
-FACE = {"periodic": 0, "wall": 1, "inlet": 2, "outlet": 3, "outlet_velocity": 4}
+FACE = {"periodic": 0, "wall": 1, "inlet": 2, "outlet": 3, "outlet_velocity": 4, "zouhe_velocity": 5,
+        "zouhe_pressure": 6}
 PROFILE = {"uniform": 0, "parabolic": 1}
 SHAPE = {"circle": 0, "sphere": 0, "ellipse": 1, "ellipsoid": 1, "outer_circle": 2}
 BC = {"halfway": 0, "mls": 1}
-ME = {"static": 0, "lattice": 1, "comoving": 2}
-MOTION = {"static": 0, "const_vel": 1, "rotate": 2, "oscillate": 3, "table": 4}
+ME = {"static": 0, "lattice": 1, "comoving": 2, "lattice_backward": 3}
+MOTION = {"static": 0, "const_vel": 1, "rotate": 2, "oscillate": 3, "table": 4, "free": 5}
+INTEGRATOR = {"euler": 0, "ab2": 1}
+REFILL = {"mean": 0, "aidun": 1, "extrapolate": 2}
 KERNEL = {"stream_collide": 0, "body": 1, "near_box": 2}
 STATUS = {0: "LBM_OK", -1: "LBM_E_INVAL", -2: "LBM_E_NOMEM", -3: "LBM_E_HIP", -4: "LBM_E_RANGE",
           -5: "LBM_E_UNSTABLE", -6: "LBM_E_STATE"}
 REC_LEN = 20
 FACE_REC_LEN = 18
 WALLS = -1  # LBM_WALLS
-MAX_BODIES = 4
+MAX_BODIES = 64
 MAX_STEADY_NOALLOC = 512  # LBM_STEADY_NOALLOC_MAX
 
 EXPORTS = ["lbm_footprint_bytes", "lbm_body_footprint_bytes", "lbm_create_domain", "lbm_destroy_domain", "lbm_set_body", "lbm_step",
@@ -41,7 +44,7 @@ EXPORTS = ["lbm_footprint_bytes", "lbm_body_footprint_bytes", "lbm_create_domain
            "lbm_batch_create", "lbm_batch_destroy", "lbm_batch_add", "lbm_batch_remove", "lbm_batch_step",
            "lbm_batch_set_config", "lbm_batch_get_config", "lbm_batch_tune", "lbm_steady_state",
            "lbm_batch_steady_state", "lbm_copy", "lbm_get_sweep_config", "lbm_set_sweep_config",
-           "lbm_batch_steady_state_noalloc", "lbm_get_moving_sets", "lbm_face_records"]
+           "lbm_batch_steady_state_noalloc", "lbm_get_moving_sets", "lbm_face_records", "lbm_body_trajectory"]
 
 
 class LbmError(RuntimeError):
@@ -56,8 +59,8 @@ class DomainDesc(C.Structure):
                 ("face", C.c_int32 * 6), ("inlet_profile", C.c_int32), ("inlet_u", C.c_double),
                 ("init_rho", C.POINTER(C.c_double)), ("init_u", C.POINTER(C.c_double)),
                 ("stream", C.c_void_p), ("device_buffer", C.c_void_p), ("device_buffer_bytes", C.c_size_t),
-                ("record_capacity", C.c_int64), ("plain_schedule", C.c_int32), ("face_records", C.c_int32),
-                ("debug_poison", C.c_int32)]
+                ("record_capacity", C.c_int64), ("split_schedule", C.c_int32), ("face_records", C.c_int32),
+                ("debug_poison", C.c_int32), ("max_bodies", C.c_int32)]
 
 
 class SweepConfig(C.Structure):
@@ -79,7 +82,9 @@ class BodyDesc(C.Structure):
     _fields_ = [("shape", C.c_int32), ("axes", C.c_double * 3), ("bc", C.c_int32), ("me_mode", C.c_int32),
                 ("motion", C.c_int32), ("c0", C.c_double * 3), ("theta0", C.c_double), ("vel", C.c_double * 3),
                 ("omega", C.c_double), ("amp", C.c_double * 3), ("period", C.c_double),
-                ("pose_table", C.POINTER(C.c_double)), ("pose_count", C.c_int64)]
+                ("pose_table", C.POINTER(C.c_double)), ("pose_count", C.c_int64), ("mass", C.c_double),
+                ("inertia", C.c_double), ("ext_force", C.c_double * 3), ("ext_torque", C.c_double),
+                ("integrator", C.c_int32), ("refill", C.c_int32)]
 
 
 _lib = None
@@ -103,6 +108,7 @@ def lib():
         L.lbm_time.restype = C.c_int64
         L.lbm_force_torque.argtypes = [C.c_void_p, C.c_int32, C.c_int64, C.c_int64, C.c_void_p]
         L.lbm_records.argtypes = [C.c_void_p, C.c_int32, C.c_int64, C.c_int64, C.c_void_p]
+        L.lbm_body_trajectory.argtypes = [C.c_void_p, C.c_int32, C.c_int64, C.c_int64, C.c_void_p]
         L.lbm_get_links.argtypes = [C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
                                     C.POINTER(C.c_int64)]
         L.lbm_get_fields.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
@@ -157,7 +163,7 @@ def _enum(table, v):
 
 def domain_desc(lattice="D2Q9", nx=64, ny=64, nz=1, tau=0.8, rho0=1.0, storage="f32", eq="bgk",
                 faces=("periodic",) * 6, inlet_profile="uniform", inlet_u=0.0, record_capacity=0,
-                plain_schedule=False, face_records=False, debug_poison=False):
+                split_schedule=False, face_records=False, debug_poison=False, max_bodies=0):
     """lbm_domain_desc of these settings (no initial fields, stream or buffer)"""
     d = DomainDesc()
     d.lattice = _enum(LATTICE, lattice)
@@ -170,16 +176,23 @@ def domain_desc(lattice="D2Q9", nx=64, ny=64, nz=1, tau=0.8, rho0=1.0, storage="
     d.inlet_profile = _enum(PROFILE, inlet_profile)
     d.inlet_u = inlet_u
     d.record_capacity = record_capacity
-    d.plain_schedule = 1 if plain_schedule else 0
+    d.split_schedule = 1 if split_schedule else 0
     d.face_records = 1 if face_records else 0
     d.debug_poison = 1 if debug_poison else 0
+    d.max_bodies = max_bodies
     return d
 
 
 def body_desc(shape="circle", axes=(1.0,), bc="halfway", me="static", motion="static", c0=(0, 0, 0), theta0=0.0,
-              vel=(0, 0, 0), omega=0.0, amp=(0, 0, 0), period=1.0, table=None):
+              vel=(0, 0, 0), omega=0.0, amp=(0, 0, 0), period=1.0, table=None, mass=0.0, inertia=0.0,
+              ext_force=(0, 0, 0), ext_torque=0.0, integrator="euler", refill="mean"):
     """(lbm_body_desc, arrays it points to) of these settings"""
     b = BodyDesc()
+    b.mass, b.inertia, b.ext_torque = mass, inertia, ext_torque
+    for a in range(3):
+        b.ext_force[a] = ext_force[a] if a < len(ext_force) else 0.0
+    b.integrator = _enum(INTEGRATOR, integrator)
+    b.refill = _enum(REFILL, refill)
     b.shape = _enum(SHAPE, shape)
     ax = list(axes) + [0.0] * (3 - len(axes))
     if b.shape == 1 and len(axes) == 1:
@@ -208,6 +221,9 @@ def footprint_bytes(w, **kw):
     """Device bytes a domain built from workload dictionary w takes, its
     bodies included (lbm_footprint_bytes + lbm_body_footprint_bytes); no GPU
     needed."""
+    nb = len(w.get("bodies", []))
+    if nb > 4 and "max_bodies" not in kw:
+        kw = dict(kw, max_bodies=nb)
     d = domain_desc(**{k: w[k] for k in _SPEC_KEYS if k in w}, **kw)
     n = C.c_size_t(0)
     _check(lib().lbm_footprint_bytes(C.byref(d), C.byref(n)))
@@ -224,10 +240,10 @@ class Domain:
 
     def __init__(self, lattice="D2Q9", nx=64, ny=64, nz=1, tau=0.8, rho0=1.0, storage="f32", eq="bgk",
                  faces=("periodic",) * 6, inlet_profile="uniform", inlet_u=0.0, init_rho=None, init_u=None,
-                 record_capacity=0, stream=None, torch_buffer=True, plain_schedule=False, face_records=False,
-                 debug_poison=False):
+                 record_capacity=0, stream=None, torch_buffer=True, split_schedule=False, face_records=False,
+                 debug_poison=False, max_bodies=0):
         d = domain_desc(lattice, nx, ny, nz, tau, rho0, storage, eq, faces, inlet_profile, inlet_u,
-                        record_capacity, plain_schedule, face_records, debug_poison)
+                        record_capacity, split_schedule, face_records, debug_poison, max_bodies)
         self.nx, self.ny, self.nz = nx, ny, (nz if d.lattice == 1 else 1)
         self.N = self.nx * self.ny * self.nz
         keep = []
@@ -264,6 +280,9 @@ class Domain:
         """Build from a plain workload dictionary (lattice, nx, ny, nz, tau, rho0,
         storage, eq, faces, inlet_profile, inlet_u, bodies)."""
         faces = tuple(w["faces"])
+        nb = len(w.get("bodies", []))
+        if nb > 4 and "max_bodies" not in kw:
+            kw = dict(kw, max_bodies=nb)
         dom = cls(lattice=w["lattice"], nx=w["nx"], ny=w["ny"], nz=w.get("nz", 1), tau=w["tau"],
                   rho0=w.get("rho0", 1.0), storage=w.get("storage", "f32"), eq=w.get("eq", "bgk"),
                   faces=faces, inlet_profile=w.get("inlet_profile", "uniform"), inlet_u=w.get("inlet_u", 0.0),
@@ -308,6 +327,15 @@ class Domain:
             count = self.t - first
         out = np.zeros((count, 6))
         _check(lib().lbm_force_torque(self._h, body_id, first, count, out.ctypes.data))
+        return out
+
+    def trajectory(self, body_id=0, first=0, count=None):
+        """poses X[3], theta, V[3], Omega_z of steps first .. first+count-1
+        (default: up to the current step, inclusive)"""
+        if count is None:
+            count = self.t - first + 1
+        out = np.zeros((count, 8))
+        _check(lib().lbm_body_trajectory(self._h, body_id, first, count, out.ctypes.data))
         return out
 
     def records(self, body_id=0, first=0, count=None):

@@ -11,7 +11,11 @@ SHAPE = {"circle": O.SHAPE_CIRCLE, "sphere": O.SHAPE_CIRCLE, "ellipse": O.SHAPE_
          "ellipsoid": O.SHAPE_ELLIPSE, "outer_circle": O.SHAPE_OUTER_CIRCLE}
 BC = {"halfway": O.BC_HALFWAY, "mls": O.BC_MLS}
 MOTION = {"static": O.MOTION_STATIC, "const_vel": O.MOTION_CONST_VEL, "rotate": O.MOTION_ROTATE,
-          "oscillate": O.MOTION_OSCILLATE, "table": O.MOTION_TABLE}
+          "oscillate": O.MOTION_OSCILLATE, "table": O.MOTION_TABLE, "free": O.MOTION_FREE}
+DRIVE = {"static": O.DRIVE_STATIC, "lattice": O.DRIVE_LATTICE, "comoving": O.DRIVE_COMOVING,
+         "lattice_backward": O.DRIVE_LATTICE}
+INTEGRATOR = {"euler": O.INTEGRATOR_EULER, "ab2": O.INTEGRATOR_AB2}
+REFILL = {"mean": O.REFILL_MEAN, "aidun": O.REFILL_AIDUN, "extrapolate": O.REFILL_EXTRAPOLATE}
 
 
 def make_oracle(w, init_rho=None, init_u=None):
@@ -25,7 +29,10 @@ def make_oracle(w, init_rho=None, init_u=None):
         d.set_body(k, SHAPE[b["shape"]], b["axes"], bc=BC[b["bc"]], motion=MOTION[b["motion"]],
                    c0=b.get("c0", (0, 0, 0)), theta0=b.get("theta0", 0.0), vel=b.get("vel", (0, 0, 0)),
                    omega=b.get("omega", 0.0), amp=b.get("amp", (0, 0, 0)),
-                   period=b.get("period", 1.0), table=b.get("table"))
+                   period=b.get("period", 1.0), table=b.get("table"), mass=b.get("mass", 0.0),
+                   inertia=b.get("inertia", 0.0), ext_force=b.get("ext_force", (0, 0, 0)),
+                   ext_torque=b.get("ext_torque", 0.0), drive=DRIVE[b.get("me", "static")],
+                   integrator=INTEGRATOR[b.get("integrator", "euler")], refill=REFILL[b.get("refill", "mean")])
     return d
 
 
@@ -37,4 +44,7 @@ def me_series(rec, mode):
         return rec[:, 0:3] + rec[:, 6:9], rec[:, 3:6] + rec[:, 9:12]
     if mode == "comoving":
         return rec[:, 12:15], rec[:, 15:18]
+    if mode == "lattice_backward":  # node terms of the step before
+        prev = np.vstack([np.zeros((1, 6)), rec[:-1, 6:12]])
+        return rec[:, 0:3] + prev[:, 0:3], rec[:, 3:6] + prev[:, 3:6]
     raise ValueError(mode)

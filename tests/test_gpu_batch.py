@@ -56,7 +56,7 @@ def test_batch_equals_each_domain_alone(overlap, own_stream, graph):
     assert ("ellipse", "rotate") in kinds and any(m == "static" for _, m in kinds)
     print("batch of", [(w["nx"], w["ny"], w["bodies"][0]["shape"], w["bodies"][0]["motion"]) for w in ws],
           f"overlap {overlap} own stream {own_stream}", flush=True)
-    alone = [make_gpu(w, plain_schedule=True) for w in ws]
+    alone = [make_gpu(w) for w in ws]
     for d in alone:
         d.step(150)
     s = torch.cuda.Stream() if own_stream else torch.cuda.current_stream()
@@ -82,7 +82,7 @@ def test_batch_fallback_for_a_large_moving_body():
     w["bodies"] = [dict(shape="ellipse", axes=(80.0, 40.0), bc="mls", me="lattice", motion="rotate",
                         c0=(150.0, 150.0, 0.0), theta0=0.2, omega=5e-4)]
     small = small_batch(count=2)
-    alone = [make_gpu(x, plain_schedule=True) for x in [w] + small]
+    alone = [make_gpu(x) for x in [w] + small]
     for d in alone:
         d.step(40)
     batch = Batch()
@@ -98,7 +98,7 @@ def test_batch_fallback_for_a_large_moving_body():
 def test_batch_members_at_different_steps_and_tuning():
     from paper_1407_4524_amd import Batch
     ws = small_batch(count=4, seed=5)
-    alone = [make_gpu(w, plain_schedule=True) for w in ws]
+    alone = [make_gpu(w) for w in ws]
     members = [make_gpu(w) for w in ws]
     for k, (a, m) in enumerate(zip(alone, members)):  # members start at steps 0, 7, 14, 21
         a.step(7 * k)

@@ -329,10 +329,10 @@ def test_split_schedule_bitwise_equals_plain(case, own_stream):
     if own_stream:
         s = torch.cuda.Stream()
         with torch.cuda.stream(s):
-            a = make_gpu(w)
+            a = make_gpu(w, split_schedule=True)
     else:
-        a = make_gpu(w)
-    b = make_gpu(w, plain_schedule=True)
+        a = make_gpu(w, split_schedule=True)
+    b = make_gpu(w)
     a.timing_enable(1)
     b.timing_enable(1)
     for chunk in (1, steps // 2 - 1, steps - steps // 2):  # several calls: the hand-over between them

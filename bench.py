@@ -16,10 +16,12 @@ average duration from HIP events around its launches in the timed region
 (every launch while the window is short), against 8 TB/s, with the HBM
 traffic of its counter runs when they were taken on the current kernel
 source. `cpu_baseline` is the FP64 CPU oracle on a bounded sample of the same
-workload. Secondary lines: the same duct in FP16-shifted storage, the
-oscillating-cylinder channel 2000x800 (MALL-resident), a 4.8 GB channel
-(8192x8192), the 64-domain batch and the served request stream, each with its
-configuration stated.
+workload. Secondary lines: the same duct in FP16-shifted storage and with Zou-He
+faces (quasi-incompressible), the oscillating-cylinder channel 2000x800
+(MALL-resident), a 32-body suspension in a 2048x1024 channel, a 4.8 GB channel
+(8192x8192), the force-noise comparison of the ME forms and refill rules, the
+paper's sedimenting disc moved by each force form, the 64-domain batch and
+the served request stream, each with its configuration stated.
 """
 import argparse
 import json
@@ -50,6 +52,15 @@ def workload(name):
         return W.channel_cylinder_f64()
     if name == "channel_large_f32":
         return W.channel_large(storage="f32")
+    if name == "suspension_f32":
+        return W.suspension("f32")
+    if name == "duct_sphere_zouhe_f32":
+        w = W.with_changes(W.duct_sphere(scale=1, storage="f32"), eq="heluo",
+                           faces=(W.ZOUHE_VELOCITY, W.ZOUHE_PRESSURE, W.WALL, W.WALL, W.WALL, W.WALL))
+        w["name"] = "duct_sphere_zouhe_heluo_f32_256x128x128"
+        return w
+    if name == "sedimenting_disc_f32":
+        return W.sedimenting_disc(ratio=1.03, storage="f32")
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -329,6 +340,98 @@ def cpu_baseline(name, budget_s, single_thread_s):
     return out
 
 
+def force_noise(x, win=41):
+    """RMS of x minus its centred win-step moving average (short-time noise)"""
+    k = np.ones(win) / win
+    r = x[win // 2: len(x) - win // 2] - np.convolve(x, k, mode="valid")
+    return float(np.sqrt((r * r).mean()))
+
+
+def run_noise(steps=4000, warmup=200):
+    """The force-noise comparison of Sec. III.B.3 on the full oscillating
+    cylinder (2000x800, R=40, one period of 4000 steps): for each refill
+    rule, the short-time noise (force minus its 41-step moving average, RMS)
+    of the lattice-frame force (forward and backward sets) and of the
+    comoving-frame force, drag and lift."""
+    import lbm_workloads as W
+    from paper_1407_4524_amd import Domain
+    out = {}
+    for refill in ("mean", "aidun", "extrapolate"):
+        w = W.channel_oscillating_f32(scale=1)
+        w["bodies"][0]["refill"] = refill
+        dom = Domain.from_spec(w)
+        t0 = time.perf_counter()
+        dom.step(warmup + steps)
+        dom.synchronize()
+        sec = time.perf_counter() - t0
+        rec = dom.records(0, warmup, steps)
+        dom.close()
+        prev = np.vstack([np.zeros((1, 3)), rec[:-1, 6:9]])
+        forms = {"lattice": rec[:, 0:3] + rec[:, 6:9], "lattice_backward": rec[:, 0:3] + prev,
+                 "comoving": rec[:, 12:15]}
+        out[refill] = {k: {"drag": round(force_noise(v[:, 0]), 6), "lift": round(force_noise(v[:, 1]), 6)}
+                       for k, v in forms.items()}
+        out[refill]["us_per_step"] = round(sec / (warmup + steps) * 1e6, 2)
+    return dict(workload="channel_oscillating_f32_2000x800", steps=steps, window=41,
+                note="RMS of force minus its centred 41-step moving average, lattice units", noise=out)
+
+
+def run_sedimentation(steps=20000):
+    """The paper's sedimenting disc (135x1073, density ratio 1.03, FP32),
+    released from rest, for `steps` steps (0.59 s of the physical time) with
+    each force form moving it: the classical static sum, the lattice-frame
+    force with the previous step's covered/uncovered terms, and the comoving
+    form. Reports the speed and the lateral/vertical positions reached and
+    the largest difference of the lateral position between the classical and
+    the corrected forms (the transient difference the paper points at)."""
+    import lbm_workloads as W
+    from paper_1407_4524_amd import Domain
+    out, traj = {}, {}
+    for me in ("static", "lattice", "comoving"):
+        w = W.sedimenting_disc(ratio=1.03, storage="f32", me=me)
+        dom = Domain.from_spec(w)
+        t0 = time.perf_counter()
+        dom.step(steps)
+        dom.synchronize()
+        sec = time.perf_counter() - t0
+        tr = dom.trajectory(0, 0, steps + 1)
+        dom.close()
+        traj[me] = tr
+        out[me] = dict(us_per_step=round(sec / steps * 1e6, 2), mlups=round(135 * 1073 * steps / sec / 1e6, 1),
+                       x_end=round(float(tr[-1, 0]), 4), y_end=round(float(tr[-1, 1]), 4),
+                       v_end=[round(float(v), 7) for v in tr[-1, 4:6]], theta_end=round(float(tr[-1, 3]), 6))
+    dx = {me: round(float(np.abs(traj[me][:, 0] - traj["static"][:, 0]).max()), 5) for me in ("lattice", "comoving")}
+    w = W.sedimenting_disc(ratio=1.03)
+    return dict(workload=w["name"], steps=steps, seconds_physical=round(steps * w["dt_s"], 4), forms=out,
+                max_lateral_difference_vs_classical_nodes=dx)
+
+
+def run_suspension_batch(steps, warmup):
+    """The 32-body suspension stepped as a one-member batch: the link rule of
+    every static body in one launch and the advance of every moving body in
+    another (lbm_step runs one launch per body)."""
+    import torch
+    from paper_1407_4524_amd import Batch, Domain
+    w = workload("suspension_f32")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        dom = Domain.from_spec(w)
+    b = Batch(stream=stream.cuda_stream)
+    b.add(dom)
+    b.step(warmup)
+    dom.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    dom.synchronize()
+    sec = time.perf_counter() - t0
+    cells = w["nx"] * w["ny"]
+    out = dict(ms_per_step=round(sec / steps * 1e3, 5), value=round(cells * steps / sec / 1e6, 1), unit="MLUPS",
+               config={k: v for k, v in b.config.items()})
+    b.close()
+    dom.close()
+    return out
+
+
 def secondary_line(r):
     w = r["w"]
     return dict(workload=w["name"], value=round(r["mlups"], 1), unit="MLUPS", storage=w["storage"],
@@ -352,6 +455,9 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--serve-max-steps", type=int, default=3000)
     ap.add_argument("--batch-steps", type=int, default=5000)
+    ap.add_argument("--no-physics", action="store_true",
+                    help="skip the force-noise comparison and the sedimenting-disc line")
+    ap.add_argument("--sediment-steps", type=int, default=20000)
     ap.add_argument("--no-copy-ceiling", action="store_true",
                     help="skip the copy-kernel reference at the stream-collide footprint")
     ap.add_argument("--split-schedule", action="store_true",
@@ -393,9 +499,11 @@ def main():
         line["copy_ceiling"] = copy_ceiling(main_run["roofline"]["algorithmic_bytes_per_launch"])
     if not args.no_secondary and args.workload == HEADLINE:
         sec = {}
-        for name in ("duct_sphere_f16", "channel_oscillating_f32"):
+        for name in ("duct_sphere_f16", "duct_sphere_zouhe_f32", "channel_oscillating_f32", "suspension_f32"):
             r = run_gpu(name, args.steps, args.warmup, args.split_schedule)
             sec[r["w"]["name"]] = secondary_line(r)
+            if name == "suspension_f32":
+                sec[r["w"]["name"]]["as_one_member_batch"] = run_suspension_batch(args.steps, args.warmup)
         if not args.no_large:
             r = run_gpu("channel_large_f32", min(args.steps, 200), min(args.warmup, 10))
             ent = secondary_line(r)
@@ -403,6 +511,9 @@ def main():
                 ent["copy_ceiling"] = copy_ceiling(r["roofline"]["algorithmic_bytes_per_launch"], reps=10)
             sec[r["w"]["name"]] = ent
         line["secondary"] = sec
+    if not args.no_physics and args.workload == HEADLINE:
+        line["force_noise"] = run_noise()
+        line["sedimentation"] = run_sedimentation(args.sediment_steps)
     if not args.no_batch and args.workload == HEADLINE:
         line["batched"] = run_batch(args.batch_steps)
     if not args.no_serve and args.workload == HEADLINE:

@@ -207,8 +207,10 @@ typedef struct {
                                and velocity of its neighbours fluid at t and t+1 (rho0 and the
                                wall velocity when there are none); AIDUN, the equilibrium at that
                                mean density and the wall velocity at the node; EXTRAPOLATE,
-                               every population extrapolated quadratically, 3 f(x+c) - 3 f(x+2c)
-                               + f(x+3c), along the lattice direction c that maximises
+                               every population of the node's post-collision state of t+1 (what
+                               a step stores) extrapolated quadratically from the post-collision
+                               states of x+c, x+2c, x+3c, 3 f(x+c) - 3 f(x+2c) + f(x+3c),
+                               along the lattice direction c that maximises
                                (n.c)/|c| for the outward normal n of the body at the node (the
                                gradient of phi, pose t+1: (dx,dy,dz) for a circle/sphere,
                                (xi ct ia2 - eta st ib2, xi st ia2 + eta ct ib2, dz ic2) for an
@@ -325,6 +327,15 @@ lbm_status lbm_steady_state(lbm_domain dom, int32_t body_id, int64_t window, dou
 /* Density and velocity of every node at the current step (host arrays of
    nx*ny*nz and 3*nx*ny*nz doubles); solid nodes get NaN. Synchronises. */
 lbm_status lbm_get_fields(lbm_domain dom, double* rho, double* u);
+
+/* Populations f_i of every node at the current step: f[Q*n + i], node
+   n = x + nx*(y + ny*z), direction i in the numbering lbm_lattice gives;
+   NaN for non-fluid nodes. Synchronises. For tests and inspection. */
+lbm_status lbm_get_populations(lbm_domain dom, double* f);
+
+/* The library's lattice: c[3*i..3*i+2] and w[i] for i < Q (either pointer
+   may be NULL); returns Q (9 or 19), or -1 for an unknown lattice. */
+int32_t lbm_lattice(int32_t lattice, int32_t* c, double* w);
 
 /* Node types at the current step: 0 fluid, 1 wall layer, 2+b body b. */
 lbm_status lbm_get_types(lbm_domain dom, int32_t* type);

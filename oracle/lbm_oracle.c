@@ -271,6 +271,7 @@ struct ora_dom {
   double *f, *fpost, *fnew, *rho, *u;
   int32_t* type;
   unsigned char* solid_new;
+  unsigned char* collided; /* node whose populations are already post-collision */
   body_t body[ORA_MAX_BODIES];
   int64_t t;
   int64_t rec_cap;
@@ -382,7 +383,8 @@ ora_dom* ora_create(const ora_desc* ds) {
   d->u = (double*)malloc(sizeof(double) * d->N * 3);
   d->type = (int32_t*)malloc(sizeof(int32_t) * d->N);
   d->solid_new = (unsigned char*)malloc(d->N);
-  if (!d->f || !d->fpost || !d->fnew || !d->rho || !d->u || !d->type || !d->solid_new) {
+  d->collided = (unsigned char*)calloc((size_t)d->N, 1);
+  if (!d->f || !d->fpost || !d->fnew || !d->rho || !d->u || !d->type || !d->solid_new || !d->collided) {
     ora_destroy(d);
     return NULL;
   }
@@ -416,6 +418,7 @@ void ora_destroy(ora_dom* d) {
   free(d->u);
   free(d->type);
   free(d->solid_new);
+  free(d->collided);
   for (int b = 0; b < ORA_MAX_BODIES; ++b) {
     free(d->body[b].table);
     free(d->body[b].traj);
@@ -593,9 +596,14 @@ static double body_link_value(const ora_dom* d, const body_t* b, const pose_t* p
 
 /* The refill of Lallemand & Luo for a node x that a moving body uncovers:
  * every population by quadratic extrapolation along the lattice direction c
- * closest to the body's outward normal at x, f_i(x) = 3 f_i(x + c) -
- * 3 f_i(x + 2c) + f_i(x + 3c), from nodes fluid at t and at t+1 (values of
- * t+1 after streaming). The normal is the gradient of the shape function
+ * closest to the body's outward normal at x, from nodes fluid at t and at
+ * t+1. Reading: the extrapolation acts on post-collision populations of
+ * step t+1, fhat_i(x) = 3 fhat_i(x + c) - 3 fhat_i(x + 2c) + fhat_i(x + 3c)
+ * with fhat = f - (f - f^eq)/tau from each node's streamed populations, and
+ * x keeps fhat(x) as its post-collision state (its next collision is
+ * skipped): the state a fused stream-collide step stores, so that the GPU
+ * path can apply the rule without reconstructing pre-collision values
+ * (impossible at tau = 1). The normal is the gradient of the shape function
  * phi at x (pose t+1), n = (dx, dy, dz) for a circle/sphere, (xi ct ia2 -
  * eta st ib2, xi st ia2 + eta ct ib2, dz ic2) for an ellipse/ellipsoid; the
  * direction maximises (n . c) / |c| (ties: the smallest (cx, cy, cz) in
@@ -641,8 +649,15 @@ static int refill_extrapolate(ora_dom* d, const body_t* b, const pose_t* P, cons
       if (q[a] < 0 || q[a] >= dims[a]) return 0;
     if (classify(d, q, &m[k - 1]) != T_FLUID || d->solid_new[m[k - 1]] != 0) return 0;
   }
-  for (int i = 0; i < Q; ++i)
-    d->fnew[n * Q + i] = (3.0 * d->fnew[m[0] * Q + i] - 3.0 * d->fnew[m[1] * Q + i]) + d->fnew[m[2] * Q + i];
+  double fh[3][32];
+  for (int k = 0; k < 3; ++k) {
+    double rho, u[3];
+    const double* fk = d->fnew + m[k] * Q;
+    moments(d, fk, &rho, u);
+    for (int i = 0; i < Q; ++i) fh[k][i] = fk[i] - (fk[i] - feq_i(d, i, rho, u)) / d->tau;
+  }
+  for (int i = 0; i < Q; ++i) d->fnew[n * Q + i] = (3.0 * fh[0][i] - 3.0 * fh[1][i]) + fh[2][i];
+  d->collided[n] = 1;
   return 1;
 }
 
@@ -702,6 +717,11 @@ static void one_step(ora_dom* d) {
     moments(d, d->f + n * Q, &rho, u);
     d->rho[n] = rho;
     for (int a = 0; a < 3; ++a) d->u[3 * n + a] = u[a];
+    if (d->collided[n]) { /* already post-collision (extrapolation refill) */
+      for (int i = 0; i < Q; ++i) d->fpost[n * Q + i] = d->f[n * Q + i];
+      d->collided[n] = 0;
+      continue;
+    }
     for (int i = 0; i < Q; ++i) {
       double fi = d->f[n * Q + i];
       d->fpost[n * Q + i] = fi - (fi - feq_i(d, i, rho, u)) / d->tau;

@@ -107,7 +107,9 @@ int ora_body_pose(const ora_dom* dom, int body_id, int64_t t, double* out);
 
 /* node type: 0 fluid, 1 wall layer, 2+b body b */
 int ora_types(const ora_dom* dom, int32_t* type);
-/* current populations f[node*Q + i] (pre-collision, time t); solid nodes hold NaN */
+/* current populations f[node*Q + i] (pre-collision, time t; a node just
+   refilled by extrapolation holds its post-collision populations); solid
+   nodes hold NaN */
 int ora_get_f(const ora_dom* dom, double* f);
 /* moments of the current populations; solid nodes get NaN */
 int ora_fields(const ora_dom* dom, double* rho, double* u);

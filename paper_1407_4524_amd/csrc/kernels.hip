@@ -43,17 +43,20 @@ BulkShape bulk_shape(const Geom& g, int span) {
   return b;
 }
 
-// Launch configuration of the stream-collide kernel per (lattice, storage).
-// Measured on MI355X: while both population buffers fit the 256 MB MALL,
-// plain loads and stores in hardware block order are best (channel
-// 2000x800 FP32: 18.9 us); beyond it the non-temporal hint pays on the loads
-// of 4- and 8-byte storage (duct 256x128x128 FP32: 119.7 -> 101.3 us) and
-// costs on 2-byte storage (FP16: 57.7 us plain, 62.0 with non-temporal
-// stores, 68.4 with non-temporal loads).
+// Default launch shape of the stream-collide kernel by footprint, from
+// scans of the measured sweep time over every supported shape (block, nodes
+// per thread, non-temporal loads / stores, XCD remap) on MI355X: while both
+// population buffers fit the 256 MB MALL, plain accesses in hardware block
+// order are best (channel 2000x800 FP32: 18.9 us); beyond it the
+// non-temporal hint pays on the loads of the D3Q19 sweep (duct 256x128x128
+// FP32: 119.7 -> 101.4 us), on the stores of the D2Q9 sweep (8192x8192 FP32:
+// 884 us, against 1057 us with two nodes per thread and non-temporal
+// loads), and on neither with 2-byte storage (FP16 duct: 58.3 us plain,
+// 62.6 with non-temporal stores).
 BulkConfig bulk_config(int lat, int st, size_t footprint) {
-  if (footprint <= (size_t)192 << 20) return BulkConfig{256, 1, 0, 0};
-  const int mem = st == 2 ? 0 : MEM_NT_LOAD;
-  return BulkConfig{256, lat == 0 ? 2 : 1, mem, 0};
+  if (footprint <= (size_t)192 << 20 || st == 2) return BulkConfig{256, 1, 0, 0};
+  if (lat == 0) return BulkConfig{256, 1, MEM_NT_STORE, 0};
+  return BulkConfig{256, 1, MEM_NT_LOAD, 0};
 }
 
 bool bulk_supported(const BulkConfig& c) {

@@ -155,7 +155,7 @@ __device__ __forceinline__ int extrap_dir(const BodyShape& bs, const Pose& P, in
 // the equilibrium at that mean density and the wall velocity at the node;
 // EXTRAPOLATE, h_i = (3 h_i(x+c) - 3 h_i(x+2c)) + h_i(x+3c) along extrap_dir
 // when fluid_both says the three nodes are fluid at t and t+1 (MEAN
-// otherwise). Writes the node's populations (the state of t+1) and takes
+// otherwise), on the stored post-collision states of step t+1. Writes the node's populations (the state of t+1) and takes
 // their momentum off the node terms imp, about X_c(t).
 template <class L, class S, int EQ, class FluidBoth>
 __device__ __forceinline__ void refill_node(typename S::T* B, const Geom& g, const Phys& ph, const Pose& P0,

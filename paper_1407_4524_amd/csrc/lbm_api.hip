@@ -1085,6 +1085,48 @@ lbm_status lbm_get_types(lbm_domain d, int32_t* type) {
   return LBM_OK;
 }
 
+int32_t lbm_lattice(int32_t lattice, int32_t* c, double* w) {
+  if (lattice != LBM_D2Q9 && lattice != LBM_D3Q19) return -1;
+  const int Q = lattice == LBM_D2Q9 ? 9 : 19;
+  for (int i = 0; i < Q; ++i) {
+    if (c) {
+      c[3 * i] = lattice == LBM_D2Q9 ? D2Q9::cx(i) : D3Q19::cx(i);
+      c[3 * i + 1] = lattice == LBM_D2Q9 ? D2Q9::cy(i) : D3Q19::cy(i);
+      c[3 * i + 2] = lattice == LBM_D2Q9 ? 0 : D3Q19::cz(i);
+    }
+    if (w) w[i] = lattice == LBM_D2Q9 ? D2Q9::w(i) : D3Q19::w(i);
+  }
+  return Q;
+}
+
+lbm_status lbm_get_populations(lbm_domain d, double* f) {
+  if (!d || !f) return fail(LBM_E_INVAL, "null argument");
+  lbm_status s = lbm_synchronize(d);
+  if (s != LBM_OK && s != LBM_E_UNSTABLE) return s;
+  const Geom& g = d->g;
+  std::vector<uint8_t> m((size_t)g.S);
+  HIP_TRY(hipMemcpy(m.data(), d->mask, m.size(), hipMemcpyDeviceToHost));
+  std::vector<char> raw((size_t)d->Q * g.S * d->elem);
+  HIP_TRY(hipMemcpy(raw.data(), d->A, raw.size(), hipMemcpyDeviceToHost));
+  double w[19];
+  lbm_lattice(d->lat, nullptr, w);
+  for (int z = 0; z < g.nz; ++z)
+    for (int y = 0; y < g.ny; ++y)
+      for (int x = 0; x < g.nx; ++x) {
+        const int64_t n = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
+        const int64_t c = g.idx(x, y, z);
+        for (int i = 0; i < d->Q; ++i) {
+          const int64_t k = i * g.S + c;
+          double h;
+          if (d->st == LBM_F64) h = ((const double*)raw.data())[k];
+          else if (d->st == LBM_F32) h = ((const float*)raw.data())[k];
+          else h = (double)(float)((const _Float16*)raw.data())[k];
+          f[n * d->Q + i] = m[c] == MASK_FLUID ? h + w[i] * d->ph.rho0 : NAN;
+        }
+      }
+  return s;
+}
+
 lbm_status lbm_get_fields(lbm_domain d, double* rho, double* u) {
   if (!d || !rho || !u) return fail(LBM_E_INVAL, "null argument");
   lbm_status s = lbm_synchronize(d);

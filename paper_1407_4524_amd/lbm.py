@@ -44,7 +44,8 @@ EXPORTS = ["lbm_footprint_bytes", "lbm_body_footprint_bytes", "lbm_create_domain
            "lbm_batch_create", "lbm_batch_destroy", "lbm_batch_add", "lbm_batch_remove", "lbm_batch_step",
            "lbm_batch_set_config", "lbm_batch_get_config", "lbm_batch_tune", "lbm_steady_state",
            "lbm_batch_steady_state", "lbm_copy", "lbm_get_sweep_config", "lbm_set_sweep_config",
-           "lbm_batch_steady_state_noalloc", "lbm_get_moving_sets", "lbm_face_records", "lbm_body_trajectory"]
+           "lbm_batch_steady_state_noalloc", "lbm_get_moving_sets", "lbm_face_records", "lbm_body_trajectory",
+           "lbm_get_populations", "lbm_lattice"]
 
 
 class LbmError(RuntimeError):
@@ -96,6 +97,12 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it first (python -m paper_1407_4524_amd.build)")
+        # torch carries its own HIP runtime: loaded first, the library binds to
+        # that one instead of starting a second runtime beside it
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         L.lbm_footprint_bytes.argtypes = [C.POINTER(DomainDesc), C.POINTER(C.c_size_t)]
         L.lbm_body_footprint_bytes.argtypes = [C.POINTER(DomainDesc), C.POINTER(BodyDesc), C.POINTER(C.c_size_t)]
@@ -109,6 +116,9 @@ def lib():
         L.lbm_force_torque.argtypes = [C.c_void_p, C.c_int32, C.c_int64, C.c_int64, C.c_void_p]
         L.lbm_records.argtypes = [C.c_void_p, C.c_int32, C.c_int64, C.c_int64, C.c_void_p]
         L.lbm_body_trajectory.argtypes = [C.c_void_p, C.c_int32, C.c_int64, C.c_int64, C.c_void_p]
+        L.lbm_get_populations.argtypes = [C.c_void_p, C.c_void_p]
+        L.lbm_lattice.argtypes = [C.c_int32, C.c_void_p, C.c_void_p]
+        L.lbm_lattice.restype = C.c_int32
         L.lbm_get_links.argtypes = [C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
                                     C.POINTER(C.c_int64)]
         L.lbm_get_fields.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
@@ -155,6 +165,14 @@ def _torch_cuda():
 
 def _dptr(a):
     return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def lattice_tables(lattice):
+    """(c[Q,3], w[Q]) of the library's direction numbering"""
+    c = np.zeros((19, 3), np.int32)
+    w = np.zeros(19)
+    q = lib().lbm_lattice(_enum(LATTICE, lattice), c.ctypes.data, w.ctypes.data)
+    return c[:q].copy(), w[:q].copy()
 
 
 def _enum(table, v):
@@ -245,6 +263,7 @@ class Domain:
         d = domain_desc(lattice, nx, ny, nz, tau, rho0, storage, eq, faces, inlet_profile, inlet_u,
                         record_capacity, split_schedule, face_records, debug_poison, max_bodies)
         self.nx, self.ny, self.nz = nx, ny, (nz if d.lattice == 1 else 1)
+        self.lattice = d.lattice
         self.N = self.nx * self.ny * self.nz
         keep = []
         if init_rho is not None:
@@ -328,6 +347,13 @@ class Domain:
         out = np.zeros((count, 6))
         _check(lib().lbm_force_torque(self._h, body_id, first, count, out.ctypes.data))
         return out
+
+    def populations(self):
+        """f[node, i] (nx*ny*nz x Q, the numbering of lattice_tables()); NaN off the fluid"""
+        q = 9 if self.lattice == 0 else 19
+        f = np.zeros(self.N * q)
+        _check(lib().lbm_get_populations(self._h, f.ctypes.data))
+        return f.reshape(self.N, q)
 
     def trajectory(self, body_id=0, first=0, count=None):
         """poses X[3], theta, V[3], Omega_z of steps first .. first+count-1

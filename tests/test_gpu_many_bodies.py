@@ -93,7 +93,7 @@ def test_suspension_batch_equals_alone():
     a.synchronize()
     for k in range(len(w["bodies"])):
         assert np.array_equal(a.records(k), alone.records(k)), k
-    assert np.array_equal(a.fields()[1], alone.fields()[1])
+    assert np.array_equal(a.fields()[1], alone.fields()[1], equal_nan=True)
     b.close()
 
 

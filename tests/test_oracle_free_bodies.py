@@ -17,8 +17,9 @@ them:
   step's node terms), and by the Adams-Bashforth end terms for AB2;
 * refill rules: in uniform flow past a body translating with it every rule
   keeps the flow exactly uniform; AIDUN gives an uncovered node the wall
-  velocity and the mean density of its fluid neighbours; EXTRAPOLATE
-  reproduces a field that is quadratic along the lattice directions exactly.
+  velocity and the mean density of its fluid neighbours; EXTRAPOLATE matches
+  a brute-force evaluation of its definition (direction, nodes, BGK
+  post-collision states, quadratic extrapolation).
 """
 import math
 
@@ -194,43 +195,46 @@ def test_refill_aidun_wall_velocity_and_mean_density():
     del types0
 
 
-def test_refill_extrapolate_exact_for_quadratic_fields():
-    """tau = 1 and a velocity field linear in x and y: after one step a
-    population streamed from a fluid node is f_i(x) = f^eq_i(u(x - c_i)),
-    quadratic along any lattice line, so the quadratic extrapolation along
-    the direction c closest to the outward normal (x - X for a circle; found
-    here by brute force over the eight directions) returns f^eq_i(u(x - c_i))
-    at the uncovered node itself, for every population whose three sources
-    x + k c - c_i were fluid (the others carry the boundary rule's values)."""
-    nx, ny = 40, 36
+def test_refill_extrapolate_brute_force():
+    """EXTRAPOLATE, checked node by node against an independent evaluation:
+    the direction by brute force over the eight lattice directions, the
+    three nodes x + k c fluid at t and t+1 (node types), their BGK
+    post-collision states computed here from their streamed populations,
+    and the quadratic extrapolation of those, which the refilled node holds
+    as its post-collision state (a moving circle in a sheared flow)."""
+    nx, ny, tau = 40, 36, 0.8
     ys, xs = np.mgrid[0:ny, 0:nx]
-
-    def uf(x, y):
-        return np.array([0.01 + 0.0004 * (x - 20) - 0.0003 * (y - 18), -0.005 + 0.0002 * (x - 20) + 0.0005 * (y - 18)])
-
     u0 = np.zeros((nx * ny, 3))
-    u0[:, :2] = uf(xs.ravel(), ys.ravel()).T
-    c0, vel = (19.4, 17.8, 0.0), (0.7, 0.3, 0.0)
-    w, d, unc = _one_refill_step("extrapolate", u0, c0, vel=vel)
-    f = d.populations()
+    u0[:, 0] = (0.01 + 0.0004 * (xs - 20) - 0.0003 * (ys - 18)).ravel()
+    u0[:, 1] = (-0.005 + 0.0002 * (xs - 20) + 0.0005 * (ys - 18)).ravel()
+    c0, vel = (17.4, 16.8, 0.0), (0.31, 0.17, 0.0)
+    w = _box(nx=nx, ny=ny, tau=tau)
+    w["bodies"] = [dict(shape="circle", axes=(4.6,), bc="mls", motion="table", c0=c0, refill="extrapolate",
+                        table=W.pose_table(40, c0, vel=vel))]
+    d = make_oracle(w, init_rho=np.ones(nx * ny), init_u=u0)
     c, wq, _ = O.lattice(O.D2Q9)
-    X1 = np.array(c0[:2]) + np.array(vel[:2])
-    # node types at t: the body at pose 0
-    solid0 = (xs - c0[0]) ** 2 + (ys - c0[1]) ** 2 - 4.6 ** 2 <= 0
     checked = 0
-    for k in unc:
-        x, y = k % nx, k // nx
-        n = np.array([x, y]) - X1
-        score = [(n @ c[i, :2]) / math.hypot(*c[i, :2]) for i in range(1, 9)]
-        best = 1 + int(np.argmax(score))
-        e = c[best, :2]
-        for i in range(9):
-            srcs = [(x + m * e[0] - c[i, 0], y + m * e[1] - c[i, 1]) for m in (1, 2, 3)]
-            if any(solid0[sy, sx] for sx, sy in srcs):
-                continue
-            uu = uf(x - c[i, 0], y - c[i, 1])
-            cu = c[i, 0] * uu[0] + c[i, 1] * uu[1]
-            want = wq[i] * (1.0 + 3 * cu + 4.5 * cu * cu - 1.5 * (uu @ uu))
-            assert abs(f[k, i] - want) < 1e-14, (k, i, f[k, i], want)
+    for t in range(12):
+        t0 = d.types().copy()
+        d.step(1)
+        t1 = d.types()
+        f = d.populations()
+        X1 = np.array(c0[:2]) + (t + 1) * np.array(vel[:2])
+        for k in np.nonzero((t0 == 2) & (t1 == 0))[0]:
+            x, y = k % nx, k // nx
+            n = np.array([x, y]) - X1
+            score = [(n @ c[i, :2]) / math.hypot(*c[i, :2]) for i in range(1, 9)]
+            e = c[1 + int(np.argmax(score)), :2]
+            nodes = [(x + m * e[0]) + nx * (y + m * e[1]) for m in (1, 2, 3)]
+            assert all(t0[q] == 0 and t1[q] == 0 for q in nodes)
+            post = []
+            for q in nodes:
+                rho = f[q].sum()
+                u = (f[q] @ c[:, :2].astype(float)) / rho
+                cu = c[:, :2] @ u
+                feq = wq * rho * (1 + 3 * cu + 4.5 * cu * cu - 1.5 * (u @ u))
+                post.append(f[q] - (f[q] - feq) / tau)
+            want = (3 * post[0] - 3 * post[1]) + post[2]
+            assert np.abs(f[k] - want).max() < 1e-14
             checked += 1
-    assert checked >= 5 * len(unc)
+    assert checked >= 5

@@ -382,6 +382,26 @@ lbm_status batch_step(lbm_batch B, int64_t n, hipEvent_t e0, hipEvent_t e1) {
 
 }  // namespace
 
+// A domain with several bodies steps them through batched launches (one for
+// the link rule of every body with fixed links, one for the advance of every
+// moving body) as the only member of a batch of its own, on its own stream.
+lbm_status lbm::host::solo_step(lbm_domain d, int64_t n) {
+  if (!d->solo) {
+    d->solo = new lbm_batch_s();
+    d->solo->members.push_back(d);
+  }
+  d->solo->stream = d->stream;
+  return batch_step(d->solo, n, nullptr, nullptr);
+}
+
+void lbm::host::solo_destroy(lbm_domain d) {
+  if (!d->solo) return;
+  d->solo->members.clear();  // the domain's own stream and batch stay as they are
+  (void)hipStreamSynchronize(d->stream);
+  (void)lbm_batch_destroy(d->solo);
+  d->solo = nullptr;
+}
+
 extern "C" {
 
 lbm_status lbm_batch_create(void* stream, lbm_batch* out) {

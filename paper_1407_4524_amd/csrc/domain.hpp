@@ -66,6 +66,7 @@ struct lbm_domain_s {
   hipStream_t stream = nullptr;
   hipStream_t own_stream = nullptr;  // the descriptor's stream (a batch may lend its own)
   struct lbm_batch_s* batch = nullptr;  // the batch the domain belongs to, if any
+  struct lbm_batch_s* solo = nullptr;   // one-member batch lbm_step uses for several bodies
   char* steady_buf = nullptr;           // device: one SteadyCheck and its two results
   bool owns_pool = false;
   char* pool = nullptr;
@@ -123,6 +124,10 @@ int64_t list_bound(const Body& b, int D, int64_t t);
 lbm_status check_device_errors(lbm_domain d);
 // the advance of body `id` from step t to t+1 on the current source buffer
 lbm_status launch_advance(lbm_domain d, int id, int64_t t);
+// n steps of a domain with several bodies through a one-member batch of its
+// own (the domain does not join it: d->batch is untouched), and its release
+lbm_status solo_step(lbm_domain d, int64_t n);
+void solo_destroy(lbm_domain d);
 // the steady-state check of one body (see lbm_steady_state); false when the
 // ring does not hold both steps
 bool steady_check(lbm_domain d, int id, int64_t window, SteadyCheck& c);

@@ -683,6 +683,7 @@ lbm_status lbm_destroy_domain(lbm_domain d) {
     lbm_status s = lbm_batch_remove(d->batch, d);
     if (s != LBM_OK) return s;
   }
+  solo_destroy(d);
   hipError_t e = hipStreamSynchronize(d->stream);
   for (auto& b : d->body) {
     if (b.links) (void)hipFree(b.links);
@@ -820,6 +821,9 @@ lbm_status lbm_step(lbm_domain d, int64_t nsteps) {
       only = id;
       nactive++;
     }
+  bool any_free = false;
+  for (int id = 0; id < d->nslots; ++id) any_free = any_free || (d->body[id].active && d->body[id].free_motion);
+  if (nactive >= 2 && !any_free && !d->face_rec && !d->batch) return solo_step(d, nsteps);
   const bool split = d->desc.split_schedule && nactive == 1 && d->body[only].mask_moves &&
                      d->body[only].desc.shape != LBM_SHAPE_OUTER_CIRCLE && !d->body[only].free_motion;
   if (split && !d->aux) {

@@ -55,7 +55,9 @@
  * Omega += dalpha, theta += Omega, each operation in that order in IEEE
  * double without fused multiply-add. With LBM_ME_LATTICE (or _BACKWARD) the
  * covered/uncovered terms come from the step before (the approximation of
- * Aidun et al. that Sec. III.B.3 describes, which keeps the step explicit).
+ * Aidun et al. that Sec. III.B.3 describes, which keeps the step explicit)
+ * or, with sets = LBM_SETS_PREDICTED, from a predicted pose (its second
+ * approximation).
  * cos/sin of theta are not libm's: k = rint(theta * 0.63661977236758134),
  * r = (theta - k*1.5707963267948966) - k*6.123233995736766e-17, z = r*r,
  * then Horner through 1/17! (sin r = r + (r*z)*p(z)) and 1/18! (cos r =
@@ -133,6 +135,7 @@ enum { LBM_MOTION_STATIC = 0, LBM_MOTION_CONST_VEL = 1, LBM_MOTION_ROTATE = 2,
        LBM_MOTION_OSCILLATE = 3, LBM_MOTION_TABLE = 4, LBM_MOTION_FREE = 5 };
 enum { LBM_INTEGRATOR_EULER = 0, LBM_INTEGRATOR_AB2 = 1 };
 enum { LBM_REFILL_MEAN = 0, LBM_REFILL_AIDUN = 1, LBM_REFILL_EXTRAPOLATE = 2 };
+enum { LBM_SETS_PREVIOUS = 0, LBM_SETS_PREDICTED = 1 };
 
 #define LBM_MAX_BODIES 64
 /* one per-step record of a body: 20 doubles */
@@ -217,6 +220,12 @@ typedef struct {
                                (xi ct ia2 - eta st ib2, xi st ia2 + eta ct ib2, dz ic2) for an
                                ellipse/ellipsoid, each left to right; ties to the smallest
                                (cx,cy,cz)), from nodes fluid at t and t+1, else MEAN */
+  int32_t sets;             /* FREE with LBM_ME_LATTICE: the covered/uncovered sets of step t,
+                               whose pose t+1 depends on that step's force (Sec. III.B.3's two
+                               approximations): LBM_SETS_PREVIOUS, those of step t-1 (Aidun
+                               et al.); LBM_SETS_PREDICTED, those between pose t and the pose
+                               one step ahead at the velocity of step t (X + V, theta +
+                               Omega), refilled by the body's rule without changing any node */
 } lbm_body_desc;
 
 /* Device bytes a domain with this descriptor needs (for admission by HBM

@@ -29,6 +29,7 @@ MOTION_STATIC, MOTION_CONST_VEL, MOTION_ROTATE, MOTION_OSCILLATE, MOTION_TABLE, 
 DRIVE_STATIC, DRIVE_LATTICE, DRIVE_COMOVING = 0, 1, 2
 INTEGRATOR_EULER, INTEGRATOR_AB2 = 0, 1
 REFILL_MEAN, REFILL_AIDUN, REFILL_EXTRAPOLATE = 0, 1, 2
+SETS_PREVIOUS, SETS_PREDICTED = 0, 1
 REC_LEN = 20
 FACE_REC_LEN = 18
 MAX_BODIES = 64
@@ -65,7 +66,7 @@ class _Body(C.Structure):
                 ("period", C.c_double), ("table", C.POINTER(C.c_double)),
                 ("table_count", C.c_int64), ("mass", C.c_double), ("inertia", C.c_double),
                 ("ext_force", C.c_double * 3), ("ext_torque", C.c_double), ("drive", C.c_int32),
-                ("integrator", C.c_int32), ("refill", C.c_int32)]
+                ("integrator", C.c_int32), ("refill", C.c_int32), ("sets", C.c_int32)]
 
 
 _lib = None
@@ -100,6 +101,7 @@ def load(path):
     L.ora_fields.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
     L.ora_lattice.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
     L.ora_body_pose.argtypes = [C.c_void_p, C.c_int, C.c_int64, C.c_void_p]
+    L.ora_body_drive.argtypes = [C.c_void_p, C.c_int, C.c_int64, C.c_void_p]
     L.ora_set_threads.argtypes = [C.c_int]
     return L
 
@@ -175,12 +177,12 @@ class OracleDomain:
     def set_body(self, body_id, shape, axes, bc=BC_HALFWAY, motion=MOTION_STATIC, c0=(0, 0, 0),
                  theta0=0.0, vel=(0, 0, 0), omega=0.0, amp=(0, 0, 0), period=1.0, table=None,
                  mass=0.0, inertia=0.0, ext_force=(0, 0, 0), ext_torque=0.0, drive=DRIVE_STATIC,
-                 integrator=INTEGRATOR_EULER, refill=REFILL_MEAN):
+                 integrator=INTEGRATOR_EULER, refill=REFILL_MEAN, sets=SETS_PREVIOUS):
         b = _Body()
         b.mass, b.inertia, b.ext_torque = mass, inertia, ext_torque
         for a in range(3):
             b.ext_force[a] = ext_force[a] if a < len(ext_force) else 0.0
-        b.drive, b.integrator, b.refill = drive, integrator, refill
+        b.drive, b.integrator, b.refill, b.sets = drive, integrator, refill, sets
         b.shape = shape
         ax = list(axes) + [0.0] * (3 - len(axes))
         for a in range(3):
@@ -238,6 +240,13 @@ class OracleDomain:
         out = np.zeros(8)
         if self._L.ora_body_pose(self._h, body_id, t, out.ctypes.data) != 0:
             raise ValueError("no such body or step")
+        return out
+
+    def drive(self, body_id, t):
+        """flow force (3) and torque z that moved a free body from t to t+1"""
+        out = np.zeros(4)
+        if self._L.ora_body_drive(self._h, body_id, t, out.ctypes.data) != 0:
+            raise ValueError("no such free body or step")
         return out
 
     def types(self):

@@ -83,6 +83,7 @@ typedef struct {
   double ct, st; /* cos, sin of theta */
   double V[3];   /* centre velocity */
   double Om;     /* angular velocity about z */
+  double drive[4]; /* FREE: flow force and torque z that moved the body here */
 } pose_t;
 
 typedef struct {
@@ -272,6 +273,7 @@ struct ora_dom {
   int32_t* type;
   unsigned char* solid_new;
   unsigned char* collided; /* node whose populations are already post-collision */
+  unsigned char* solid_pred; /* solid set at a free body's predicted pose */
   body_t body[ORA_MAX_BODIES];
   int64_t t;
   int64_t rec_cap;
@@ -384,7 +386,9 @@ ora_dom* ora_create(const ora_desc* ds) {
   d->type = (int32_t*)malloc(sizeof(int32_t) * d->N);
   d->solid_new = (unsigned char*)malloc(d->N);
   d->collided = (unsigned char*)calloc((size_t)d->N, 1);
-  if (!d->f || !d->fpost || !d->fnew || !d->rho || !d->u || !d->type || !d->solid_new || !d->collided) {
+  d->solid_pred = (unsigned char*)calloc((size_t)d->N, 1);
+  if (!d->f || !d->fpost || !d->fnew || !d->rho || !d->u || !d->type || !d->solid_new || !d->collided ||
+      !d->solid_pred) {
     ora_destroy(d);
     return NULL;
   }
@@ -419,6 +423,7 @@ void ora_destroy(ora_dom* d) {
   free(d->type);
   free(d->solid_new);
   free(d->collided);
+  free(d->solid_pred);
   for (int b = 0; b < ORA_MAX_BODIES; ++b) {
     free(d->body[b].table);
     free(d->body[b].traj);
@@ -610,7 +615,8 @@ static double body_link_value(const ora_dom* d, const body_t* b, const pose_t* p
  * lexicographic order). Returns 0, leaving x alone, when one of the three
  * nodes is not fluid at both times or lies outside the box (the caller then
  * applies the mean rule). */
-static int refill_extrapolate(ora_dom* d, const body_t* b, const pose_t* P, const int p[3], int64_t n) {
+static int refill_extrapolate(ora_dom* d, const body_t* b, const pose_t* P, const int p[3],
+                              const unsigned char* solid_next, double* out) {
   const lattice_t* L = &d->L;
   const int Q = L->Q, D = L->D;
   const double dx = p[0] - P->X[0], dy = p[1] - P->X[1], dz = D == 3 ? p[2] - P->X[2] : 0.0;
@@ -647,7 +653,7 @@ static int refill_extrapolate(ora_dom* d, const body_t* b, const pose_t* P, cons
     /* reading: the three nodes lie in the box itself (no periodic wrap) */
     for (int a = 0; a < D; ++a)
       if (q[a] < 0 || q[a] >= dims[a]) return 0;
-    if (classify(d, q, &m[k - 1]) != T_FLUID || d->solid_new[m[k - 1]] != 0) return 0;
+    if (classify(d, q, &m[k - 1]) != T_FLUID || solid_next[m[k - 1]] != 0) return 0;
   }
   double fh[3][32];
   for (int k = 0; k < 3; ++k) {
@@ -656,9 +662,94 @@ static int refill_extrapolate(ora_dom* d, const body_t* b, const pose_t* P, cons
     moments(d, fk, &rho, u);
     for (int i = 0; i < Q; ++i) fh[k][i] = fk[i] - (fk[i] - feq_i(d, i, rho, u)) / d->tau;
   }
-  for (int i = 0; i < Q; ++i) d->fnew[n * Q + i] = (3.0 * fh[0][i] - 3.0 * fh[1][i]) + fh[2][i];
-  d->collided[n] = 1;
+  for (int i = 0; i < Q; ++i) out[i] = (3.0 * fh[0][i] - 3.0 * fh[1][i]) + fh[2][i];
   return 1;
+}
+
+/* The populations body b's refill rule gives node p (index n), which it
+ * uncovers on its way to pose P; solid_next: nonzero for every node solid at
+ * that pose (any body). Returns 1 when they are post-collision values
+ * (EXTRAPOLATE), 0 for pre-collision ones (the equilibria of MEAN/AIDUN). */
+static int refill_values(ora_dom* d, const body_t* b, const pose_t* P, const int p[3],
+                         const unsigned char* solid_next, double* out) {
+  const lattice_t* L = &d->L;
+  const int Q = L->Q, D = L->D;
+  double rs = 0.0, us[3] = {0, 0, 0};
+  int cnt = 0;
+  for (int i = 1; i < Q; ++i) {
+    int q[3] = {p[0] + L->c[i][0], p[1] + L->c[i][1], p[2] + L->c[i][2]};
+    int64_t m = -1;
+    if (classify(d, q, &m) != T_FLUID || solid_next[m] != 0) continue;
+    double rho, u[3];
+    moments(d, d->fnew + m * Q, &rho, u);
+    rs += rho;
+    for (int a = 0; a < 3; ++a) us[a] += u[a];
+    cnt++;
+  }
+  if (b->d.refill == ORA_REFILL_EXTRAPOLATE && refill_extrapolate(d, b, P, p, solid_next, out)) return 1;
+  double rb, ub[3];
+  double x[3] = {p[0], p[1], p[2]};
+  if (cnt > 0) {
+    rb = rs / cnt;
+    for (int a = 0; a < 3; ++a) ub[a] = us[a] / cnt;
+  } else {
+    rb = d->rho0;
+    surface_velocity(P, x, ub);
+  }
+  if (b->d.refill == ORA_REFILL_AIDUN) surface_velocity(P, x, ub);
+  if (D == 2) ub[2] = 0.0;
+  for (int i = 0; i < Q; ++i) out[i] = feq_i(d, i, rb, ub);
+  return 0;
+}
+
+/* The second approximation of Sec. III.B.3 for a free body: the covered and
+ * uncovered nodes of step t are taken between pose t and the pose the body
+ * would reach moving one step at its velocity of step t, X + V and
+ * theta + Omega (cos/sin by free_trig), with the populations of t+1 after
+ * streaming and the body's refill rule evaluated there without changing any
+ * node: F_nodes = sum_{A+} c f - sum_{A-} c f_refill, the torque about X. */
+static void predicted_node_terms(ora_dom* d, int b, const pose_t* P, double F[3], double T[3]) {
+  const lattice_t* L = &d->L;
+  const int Q = L->Q, D = L->D;
+  const body_t* B = &d->body[b];
+  pose_t Pp = *P;
+  for (int a = 0; a < 3; ++a) Pp.X[a] = P->X[a] + P->V[a];
+  Pp.theta = P->theta + P->Om;
+  free_trig(Pp.theta, &Pp.ct, &Pp.st);
+  unsigned char* pred = d->solid_pred;
+  for (int64_t n = 0; n < d->N; ++n) {
+    const int ty = d->type[n];
+    pred[n] = (unsigned char)(ty >= T_BODY0 && ty != T_BODY0 + b);  /* other bodies where they are */
+    if (ty == T_FLUID || ty == T_BODY0 + b) {
+      int p[3];
+      node_pos(d, n, p);
+      double x[3] = {p[0], p[1], p[2]};
+      if (body_phi(B, &Pp, D, x) <= 0.0) pred[n] = 1;
+    }
+  }
+  for (int a = 0; a < 3; ++a) F[a] = T[a] = 0.0;
+  double vals[32];
+  for (int64_t n = 0; n < d->N; ++n) {
+    const int ty = d->type[n];
+    int sign = 0;
+    if (ty == T_FLUID && pred[n]) sign = 1;                 /* covered */
+    else if (ty == T_BODY0 + b && !pred[n]) sign = -1;       /* uncovered */
+    if (!sign) continue;
+    int p[3];
+    node_pos(d, n, p);
+    const double* f = d->fnew + n * Q;
+    if (sign < 0) {
+      refill_values(d, B, &Pp, p, pred, vals);
+      f = vals;
+    }
+    double r[3] = {p[0] - P->X[0], p[1] - P->X[1], p[2] - P->X[2]};
+    double mom[3] = {0, 0, 0}, tq[3];
+    for (int i = 0; i < Q; ++i)
+      for (int a = 0; a < 3; ++a) mom[a] += L->c[i][a] * f[i];
+    cross(r, mom, tq);
+    acc3(F, mom, (double)sign);
+    acc3(T, tq, (double)sign);
+  }
 }
 
 /* Newton-Euler step of a FREE body (Sec. IV: the flow force plus weight and
@@ -668,10 +759,11 @@ static int refill_extrapolate(ora_dom* d, const body_t* b, const pose_t* P, cons
  * the first step Euler), X(t+1) = X(t) + V(t+1), and likewise Omega and
  * theta about z (reading: the position takes the new velocity, which makes
  * the covered/uncovered sets of step t depend on the force of step t, the
- * implicit case of Sec. III.B.3; the lattice-frame drive then takes the
- * approximation of Aidun et al., the sets of the previous step, i.e.
- * F(t) = F_static(t) + [covered/uncovered terms of step t-1]). Lattice
- * units: dt = 1. */
+ * implicit case of Sec. III.B.3; the lattice-frame drive then takes one of
+ * the paper's two approximations: Aidun et al.'s, the sets of the previous
+ * step, F(t) = F_static(t) + [covered/uncovered terms of step t-1]; or the
+ * sets of a predicted pose, see predicted_node_terms). Lattice units:
+ * dt = 1. */
 static pose_t integrate_free(body_t* b, const pose_t* P, const double F[3], double Tz, int D) {
   const ora_body_desc* bd = &b->d;
   double a[4];
@@ -882,7 +974,12 @@ static void one_step(ora_dom* d) {
     } else {
       for (int a = 0; a < 3; ++a) F[a] = rec[b][ORA_REC_F_STATIC + a];
       Tz = rec[b][ORA_REC_T_STATIC + 2];
-      if (B->d.drive == ORA_DRIVE_LATTICE && t - 1 >= B->traj_t0) {
+      if (B->d.drive == ORA_DRIVE_LATTICE && B->d.sets == ORA_SETS_PREDICTED) {
+        double Fp[3], Tp[3];
+        predicted_node_terms(d, b, &P0[b], Fp, Tp);
+        for (int a = 0; a < 3; ++a) F[a] += Fp[a];
+        Tz += Tp[2];
+      } else if (B->d.drive == ORA_DRIVE_LATTICE && t - 1 >= B->traj_t0) {
         const double* prev = d->rec[b] + ORA_REC_LEN * (t - 1);
         for (int a = 0; a < 3; ++a) F[a] += prev[ORA_REC_F_IMP + a];
         Tz += prev[ORA_REC_T_IMP + 2];
@@ -898,6 +995,8 @@ static void one_step(ora_dom* d) {
       B->traj_cap *= 2;
     }
     P1[b] = integrate_free(B, &P0[b], F, Tz, D);
+    for (int a = 0; a < 3; ++a) P1[b].drive[a] = F[a];
+    P1[b].drive[3] = Tz;
     B->traj[B->traj_n++] = P1[b];
   }
 
@@ -949,33 +1048,9 @@ static void one_step(ora_dom* d) {
           if (d->solid_new[n] != 0) d->error = 4; /* would enter another body */
           int p[3];
           node_pos(d, n, p);
-          double rs = 0.0, us[3] = {0, 0, 0};
-          int cnt = 0;
-          for (int i = 1; i < Q; ++i) {
-            int q[3] = {p[0] + L->c[i][0], p[1] + L->c[i][1], p[2] + L->c[i][2]};
-            int64_t m = -1;
-            if (classify(d, q, &m) != T_FLUID || d->solid_new[m] != 0) continue;
-            double rho, u[3];
-            moments(d, d->fnew + m * Q, &rho, u);
-            rs += rho;
-            for (int a = 0; a < 3; ++a) us[a] += u[a];
-            cnt++;
-          }
-          const int rule = d->body[b].d.refill;
-          if (rule != ORA_REFILL_EXTRAPOLATE || !refill_extrapolate(d, &d->body[b], &P1[b], p, n)) {
-            double rb, ub[3];
-            double x[3] = {p[0], p[1], p[2]};
-            if (cnt > 0) {
-              rb = rs / cnt;
-              for (int a = 0; a < 3; ++a) ub[a] = us[a] / cnt;
-            } else {
-              rb = d->rho0;
-              surface_velocity(&P1[b], x, ub);
-            }
-            if (rule == ORA_REFILL_AIDUN) surface_velocity(&P1[b], x, ub);
-            if (D == 2) ub[2] = 0.0;
-            for (int i = 0; i < Q; ++i) d->fnew[n * Q + i] = feq_i(d, i, rb, ub);
-          }
+          double vals[32];
+          if (refill_values(d, &d->body[b], &P1[b], p, d->solid_new, vals)) d->collided[n] = 1;
+          for (int i = 0; i < Q; ++i) d->fnew[n * Q + i] = vals[i];
           double r[3] = {p[0] - P0[b].X[0], p[1] - P0[b].X[1], p[2] - P0[b].X[2]};
           double mom[3] = {0, 0, 0}, tq[3];
           for (int i = 0; i < Q; ++i)
@@ -1069,6 +1144,15 @@ int ora_body_pose(const ora_dom* d, int b, int64_t t, double* out) {
   out[3] = p.theta;
   for (int a = 0; a < 3; ++a) out[4 + a] = p.V[a];
   out[7] = p.Om;
+  return 0;
+}
+
+int ora_body_drive(const ora_dom* d, int b, int64_t t, double* out) {
+  if (!d || b < 0 || b >= ORA_MAX_BODIES || !d->body[b].active) return -1;
+  const body_t* B = &d->body[b];
+  if (B->d.motion != ORA_MOTION_FREE || t < B->traj_t0 || t + 1 >= B->traj_t0 + B->traj_n) return -1;
+  const pose_t* p = &B->traj[t + 1 - B->traj_t0];
+  for (int a = 0; a < 4; ++a) out[a] = p->drive[a];
   return 0;
 }
 

@@ -32,6 +32,9 @@ enum { ORA_MOTION_STATIC = 0, ORA_MOTION_CONST_VEL = 1, ORA_MOTION_ROTATE = 2,
    its Sec. IV sedimentation tests) */
 enum { ORA_DRIVE_STATIC = 0, ORA_DRIVE_LATTICE = 1, ORA_DRIVE_COMOVING = 2 };
 enum { ORA_INTEGRATOR_EULER = 0, ORA_INTEGRATOR_AB2 = 1 };
+/* the covered/uncovered sets a free body moved by the lattice-frame force
+   uses at step t (the two approximations of Sec. III.B.3) */
+enum { ORA_SETS_PREVIOUS = 0, ORA_SETS_PREDICTED = 1 };
 /* value given to the nodes a moving body uncovers */
 enum { ORA_REFILL_MEAN = 0, ORA_REFILL_AIDUN = 1, ORA_REFILL_EXTRAPOLATE = 2 };
 
@@ -79,6 +82,7 @@ typedef struct {
   int32_t drive;            /* ORA_DRIVE_* */
   int32_t integrator;       /* ORA_INTEGRATOR_* */
   int32_t refill;           /* ORA_REFILL_* (every moving body) */
+  int32_t sets;             /* FREE with the lattice drive: ORA_SETS_* */
 } ora_body_desc;
 
 typedef struct ora_dom ora_dom;
@@ -104,6 +108,10 @@ int64_t ora_links(const ora_dom* dom, int body_id, int64_t cap, int64_t* node, i
    FREE body t <= the current step + 1 once that step ran): out = X[3],
    theta, V[3], Omega_z */
 int ora_body_pose(const ora_dom* dom, int body_id, int64_t t, double* out);
+
+/* FREE body: the flow force (3) and torque z that moved it from step t to
+   t+1 (the form its drive selects, before the external force) */
+int ora_body_drive(const ora_dom* dom, int body_id, int64_t t, double* out);
 
 /* node type: 0 fluid, 1 wall layer, 2+b body b */
 int ora_types(const ora_dom* dom, int32_t* type);

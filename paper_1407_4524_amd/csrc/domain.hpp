@@ -51,6 +51,7 @@ struct Body {
   bool free_motion = false;
   double* traj = nullptr;
   double* dyn = nullptr;
+  double* pred = nullptr;  // node terms of the predicted pose (LBM_SETS_PREDICTED)
   int64_t t_placed = 0;
 };
 

@@ -237,8 +237,9 @@ hipError_t launch_body_advance(int lat, int st, int eq, void* B, uint8_t* mask, 
 }
 
 __global__ __launch_bounds__(64) void k_body_integrate(const double* __restrict__ rec_t,
-                                                       const double* __restrict__ rec_tm1, double* pose,
-                                                       double* traj, double* dyn, FreeBody fb, int* err) {
+                                                       const double* __restrict__ rec_tm1,
+                                                       const double* __restrict__ pred, double* pose, double* traj,
+                                                       double* dyn, FreeBody fb, int* err) {
 #pragma clang fp contract(off)
   if (threadIdx.x != 0) return;
   const Pose P = reinterpret_cast<const Pose*>(pose)[0];
@@ -249,7 +250,10 @@ __global__ __launch_bounds__(64) void k_body_integrate(const double* __restrict_
   } else {  // static terms, plus the node terms of the step before (lattice frame)
     for (int a = 0; a < 3; ++a) F[a] = rec_t[a];
     Tz = rec_t[5];
-    if ((fb.drive == 1 || fb.drive == 3) && rec_tm1) {
+    if ((fb.drive == 1 || fb.drive == 3) && fb.predicted) {  // node terms of the predicted pose
+      for (int a = 0; a < 3; ++a) F[a] += pred[a];
+      Tz += pred[5];
+    } else if ((fb.drive == 1 || fb.drive == 3) && rec_tm1) {
       for (int a = 0; a < 3; ++a) F[a] += rec_tm1[6 + a];
       Tz += rec_tm1[11];
     }
@@ -287,9 +291,21 @@ __global__ __launch_bounds__(64) void k_body_integrate(const double* __restrict_
   dyn[4] = 1.0;
 }
 
-hipError_t launch_body_integrate(const double* rec_t, const double* rec_tm1, double* pose, double* traj, double* dyn,
-                                 const FreeBody& fb, int* err, hipStream_t s) {
-  hipLaunchKernelGGL(k_body_integrate, dim3(1), dim3(64), 0, s, rec_t, rec_tm1, pose, traj, dyn, fb, err);
+hipError_t launch_body_integrate(const double* rec_t, const double* rec_tm1, const double* pred, double* pose,
+                                 double* traj, double* dyn, const FreeBody& fb, int* err, hipStream_t s) {
+  if (fb.predicted && !pred) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_body_integrate, dim3(1), dim3(64), 0, s, rec_t, rec_tm1, pred, pose, traj, dyn, fb, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_body_predict(int lat, int st, int eq, const void* B, const uint8_t* mask, const double* pose,
+                               const BodyShape& bs, int body, const Geom& g, const Phys& ph, double* out,
+                               hipStream_t s) {
+  if (bs.shape == SHAPE_OUTER_CIRCLE) return hipErrorInvalidValue;
+  with_types(lat, st, eq, [&](auto Lt, auto St, auto E) {
+    LBM_TYPES
+    O::body_predict(B, mask, pose, bs, body, g, ph, out, s);
+  });
   return hipGetLastError();
 }
 

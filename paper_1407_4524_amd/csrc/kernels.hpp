@@ -101,6 +101,14 @@ hipError_t launch_body_advance(int lat, int st, int eq, void* B, uint8_t* mask, 
                                int* err, hipStream_t s, int64_t region_cells, int64_t region_rows, int64_t list_nodes,
                                hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 
+// The node terms of a FREE body's step t over the covered and uncovered
+// nodes between its pose t (pose[0..15], device) and the pose one step at
+// its velocity of step t ahead (the second approximation of Sec. III.B.3),
+// on the state of t+1 in B, nothing written but out[0..5] (F, T about X).
+hipError_t launch_body_predict(int lat, int st, int eq, const void* B, const uint8_t* mask, const double* pose,
+                               const BodyShape& bs, int body, const Geom& g, const Phys& ph, double* out,
+                               hipStream_t s);
+
 // Steady-state check of one body: relative change of its drag between
 // steps t - 1 - window and t - 1 (records of ring `rec`, slot stride
 // rec_stride doubles); out[2k] = relative change, out[2k+1] = drag at t - 1.
@@ -194,11 +202,12 @@ hipError_t launch_batch_body_step(int lat, int st, int eq, const BatchDomain* do
 struct FreeBody {
   double mass, inertia, ext_force[3], ext_torque;
   int integrator, drive, shape, D;
+  int predicted;  // the lattice drive takes the predicted node terms (pred) instead of those of t-1
   double axes[3];
   int glo[3], ghi[3];
 };
-hipError_t launch_body_integrate(const double* rec_t, const double* rec_tm1, double* pose, double* traj, double* dyn,
-                                 const FreeBody& fb, int* err, hipStream_t s);
+hipError_t launch_body_integrate(const double* rec_t, const double* rec_tm1, const double* pred, double* pose,
+                                 double* traj, double* dyn, const FreeBody& fb, int* err, hipStream_t s);
 
 // *counter += k, one thread (closes a captured step sequence); *counter = v
 hipError_t launch_add_step(int64_t* counter, int64_t k, hipStream_t s);
@@ -230,6 +239,8 @@ struct Ops {
                            int mode, const Geom& g, const Phys& ph, double* rec_t, double* rec_t1, int* err,
                            hipStream_t s, int64_t region_cells, int64_t region_rows, int64_t list_nodes,
                            hipEvent_t e0, hipEvent_t e1);
+  static void body_predict(const void* B, const uint8_t* mask, const double* pose, const BodyShape& bs, int body,
+                           const Geom& g, const Phys& ph, double* out, hipStream_t s);
   static void batch_bulk(const BatchDomain* doms, const BatchTile* tiles, int ntiles, const BulkConfig& cfg,
                          int64_t step, hipStream_t s, int part, hipEvent_t e0, hipEvent_t e1, const int64_t* sbase);
   static void batch_links(const BatchDomain* doms, const BatchBody* bodies, int nbodies, int grid, int64_t step,

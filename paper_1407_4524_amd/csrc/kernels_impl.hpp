@@ -157,7 +157,7 @@ __device__ __forceinline__ int extrap_dir(const BodyShape& bs, const Pose& P, in
 // when fluid_both says the three nodes are fluid at t and t+1 (MEAN
 // otherwise), on the stored post-collision states of step t+1. Writes the node's populations (the state of t+1) and takes
 // their momentum off the node terms imp, about X_c(t).
-template <class L, class S, int EQ, class FluidBoth>
+template <class L, class S, int EQ, bool STORE = true, class FluidBoth>
 __device__ __forceinline__ void refill_node(typename S::T* B, const Geom& g, const Phys& ph, const Pose& P0,
                                             const Pose& P1, const BodyShape& bs, int x, int y, int z, double rs,
                                             const double us[3], double cnt, FluidBoth fluid_both, double imp[8]) {
@@ -205,7 +205,7 @@ __device__ __forceinline__ void refill_node(typename S::T* B, const Geom& g, con
   double m[3] = {0, 0, 0};
 #pragma unroll
   for (int q = 0; q < L::Q; ++q) {
-    S::store_plain(B + q * g.S + c, hv[q]);
+    if constexpr (STORE) S::store_plain(B + q * g.S + c, hv[q]);
     const double v = S::round_trip(hv[q]);
     m[0] += L::cx(q) * v;
     m[1] += L::cy(q) * v;
@@ -1351,6 +1351,87 @@ __global__ __launch_bounds__(NT) void k_body_step_free(typename S::T* B, uint8_t
                                  StepBox{});
 }
 
+// Node terms of a free body over the covered and uncovered nodes between
+// its pose t and the predicted pose X + V, theta + Omega (cos/sin by
+// free_trig), on the state of t+1, written to out[0..5]: one workgroup
+// scans the node box of pose t (it holds both bodies and the layer around
+// them, the body moving less than a node per step); statuses at the
+// predicted pose come from the shape inside the box and from the mask
+// beyond it. The refill rule of the body gives the uncovered nodes' values
+// (computed, not stored).
+template <class L, class S, int EQ>
+__global__ __launch_bounds__(ADV_BLOCK) void k_body_predict(const typename S::T* B, const uint8_t* mask,
+                                                            const double* pose, BodyShape bs, int body, Geom g,
+                                                            Phys ph, double* out) {
+#pragma clang fp contract(off)
+  __shared__ double sm[6 * ADV_BLOCK / 64];
+  __shared__ double red[6];
+  const Pose P = reinterpret_cast<const Pose*>(pose)[0];
+  Pose Pp = P;
+  for (int a = 0; a < 3; ++a) Pp.X[a] = P.X[a] + P.V[a];
+  Pp.theta = P.theta + P.Om;
+  free_trig(Pp.theta, Pp.ct, Pp.st);
+  const uint8_t self = (uint8_t)(MASK_BODY0 + body);
+  Region R;
+  for (int a = 0; a < 3; ++a) {
+    R.lo[a] = (int)P.lo[a];
+    R.n[a] = (int)P.hi[a] - (int)P.lo[a] + 1;
+  }
+  R.total = (int64_t)R.n[0] * R.n[1] * R.n[2];
+  auto next = [&](int x, int y, int z) -> uint8_t {  // status at the predicted pose
+    const uint8_t m = mask[g.idx(x, y, z)];
+    if (!R.contains(x, y, z) || (m != MASK_FLUID && m != self)) return m;
+    return shape_phi(bs, Pp, (double)x, (double)y, (double)z) <= 0.0 ? self : (uint8_t)MASK_FLUID;
+  };
+  auto fluid_both = [&](int x, int y, int z) {
+    return mask[g.idx(x, y, z)] == MASK_FLUID && next(x, y, z) == MASK_FLUID;
+  };
+  double imp[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int64_t k = threadIdx.x; k < R.total; k += ADV_BLOCK) {
+    int x, y, z;
+    R.at(k, x, y, z);
+    const int64_t c = g.idx(x, y, z);
+    const uint8_t old = mask[c];
+    if (old != MASK_FLUID && old != self) continue;
+    const bool will = shape_phi(bs, Pp, (double)x, (double)y, (double)z) <= 0.0;
+    if (old == MASK_FLUID && will) {  // covered
+      double m[3] = {0, 0, 0};
+#pragma unroll
+      for (int q = 1; q < L::Q; ++q) {
+        const double v = (double)S::load(B + q * g.S + c);
+        m[0] += L::cx(q) * v;
+        m[1] += L::cy(q) * v;
+        m[2] += L::cz(q) * v;
+      }
+      const double r[3] = {x - P.X[0], y - P.X[1], z - P.X[2]};
+      imp[0] += m[0];
+      imp[1] += m[1];
+      imp[2] += m[2];
+      imp[3] += r[1] * m[2] - r[2] * m[1];
+      imp[4] += r[2] * m[0] - r[0] * m[2];
+      imp[5] += r[0] * m[1] - r[1] * m[0];
+    } else if (old == self && !will) {  // uncovered
+      double rs = 0, us[3] = {0, 0, 0}, cnt = 0;
+#pragma unroll
+      for (int q = 1; q < L::Q; ++q) {
+        const int xn = x + L::cx(q), yn = y + L::cy(q), zn = z + L::cz(q);
+        if (!fluid_both(xn, yn, zn)) continue;
+        double hn[L::Q], dn, un[3];
+        moments_at<L, S>(B, g, g.idx(xn, yn, zn), ph.rho0, EQ, hn, dn, un);
+        rs += ph.rho0 + dn;
+        us[0] += un[0];
+        us[1] += un[1];
+        us[2] += un[2];
+        cnt += 1.0;
+      }
+      refill_node<L, S, EQ, false>(const_cast<typename S::T*>(B), g, ph, P, Pp, bs, x, y, z, rs, us, cnt, fluid_both,
+                                   imp);
+    }
+  }
+  block_sum<6, ADV_BLOCK>(imp, red, sm);
+  if (threadIdx.x < 6) out[threadIdx.x] = red[threadIdx.x];
+}
+
 // ---------------------------------------------------------------------------
 // batches: many domains per launch; every argument that differs between
 // domains comes from a device table, the batch step s from the launch
@@ -1569,6 +1650,13 @@ void Ops<L, S, EQ>::body_advance(void* B, uint8_t* mask, uint8_t* mask_next, Lin
     launch_timed(k_body_advance<L, S, EQ>, dim3(1), dim3(ADV_BLOCK), 0, s, e0, e1, b, mask, mask_next, links,
                  n_links, cap, pose, bs, bc, body, mode, g, ph, rec_t, rec_t1, err);
   }
+}
+
+template <class L, class S, int EQ>
+void Ops<L, S, EQ>::body_predict(const void* B, const uint8_t* mask, const double* pose, const BodyShape& bs,
+                                 int body, const Geom& g, const Phys& ph, double* out, hipStream_t s) {
+  hipLaunchKernelGGL((k_body_predict<L, S, EQ>), dim3(1), dim3(ADV_BLOCK), 0, s, (const typename S::T*)B, mask, pose,
+                     bs, body, g, ph, out);
 }
 
 template <class L, class S, int EQ>

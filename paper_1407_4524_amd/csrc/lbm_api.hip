@@ -420,8 +420,9 @@ static lbm_status start_free_motion(lbm_domain d, Body& b) {
   HIP_TRY(hipMalloc(&b.pose_dev, b.pose_cap * POSE_LEN * sizeof(double)));
   HIP_TRY(hipHostMalloc(&b.pose_pinned, POSE_LEN * sizeof(double), hipHostMallocDefault));
   HIP_TRY(hipMalloc(&b.traj, (size_t)d->rec_cap * 8 * sizeof(double)));
-  HIP_TRY(hipMalloc(&b.dyn, 8 * sizeof(double)));
-  HIP_TRY(hipMemsetAsync(b.dyn, 0, 8 * sizeof(double), d->stream));
+  HIP_TRY(hipMalloc(&b.dyn, 16 * sizeof(double)));
+  HIP_TRY(hipMemsetAsync(b.dyn, 0, 16 * sizeof(double), d->stream));
+  b.pred = b.dyn + 8;
   memcpy(b.pose_pinned, &p0, sizeof(Pose));
   HIP_TRY(hipMemcpyAsync(b.pose_dev, b.pose_pinned, sizeof(Pose), hipMemcpyHostToDevice, d->stream));
   const double row[8] = {p0.X[0], p0.X[1], p0.X[2], p0.theta, p0.V[0], p0.V[1], p0.V[2], p0.Om};
@@ -476,8 +477,13 @@ static lbm_status launch_integrate(lbm_domain d, int id, int64_t t) {
   fb.drive = bd.me_mode;
   fb.shape = bd.shape;
   fb.D = d->D;
+  fb.predicted = (bd.me_mode == LBM_ME_LATTICE || bd.me_mode == LBM_ME_LATTICE_BACKWARD) &&
+                 bd.sets == LBM_SETS_PREDICTED;
+  if (fb.predicted)
+    HIP_TRY(launch_body_predict(d->lat, d->st, d->eq, d->A, d->mask, pose_at(b, t), b.shape, id, d->g, d->ph, b.pred,
+                                d->stream));
   const double* rec_tm1 = t > b.t_placed ? rec_slot(d, t - 1, id) : nullptr;
-  HIP_TRY(launch_body_integrate(rec_slot(d, t, id), rec_tm1, const_cast<double*>(pose_at(b, t)),
+  HIP_TRY(launch_body_integrate(rec_slot(d, t, id), rec_tm1, b.pred, const_cast<double*>(pose_at(b, t)),
                                 b.traj + ((t + 1) % d->rec_cap) * 8, b.dyn, fb, d->err, d->stream));
   return LBM_OK;
 }
@@ -727,6 +733,7 @@ lbm_status lbm_set_body(lbm_domain d, int32_t id, const lbm_body_desc* bd) {
     if (bd->integrator != LBM_INTEGRATOR_EULER && bd->integrator != LBM_INTEGRATOR_AB2)
       return fail(LBM_E_INVAL, "unknown integrator");
     if (d->batch) return fail(LBM_E_STATE, "a free body is stepped alone, not in a batch");
+    if (bd->sets != LBM_SETS_PREVIOUS && bd->sets != LBM_SETS_PREDICTED) return fail(LBM_E_INVAL, "unknown sets");
   }
   const int na = bd->shape == LBM_SHAPE_ELLIPSE ? d->D : 1;
   for (int a = 0; a < na; ++a)

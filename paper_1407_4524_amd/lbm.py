@@ -29,6 +29,7 @@ ME = {"static": 0, "lattice": 1, "comoving": 2, "lattice_backward": 3}
 MOTION = {"static": 0, "const_vel": 1, "rotate": 2, "oscillate": 3, "table": 4, "free": 5}
 INTEGRATOR = {"euler": 0, "ab2": 1}
 REFILL = {"mean": 0, "aidun": 1, "extrapolate": 2}
+SETS = {"previous": 0, "predicted": 1}
 KERNEL = {"stream_collide": 0, "body": 1, "near_box": 2}
 STATUS = {0: "LBM_OK", -1: "LBM_E_INVAL", -2: "LBM_E_NOMEM", -3: "LBM_E_HIP", -4: "LBM_E_RANGE",
           -5: "LBM_E_UNSTABLE", -6: "LBM_E_STATE"}
@@ -85,7 +86,7 @@ class BodyDesc(C.Structure):
                 ("omega", C.c_double), ("amp", C.c_double * 3), ("period", C.c_double),
                 ("pose_table", C.POINTER(C.c_double)), ("pose_count", C.c_int64), ("mass", C.c_double),
                 ("inertia", C.c_double), ("ext_force", C.c_double * 3), ("ext_torque", C.c_double),
-                ("integrator", C.c_int32), ("refill", C.c_int32)]
+                ("integrator", C.c_int32), ("refill", C.c_int32), ("sets", C.c_int32)]
 
 
 _lib = None
@@ -203,7 +204,7 @@ def domain_desc(lattice="D2Q9", nx=64, ny=64, nz=1, tau=0.8, rho0=1.0, storage="
 
 def body_desc(shape="circle", axes=(1.0,), bc="halfway", me="static", motion="static", c0=(0, 0, 0), theta0=0.0,
               vel=(0, 0, 0), omega=0.0, amp=(0, 0, 0), period=1.0, table=None, mass=0.0, inertia=0.0,
-              ext_force=(0, 0, 0), ext_torque=0.0, integrator="euler", refill="mean"):
+              ext_force=(0, 0, 0), ext_torque=0.0, integrator="euler", refill="mean", sets="previous"):
     """(lbm_body_desc, arrays it points to) of these settings"""
     b = BodyDesc()
     b.mass, b.inertia, b.ext_torque = mass, inertia, ext_torque
@@ -211,6 +212,7 @@ def body_desc(shape="circle", axes=(1.0,), bc="halfway", me="static", motion="st
         b.ext_force[a] = ext_force[a] if a < len(ext_force) else 0.0
     b.integrator = _enum(INTEGRATOR, integrator)
     b.refill = _enum(REFILL, refill)
+    b.sets = _enum(SETS, sets)
     b.shape = _enum(SHAPE, shape)
     ax = list(axes) + [0.0] * (3 - len(axes))
     if b.shape == 1 and len(axes) == 1:

@@ -16,6 +16,7 @@ DRIVE = {"static": O.DRIVE_STATIC, "lattice": O.DRIVE_LATTICE, "comoving": O.DRI
          "lattice_backward": O.DRIVE_LATTICE}
 INTEGRATOR = {"euler": O.INTEGRATOR_EULER, "ab2": O.INTEGRATOR_AB2}
 REFILL = {"mean": O.REFILL_MEAN, "aidun": O.REFILL_AIDUN, "extrapolate": O.REFILL_EXTRAPOLATE}
+SETS = {"previous": O.SETS_PREVIOUS, "predicted": O.SETS_PREDICTED}
 
 
 def make_oracle(w, init_rho=None, init_u=None):
@@ -32,7 +33,8 @@ def make_oracle(w, init_rho=None, init_u=None):
                    period=b.get("period", 1.0), table=b.get("table"), mass=b.get("mass", 0.0),
                    inertia=b.get("inertia", 0.0), ext_force=b.get("ext_force", (0, 0, 0)),
                    ext_torque=b.get("ext_torque", 0.0), drive=DRIVE[b.get("me", "static")],
-                   integrator=INTEGRATOR[b.get("integrator", "euler")], refill=REFILL[b.get("refill", "mean")])
+                   integrator=INTEGRATOR[b.get("integrator", "euler")], refill=REFILL[b.get("refill", "mean")],
+                   sets=SETS[b.get("sets", "previous")])
     return d
 
 

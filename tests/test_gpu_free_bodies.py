@@ -1,5 +1,6 @@
 """Free bodies (Newton-Euler motion under the flow force: the sedimentation
-tests of the paper's Sec. IV), the refill rules of Sec. III.B.3 and the
+tests of the paper's Sec. IV, with both approximations of the covered and
+uncovered sets of Sec. III.B.3), the refill rules of Sec. III.B.3 and the
 backward-in-time lattice force, on the GPU through the C ABI against the CPU
 oracle on the same inputs.
 
@@ -31,20 +32,24 @@ def _traj_oracle(o, steps):
     return np.array([o.pose(0, t) for t in range(steps + 1)])
 
 
-def _small_sedimenting(shape="circle", storage="f64", me="lattice", integrator="euler", refill="mean", ratio=1.05):
+def _small_sedimenting(shape="circle", storage="f64", me="lattice", integrator="euler", refill="mean", ratio=1.05,
+                       sets="previous"):
     axes = (6.2,) if shape == "circle" else (7.0, 3.6)
-    return W.sedimenting(44, 150, shape, axes, (25.3, 112.6, 0.0), ratio, 1e-3, storage=storage, tau=0.7,
-                         theta0=math.pi / 4 if shape == "ellipse" else 0.0, me=me, integrator=integrator,
-                         refill=refill)
+    w = W.sedimenting(44, 150, shape, axes, (25.3, 112.6, 0.0), ratio, 1e-3, storage=storage, tau=0.7,
+                      theta0=math.pi / 4 if shape == "ellipse" else 0.0, me=me, integrator=integrator, refill=refill)
+    w["bodies"][0]["sets"] = sets
+    return w
 
 
-@pytest.mark.parametrize("shape,me,integrator", [("circle", "lattice", "euler"), ("circle", "static", "euler"),
-                                                 ("circle", "comoving", "ab2"), ("ellipse", "lattice", "ab2"),
-                                                 ("ellipse", "comoving", "euler")])
-def test_free_body_trajectory_f64(shape, me, integrator):
-    w = _small_sedimenting(shape, "f64", me, integrator)
+@pytest.mark.parametrize("shape,me,integrator,sets,refill", [
+    ("circle", "lattice", "euler", "previous", "mean"), ("circle", "static", "euler", "previous", "mean"),
+    ("circle", "comoving", "ab2", "previous", "mean"), ("ellipse", "lattice", "ab2", "previous", "mean"),
+    ("ellipse", "comoving", "euler", "previous", "mean"), ("circle", "lattice", "euler", "predicted", "mean"),
+    ("ellipse", "lattice", "ab2", "predicted", "extrapolate"), ("circle", "lattice", "euler", "predicted", "aidun")])
+def test_free_body_trajectory_f64(shape, me, integrator, sets, refill):
+    w = _small_sedimenting(shape, "f64", me, integrator, refill=refill, sets=sets)
     steps = 600
-    print(f"free {shape}, {me} force, {integrator}, {steps} steps", flush=True)
+    print(f"free {shape}, {me} force, {integrator}, {sets} sets, {refill} refill, {steps} steps", flush=True)
     g, o = run_pair(w, steps)
     tg = g.trajectory(0, 0, steps + 1)
     to = _traj_oracle(o, steps)

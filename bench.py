@@ -265,7 +265,8 @@ def run_batch(steps, count=64, seed=0, tune_steps=5):
                 speedup=round(t_plain / best["seconds"], 2), tuner_choice=chosen, tuner_trials=len(trials))
 
 
-def run_serving(count, max_steps, seed=0, rate=200.0, budget_gb=64.0):
+def run_serving(count, max_steps, seed=0, rate=200.0, budget_gb=64.0, progress=False,
+                parts=("batched", "plain", "loaded")):
     """Served solves: a Poisson stream of requests (80 % D2Q9 sides
     128..1024, 20 % D3Q19 sides 48..160, FP32/FP16-shifted, static or
     rotating bodies) with continuous batching and admission by device
@@ -277,9 +278,21 @@ def run_serving(count, max_steps, seed=0, rate=200.0, budget_gb=64.0):
     import lbm_workloads as W
     from paper_1407_4524_amd.serve import GpuEngine, Server, serve_plain, summary
 
-    def batched(reqs):
+    def report(label):
+        if not progress:
+            return None
+        done = [0]
+
+        def cb(r):
+            done[0] += 1
+            state = "failed: " + r.error if r.failed else ("steady" if r.converged else "capped")
+            print(f"served ({label}) {done[0]}/{count}: request {r.id}, {r.steps} steps, {state}",
+                  file=sys.stderr, flush=True)
+        return cb
+
+    def batched(reqs, label="batched"):
         eng = GpuEngine()
-        srv = Server(eng, budget_gb * 2 ** 30, epoch=500, window=500, tol=1e-6)
+        srv = Server(eng, budget_gb * 2 ** 30, epoch=500, window=500, tol=1e-6, on_result=report(label))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         res = srv.run(reqs)
@@ -290,20 +303,32 @@ def run_serving(count, max_steps, seed=0, rate=200.0, budget_gb=64.0):
         return out, res
 
     reqs = W.serving_requests(count=count, seed=seed, rate=rate, max_steps=max_steps)
-    sat, res_b = batched(reqs)
-    t0 = time.perf_counter()
-    res_p = serve_plain(reqs, epoch=500, window=500, tol=1e-6)
-    plain = summary(res_p, time.perf_counter() - t0)
-    by_id = {r.id: r for r in res_p}
-    same = all(r.force_torque == by_id[r.id].force_torque and r.steps == by_id[r.id].steps for r in res_b)
-    load_rate = 0.7 * sat["solves_per_s"]
-    loaded, _ = batched(W.serving_requests(count=count, seed=seed + 1, rate=load_rate, max_steps=max_steps))
     note = ("the configured stream (256 requests, 50000-step cap)" if (count, max_steps) == (256, 50000) else
             f"reduced from the configured 256 requests / 50000-step cap to {count} requests / {max_steps} steps")
-    return dict(workload=f"served_{count}_requests_cap{max_steps}", requests=count, max_steps=max_steps,
-                offered_rate_per_s=rate, note=note, batched=sat, plain=plain,
-                speedup=round(plain["seconds"] / sat["seconds"], 2), results_equal_alone=same,
-                at_70pct_capacity=dict(offered_rate_per_s=round(load_rate, 3), **loaded))
+    out = dict(workload=f"served_{count}_requests_cap{max_steps}", requests=count, max_steps=max_steps,
+               offered_rate_per_s=rate, note=note)
+    sat = res_b = None
+    if "batched" in parts:
+        sat, res_b = batched(reqs)
+        out["batched"] = sat
+    if "plain" in parts:
+        t0 = time.perf_counter()
+        res_p = serve_plain(reqs, epoch=500, window=500, tol=1e-6, on_result=report("one at a time"))
+        out["plain"] = summary(res_p, time.perf_counter() - t0)
+        if res_b is not None:
+            by_id = {r.id: r for r in res_p}
+            ok = [r for r in res_b if not r.failed]
+            out["speedup"] = round(out["plain"]["seconds"] / sat["seconds"], 2)
+            out["results_equal_alone"] = all(r.force_torque == by_id[r.id].force_torque and
+                                             r.steps == by_id[r.id].steps for r in ok)
+            out["same_requests_failed"] = sorted(r.id for r in res_b if r.failed) == sorted(
+                r.id for r in res_p if r.failed)
+    if "loaded" in parts and sat is not None:
+        load_rate = 0.7 * sat["solves_per_s"]
+        loaded, _ = batched(W.serving_requests(count=count, seed=seed + 1, rate=load_rate, max_steps=max_steps),
+                            "at 70 % of capacity")
+        out["at_70pct_capacity"] = dict(offered_rate_per_s=round(load_rate, 3), **loaded)
+    return out
 
 
 def cpu_baseline(name, budget_s, single_thread_s):
@@ -428,6 +453,9 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the served-requests line")
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--serve-max-steps", type=int, default=3000)
+    ap.add_argument("--serve-progress", action="store_true", help="a line on stderr per finished request")
+    ap.add_argument("--serve-parts", default="batched,plain,loaded",
+                    help="which served runs: batched, plain (one at a time), loaded (batched at 70%% of capacity)")
     ap.add_argument("--batch-steps", type=int, default=5000)
     ap.add_argument("--no-physics", action="store_true",
                     help="skip the force-noise comparison and the sedimenting-disc line")
@@ -493,7 +521,8 @@ def main():
     if not args.no_batch and args.workload == HEADLINE:
         line["batched"] = run_batch(args.batch_steps)
     if not args.no_serve and args.workload == HEADLINE:
-        line["served"] = run_serving(args.serve_requests, args.serve_max_steps)
+        line["served"] = run_serving(args.serve_requests, args.serve_max_steps, progress=args.serve_progress,
+                                     parts=tuple(args.serve_parts.split(",")))
     if not args.no_cpu_baseline and rank == 0:
         line["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds, args.cpu_single_seconds)
     if rank == 0:

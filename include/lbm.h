@@ -5,14 +5,16 @@
  * The operation: the time step of the lattice-Boltzmann equation (BGK
  * collision then streaming, Sec. II, Eqs. LBE, collision, streaming) for a
  * flow around submerged bodies whose motion is prescribed (Sec. III: Omega(t)
- * is a given function of t, strictly inside the simulated region), with the
+ * is a given function of t, strictly inside the simulated region) or follows
+ * from the computed force (Newton-Euler, the tests of Sec. IV), with the
  * interpolated boundary rule of Sec. II.A (Filippova-Haenel with the
  * Mei-Luo-Shyy choices; halfway bounce-back as the special case Delta = 1/2)
  * and the flow force and torque on each body by momentum exchange, every
  * step, in the three forms the paper derives:
  *   static     Eqs. flow_force_2 / flow_torque_2,
  *   lattice    Eqs. ForceInMovement / TorqueInMovement (static sums plus the
- *              covered/uncovered-node terms, sets taken forward in time),
+ *              covered/uncovered-node terms, sets taken forward in time, or
+ *              backward in time as Aidun et al. and Wen et al. take them),
  *   comoving   Eqs. ForceInMovementMovingFrame / TorqueInMovementMovingFrame
  *              (node terms dropped).
  *

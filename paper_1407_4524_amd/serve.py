@@ -157,7 +157,8 @@ class Server:
     scheduling logic runs without a GPU in the tests."""
 
     def __init__(self, engine, memory_budget, max_active=256, epoch=500, window=500, tol=1e-6,
-                 clock=time.perf_counter, sleep=time.sleep):
+                 clock=time.perf_counter, sleep=time.sleep, on_result=None):
+        self.on_result = on_result  # called with every Result as it is made
         self.engine = engine
         self.budget = int(memory_budget)
         self.max_active = max_active
@@ -176,7 +177,7 @@ class Server:
         pending = collections.deque(sorted(requests, key=lambda r: r["arrival"]))
         active = {}  # handle -> (request, footprint, admitted)
         used = 0
-        results = []
+        results = _Results(self.on_result)
         t0 = self.clock()
         while pending or active:
             now = self.clock() - t0
@@ -222,35 +223,61 @@ class Server:
                     results.append(Result(r["id"], t, steady == 1, rel, ft, r["arrival"], adm, done_at))
                     used -= fp
                     del active[h]
-        return results
+        return list(results)
+
+
+class _Results(list):
+    """A list of results that reports every one appended to a callback."""
+
+    def __init__(self, on_result=None):
+        super().__init__()
+        self.on_result = on_result
+
+    def append(self, r):
+        super().append(r)
+        if self.on_result:
+            self.on_result(r)
 
 
 def serve_plain(requests, epoch=500, window=500, tol=1e-6, record_capacity=2048, clock=time.perf_counter,
-                sleep=time.sleep):
+                sleep=time.sleep, on_result=None):
     """The same stream served one request at a time, each on its own domain
     and launches (lbm_step), with the same epochs and steady-state test."""
     from . import lbm
-    results = []
+    results = _Results(on_result)
     t0 = clock()
     for r in sorted(requests, key=lambda r: r["arrival"]):
         now = clock() - t0
         if now < r["arrival"]:
             sleep(r["arrival"] - now)
         adm = clock() - t0
-        dom = lbm.Domain.from_spec(r["spec"], record_capacity=record_capacity)
-        while True:
-            dom.step(epoch)
-            t = dom.t
-            if t - 1 - window >= 0:
-                steady, rel = dom.steady_state(window, tol)
-            else:
-                steady, rel = False, float("nan")
-            if steady or t >= r["max_steps"]:
-                break
-        ft = tuple(float(x) for x in dom.force_torque(0, t - 1, 1)[0])
-        dom.close()
-        results.append(Result(r["id"], t, bool(steady), rel, ft, r["arrival"], adm, clock() - t0))
-    return results
+        try:
+            dom = lbm.Domain.from_spec(r["spec"], record_capacity=record_capacity)
+        except lbm.LbmError as e:  # refused by the library
+            results.append(Result(r["id"], 0, False, float("nan"), (float("nan"),) * 6, r["arrival"], adm,
+                                  clock() - t0, failed=True, error=str(e)))
+            continue
+        error = ""
+        try:
+            while True:
+                dom.step(epoch)
+                t = dom.t
+                if t - 1 - window >= 0:
+                    steady, rel = dom.steady_state(window, tol)
+                else:
+                    steady, rel = False, float("nan")
+                if steady or t >= r["max_steps"]:
+                    break
+            ft = tuple(float(x) for x in dom.force_torque(0, t - 1, 1)[0])
+        except lbm.LbmError as e:  # a device error (e.g. instability) fails this request only
+            error, t, steady, rel, ft = str(e), dom.t, False, float("nan"), (float("nan"),) * 6
+        try:
+            dom.close()
+        except lbm.LbmError:
+            pass
+        results.append(Result(r["id"], t, bool(steady), rel, ft, r["arrival"], adm, clock() - t0,
+                              failed=bool(error), error=error))
+    return list(results)
 
 
 def summary(results, wall=None):

@@ -169,3 +169,50 @@ def test_failed_requests_finish_as_failed_and_release_memory():
         if k not in (1, 4):
             assert not r.failed and r.converged
     assert eng.used == 0 and not eng.active and eng.peak_used <= budget
+
+
+def test_one_at_a_time_failures_do_not_stop_the_stream(monkeypatch):
+    """the one-request-at-a-time reference also ends a refused request and one
+    whose domain turns unstable as failed results, and serves the rest"""
+    from paper_1407_4524_amd import lbm
+    from paper_1407_4524_amd.serve import serve_plain
+
+    class FakeDomain:
+        closed = 0
+
+        def __init__(self, spec):
+            if spec.get("refuse"):
+                raise lbm.LbmError(-4, "refused")
+            self.spec, self.t = spec, 0
+
+        @classmethod
+        def from_spec(cls, spec, record_capacity=0):
+            return cls(spec)
+
+        def step(self, n):
+            self.t += n
+            if self.t >= self.spec.get("breaks", 1 << 30):
+                raise lbm.LbmError(-5, "speed")
+
+        def steady_state(self, window, tol):
+            return self.t >= self.spec["conv"], 0.0
+
+        def force_torque(self, body, t0, n):
+            return [(float(self.spec["id"]),) + (0.0,) * 5]
+
+        def close(self):
+            FakeDomain.closed += 1
+
+    monkeypatch.setattr(lbm, "Domain", FakeDomain)
+    reqs = requests(8, seed=5)
+    reqs[2]["spec"]["refuse"] = True
+    reqs[5]["spec"]["breaks"] = 1000
+    clock = FakeClock()
+    res = {r.id: r for r in serve_plain(reqs, clock=clock, sleep=clock.sleep)}
+    assert sorted(res) == list(range(8))
+    assert res[2].failed and "LBM_E_RANGE" in res[2].error and res[2].steps == 0
+    assert res[5].failed and "UNSTABLE" in res[5].error and res[5].steps == 1000
+    for k, r in res.items():
+        if k not in (2, 5):
+            assert not r.failed and r.converged and r.force_torque[0] == float(k)
+    assert FakeDomain.closed == 7

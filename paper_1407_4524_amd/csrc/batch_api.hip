@@ -89,10 +89,11 @@ struct Plan {
   std::vector<BatchDomain> doms;
   std::vector<BatchTile> tiles, near_tiles;
   std::vector<BatchBody> links, moving;
+  std::vector<BatchBody> wide;                // advanced by the many-workgroup kernels
   std::vector<std::pair<int, int>> fallback;  // (member, body) advanced by its own launches
-  int link_grid = 1, max_links = 0;
+  int link_grid = 1, max_links = 0, wide_slabs = 0;
   int64_t max_cells = 0;
-  size_t off_tiles = 0, off_near = 0, off_links = 0, off_moving = 0, bytes = 0;
+  size_t off_tiles = 0, off_near = 0, off_links = 0, off_moving = 0, off_wide = 0, bytes = 0;
 };
 
 // Near box of a member for the steps t0 .. t0+n-1 of a call: the node boxes
@@ -195,16 +196,22 @@ lbm_status make_plan(lbm_batch B, int64_t n, Plan& P) {
         P.max_links = std::max(P.max_links, b.n_host);
         continue;
       }
-      bool fits = b.desc.shape != LBM_SHAPE_OUTER_CIRCLE;
-      int64_t cells = 0;
-      for (int64_t k = 0; k < n && fits; ++k) {
-        const int64_t c = region_cells(b, d->D, d->t + k, 1);
-        fits = body_step_fits(c, region_rows(b, d->t + k, 1), list_bound(b, d->D, d->t + k));
-        cells = std::max(cells, c);
-      }
-      if (fits) {
+      // every step of the call takes the same kernel (batch_step splits a
+      // call where a body changes kernels)
+      if (step_fits(b, d->D, d->t)) {
+        int64_t cells = 0;
+        for (int64_t k = 0; k < n; ++k) cells = std::max(cells, region_cells(b, d->D, d->t + k, 1));
         P.moving.push_back(bb);
         P.max_cells = std::max(P.max_cells, cells);
+      } else if (b.wide) {
+        int64_t rows = 0;
+        for (int64_t k = 0; k < n; ++k) rows = std::max(rows, region_rows(b, d->t + k, 1));
+        lbm_status s = ensure_wide(b, (int)((rows + WIDE_ROWS - 1) / WIDE_ROWS), B->stream);
+        if (s != LBM_OK) return s;
+        bb.wide = b.wide;
+        bb.wide_slabs = b.wide_slabs;
+        P.wide.push_back(bb);
+        P.wide_slabs = std::max(P.wide_slabs, b.wide_slabs);
       } else {
         P.fallback.push_back({(int)i, id});
       }
@@ -216,7 +223,8 @@ lbm_status make_plan(lbm_batch B, int64_t n, Plan& P) {
   P.off_near = P.off_tiles + align256(P.tiles.size() * sizeof(BatchTile));
   P.off_links = P.off_near + align256(P.near_tiles.size() * sizeof(BatchTile));
   P.off_moving = P.off_links + align256(P.links.size() * sizeof(BatchBody));
-  P.bytes = P.off_moving + align256(P.moving.size() * sizeof(BatchBody));
+  P.off_wide = P.off_moving + align256(P.moving.size() * sizeof(BatchBody));
+  P.bytes = P.off_wide + align256(P.wide.size() * sizeof(BatchBody));
   return LBM_OK;
 }
 
@@ -238,6 +246,7 @@ lbm_status upload(lbm_batch B, const Plan& P) {
   memcpy(B->pinned + P.off_near, P.near_tiles.data(), P.near_tiles.size() * sizeof(BatchTile));
   memcpy(B->pinned + P.off_links, P.links.data(), P.links.size() * sizeof(BatchBody));
   memcpy(B->pinned + P.off_moving, P.moving.data(), P.moving.size() * sizeof(BatchBody));
+  memcpy(B->pinned + P.off_wide, P.wide.data(), P.wide.size() * sizeof(BatchBody));
   HIP_TRY(hipMemcpyAsync(B->dev, B->pinned, P.bytes, hipMemcpyHostToDevice, B->stream));
   return LBM_OK;
 }
@@ -257,6 +266,7 @@ static lbm_status enqueue_steps(lbm_batch B, const Plan& P, int64_t k0, int64_t 
   const auto* near_tiles = reinterpret_cast<const BatchTile*>(B->dev + P.off_near);
   const auto* links = reinterpret_cast<const BatchBody*>(B->dev + P.off_links);
   const auto* moving = reinterpret_cast<const BatchBody*>(B->dev + P.off_moving);
+  const auto* wide = reinterpret_cast<const BatchBody*>(B->dev + P.off_wide);
   const BulkConfig bc{B->cfg.block, B->cfg.cells_per_thread, 0, B->cfg.remap};
   const BulkConfig nc{B->cfg.block, B->cfg.cells_per_thread, 0, 0};
   const int lat = first->lat, st = first->st, eq = first->eq;
@@ -289,6 +299,8 @@ static lbm_status enqueue_steps(lbm_batch B, const Plan& P, int64_t k0, int64_t 
     else if (!P.moving.empty())
       HIP_TRY(launch_batch_body_step(lat, st, eq, doms, moving, (int)P.moving.size(), P.max_cells, k, main,
                                      sbase));
+    if (!P.wide.empty())
+      HIP_TRY(launch_batch_wide(lat, st, eq, doms, wide, (int)P.wide.size(), P.wide_slabs, k, main, sbase));
     for (const auto& f : P.fallback) {  // never in a captured sequence
       lbm_domain d = B->members[f.first];
       Body& b = d->body[f.second];
@@ -314,8 +326,43 @@ static void drop_graph(lbm_batch B) {
   B->graph = nullptr;
 }
 
+// The longest run of the next n steps (at least one) over which every
+// moving body keeps its advance kernel (the single-workgroup list kernel or
+// the many-workgroup one), as lbm_step chooses them step by step.
+static lbm_status uniform_steps(lbm_batch B, int64_t n, int64_t& run) {
+  run = n;
+  for (lbm_domain d : B->members)
+    for (int id = 0; id < d->nslots; ++id) {
+      Body& b = d->body[id];
+      if (!b.active || !b.mask_moves) continue;
+      lbm_status s = ensure_poses(d, b, d->t, d->t + n);
+      if (s != LBM_OK) return s;
+      const bool f0 = step_fits(b, d->D, d->t);
+      for (int64_t k = 1; k < run; ++k)
+        if (step_fits(b, d->D, d->t + k) != f0) {
+          run = k;
+          break;
+        }
+    }
+  return LBM_OK;
+}
+
+static lbm_status batch_run(lbm_batch B, int64_t n, hipEvent_t e0, hipEvent_t e1);
+
 lbm_status batch_step(lbm_batch B, int64_t n, hipEvent_t e0, hipEvent_t e1) {
   if (n <= 0 || B->members.empty()) return LBM_OK;
+  for (int64_t done = 0; done < n;) {
+    int64_t run = 0;
+    lbm_status s = uniform_steps(B, n - done, run);
+    if (s != LBM_OK) return s;
+    s = batch_run(B, run, done == 0 ? e0 : nullptr, done + run == n ? e1 : nullptr);
+    if (s != LBM_OK) return s;
+    done += run;
+  }
+  return LBM_OK;
+}
+
+static lbm_status batch_run(lbm_batch B, int64_t n, hipEvent_t e0, hipEvent_t e1) {
   Plan P;
   lbm_status s = make_plan(B, n, P);  // synchronises the stream (table upload): the last graph is done
   if (s != LBM_OK) return s;

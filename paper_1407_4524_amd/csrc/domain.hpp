@@ -53,6 +53,10 @@ struct Body {
   double* dyn = nullptr;
   double* pred = nullptr;  // node terms of the predicted pose (LBM_SETS_PREDICTED)
   int64_t t_placed = 0;
+  // scratch of the many-workgroup advance (moving bodies that are not outer
+  // circles): wide_slabs workgroups of WIDE_ROWS region rows each
+  double* wide = nullptr;
+  int wide_slabs = 0;
 };
 
 }  // namespace host
@@ -122,7 +126,19 @@ int64_t region_cells(const Body& b, int D, int64_t t, int mode);
 int64_t region_rows(const Body& b, int64_t t, int mode);
 // upper bound of the near-surface node list of body b's advance from t
 int64_t list_bound(const Body& b, int D, int64_t t);
+// whether the advance of a moving body (prescribed motion) from step t runs
+// in the single-workgroup list kernel (body_step_fits of its region, rows
+// and list); the list is bounded only when the region fits
+bool step_fits(const Body& b, int D, int64_t t);
 lbm_status check_device_errors(lbm_domain d);
+// whether a body may advance in the many-workgroup kernels (it holds their
+// scratch), and the slabs its region needs at any pose while it moves less
+// than a node per step (free bodies: always) in a domain of n nodes per axis
+bool wide_advance(int D, const lbm_body_desc& bd);
+int wide_slab_bound(int D, const int n[3], const lbm_body_desc& bd);
+// makes the body's scratch hold at least `slabs` slabs; a larger one is
+// allocated (and zeroed) after `s` has drained
+lbm_status ensure_wide(Body& b, int slabs, hipStream_t s);
 // the advance of body `id` from step t to t+1 on the current source buffer
 lbm_status launch_advance(lbm_domain d, int id, int64_t t);
 // n steps of a domain with several bodies through a one-member batch of its

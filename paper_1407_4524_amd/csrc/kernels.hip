@@ -227,11 +227,12 @@ hipError_t launch_body_advance(int lat, int st, int eq, void* B, uint8_t* mask, 
                                int* n_links, int cap, const double* pose, const double* pose_host, const BodyShape& bs,
                                int bc, int body, int mode, const Geom& g, const Phys& ph, double* rec_t, double* rec_t1,
                                int* err, hipStream_t s, int64_t region_cells, int64_t region_rows, int64_t list_nodes,
-                               hipEvent_t e0, hipEvent_t e1) {
+                               double* wide, int wide_slabs, hipEvent_t e0, hipEvent_t e1) {
+  if (wide && wide_slabs <= 0) return hipErrorInvalidValue;
   with_types(lat, st, eq, [&](auto Lt, auto St, auto E) {
     LBM_TYPES
     O::body_advance(B, mask, mask_next, links, n_links, cap, pose, pose_host, bs, bc, body, mode, g, ph, rec_t,
-                    rec_t1, err, s, region_cells, region_rows, list_nodes, e0, e1);
+                    rec_t1, err, s, region_cells, region_rows, list_nodes, wide, wide_slabs, e0, e1);
   });
   return hipGetLastError();
 }
@@ -417,6 +418,16 @@ hipError_t launch_batch_body_step(int lat, int st, int eq, const BatchDomain* do
   with_types(lat, st, eq, [&](auto Lt, auto St, auto E) {
     LBM_TYPES
     O::batch_body_step(doms, bodies, nbodies, lds, step, s, sbase);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_wide(int lat, int st, int eq, const BatchDomain* doms, const BatchBody* bodies, int nbodies,
+                             int max_slabs, int64_t step, hipStream_t s, const int64_t* sbase) {
+  if (nbodies <= 0 || max_slabs <= 0) return hipErrorInvalidValue;
+  with_types(lat, st, eq, [&](auto Lt, auto St, auto E) {
+    LBM_TYPES
+    O::batch_wide(doms, bodies, nbodies, max_slabs, step, s, sbase);
   });
   return hipGetLastError();
 }

@@ -16,6 +16,17 @@ constexpr int STEP_LIST = 2048;       // window nodes
 constexpr int STEP_CELLS = 20480;     // status box nodes (two bytes each)
 constexpr int STEP_LINKS = 8192;      // links held in LDS (the rest go through global memory)
 constexpr int LINK_BLOCK = 256;       // threads per block of the link-rule kernel
+// Advance of a moving body over many workgroups (bodies too large for the
+// single-workgroup kernels): region rows per workgroup, threads per
+// workgroup, links of a workgroup held in LDS (the rest go through global
+// memory). The body's scratch holds, per workgroup, 20 sums and a link
+// count, then one arrival counter (zero between launches).
+constexpr int WIDE_ROWS = 16;
+constexpr int WIDE_BLOCK = 256;
+constexpr int WIDE_LINKS = 4096;
+inline size_t wide_scratch_bytes(int slabs) {
+  return (size_t)slabs * (20 * sizeof(double) + sizeof(int)) + sizeof(unsigned);
+}
 
 struct BulkShape {
   int nbx, nrows, nplanes, nblocks;
@@ -94,12 +105,16 @@ hipError_t launch_poison_body(int lat, int st, int eq, void* A, void* B, const u
 hipError_t launch_fold(const double* ring, int nchunks, int ring_steps, int64_t t0, int64_t nsteps, double* rec,
                        int64_t rec_cap, int64_t rec_stride, bool zero_nodes, hipStream_t s);
 // pose: the poses of t and t+1 on the device; pose_host: the same two on the
-// host (read at the call)
+// host (read at the call). wide (optional): the body's scratch for the
+// many-workgroup advance, of wide_slabs workgroups; an advance (mode 1) of a
+// body that is not an outer circle and does not fit the single-workgroup
+// list kernel takes it when given.
 hipError_t launch_body_advance(int lat, int st, int eq, void* B, uint8_t* mask, uint8_t* mask_next, Link* links,
                                int* n_links, int cap, const double* pose, const double* pose_host, const BodyShape& bs,
                                int bc, int body, int mode, const Geom& g, const Phys& ph, double* rec_t, double* rec_t1,
                                int* err, hipStream_t s, int64_t region_cells, int64_t region_rows, int64_t list_nodes,
-                               hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+                               double* wide = nullptr, int wide_slabs = 0, hipEvent_t ev_start = nullptr,
+                               hipEvent_t ev_stop = nullptr);
 
 // The node terms of a FREE body's step t over the covered and uncovered
 // nodes between its pose t (pose[0..15], device) and the pose one step at
@@ -168,6 +183,8 @@ struct BatchBody {
   unsigned* counter;
   int* err;
   int64_t t0;          // the member's step at batch step 0
+  double* wide;        // scratch of the many-workgroup advance (wide_scratch_bytes(wide_slabs))
+  int wide_slabs;
 };
 
 // (block, nodes per thread) of the batched stream-collide variants
@@ -195,6 +212,10 @@ hipError_t launch_batch_body_links(int lat, int st, int eq, const BatchDomain* d
 hipError_t launch_batch_body_step(int lat, int st, int eq, const BatchDomain* doms, const BatchBody* bodies,
                                   int nbodies, int64_t max_region_cells, int64_t step, hipStream_t s,
                                   const int64_t* sbase = nullptr);
+// the many-workgroup advance of every body in `bodies` after batch step
+// `step` (two launches, max_slabs workgroups per body)
+hipError_t launch_batch_wide(int lat, int st, int eq, const BatchDomain* doms, const BatchBody* bodies, int nbodies,
+                             int max_slabs, int64_t step, hipStream_t s, const int64_t* sbase = nullptr);
 // Newton-Euler step of a FREE body (include/lbm.h): from the flow force of
 // the record rec_t (and the node terms of rec_tm1, optional) and the pose in
 // pose[0..15], the pose of the next step into pose[16..31] and traj[0..7];
@@ -238,7 +259,7 @@ struct Ops {
                            const double* pose, const double* pose_host, const BodyShape& bs, int bc, int body,
                            int mode, const Geom& g, const Phys& ph, double* rec_t, double* rec_t1, int* err,
                            hipStream_t s, int64_t region_cells, int64_t region_rows, int64_t list_nodes,
-                           hipEvent_t e0, hipEvent_t e1);
+                           double* wide, int wide_slabs, hipEvent_t e0, hipEvent_t e1);
   static void body_predict(const void* B, const uint8_t* mask, const double* pose, const BodyShape& bs, int body,
                            const Geom& g, const Phys& ph, double* out, hipStream_t s);
   static void batch_bulk(const BatchDomain* doms, const BatchTile* tiles, int ntiles, const BulkConfig& cfg,
@@ -250,6 +271,8 @@ struct Ops {
                                const int64_t* sbase);
   static void batch_body_step(const BatchDomain* doms, const BatchBody* bodies, int nbodies, size_t lds,
                               int64_t step, hipStream_t s, const int64_t* sbase);
+  static void batch_wide(const BatchDomain* doms, const BatchBody* bodies, int nbodies, int max_slabs, int64_t step,
+                         hipStream_t s, const int64_t* sbase);
 };
 
 #define LBM_OPS_FOR(MACRO, Lt, St) \

@@ -304,6 +304,13 @@ int64_t lbm::host::list_bound(const Body& b, int D, int64_t t) {
   return step_list_nodes(b.shape, p0[0], p0[1], D);
 }
 
+bool lbm::host::step_fits(const Body& b, int D, int64_t t) {
+  if (b.shape.shape == SHAPE_OUTER_CIRCLE) return false;
+  const int64_t cells = region_cells(b, D, t, 1), rows = region_rows(b, t, 1);
+  if (!body_step_fits(cells, rows, 0)) return false;
+  return body_step_fits(cells, rows, list_bound(b, D, t));
+}
+
 lbm_status lbm::host::check_device_errors(lbm_domain d) {
   int e[4] = {0, 0, 0, 0};
   HIP_TRY(hipMemcpy(e, d->err, sizeof(e), hipMemcpyDeviceToHost));
@@ -433,12 +440,11 @@ static lbm_status start_free_motion(lbm_domain d, Body& b) {
   return LBM_OK;
 }
 
-// Sizes of a FREE body's advance that hold at any pose (the host does not
-// know the pose): per axis the region spans at most 2h + 8 nodes for the
-// half-width h of the body (two poses less than one node apart, two
-// layers each side), the status box two more.
-static void free_bounds(const Body& b, int D, int64_t& cells, int64_t& rows, int64_t& list) {
-  const lbm_body_desc& bd = b.desc;
+// Per axis the region of a body's advance (node boxes of two poses less than
+// a node apart, two layers each side) spans at most 2h + 8 nodes for the
+// half-width h of the body; `cells` adds the one-node margin of the status
+// box.
+static void region_bounds(int D, const lbm_body_desc& bd, int64_t& cells, int64_t& rows) {
   double h[3];
   if (bd.shape == LBM_SHAPE_ELLIPSE) {
     h[0] = h[1] = std::max(bd.axes[0], bd.axes[1]);
@@ -453,7 +459,47 @@ static void free_bounds(const Body& b, int D, int64_t& cells, int64_t& rows, int
     cells *= n + 2;
     if (a > 0) rows *= n;
   }
-  list = cells <= STEP_LIST ? cells : (int64_t)STEP_LIST + 1;  // larger bodies take the box-scan advance
+}
+
+// A moving body advances, step by step, in the single-workgroup list kernel
+// while its region and near-surface list fit it, and in the many-workgroup
+// kernels otherwise; every body whose solid set moves (outer circles aside)
+// holds the latter's scratch. A batch takes the same decision for every step
+// (it splits a call where a body changes kernels), so a body's records do not
+// depend on how it is stepped.
+bool lbm::host::wide_advance(int D, const lbm_body_desc& bd) {
+  (void)D;
+  const bool round = bd.shape != LBM_SHAPE_ELLIPSE;
+  const bool moves = !(bd.motion == LBM_MOTION_STATIC || (round && bd.motion == LBM_MOTION_ROTATE));
+  return moves && bd.shape != LBM_SHAPE_OUTER_CIRCLE;
+}
+
+int lbm::host::wide_slab_bound(int D, const int n[3], const lbm_body_desc& bd) {
+  int64_t cells, rows;
+  region_bounds(D, bd, cells, rows);
+  rows = std::min<int64_t>(rows, D == 2 ? n[1] : (int64_t)n[1] * n[2]);  // within the domain
+  return (int)((rows + WIDE_ROWS - 1) / WIDE_ROWS);
+}
+
+lbm_status lbm::host::ensure_wide(Body& b, int slabs, hipStream_t s) {
+  if (slabs <= b.wide_slabs) return LBM_OK;
+  HIP_TRY(hipStreamSynchronize(s));  // the old scratch may still be in use
+  if (b.wide) HIP_TRY(hipFree(b.wide));
+  b.wide = nullptr;
+  b.wide_slabs = 0;
+  HIP_TRY(hipMalloc(&b.wide, wide_scratch_bytes(slabs)));
+  HIP_TRY(hipMemsetAsync(b.wide, 0, wide_scratch_bytes(slabs), s));
+  b.wide_slabs = slabs;
+  return LBM_OK;
+}
+
+// Sizes of a FREE body's advance that hold at any pose (the host does not
+// know the pose): the bounds of region_bounds; a list bound beyond the list
+// kernel's when the box is, so that the kernel a free body takes is the same
+// at every step.
+static void free_bounds(const Body& b, int D, int64_t& cells, int64_t& rows, int64_t& list) {
+  region_bounds(D, b.desc, cells, rows);
+  list = cells <= STEP_LIST ? cells : (int64_t)STEP_LIST + 1;
 }
 
 // The Newton-Euler step of a FREE body from the records of step t: the pose
@@ -506,12 +552,17 @@ lbm_status lbm::host::launch_advance(lbm_domain d, int id, int64_t t) {
   } else {
     cells = region_cells(b, d->D, t, 1);
     rows = region_rows(b, t, 1);
-    list = list_bound(b, d->D, t);
+    // the list bound only decides when the region fits the list kernel
+    list = body_step_fits(cells, rows, 0) ? list_bound(b, d->D, t) : (int64_t)STEP_LIST + 1;
+    if (b.wide) {
+      s = ensure_wide(b, (int)((rows + WIDE_ROWS - 1) / WIDE_ROWS), d->stream);
+      if (s != LBM_OK) return s;
+    }
   }
   HIP_TRY(launch_body_advance(d->lat, d->st, d->eq, d->A, d->mask, d->mask_next, b.links, b.n_links, b.cap,
                               pose_at(b, t), b.free_motion ? nullptr : pose_host_at(b, t), b.shape, b.desc.bc, id,
                               1, d->g, d->ph, rec_slot(d, t, id), rec_slot(d, t + 1, id), d->err, d->stream, cells,
-                              rows, list, e0, e1));
+                              rows, list, b.wide, b.wide_slabs, e0, e1));
   return LBM_OK;
 }
 
@@ -553,6 +604,7 @@ static lbm_status undo_placement(lbm_domain d, int id) {
   if (b.pose_pinned) (void)hipHostFree(b.pose_pinned);
   if (b.traj) (void)hipFree(b.traj);
   if (b.dyn) (void)hipFree(b.dyn);
+  if (b.wide) (void)hipFree(b.wide);
   b = Body();
   return LBM_OK;
 }
@@ -598,6 +650,10 @@ lbm_status lbm_body_footprint_bytes(const lbm_domain_desc* desc, const lbm_body_
   const size_t cap = (size_t)link_capacity(D, bd);
   *bytes = cap * sizeof(Link) + sizeof(int) + (cap + 63) / 64 * 12 * sizeof(double) +
            (size_t)POSE_WINDOW * POSE_LEN * sizeof(double);
+  if (wide_advance(D, *bd)) {
+    const int n[3] = {desc->nx, desc->ny, D == 3 ? desc->nz : 1};
+    *bytes += wide_scratch_bytes(wide_slab_bound(D, n, *bd));
+  }
   return LBM_OK;
 }
 
@@ -700,6 +756,7 @@ lbm_status lbm_destroy_domain(lbm_domain d) {
     if (b.dyn) (void)hipFree(b.dyn);
     if (b.pose_dev) (void)hipFree(b.pose_dev);
     if (b.pose_pinned) (void)hipHostFree(b.pose_pinned);
+    if (b.wide) (void)hipFree(b.wide);
   }
   if (d->aux) {
     hipError_t ea = hipStreamSynchronize(d->aux);
@@ -797,6 +854,11 @@ lbm_status lbm_set_body(lbm_domain d, int32_t id, const lbm_body_desc* bd) {
   }
   b.ring_chunks = std::max(1, (b.n_host + 63) / 64);
   HIP_TRY(hipMalloc(&b.ring, (size_t)PART_RING * b.ring_chunks * 12 * sizeof(double)));
+  if (wide_advance(d->D, *bd)) {
+    const int n[3] = {d->g.nx, d->g.ny, d->g.nz};
+    s = ensure_wide(b, wide_slab_bound(d->D, n, *bd), d->stream);
+    if (s != LBM_OK) return s;
+  }
   b.part_n = 0;
   b.active = true;
   b.bc_ready = false;

@@ -181,9 +181,9 @@ def test_all_eight_seeded_batch_members_against_the_oracle():
 # single domains
 
 
-def test_global_memory_advance_against_the_oracle():
+def test_large_region_advance_against_the_oracle():
     """a rotating 80x40 ellipse in a 420x300 channel: its region is too large
-    for the single-workgroup LDS kernels, so the global-memory advance runs;
+    for the single-workgroup list kernel, so the many-workgroup advance runs;
     counts every step and links bit-exact, force/torque within 1e-4"""
     w = copy.deepcopy(W.batched_domains(count=1, seed=0)[0])
     w.update(nx=420, ny=300)
@@ -194,7 +194,7 @@ def test_global_memory_advance_against_the_oracle():
     rg, ro = g.records(0), o.records(0)
     assert (rg[:, 18:20] == ro[:, 18:20]).all() and ro[:, 18].sum() > 0
     n = same_links(g, o)
-    check_series(rg, o, 0, "lattice", 80.0, TOL_FT["f32"], f"global-memory advance ({n} links)")
+    check_series(rg, o, 0, "lattice", 80.0, TOL_FT["f32"], f"many-workgroup advance ({n} links)")
     check_series(rg, o, 0, "comoving", 80.0, TOL_FT["f32"], "  comoving form")
 
 

@@ -12,8 +12,8 @@ printed), link lists bit-exact at the end, force series within 1e-9; FP32
 storage, velocity within 1e-4 of its largest value, positions within 1e-3
 nodes. Prescribed motions with the AIDUN and EXTRAPOLATE refills keep the
 bars of the other prescribed-motion tests (counts bit-exact, force within
-1e-10 FP64 / 1e-4 FP32), on each of the three advance kernels (the
-list-based one, the box-in-LDS one and the box scan in global memory).
+1e-10 FP64 / 1e-4 FP32), on both advance kernels (the single-workgroup
+list kernel and the many-workgroup one).
 """
 import copy
 import math
@@ -142,9 +142,8 @@ def test_refill_rules_list_kernel(refill, storage):
 @pytest.mark.parametrize("refill", ["aidun", "extrapolate"])
 def test_refill_rules_box_kernels(refill):
     """A translating sphere of radius 8 in D3Q19 (its surface list is too long
-    for the list kernel: the box-in-LDS advance runs) and the rotating 80x40
-    ellipse of the global-memory advance, FP32: counts bit-exact, lattice
-    force within 1e-4."""
+    for the list kernel: the many-workgroup advance runs) and a rotating 80x40
+    ellipse, FP32: counts bit-exact, lattice force within 1e-4."""
     R = 8.0
     w3 = dict(name="sphere_move", lattice="D3Q19", nx=64, ny=40, nz=40, tau=0.7, rho0=1.0, eq="bgk",
               faces=W.PERIODIC_FACES, inlet_profile="uniform", inlet_u=0.0, storage="f32", rho_noise=0.0, seed=0,

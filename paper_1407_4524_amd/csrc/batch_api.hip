@@ -267,8 +267,12 @@ static lbm_status enqueue_steps(lbm_batch B, const Plan& P, int64_t k0, int64_t 
   const auto* links = reinterpret_cast<const BatchBody*>(B->dev + P.off_links);
   const auto* moving = reinterpret_cast<const BatchBody*>(B->dev + P.off_moving);
   const auto* wide = reinterpret_cast<const BatchBody*>(B->dev + P.off_wide);
-  const BulkConfig bc{B->cfg.block, B->cfg.cells_per_thread, 0, B->cfg.remap};
-  const BulkConfig nc{B->cfg.block, B->cfg.cells_per_thread, 0, 0};
+  // buffer resources while every member's population buffer is below 4 GiB
+  size_t largest = 0;
+  for (lbm_domain d : B->members) largest = std::max(largest, (size_t)d->Q * d->g.S * d->elem);
+  const int buf = largest < ((size_t)1 << 32) ? 1 : 0;
+  const BulkConfig bc{B->cfg.block, B->cfg.cells_per_thread, 0, B->cfg.remap, buf};
+  const BulkConfig nc{B->cfg.block, B->cfg.cells_per_thread, 0, 0, buf};
   const int lat = first->lat, st = first->st, eq = first->eq;
   // 2D: the link rule of the bodies with fixed links for step k+1 joins the
   // advance launch of step k (at the first step of a sequence it runs on its

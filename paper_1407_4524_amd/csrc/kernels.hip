@@ -2,6 +2,8 @@
 // dispatch of each launch to the Ops<lattice, storage, equilibrium>
 // instantiation that holds its kernels (inst_*.hip), plus the steady-state
 // kernel, which does not depend on the lattice.
+#include <vector>
+
 #include "kernels.hpp"
 #include "reduce.hpp"
 #include "rows.hpp"
@@ -354,11 +356,37 @@ int64_t step_list_nodes(const BodyShape& bs, const Pose& P0, const Pose& P1, int
     lo[a] = l;
     n[a] = h - l + 1;
   }
+  // the chord of every row of the region and the rows around it, at both
+  // poses, once; each row's windows then combine those of its neighbour rows
+  // exactly as row_windows does (min / max are exact, so the windows are the
+  // same)
+  const int my = n[1] + 2, mz = D == 3 ? n[2] + 2 : 1, dz0 = D == 3 ? 1 : 0;
+  struct Chord {
+    double a, b;
+    bool hit;
+  };
+  thread_local std::vector<Chord> ch;
+  ch.resize((size_t)2 * my * mz);
+  for (int k = 0; k < 2; ++k)
+    for (int zz = 0; zz < mz; ++zz)
+      for (int yy = 0; yy < my; ++yy) {
+        Chord& c = ch[((size_t)k * mz + zz) * my + yy];
+        c.a = c.b = 0.0;
+        c.hit = row_chord(bs, k ? P1 : P0, lo[1] - 1 + yy, lo[2] - dz0 + zz, c.a, c.b);
+      }
   int64_t total = 0;
   for (int r = 0; r < n[1] * n[2]; ++r) {
+    const int yy = 1 + r % n[1], zz = dz0 + r / n[1];
+    RowExtent e;
+    for (int dz = -dz0; dz <= dz0; ++dz)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int k = 0; k < 2; ++k) {
+          const Chord& c = ch[((size_t)k * mz + zz + dz) * my + yy + dy];
+          e.add(c.hit, c.a, c.b);
+        }
     int w[4] = {0, -1, 0, -1};
-    const int k = row_windows(bs, P0, P1, lo[1] + r % n[1], lo[2] + r / n[1], D, 2, lo[0], lo[0] + n[0] - 1, w);
-    for (int q = 0; q < k; ++q) total += w[2 * q + 1] - w[2 * q] + 1 + 2;  // + 2: rounding of the chord ends
+    const int nw = windows_of(e, 2, lo[0], lo[0] + n[0] - 1, w);
+    for (int q = 0; q < nw; ++q) total += w[2 * q + 1] - w[2 * q] + 1 + 2;  // + 2: rounding of the chord ends
   }
   return total;
 }
@@ -384,12 +412,12 @@ hipError_t launch_batch_bulk(int lat, int st, int eq, const BatchDomain* doms, c
 
 int batch_link_grid(int lat, int max_links) {
   if (lat == 0) return 1;  // 2D: one 1024-thread workgroup per body
-  return std::max(1, std::min(64, (max_links + LINK_BLOCK - 1) / LINK_BLOCK));
+  return std::max(1, (max_links + 63) / 64);  // 3D: one wavefront per chunk of 64 links
 }
 
 hipError_t launch_batch_links(int lat, int st, int eq, const BatchDomain* doms, const BatchBody* bodies, int nbodies,
                               int grid, int64_t step, hipStream_t s, const int64_t* sbase) {
-  if (nbodies <= 0 || grid <= 0 || grid > 64 || (lat == 0 && grid != 1)) return hipErrorInvalidValue;
+  if (nbodies <= 0 || grid <= 0 || (lat == 0 && grid != 1)) return hipErrorInvalidValue;
   with_types(lat, st, eq, [&](auto Lt, auto St, auto E) {
     LBM_TYPES
     O::batch_links(doms, bodies, nbodies, grid, step, s, sbase);

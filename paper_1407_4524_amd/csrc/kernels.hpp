@@ -35,9 +35,13 @@ BulkShape bulk_shape(const Geom& g, int span);
 
 // stream-collide launch shape: threads per block, nodes per thread, memory
 // mode (bit 0: non-temporal stores of the new state, bit 1: non-temporal
-// loads of the old one), XCD-aware block order
+// loads of the old one), XCD-aware block order; buf (batched sweep): every
+// member's population buffer is below 4 GiB, so the loads and stores go
+// through raw buffer resources with 32-bit offsets (the single-domain sweep
+// decides this from its own buffer)
 struct BulkConfig {
   int block, cells_per_thread, nontemporal, remap;
+  int buf = 0;
 };
 enum { MEM_NT_STORE = 1, MEM_NT_LOAD = 2 };
 BulkConfig bulk_config(int lat, int st, size_t footprint);
@@ -200,7 +204,7 @@ hipError_t launch_batch_bulk(int lat, int st, int eq, const BatchDomain* doms, c
                              hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr,
                              const int64_t* sbase = nullptr);
 // blocks per body of the batched link-rule launch for bodies of up to
-// max_links links
+// max_links links (2D: one workgroup; 3D: one wavefront per chunk of 64)
 int batch_link_grid(int lat, int max_links);
 hipError_t launch_batch_links(int lat, int st, int eq, const BatchDomain* doms, const BatchBody* bodies, int nbodies,
                               int grid, int64_t step, hipStream_t s, const int64_t* sbase = nullptr);

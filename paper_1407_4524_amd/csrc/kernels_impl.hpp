@@ -1448,7 +1448,7 @@ __device__ __forceinline__ double* batch_rec(const BatchBody& b, int64_t t) {
 
 // part 0: tile rows of every node; 1: the same without the members' near
 // boxes; 2: tiles of the near boxes (rows numbered within the box)
-template <class L, class S, int EQ, int BX, int CPT>
+template <class L, class S, int EQ, int BX, int CPT, int MEM, bool BUF>
 __global__ __launch_bounds__(BX) void k_stream_collide_batch(const BatchDomain* __restrict__ doms,
                                                              const BatchTile* __restrict__ tiles, int ntiles,
                                                              int remap, int64_t s, int part,
@@ -1469,15 +1469,16 @@ __global__ __launch_bounds__(BX) void k_stream_collide_batch(const BatchDomain* 
     const int nrows = D.hole[3] - D.hole[2] + 1;
     const int y = D.hole[2] + tl.row % nrows;
     const int z = D.hole[4] + tl.row / nrows;
-    stream_collide_span<L, S, EQ, BX, CPT, 0>(A, B, g, ph, D.hole[0] + tl.bx * (BX * CPT) + threadIdx.x, y, z,
-                                              D.hole[1], no_hole, rin, rout, D.mask, D.unstable);
+    stream_collide_span<L, S, EQ, BX, CPT, MEM, BUF>(A, B, g, ph, D.hole[0] + tl.bx * (BX * CPT) + threadIdx.x, y,
+                                                     z, D.hole[1], no_hole, rin, rout, D.mask, D.unstable);
     return;
   }
   const int nrows = g.hi[1] - g.lo[1] + 1;
   const int y = g.lo[1] + tl.row % nrows;
   const int z = g.lo[2] + tl.row / nrows;
-  stream_collide_span<L, S, EQ, BX, CPT, 0>(A, B, g, ph, g.lo[0] + tl.bx * (BX * CPT) + threadIdx.x, y, z,
-                                            g.hi[0], part == 1 ? D.hole : no_hole, rin, rout, D.mask, D.unstable);
+  stream_collide_span<L, S, EQ, BX, CPT, MEM, BUF>(A, B, g, ph, g.lo[0] + tl.bx * (BX * CPT) + threadIdx.x, y, z,
+                                                   g.hi[0], part == 1 ? D.hole : no_hole, rin, rout, D.mask,
+                                                   D.unstable);
 }
 
 // grid (blocks per body, bodies), NTL threads per block: the boundary rule +
@@ -1493,6 +1494,55 @@ __global__ __launch_bounds__(NTL) void k_links_batch(const BatchDomain* __restri
   const int64_t t = b.t0 + s;
   links_block<L, S, EQ, NTL>((typename S::T*)D.buf[s & 1], b.links, b.n_host, b.pose + (t - b.pose_base) * POSE_DOUBLES,
                         b.bc, b.mask, D.g, D.ph, b.partials, b.counter, batch_rec(b, t), blockIdx.x, gridDim.x);
+}
+
+// The link rule of batch step s in two launches, without a grid-wide
+// handshake: k_links_batch_part writes every chunk's 12 sums (as the waves of
+// links_block do), k_fold_batch adds them per body in the order of
+// links_block's last block, so the records are the same bits. Used in 3D,
+// where a body's links span many workgroups (a device-scope fence per
+// workgroup costs far more than the second launch).
+template <class L, class S, int EQ>
+__global__ __launch_bounds__(64) void k_links_batch_part(const BatchDomain* __restrict__ doms,
+                                                         const BatchBody* __restrict__ bodies, int64_t s,
+                                                         const int64_t* __restrict__ sbase) {
+  s += sbase ? *sbase : 0;
+  const BatchBody& b = bodies[blockIdx.y];
+  const int c = (int)blockIdx.x;  // chunk of 64 links
+  if (c * 64 >= b.n_host) return;
+  const BatchDomain& D = doms[b.dom];
+  const int64_t t = b.t0 + s;
+  const Pose P = *reinterpret_cast<const Pose*>(b.pose + (t - b.pose_base) * POSE_DOUBLES);
+  const int lane = threadIdx.x;
+  double acc[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  const int k = c * 64 + lane;
+  if (k < b.n_host) link_rule_m<L, S, EQ>((typename S::T*)D.buf[s & 1], b.links[k], P, b.bc, b.mask, D.g, D.ph, acc);
+#pragma unroll
+  for (int j = 0; j < 12; ++j) {
+    const double v = wave_sum(acc[j]);
+    if (lane == j) b.partials[c * 12 + j] = v;
+  }
+}
+
+template <class L>
+__global__ __launch_bounds__(64) void k_fold_batch(const BatchBody* __restrict__ bodies, int64_t s,
+                                                   const int64_t* __restrict__ sbase) {
+  s += sbase ? *sbase : 0;
+  const BatchBody& b = bodies[blockIdx.x];
+  const int lane = threadIdx.x;
+  const int nchunks = (b.n_host + 63) >> 6;
+  double acc[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int c = lane; c < nchunks; c += 64)
+#pragma unroll
+    for (int j = 0; j < 12; ++j) acc[j] += b.partials[c * 12 + j];
+  double* rec = batch_rec(b, b.t0 + s);
+#pragma unroll
+  for (int j = 0; j < 12; ++j) {
+    const double v = wave_sum(acc[j]);
+    if (lane == j) rec[j < 6 ? j : j + 6] = v;  // static -> 0..5, comoving -> 12..17
+  }
+  if (lane >= 12 && lane < 18) rec[lane - 6] = 0.0;  // node terms 6..11
+  if (lane >= 18 && lane < 20) rec[lane] = 0.0;      // counts 18, 19
 }
 
 // one workgroup per moving body: its advance after batch step s's bulk update
@@ -1702,11 +1752,18 @@ template <class L, class S, int EQ>
 void Ops<L, S, EQ>::batch_bulk(const BatchDomain* doms, const BatchTile* tiles, int ntiles, const BulkConfig& cfg,
                                int64_t step, hipStream_t s, int part, hipEvent_t e0, hipEvent_t e1,
                                const int64_t* sbase) {
-#define LBM_BATCH_CASE(BX_, CPT_)                                                                          \
-  if (cfg.block == BX_ && cfg.cells_per_thread == CPT_) {                                                  \
-    launch_timed(k_stream_collide_batch<L, S, EQ, BX_, CPT_>, dim3(ntiles), dim3(BX_), 0, s, e0, e1, doms, tiles, \
-                 ntiles, cfg.remap, step, part, sbase);                                                    \
-    return;                                                                                                \
+  // buffer-resource accesses with 32-bit offsets, or plain global accesses
+  // when a member's buffer is 4 GiB or more (plain memory mode either way:
+  // non-temporal loads, the choice for a single D3Q19 domain beyond the
+  // last-level cache, made the served mix of many small 3D members slower)
+#define LBM_BATCH_LAUNCH(BX_, CPT_, BUF_)                                                                     \
+  launch_timed(k_stream_collide_batch<L, S, EQ, BX_, CPT_, 0, BUF_>, dim3(ntiles), dim3(BX_), 0, s, e0, e1, doms, \
+               tiles, ntiles, cfg.remap, step, part, sbase)
+#define LBM_BATCH_CASE(BX_, CPT_)                         \
+  if (cfg.block == BX_ && cfg.cells_per_thread == CPT_) { \
+    if (cfg.buf) LBM_BATCH_LAUNCH(BX_, CPT_, true);       \
+    else LBM_BATCH_LAUNCH(BX_, CPT_, false);              \
+    return;                                               \
   }
   LBM_BATCH_CASE(64, 1)
   LBM_BATCH_CASE(128, 1)
@@ -1714,16 +1771,19 @@ void Ops<L, S, EQ>::batch_bulk(const BatchDomain* doms, const BatchTile* tiles, 
   LBM_BATCH_CASE(64, 2)
   LBM_BATCH_CASE(128, 2)
 #undef LBM_BATCH_CASE
+#undef LBM_BATCH_LAUNCH
 }
 
 template <class L, class S, int EQ>
 void Ops<L, S, EQ>::batch_links(const BatchDomain* doms, const BatchBody* bodies, int nbodies, int grid, int64_t step,
                                 hipStream_t s, const int64_t* sbase) {
-  if constexpr (L::D == 2)
+  if constexpr (L::D == 2) {
     hipLaunchKernelGGL((k_links_batch<L, S, EQ, 1024>), dim3(1, nbodies), dim3(1024), 0, s, doms, bodies, step, sbase);
-  else
-    hipLaunchKernelGGL((k_links_batch<L, S, EQ, LINK_BLOCK>), dim3(grid, nbodies), dim3(LINK_BLOCK), 0, s, doms,
-                       bodies, step, sbase);
+  } else {
+    // grid: chunks of 64 links of the largest body
+    hipLaunchKernelGGL((k_links_batch_part<L, S, EQ>), dim3(grid, nbodies), dim3(64), 0, s, doms, bodies, step, sbase);
+    hipLaunchKernelGGL(k_fold_batch<L>, dim3(nbodies), dim3(64), 0, s, bodies, step, sbase);
+  }
 }
 
 template <class L, class S, int EQ>

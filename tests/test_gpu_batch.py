@@ -73,9 +73,9 @@ def test_batch_equals_each_domain_alone(overlap, own_stream, graph):
     batch.close()
 
 
-def test_batch_fallback_for_a_large_moving_body():
-    """a rotating ellipse whose region exceeds the one-workgroup LDS kernel
-    is advanced by its own launches inside the batched step"""
+def test_batch_large_moving_body():
+    """a rotating ellipse whose region exceeds the single-workgroup list
+    kernel is advanced by the many-workgroup kernels inside the batched step"""
     from paper_1407_4524_amd import Batch
     w = copy.deepcopy(W.batched_domains(count=1, seed=0)[0])
     w.update(nx=420, ny=300)
@@ -90,6 +90,40 @@ def test_batch_fallback_for_a_large_moving_body():
     for d in members:
         batch.add(d)
     batch.step(40)
+    for a, b in zip(members, alone):
+        assert_same(a, b)
+    batch.close()
+
+
+@pytest.mark.parametrize("graph", [0, 1])
+def test_batch_3d_many_links(graph):
+    """D3Q19 FP32 members: a static sphere of radius 18 (more than 16384
+    links, so its link rule spans more than 256 wavefronts), a rotating
+    ellipsoid (many-workgroup advance) and a small translating sphere (list
+    kernel), batched in calls of 70 and 30 steps, against each alone"""
+    from paper_1407_4524_amd import Batch
+    base = dict(lattice="D3Q19", tau=0.7, rho0=1.0, eq="bgk", faces=W.DUCT_FACES, inlet_profile="uniform",
+                inlet_u=0.02, storage="f32", rho_noise=0.0, seed=0)
+    ws = [dict(base, name="sphere18", nx=96, ny=48, nz=48,
+               bodies=[dict(shape="circle", axes=(18.0,), bc="mls", me="static", motion="static",
+                            c0=(40.3, 24.1, 23.8))]),
+          dict(base, name="ellipsoid", nx=48, ny=40, nz=40,
+               bodies=[dict(shape="ellipse", axes=(9.0, 6.0, 5.0), bc="mls", me="lattice", motion="rotate",
+                            c0=(20.3, 19.8, 20.1), theta0=0.3, omega=0.01)]),
+          dict(base, name="small_sphere", nx=40, ny=32, nz=32,
+               bodies=[dict(shape="circle", axes=(3.0,), bc="mls", me="lattice", motion="const_vel",
+                            c0=(12.2, 15.7, 16.1), vel=(0.02, 0.0, 0.0))])]
+    alone = [make_gpu(w) for w in ws]
+    for d in alone:
+        d.step(100)
+    assert len(alone[0].links(0)[0]) > 16384
+    batch = Batch()
+    batch.config = dict(batch.config, graph=graph)
+    members = [make_gpu(w) for w in ws]
+    for d in members:
+        batch.add(d)
+    for n in (70, 30):
+        batch.step(n)
     for a, b in zip(members, alone):
         assert_same(a, b)
     batch.close()

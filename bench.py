@@ -451,8 +451,8 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the 4.8 GB channel line")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-domain batched line")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-requests line")
-    ap.add_argument("--serve-requests", type=int, default=64)
-    ap.add_argument("--serve-max-steps", type=int, default=3000)
+    ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--serve-max-steps", type=int, default=2000)
     ap.add_argument("--serve-progress", action="store_true", help="a line on stderr per finished request")
     ap.add_argument("--serve-parts", default="batched,plain,loaded",
                     help="which served runs: batched, plain (one at a time), loaded (batched at 70%% of capacity)")

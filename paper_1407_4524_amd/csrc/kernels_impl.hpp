@@ -1710,12 +1710,12 @@ void Ops<L, S, EQ>::body_advance(void* B, uint8_t* mask, uint8_t* mask_next, Lin
   const size_t lds = ((size_t)2 * region_cells + 15) / 16 * 16;
   const bool fits = body_step_fits(region_cells, region_rows, list_nodes);
   if (mode == 1 && wide && bs.shape != SHAPE_OUTER_CIRCLE && !fits) {
-    if (e0) hipEventRecord(e0, s);
+    if (e0) (void)hipEventRecord(e0, s);
     hipLaunchKernelGGL((k_wide_sets<L, S, EQ>), dim3(wide_slabs), dim3(WIDE_BLOCK), 0, s, b, mask, pose, bs, body,
                        g, ph, wide, wide_slabs, err);
     hipLaunchKernelGGL((k_wide_links<L, S, EQ>), dim3(wide_slabs), dim3(WIDE_BLOCK), 0, s, b, mask, links, n_links,
                        cap, pose, bs, bc, body, g, ph, wide, wide_slabs, rec_t, rec_t1, err);
-    if (e1) hipEventRecord(e1, s);
+    if (e1) (void)hipEventRecord(e1, s);
   } else if (mode == 1 && !pose_host && bs.shape != SHAPE_OUTER_CIRCLE && fits) {
     constexpr int NT = L::D == 2 ? 1024 : 512;
     launch_timed(k_body_step_free<L, S, EQ, NT>, dim3(1), dim3(NT), lds, s, e0, e1, b, mask, links, n_links, cap,

@@ -401,7 +401,10 @@ typedef struct lbm_batch_s* lbm_batch;
 /* Launch shape of a batch. block x cells_per_thread nodes per tile, one of
    (64,1) (128,1) (256,1) (64,2) (128,2); remap 1 = blocks ordered so that
    each XCD takes a contiguous run of tiles; order 0 = tiles member by
-   member, 1 = largest members first, 2 = rows of all members interleaved;
+   member, 1 = largest members first, 2 = rows of all members interleaved,
+   3 = tiles of `block` consecutive active nodes that run across rows (x,
+   then y, then z; largest members first; cells_per_thread 1 only), so that
+   short rows leave no lanes idle;
    overlap 1 = each member's nodes near its bodies (the node boxes of the
    poses of the call plus one layer) are updated on the batch's stream
    together with the body work, the rest on a second stream the batch owns

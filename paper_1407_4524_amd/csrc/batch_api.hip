@@ -45,7 +45,8 @@ size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
 bool config_ok(const lbm_batch_config& c) {
   return batch_bulk_supported(c.block, c.cells_per_thread) && (c.remap == 0 || c.remap == 1) && c.order >= 0 &&
-         c.order <= 2 && (c.overlap == 0 || c.overlap == 1) && (c.graph == 0 || c.graph == 1);
+         c.order <= 3 && (c.order < 3 || c.cells_per_thread == 1) && (c.overlap == 0 || c.overlap == 1) &&
+         (c.graph == 0 || c.graph == 1);
 }
 
 // steps per captured sequence of a graph-mode call (even: the buffer parity
@@ -70,7 +71,14 @@ std::vector<BatchTile> make_tiles(const std::vector<lbm_domain>& m, const lbm_ba
     return (g.hi[1] - g.lo[1] + 1) * (g.hi[2] - g.lo[2] + 1);
   };
   std::vector<BatchTile> tiles;
-  if (c.order == 2) {
+  if (c.order == 3) {  // spans of `span` consecutive active nodes across rows, largest members first
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return active_nodes(m[a]->g) > active_nodes(m[b]->g); });
+    for (int i : order) {
+      const int64_t n = active_nodes(m[i]->g);
+      for (int64_t f = 0; f < n; f += span) tiles.push_back(BatchTile{(uint16_t)i, 0, (int32_t)f});
+    }
+  } else if (c.order == 2) {
     int maxrows = 0;
     for (size_t i = 0; i < m.size(); ++i) maxrows = std::max(maxrows, nrows((int)i));
     for (int r = 0; r < maxrows; ++r)
@@ -273,6 +281,7 @@ static lbm_status enqueue_steps(lbm_batch B, const Plan& P, int64_t k0, int64_t 
   const int buf = largest < ((size_t)1 << 32) ? 1 : 0;
   const BulkConfig bc{B->cfg.block, B->cfg.cells_per_thread, 0, B->cfg.remap, buf};
   const BulkConfig nc{B->cfg.block, B->cfg.cells_per_thread, 0, 0, buf};
+  const int flat = B->cfg.order == 3 ? 1 : 0;  // tiles of P.tiles are spans across rows
   const int lat = first->lat, st = first->st, eq = first->eq;
   // 2D: the link rule of the bodies with fixed links for step k+1 joins the
   // advance launch of step k (at the first step of a sequence it runs on its
@@ -284,7 +293,7 @@ static lbm_status enqueue_steps(lbm_batch B, const Plan& P, int64_t k0, int64_t 
       else HIP_TRY(hipEventRecord(B->e_near, main));
       HIP_TRY(hipStreamWaitEvent(B->aux, B->e_near, 0));
       HIP_TRY(launch_batch_bulk(lat, st, eq, doms, tiles, (int)P.tiles.size(), bc, k, B->aux, 1, nullptr,
-                                capture ? nullptr : B->e_far, sbase));
+                                capture ? nullptr : B->e_far, sbase, flat));
       if (capture) HIP_TRY(hipEventRecord(B->e_far, B->aux));
     }
     if (!P.links.empty() && (!fuse || k == k0))
@@ -295,7 +304,7 @@ static lbm_status enqueue_steps(lbm_batch B, const Plan& P, int64_t k0, int64_t 
       if (capture) HIP_TRY(hipEventRecord(B->e_near, main));
     } else {
       HIP_TRY(launch_batch_bulk(lat, st, eq, doms, tiles, (int)P.tiles.size(), bc, k, main, 0, nullptr, nullptr,
-                                sbase));
+                                sbase, flat));
     }
     if (fuse && k + 1 < k1)
       HIP_TRY(launch_batch_body_links(lat, st, eq, doms, moving, (int)P.moving.size(), links, (int)P.links.size(),
@@ -665,7 +674,8 @@ lbm_status lbm_batch_tune(lbm_batch B, int32_t trial_steps, lbm_batch_config* ch
   for (int overlap = 0; overlap <= 1 && s == LBM_OK; ++overlap)
   for (const auto& v : BATCH_BULK_VARIANTS)
     for (int remap = 0; remap <= 1 && s == LBM_OK; ++remap)
-      for (int order = 0; order <= 2 && s == LBM_OK; ++order) {
+      for (int order = 0; order <= 3 && s == LBM_OK; ++order) {
+        if (order == 3 && v[1] != 1) continue;
         B->cfg = lbm_batch_config{v[0], v[1], remap, order, overlap, 0, 0.0};
         s = batch_step(B, trial_steps, e0, e1);
         if (s != LBM_OK) break;

@@ -399,13 +399,14 @@ bool batch_bulk_supported(int block, int cells_per_thread) {
 
 hipError_t launch_batch_bulk(int lat, int st, int eq, const BatchDomain* doms, const BatchTile* tiles, int ntiles,
                              const BulkConfig& cfg, int64_t step, hipStream_t s, int part, hipEvent_t ev_start,
-                             hipEvent_t ev_stop, const int64_t* sbase) {
-  if (ntiles <= 0 || !batch_bulk_supported(cfg.block, cfg.cells_per_thread) || part < 0 || part > 2)
+                             hipEvent_t ev_stop, const int64_t* sbase, int flat) {
+  if (ntiles <= 0 || !batch_bulk_supported(cfg.block, cfg.cells_per_thread) || part < 0 || part > 2 ||
+      (flat && (part == 2 || cfg.cells_per_thread != 1)))
     return hipErrorInvalidValue;
   if (ev_start != nullptr && ev_stop == nullptr) return hipErrorInvalidValue;
   with_types(lat, st, eq, [&](auto Lt, auto St, auto E) {
     LBM_TYPES
-    O::batch_bulk(doms, tiles, ntiles, cfg, step, s, part, ev_start, ev_stop, sbase);
+    O::batch_bulk(doms, tiles, ntiles, cfg, step, s, part, ev_start, ev_stop, sbase, flat);
   });
   return hipGetLastError();
 }

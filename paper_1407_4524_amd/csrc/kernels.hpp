@@ -199,10 +199,13 @@ bool batch_bulk_supported(int block, int cells_per_thread);
 // boxes, 2 near-box tiles (rows numbered within the box)
 // sbase (optional, device): added to `step` by the kernels, for step
 // sequences captured once and replayed
+// flat (parts 0 and 1): tile.row is the first of `block` consecutive active
+// nodes of the member in x, y, z order (a span may cross rows; one node per
+// thread)
 hipError_t launch_batch_bulk(int lat, int st, int eq, const BatchDomain* doms, const BatchTile* tiles, int ntiles,
                              const BulkConfig& cfg, int64_t step, hipStream_t s, int part = 0,
                              hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr,
-                             const int64_t* sbase = nullptr);
+                             const int64_t* sbase = nullptr, int flat = 0);
 // blocks per body of the batched link-rule launch for bodies of up to
 // max_links links (2D: one workgroup; 3D: one wavefront per chunk of 64)
 int batch_link_grid(int lat, int max_links);
@@ -267,7 +270,8 @@ struct Ops {
   static void body_predict(const void* B, const uint8_t* mask, const double* pose, const BodyShape& bs, int body,
                            const Geom& g, const Phys& ph, double* out, hipStream_t s);
   static void batch_bulk(const BatchDomain* doms, const BatchTile* tiles, int ntiles, const BulkConfig& cfg,
-                         int64_t step, hipStream_t s, int part, hipEvent_t e0, hipEvent_t e1, const int64_t* sbase);
+                         int64_t step, hipStream_t s, int part, hipEvent_t e0, hipEvent_t e1, const int64_t* sbase,
+                         int flat);
   static void batch_links(const BatchDomain* doms, const BatchBody* bodies, int nbodies, int grid, int64_t step,
                           hipStream_t s, const int64_t* sbase);
   static void batch_body_links(const BatchDomain* doms, const BatchBody* moving, int n_moving,

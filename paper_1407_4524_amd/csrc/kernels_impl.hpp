@@ -1452,7 +1452,7 @@ template <class L, class S, int EQ, int BX, int CPT, int MEM, bool BUF>
 __global__ __launch_bounds__(BX) void k_stream_collide_batch(const BatchDomain* __restrict__ doms,
                                                              const BatchTile* __restrict__ tiles, int ntiles,
                                                              int remap, int64_t s, int part,
-                                                             const int64_t* __restrict__ sbase) {
+                                                             const int64_t* __restrict__ sbase, int flat) {
   s += sbase ? *sbase : 0;  // a captured step sequence takes its first step from the device
   const int blk = remap ? xcd_block(blockIdx.x, ntiles) : blockIdx.x;
   const BatchTile tl = tiles[blk];
@@ -1474,6 +1474,17 @@ __global__ __launch_bounds__(BX) void k_stream_collide_batch(const BatchDomain* 
     return;
   }
   const int nrows = g.hi[1] - g.lo[1] + 1;
+  if (flat) {  // node tl.row + t of the member's active nodes (x fastest); past the last one: no update
+    const int nxa = g.hi[0] - g.lo[0] + 1;
+    const int64_t total = (int64_t)nxa * nrows * (g.hi[2] - g.lo[2] + 1);
+    const int64_t f = (int64_t)tl.row + threadIdx.x;
+    const int ff = (int)(f < total ? f : total - 1);
+    const int r = ff / nxa;
+    const int x = f < total ? g.lo[0] + (ff - r * nxa) : g.hi[0] + 1;
+    stream_collide_span<L, S, EQ, BX, 1, MEM, BUF>(A, B, g, ph, x, g.lo[1] + r % nrows, g.lo[2] + r / nrows, g.hi[0],
+                                                 part == 1 ? D.hole : no_hole, rin, rout, D.mask, D.unstable);
+    return;
+  }
   const int y = g.lo[1] + tl.row % nrows;
   const int z = g.lo[2] + tl.row / nrows;
   stream_collide_span<L, S, EQ, BX, CPT, MEM, BUF>(A, B, g, ph, g.lo[0] + tl.bx * (BX * CPT) + threadIdx.x, y, z,
@@ -1751,14 +1762,14 @@ void Ops<L, S, EQ>::body_predict(const void* B, const uint8_t* mask, const doubl
 template <class L, class S, int EQ>
 void Ops<L, S, EQ>::batch_bulk(const BatchDomain* doms, const BatchTile* tiles, int ntiles, const BulkConfig& cfg,
                                int64_t step, hipStream_t s, int part, hipEvent_t e0, hipEvent_t e1,
-                               const int64_t* sbase) {
+                               const int64_t* sbase, int flat) {
   // buffer-resource accesses with 32-bit offsets, or plain global accesses
   // when a member's buffer is 4 GiB or more (plain memory mode either way:
   // non-temporal loads, the choice for a single D3Q19 domain beyond the
   // last-level cache, made the served mix of many small 3D members slower)
 #define LBM_BATCH_LAUNCH(BX_, CPT_, BUF_)                                                                     \
   launch_timed(k_stream_collide_batch<L, S, EQ, BX_, CPT_, 0, BUF_>, dim3(ntiles), dim3(BX_), 0, s, e0, e1, doms, \
-               tiles, ntiles, cfg.remap, step, part, sbase)
+               tiles, ntiles, cfg.remap, step, part, sbase, flat)
 #define LBM_BATCH_CASE(BX_, CPT_)                         \
   if (cfg.block == BX_ && cfg.cells_per_thread == CPT_) { \
     if (cfg.buf) LBM_BATCH_LAUNCH(BX_, CPT_, true);       \

@@ -76,9 +76,13 @@ class GpuEngine:
         if k not in self.groups:
             stream = self.torch.cuda.Stream()  # default priority
             batch = self.lbm.Batch(stream=stream.cuda_stream)
-            # one-wavefront row tiles: the rows of the small members (48..160
-            # nodes in 3D) leave fewer lanes idle than with 256-thread tiles
-            batch.config = dict(batch.config, block=64, cells_per_thread=1)
+            # launch shapes measured on the served mix: the short rows of the
+            # 3D members (46..158 nodes) are swept in spans that run across
+            # rows, the 2D members in one-wavefront row tiles
+            if spec["lattice"] == "D3Q19":
+                batch.config = dict(batch.config, block=256, cells_per_thread=1, order=3, overlap=1)
+            else:
+                batch.config = dict(batch.config, block=64, cells_per_thread=1, overlap=1)
             self.groups[k] = [batch, stream]
         batch, stream = self.groups[k]
         with self.torch.cuda.stream(stream):

@@ -43,12 +43,14 @@ def assert_same(a, b):
     assert np.array_equal(ra, rb, equal_nan=True) and np.array_equal(ua, ub, equal_nan=True)
 
 
-@pytest.mark.parametrize("overlap,own_stream,graph", [(1, True, 0), (1, False, 0), (0, False, 0), (0, True, 1),
-                                                      (1, True, 1)])
-def test_batch_equals_each_domain_alone(overlap, own_stream, graph):
+@pytest.mark.parametrize("overlap,own_stream,graph,order", [(1, True, 0, 0), (1, False, 0, 0), (0, False, 0, 0),
+                                                            (0, True, 1, 0), (1, True, 1, 0), (0, True, 0, 3),
+                                                            (1, True, 1, 3)])
+def test_batch_equals_each_domain_alone(overlap, own_stream, graph, order):
     """overlap on a stream of the batch's own uses the CU-masked second
     stream, on the default stream a plain one; graph mode replays a captured
-    32-step sequence in the 100-step call (3 replays and 4 ordinary steps)"""
+    32-step sequence in the 100-step call (3 replays and 4 ordinary steps);
+    order 3 sweeps spans of consecutive nodes across rows"""
     import torch
     from paper_1407_4524_amd import Batch
     ws = small_batch()
@@ -61,7 +63,7 @@ def test_batch_equals_each_domain_alone(overlap, own_stream, graph):
         d.step(150)
     s = torch.cuda.Stream() if own_stream else torch.cuda.current_stream()
     batch = Batch(stream=s.cuda_stream)
-    batch.config = dict(batch.config, overlap=overlap, graph=graph)
+    batch.config = dict(batch.config, overlap=overlap, graph=graph, order=order, cells_per_thread=1)
     with torch.cuda.stream(s):
         members = [make_gpu(w) for w in ws]
     for d in members:
@@ -118,7 +120,7 @@ def test_batch_3d_many_links(graph):
         d.step(100)
     assert len(alone[0].links(0)[0]) > 16384
     batch = Batch()
-    batch.config = dict(batch.config, graph=graph)
+    batch.config = dict(batch.config, graph=graph, order=3 if graph else 0, block=64, cells_per_thread=1)
     members = [make_gpu(w) for w in ws]
     for d in members:
         batch.add(d)
@@ -141,12 +143,14 @@ def test_batch_members_at_different_steps_and_tuning():
     for d in members:
         batch.add(d)
     chosen, trials = batch.tune(trial_steps=3)
-    # 60 shapes of 3 steps, then the best shape in ordinary and graph mode over 64 steps each
-    assert len(trials) == 63 and chosen["us_per_step"] == min(t["us_per_step"] for t in trials[60:])
-    assert {t["graph"] for t in trials[60:]} == {0, 1}
+    # 72 shapes of 3 steps (60 with row tiles, 12 with spans across rows), then
+    # the best shape in ordinary and graph mode over 64 steps each
+    assert len(trials) == 75 and chosen["us_per_step"] == min(t["us_per_step"] for t in trials[72:])
+    assert {t["graph"] for t in trials[72:]} == {0, 1}
+    assert sum(t["order"] == 3 for t in trials[:72]) == 12
     batch.step(20)
     for a in alone:
-        a.step(60 * 3 + 3 * 64 + 20)
+        a.step(72 * 3 + 3 * 64 + 20)
     for a, m in zip(alone, members):
         assert_same(m, a)
     # a member can still be stepped on its own while it belongs to the batch

@@ -165,3 +165,29 @@ def test_kernel_switch_against_oracle_and_batch():
     assert np.array_equal(a.records(0), rg)
     assert np.array_equal(a.fields()[1], g.fields()[1], equal_nan=True)
     b.close()
+
+
+def test_flat_ellipsoid_many_links_per_slab_f32():
+    """a flat ellipsoid (48, 46, 3) rotating about z at 1e-3 rad/step in a
+    120 x 112 x 24 duct (73 thousand links): the slabs of rows just above and
+    below its flat faces hold up to about 5000 links, more than a workgroup
+    keeps in LDS (4096), so the rest go through global memory; links, counts
+    and force against the oracle"""
+    w = dict(name="flat_ellipsoid_f32", lattice="D3Q19", nx=120, ny=112, nz=24, tau=0.7, rho0=1.0, eq="bgk",
+             faces=W.DUCT_FACES, inlet_profile="uniform", inlet_u=0.01, storage="f32", rho_noise=0.0, seed=0,
+             bodies=[dict(shape="ellipse", axes=(48.0, 46.0, 3.0), bc="mls", me="lattice", motion="rotate",
+                          c0=(60.2, 56.1, 11.8), theta0=0.4, omega=1e-3)])
+    print(f"{w['name']}, 30 steps", flush=True)
+    g, o = run_pair(w, 30)
+    ng, dg, lg = g.links(0)
+    no, do, lo = o.links(0)
+    print(f"{len(no)} links")
+    assert len(no) > 60000
+    assert np.array_equal(ng, no) and np.array_equal(dg, do) and np.abs(lg - lo).max() == 0.0
+    rg, ro = g.records(0), o.records(0)
+    assert np.array_equal(rg[:, 18:20], ro[:, 18:20]) and ro[:, 19].sum() > 0
+    F, T = ora_series(o, 0, "lattice")
+    eF, eT = series_error(rg[:, 0:6] + rg[:, 6:12], F, T, 48.0,
+                          scale=max(np.abs(F).max(), np.abs(T).max() / 48.0))
+    print(f"lattice: F {eF:.2e} T {eT:.2e}")
+    assert eF < 1e-4 and eT < 1e-4

@@ -91,8 +91,8 @@
  * passes device_buffer, which then must outlive the domain. The caller owns
  * every host pointer; the library copies what it keeps. The stream is
  * borrowed. One thread per domain at a time. lbm_step only enqueues work
- * (see lbm_step for the one synchronisation of a domain with several
- * bodies); errors raised on the device surface at the next call
+ * (see lbm_step for the one synchronisation of a domain with moving or
+ * several bodies); errors raised on the device surface at the next call
  * that reads results (lbm_force_torque, lbm_records, lbm_get_*). Work the
  * caller enqueues on the stream after lbm_step sees the whole step (see
  * split_schedule for the second stream a domain may use).
@@ -266,12 +266,13 @@ lbm_status lbm_destroy_domain(lbm_domain dom);
 lbm_status lbm_set_body(lbm_domain dom, int32_t body_id, const lbm_body_desc* body);
 
 /* Advances nsteps time steps. Enqueue only, except that a domain with two
-   or more bodies (none of them FREE, no face records, not in a batch) steps
-   its bodies through batched launches -- the link rule of every body with
-   fixed links in one launch, the advance of every moving body in another,
-   as a one-member batch of the domain's own -- and such a call synchronises
-   the stream once (the launch tables' upload). Results are the same bits
-   either way. */
+   or more bodies, or with one body whose solid set moves (none of them
+   FREE, no face records, not in a batch, no split_schedule), is stepped as
+   a one-member batch of the domain's own -- the link rule of every body
+   with fixed links in one launch, the advance of every moving body in
+   another, the nodes away from the bodies updated on a second stream beside
+   the body work -- and such a call synchronises the stream once (the launch
+   tables' upload). Results are the same bits either way. */
 lbm_status lbm_step(lbm_domain dom, int64_t nsteps);
 
 /* Blocks until the domain's queued work is done and reports device errors. */

@@ -282,6 +282,17 @@ static lbm_status enqueue_steps(lbm_batch B, const Plan& P, int64_t k0, int64_t 
   const BulkConfig bc{B->cfg.block, B->cfg.cells_per_thread, 0, B->cfg.remap, buf};
   const BulkConfig nc{B->cfg.block, B->cfg.cells_per_thread, 0, 0, buf};
   const int flat = B->cfg.order == 3 ? 1 : 0;  // tiles of P.tiles are spans across rows
+  // a domain that lbm_step advances through a one-member batch of its own
+  // keeps its kernel timing: the update of every node but the near box (or
+  // of every node) is its stream-collide launch
+  const lbm_domain solo = B->members.size() == 1 && B->members[0]->solo == B ? B->members[0] : nullptr;
+  int64_t timed_nodes = 0;
+  if (solo) {
+    const int* h = P.doms[0].hole;
+    timed_nodes = active_nodes(solo->g);
+    if (split && h[0] <= h[1])
+      timed_nodes -= (int64_t)(h[1] - h[0] + 1) * (h[3] - h[2] + 1) * (h[5] - h[4] + 1);
+  }
   const int lat = first->lat, st = first->st, eq = first->eq;
   // 2D: the link rule of the bodies with fixed links for step k+1 joins the
   // advance launch of step k (at the first step of a sequence it runs on its
@@ -292,9 +303,14 @@ static lbm_status enqueue_steps(lbm_batch B, const Plan& P, int64_t k0, int64_t 
       if (k > k0) HIP_TRY(hipStreamWaitEvent(main, B->e_far, 0));
       else HIP_TRY(hipEventRecord(B->e_near, main));
       HIP_TRY(hipStreamWaitEvent(B->aux, B->e_near, 0));
-      HIP_TRY(launch_batch_bulk(lat, st, eq, doms, tiles, (int)P.tiles.size(), bc, k, B->aux, 1, nullptr,
-                                capture ? nullptr : B->e_far, sbase, flat));
-      if (capture) HIP_TRY(hipEventRecord(B->e_far, B->aux));
+      hipEvent_t t0 = nullptr, t1 = nullptr;
+      if (solo && !capture) {
+        lbm_status ts = timing_slot(solo, LBM_KERNEL_STREAM_COLLIDE, timed_nodes, t0, t1);
+        if (ts != LBM_OK) return ts;
+      }
+      HIP_TRY(launch_batch_bulk(lat, st, eq, doms, tiles, (int)P.tiles.size(), bc, k, B->aux, 1, t0,
+                                t1 ? t1 : (capture ? nullptr : B->e_far), sbase, flat));
+      if (capture || t1) HIP_TRY(hipEventRecord(B->e_far, B->aux));
     }
     if (!P.links.empty() && (!fuse || k == k0))
       HIP_TRY(launch_batch_links(lat, st, eq, doms, links, (int)P.links.size(), P.link_grid, k, main, sbase));
@@ -303,8 +319,12 @@ static lbm_status enqueue_steps(lbm_batch B, const Plan& P, int64_t k0, int64_t 
                                 capture ? nullptr : B->e_near, sbase));
       if (capture) HIP_TRY(hipEventRecord(B->e_near, main));
     } else {
-      HIP_TRY(launch_batch_bulk(lat, st, eq, doms, tiles, (int)P.tiles.size(), bc, k, main, 0, nullptr, nullptr,
-                                sbase, flat));
+      hipEvent_t t0 = nullptr, t1 = nullptr;
+      if (solo && !capture) {
+        lbm_status ts = timing_slot(solo, LBM_KERNEL_STREAM_COLLIDE, timed_nodes, t0, t1);
+        if (ts != LBM_OK) return ts;
+      }
+      HIP_TRY(launch_batch_bulk(lat, st, eq, doms, tiles, (int)P.tiles.size(), bc, k, main, 0, t0, t1, sbase, flat));
     }
     if (fuse && k + 1 < k1)
       HIP_TRY(launch_batch_body_links(lat, st, eq, doms, moving, (int)P.moving.size(), links, (int)P.links.size(),

@@ -559,25 +559,34 @@ struct Region {
   }
 };
 
+// Inclusive prefix sum of an int over the 64 lanes of a wavefront: DPP row
+// shifts within each row of 16 lanes, then the totals of the rows below
+// (read out of lanes 15, 31, 47) added on; no LDS round trip.
+__device__ __forceinline__ int wave_inclusive_scan(int x) {
+  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr:1
+  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);  // row_shr:2
+  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr:4
+  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);  // row_shr:8
+  const int lane = threadIdx.x & 63;
+  const int r0 = __builtin_amdgcn_readlane(x, 15), r1 = __builtin_amdgcn_readlane(x, 31),
+            r2 = __builtin_amdgcn_readlane(x, 47);
+  return x + (lane >= 16 ? r0 : 0) + (lane >= 32 ? r1 : 0) + (lane >= 48 ? r2 : 0);
+}
+
+// Exclusive prefix sum over the NT threads of a block (thread order); the
+// total lands in sm[NT / 64]. Every thread of the block must call it.
 template <int NT = 1024>
 __device__ inline int block_exclusive_scan(int v, int* sm /* NT/64 + 1 */) {
+  static_assert(NT % 64 == 0 && NT / 64 <= 64, "whole wavefronts, at most 64");
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  int x = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    int y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
+  const int x = wave_inclusive_scan(v);
   if (lane == 63) sm[wave] = x;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int s = 0;
-    for (int w = 0; w < NT / 64; ++w) {
-      int t = sm[w];
-      sm[w] = s;
-      s += t;
-    }
-    sm[NT / 64] = s;
+  if (wave == 0) {  // the wavefront totals, scanned by the first wavefront
+    const int t = lane < NT / 64 ? sm[lane] : 0;
+    const int it = wave_inclusive_scan(t);
+    if (lane < NT / 64) sm[lane] = it - t;
+    if (lane == NT / 64 - 1) sm[NT / 64] = it;
   }
   __syncthreads();
   return sm[wave] + x - v;

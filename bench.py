@@ -109,7 +109,11 @@ def timing_period(steps):
     return 1 if steps <= 1024 else max(1, steps // 512)
 
 
-def run_gpu(name, steps, warmup, split_schedule=False):
+# lbm_domain_desc.split_schedule of each --schedule choice
+SCHEDULES = {"auto": 0, "split": 1, "plain": -1}
+
+
+def run_gpu(name, steps, warmup, split_schedule=0):
     import torch
     from paper_1407_4524_amd import Domain
     w = workload(name)
@@ -467,9 +471,11 @@ def main():
     ap.add_argument("--sediment-steps", type=int, default=20000)
     ap.add_argument("--no-copy-ceiling", action="store_true",
                     help="skip the copy-kernel reference at the stream-collide footprint")
-    ap.add_argument("--split-schedule", action="store_true",
-                    help="with a single moving body, update the nodes away from it on a second stream, "
-                         "overlapping the body's advance")
+    ap.add_argument("--schedule", choices=sorted(SCHEDULES), default="auto",
+                    help="a single body's step: auto (the library's default: a moving body's domain steps as "
+                         "a one-member batch, a fixed body's in the plain schedule), split (the nodes away from "
+                         "the body updated on a second stream beside the body work) or plain (one launch after "
+                         "another)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
@@ -478,7 +484,7 @@ def main():
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
 
-    main_run = run_gpu(args.workload, args.steps, args.warmup, args.split_schedule)
+    main_run = run_gpu(args.workload, args.steps, args.warmup, SCHEDULES[args.schedule])
     w = main_run["w"]
     line = {
         "metric": METRIC,
@@ -498,7 +504,7 @@ def main():
                    "force_accumulation": "f64", "bodies": len(w["bodies"]),
                    "me": w["bodies"][0]["me"] if w["bodies"] else None, "parallelism": "single-gpu",
                    "footprint_bytes": main_run["footprint_bytes"],
-                   "schedule": "split" if args.split_schedule else "plain"},
+                   "schedule": args.schedule, "near_box_launches": "near_box" in main_run["kernels"]},
         "roofline": main_run["roofline"],
         "kernels": main_run["kernels"],
     }
@@ -507,7 +513,7 @@ def main():
     if not args.no_secondary and args.workload == HEADLINE:
         sec = {}
         for name in ("duct_sphere_f16", "duct_sphere_zouhe_f32", "channel_oscillating_f32", "suspension_f32"):
-            r = run_gpu(name, args.steps, args.warmup, args.split_schedule)
+            r = run_gpu(name, args.steps, args.warmup, SCHEDULES[args.schedule])
             sec[r["w"]["name"]] = secondary_line(r)
             if name == "suspension_f32":
                 sec[r["w"]["name"]]["note"] = ("lbm_step steps the 32 bodies through batched launches (one for the "

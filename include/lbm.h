@@ -170,14 +170,20 @@ typedef struct {
   void* device_buffer;      /* optional caller-owned device memory; NULL = library allocates */
   size_t device_buffer_bytes;
   int64_t record_capacity;  /* steps kept in each body's record ring; 0 = 65536 */
-  int32_t split_schedule;   /* 0 (default): each step runs the link rule, the stream-collide
-                               update and the body advance one after another on `stream`;
-                               1: with a single moving body, the update of the nodes away
-                               from it runs on a second stream the domain owns (default
-                               priority), overlapping the body's advance, and every call
-                               leaves `stream` waiting for it. Results are bitwise the same.
-                               The split costs two cross-stream waits per step on the host,
-                               which on small domains outweighs the overlap */
+  int32_t split_schedule;   /* schedule of a domain with a single body (not FREE, not an outer
+                               circle). Split: the update of the nodes away from the body
+                               runs on a second stream the domain owns (default priority),
+                               beside the body's link rule or advance and the update of a
+                               near box around it on `stream`, and every call leaves `stream`
+                               waiting for it. Plain: the link rule, the stream-collide
+                               update and the advance one after another on `stream`.
+                               0 (default): a moving body steps as a one-member batch (see
+                               lbm_step), a body with fixed links in the plain schedule;
+                               1: split; -1: plain. Results are bitwise the same in every
+                               schedule. The split costs two cross-stream waits per step on
+                               the host, and the far update loses bandwidth to the kernels
+                               running beside it, which outweighs the overlap on the
+                               domains measured */
   int32_t face_records;     /* 1: the momentum exchange of the domain faces is recorded every
                                step (lbm_face_records, lbm_force_torque with LBM_WALLS); one
                                small kernel per step over the face nodes. 0: not recorded */
@@ -267,7 +273,7 @@ lbm_status lbm_set_body(lbm_domain dom, int32_t body_id, const lbm_body_desc* bo
 
 /* Advances nsteps time steps. Enqueue only, except that a domain with two
    or more bodies, or with one body whose solid set moves (none of them
-   FREE, no face records, not in a batch, no split_schedule), is stepped as
+   FREE, no face records, not in a batch, split_schedule 0), is stepped as
    a one-member batch of the domain's own -- the link rule of every body
    with fixed links in one launch, the advance of every moving body in
    another, the nodes away from the bodies updated on a second stream beside

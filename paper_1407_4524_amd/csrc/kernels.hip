@@ -54,9 +54,11 @@ BulkShape bulk_shape(const Geom& g, int span) {
 // FP32: 119.7 -> 101.4 us), on the stores of the D2Q9 sweep (8192x8192 FP32:
 // 884 us, against 1057 us with two nodes per thread and non-temporal
 // loads), and on neither with 2-byte storage (FP16 duct: 58.3 us plain,
-// 62.6 with non-temporal stores).
+// 62.6 with non-temporal stores); the D2Q9 sweep in 2-byte storage takes
+// two nodes per thread (8192x8192 FP16: 423 us against 519 us with one).
 BulkConfig bulk_config(int lat, int st, size_t footprint) {
-  if (footprint <= (size_t)192 << 20 || st == 2) return BulkConfig{256, 1, 0, 0};
+  if (footprint <= (size_t)192 << 20) return BulkConfig{256, 1, 0, 0};
+  if (st == 2) return lat == 0 ? BulkConfig{128, 2, 0, 0} : BulkConfig{256, 1, 0, 0};
   if (lat == 0) return BulkConfig{256, 1, MEM_NT_STORE, 0};
   return BulkConfig{256, 1, MEM_NT_LOAD, 0};
 }

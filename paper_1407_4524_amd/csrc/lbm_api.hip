@@ -78,6 +78,7 @@ static lbm_status check_desc(const lbm_domain_desc* d) {
   if (d->max_bodies < 0 || d->max_bodies > LBM_MAX_BODIES) return fail(LBM_E_INVAL, "max_bodies out of range");
   if ((d->face_records != 0 && d->face_records != 1) || (d->debug_poison != 0 && d->debug_poison != 1))
     return fail(LBM_E_INVAL, "face_records and debug_poison are 0 or 1");
+  if (d->split_schedule < -1 || d->split_schedule > 1) return fail(LBM_E_INVAL, "split_schedule is -1, 0 or 1");
   return LBM_OK;
 }
 
@@ -868,16 +869,19 @@ lbm_status lbm_set_body(lbm_domain d, int32_t id, const lbm_body_desc* bd) {
 // One step is, in order: the boundary rule + momentum exchange of bodies
 // whose links are fixed (k_links, on the source buffer), the stream-collide
 // update of every node, and the advance of bodies whose solid set moves (on
-// the new state). With a single body whose solid set moves and the split
-// schedule asked for, the update is split in two: the nodes of a near box
-// around the body are updated on the domain's stream, followed there by the
-// body's advance, while every other node is updated on the domain's second
-// stream. The far update of step t waits for the near update of step t-1,
-// and the near update of step t for the far update of step t-1, so the
-// advance of step t-1 overlaps the far update of step t. The near box holds
-// the node boxes of poses t-1, t and t+1 plus one layer: every node an
-// advance touches lies inside it, away from the rows the far update reads.
-// Every node is updated from the same values either way.
+// the new state). In the split schedule of a single body the update is split
+// in two: the nodes of a near box around the body are updated on the
+// domain's stream, after the body's link rule there (fixed links) or followed
+// there by the body's advance (moving solid set), while every other node is
+// updated on the domain's second stream. The far update of step t waits for
+// the near update of step t-1, and the near update and link rule of step t
+// for the far update of step t-1, so the body work of one step overlaps a
+// far update. The near box holds the node boxes of poses t-1, t and t+1 plus
+// one layer: every node the link rule or an advance reads or writes (the
+// pose's node box holds the body, its links' fluid nodes and the second
+// fluid nodes the interpolated rule reads) lies inside it, away from the
+// nodes the far update reads and writes. Every node is updated from the same
+// values either way.
 lbm_status lbm_step(lbm_domain d, int64_t nsteps) {
   if (!d) return fail(LBM_E_INVAL, "null domain");
   if (nsteps < 0) return fail(LBM_E_INVAL, "negative step count");
@@ -892,18 +896,26 @@ lbm_status lbm_step(lbm_domain d, int64_t nsteps) {
     }
   bool any_free = false;
   for (int id = 0; id < d->nslots; ++id) any_free = any_free || (d->body[id].active && d->body[id].free_motion);
-  const bool one_moving = nactive == 1 && d->body[only].mask_moves && !d->body[only].free_motion &&
-                          d->body[only].desc.shape != LBM_SHAPE_OUTER_CIRCLE;
+  const bool single = nactive == 1 && !d->body[only].free_motion && d->body[only].desc.shape != LBM_SHAPE_OUTER_CIRCLE;
+  const bool one_moving = single && d->body[only].mask_moves;
+  const int ask = d->desc.split_schedule;
   // several bodies, or one body whose solid set moves: batched launches of
   // the domain's own one-member batch, whose overlapped step updates the
   // nodes away from the bodies beside the body work (the 2000 x 800
   // oscillating cylinder: 34.6 us per step against 39.1 us with the launches
   // below); bodies with fixed links alone keep the deferred link-rule sums
-  if ((nactive >= 2 || (one_moving && !d->desc.split_schedule)) && !any_free && !d->face_rec && !d->batch)
+  if ((nactive >= 2 || (one_moving && ask == 0)) && !any_free && !d->face_rec && !d->batch)
     return solo_step(d, nsteps);
-  const bool split = d->desc.split_schedule && one_moving;
+  // a single body in the split schedule only when asked for: beside other
+  // kernels the far update loses about a tenth of its bandwidth (the 256 x
+  // 128 x 128 duct with a fixed sphere: 117 us per step split against 110.5
+  // us plain), more than the link rule it hides
+  const bool split = single && ask == 1;
   if (split && !d->aux) {
-    lbm_status sa = create_far_stream(d->stream, &d->aux, FAR_CU_EVERY);
+    // compute units kept free for a moving body's one-workgroup advance; a
+    // fixed body's link rule needs none (with one unit in 32 masked off the
+    // duct's far update took 129 us against 113 us unmasked)
+    lbm_status sa = create_far_stream(d->stream, &d->aux, one_moving ? FAR_CU_EVERY : 0);
     if (sa != LBM_OK) return sa;
     HIP_TRY(hipEventCreateWithFlags(&d->e_near, hipEventDisableTiming | hipEventDisableSystemFence));
     HIP_TRY(hipEventCreateWithFlags(&d->e_far, hipEventDisableTiming | hipEventDisableSystemFence));

@@ -9,6 +9,17 @@
 
 namespace lbm {
 
+// The update's arithmetic: every fused multiply-add is written out
+// (fmadd) and the functions that compute a node's new populations let the
+// compiler form no other, so that the bits of a node's update do not depend
+// on the kernel or launch shape the code is compiled into (left to the
+// compiler, the fusions followed the surrounding code).
+template <class C>
+__device__ __forceinline__ C fmadd(C a, C b, C c) {
+  if constexpr (sizeof(C) == 8) return __builtin_fma(a, b, c);
+  else return __builtin_fmaf(a, b, c);
+}
+
 // ---------------------------------------------------------------------------
 // domain faces, applied on the pull side
 
@@ -64,6 +75,7 @@ __device__ __forceinline__ int64_t xface_delta(const Geom& g, int i, bool lo_sid
 // precomputed on the host).
 template <class C>
 __device__ __forceinline__ C inlet_speed(const Geom& g, const Phys& ph, C yB, C zB) {
+#pragma clang fp contract(off)
   C u = (C)ph.inlet_u;
   if (ph.inlet_profile == 1) {
     if (g.face[2] == FACE_WALL) u *= (C)ph.inlet_ky * ((yB - (C)0.5) * ((C)(g.ny - 1.5) - yB));
@@ -86,6 +98,7 @@ __device__ __forceinline__ C inlet_speed(const Geom& g, const Phys& ph, C yB, C 
 // which give the node zero tangential momentum.
 template <class L, int EQ, int SIDE, class C>
 __device__ __forceinline__ void zou_he(C* h, bool velocity, C ux, C rho0) {
+#pragma clang fp contract(off)
   C k0 = 0, kb = 0, ty = 0, tz = 0;
 #pragma unroll
   for (int i = 0; i < L::Q; ++i) {
@@ -97,15 +110,15 @@ __device__ __forceinline__ void zou_he(C* h, bool velocity, C ux, C rho0) {
       kb += h[i];
     }
   }
-  const C known = k0 + (C)2 * kb;
+  const C known = fmadd((C)2, kb, k0);
   C jx;
-  if (velocity) jx = EQ ? rho0 * ux : (rho0 + known) / ((C)1 - (C)SIDE * ux) * ux;
+  if (velocity) jx = EQ ? rho0 * ux : (rho0 + known) / fmadd(-(C)SIDE, ux, (C)1) * ux;
   else jx = -(C)SIDE * known;
   const C ny = (C)0.5 * ty, nz = (C)0.5 * tz;
 #pragma unroll
   for (int i = 1; i < L::Q; ++i) {
     if (L::cx(i) != SIDE) continue;
-    C v = h[L::opp(i)] + (C)(6.0 * L::w(i) * SIDE) * jx;
+    C v = fmadd((C)(6.0 * L::w(i) * SIDE), jx, h[L::opp(i)]);
     if (L::cy(i)) v += L::cy(i) > 0 ? -ny : ny;
     if (L::D == 3 && L::cz(i)) v += L::cz(i) > 0 ? -nz : nz;
     h[i] = v;
@@ -133,6 +146,7 @@ __device__ __forceinline__ int xface_index(const Geom& g, int x, int y, int z) {
 template <class L, class S, int EQ>
 __device__ __forceinline__ void collide(typename S::C* h, typename S::C rho0, typename S::C omega,
                                         typename S::C& rho_out, typename S::C& uu_out) {
+#pragma clang fp contract(off)
   using C = typename S::C;
   C drho = h[0], jx = 0, jy = 0, jz = 0;
 #pragma unroll
@@ -149,13 +163,13 @@ __device__ __forceinline__ void collide(typename S::C* h, typename S::C rho0, ty
   const C rhoU = EQ ? rho0 : rho;
   const C inv = (C)1 / rhoU;
   const C ux = jx * inv, uy = jy * inv, uz = jz * inv;
-  const C uu = ux * ux + uy * uy + uz * uz;
+  const C uu = fmadd(ux, ux, fmadd(uy, uy, uz * uz));
   uu_out = uu;
   // even part common to all directions: drho - rhoU 3/2 u.u
-  const C t = drho - rhoU * ((C)1.5 * uu);
+  const C t = fmadd(-rhoU, (C)1.5 * uu, drho);
   const C keep = (C)1 - omega;
   const C r45 = (C)4.5 * rhoU, r3 = (C)3 * rhoU;
-  h[0] = keep * h[0] + omega * ((C)L::w(0) * t);
+  h[0] = fmadd(keep, h[0], omega * ((C)L::w(0) * t));
 #pragma unroll
   for (int i = 1; i < L::Q; ++i) {
     const int o = L::opp(i);
@@ -165,10 +179,10 @@ __device__ __forceinline__ void collide(typename S::C* h, typename S::C rho0, ty
     if (L::cy(i)) cu += L::cy(i) > 0 ? uy : -uy;
     if (L::D == 3 && L::cz(i)) cu += L::cz(i) > 0 ? uz : -uz;
     const C wo = omega * (C)L::w(i);
-    const C a = wo * (t + r45 * (cu * cu));  // omega times the even part of f^eq_i - w_i rho0
-    const C b = wo * (r3 * cu);              // omega times the odd part
-    h[i] = keep * h[i] + (a + b);
-    h[o] = keep * h[o] + (a - b);
+    const C a = wo * fmadd(r45, cu * cu, t);  // omega times the even part of f^eq_i - w_i rho0
+    const C r3cu = r3 * cu;                   // wo r3cu: omega times the odd part
+    h[i] = fmadd(keep, h[i], fmadd(wo, r3cu, a));
+    h[o] = fmadd(keep, h[o], fmadd(-wo, r3cu, a));
   }
   rho_out = rho;
 }
@@ -288,8 +302,8 @@ __device__ __forceinline__ void stream_collide_row(const typename S::T* __restri
         apply = L::cx(i) == 1 ? (inlet & xlo) : (outvel & xhi);
       }
       if (apply)
-        h[k][i] += (C)(6.0 * L::w(i) * L::cx(i)) * rho_w[k] *
-                   inlet_speed<C>(g, ph, (C)y - (C)(0.5 * L::cy(i)), (C)z - (C)(0.5 * L::cz(i)));
+        h[k][i] = fmadd((C)(6.0 * L::w(i) * L::cx(i)) * rho_w[k],
+                        inlet_speed<C>(g, ph, (C)y - (C)(0.5 * L::cy(i)), (C)z - (C)(0.5 * L::cz(i))), h[k][i]);
     }
   }
   // Zou-He faces: the entering populations of the x-face nodes rebuilt

@@ -195,7 +195,7 @@ def domain_desc(lattice="D2Q9", nx=64, ny=64, nz=1, tau=0.8, rho0=1.0, storage="
     d.inlet_profile = _enum(PROFILE, inlet_profile)
     d.inlet_u = inlet_u
     d.record_capacity = record_capacity
-    d.split_schedule = 1 if split_schedule else 0
+    d.split_schedule = int(split_schedule)  # False/0: the default schedule, True/1: split, -1: plain
     d.face_records = 1 if face_records else 0
     d.debug_poison = 1 if debug_poison else 0
     d.max_bodies = max_bodies

@@ -360,6 +360,46 @@ def test_split_schedule_bitwise_equals_plain(case, own_stream):
     b.close()
 
 
+@pytest.mark.parametrize("case", ["sphere_f32", "sphere_f16_face_records", "cylinder_f64"])
+def test_split_schedule_fixed_body_bitwise_equals_plain(case):
+    """a body with fixed links in the split schedule (its link rule and the
+    near box's update on the domain's stream beside the far update on the
+    second) against the plain schedule, bit for bit: records, fields and,
+    with face records on, the faces' momentum exchange; the default is the
+    plain schedule"""
+    import torch
+    if case == "cylinder_f64":
+        w, steps, faces = W.channel_cylinder_f64(), 300, False
+    else:
+        w, steps, faces = W.duct_sphere(scale=4, storage=case[7:10]), 120, case.endswith("records")
+    print(f"split vs plain schedule, fixed body: {w['name']} ({case}), {steps} steps", flush=True)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        a = make_gpu(w, split_schedule=1, face_records=faces)
+    b = make_gpu(w, split_schedule=-1, face_records=faces)
+    c = make_gpu(w, face_records=faces)
+    for d in (a, b, c):
+        d.timing_enable(1)
+    for chunk in (1, steps // 2 - 1, steps - steps // 2):
+        for d in (a, b, c):
+            d.step(chunk)
+    _, na, nodes_a = a.timing_read("stream_collide")
+    _, nn, nodes_n = a.timing_read("near_box")
+    _, nb, nodes_b = b.timing_read("stream_collide")
+    assert na == nn == nb == steps, "every split step is a far and a near launch"
+    assert nodes_a + nodes_n == nodes_b and 0 < nodes_n < nodes_a
+    assert a.timing_read("body")[1] == b.timing_read("body")[1] == steps  # the link rule once per step
+    assert c.timing_read("near_box")[1] == 0, "a fixed body keeps the plain schedule by default"
+    assert np.array_equal(a.records(0), b.records(0)) and np.array_equal(c.records(0), b.records(0))
+    if faces:
+        assert np.array_equal(a.face_records(0, steps), b.face_records(0, steps))
+    rho_a, u_a = a.fields()
+    rho_b, u_b = b.fields()
+    assert np.array_equal(rho_a, rho_b, equal_nan=True) and np.array_equal(u_a, u_b, equal_nan=True)
+    for d in (a, b, c):
+        d.close()
+
+
 def test_rotating_ellipsoid_with_a_large_surface():
     """a moving body whose region fits the one-workgroup kernel but whose
     near-surface node list would not is advanced by the box-scan kernel

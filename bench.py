@@ -410,19 +410,23 @@ def run_noise(steps=4000, warmup=200):
                 note="RMS of force minus its centred 41-step moving average, lattice units", noise=out)
 
 
-def run_sedimentation(steps=20000):
-    """The paper's sedimenting disc (135x1073, density ratio 1.03, FP32),
-    released from rest, for `steps` steps (0.59 s of the physical time) with
+def run_sedimentation(steps=20000, shape="disc"):
+    """The paper's sedimenting disc (135x1073, density ratio 1.03, FP32) or
+    ellipse (135x1676, aspect ratio 2, density ratio 1.1, released at 45
+    degrees), from rest, for `steps` steps (0.59 s of the physical time) with
     each force form moving it: the classical static sum, the lattice-frame
     force with the previous step's covered/uncovered terms, and the comoving
-    form. Reports the speed and the lateral/vertical positions reached and
-    the largest difference of the lateral position between the classical and
-    the corrected forms (the transient difference the paper points at)."""
+    form. Reports the speed and the lateral/vertical positions and angle
+    reached and the largest difference of the lateral position (and angle)
+    between the classical and the corrected forms (the transient difference
+    the paper points at)."""
     import lbm_workloads as W
     from paper_1407_4524_amd import Domain
+    make = (lambda **kw: W.sedimenting_disc(ratio=1.03, **kw)) if shape == "disc" else \
+        (lambda **kw: W.sedimenting_ellipse(ratio=1.1, **kw))
     out, traj = {}, {}
     for me in ("static", "lattice", "comoving"):
-        w = W.sedimenting_disc(ratio=1.03, storage="f32", me=me)
+        w = make(storage="f32", me=me)
         dom = Domain.from_spec(w)
         t0 = time.perf_counter()
         dom.step(steps)
@@ -431,13 +435,17 @@ def run_sedimentation(steps=20000):
         tr = dom.trajectory(0, 0, steps + 1)
         dom.close()
         traj[me] = tr
-        out[me] = dict(us_per_step=round(sec / steps * 1e6, 2), mlups=round(135 * 1073 * steps / sec / 1e6, 1),
+        out[me] = dict(us_per_step=round(sec / steps * 1e6, 2), mlups=round(w["nx"] * w["ny"] * steps / sec / 1e6, 1),
                        x_end=round(float(tr[-1, 0]), 4), y_end=round(float(tr[-1, 1]), 4),
                        v_end=[round(float(v), 7) for v in tr[-1, 4:6]], theta_end=round(float(tr[-1, 3]), 6))
     dx = {me: round(float(np.abs(traj[me][:, 0] - traj["static"][:, 0]).max()), 5) for me in ("lattice", "comoving")}
-    w = W.sedimenting_disc(ratio=1.03)
-    return dict(workload=w["name"], steps=steps, seconds_physical=round(steps * w["dt_s"], 4), forms=out,
-                max_lateral_difference_vs_classical_nodes=dx)
+    w = make()
+    res = dict(workload=w["name"], steps=steps, seconds_physical=round(steps * w["dt_s"], 4), forms=out,
+               max_lateral_difference_vs_classical_nodes=dx)
+    if shape != "disc":
+        res["max_angle_difference_vs_classical_rad"] = {
+            me: round(float(np.abs(traj[me][:, 3] - traj["static"][:, 3]).max()), 6) for me in ("lattice", "comoving")}
+    return res
 
 
 def secondary_line(r):
@@ -534,6 +542,7 @@ def main():
     if not args.no_physics and args.workload == HEADLINE:
         line["force_noise"] = run_noise()
         line["sedimentation"] = run_sedimentation(args.sediment_steps)
+        line["sedimentation_ellipse"] = run_sedimentation(args.sediment_steps, shape="ellipse")
     if not args.no_batch and args.workload == HEADLINE:
         line["batched"] = run_batch(args.batch_steps)
     if not args.no_serve and args.workload == HEADLINE:

@@ -85,6 +85,30 @@ def test_free_disc_full_size_f32():
     assert ev < 1e-4 and ex < 1e-3
 
 
+def test_free_ellipse_full_size_f32():
+    """The paper's sedimenting ellipse (135 x 1676, aspect ratio 2, density
+    ratio 1.1, released at 45 degrees) in FP32 storage, 1000 steps against the
+    FP64 oracle: velocity and spin within 1e-4 of their largest values,
+    position within 1e-3 nodes, angle within 1e-4 of its largest change
+    (the spin's bar integrated)."""
+    w = W.sedimenting_ellipse(ratio=1.1, storage="f32")
+    steps = 1000
+    print(f"{w['name']}, {steps} steps", flush=True)
+    g, o = run_pair(w, steps)
+    tg = g.trajectory(0, 0, steps + 1)
+    to = _traj_oracle(o, steps)
+    vmax, wmax = np.abs(to[:, 4:6]).max(), np.abs(to[:, 7]).max()
+    ev = np.abs(tg[:, 4:6] - to[:, 4:6]).max() / vmax
+    ew = np.abs(tg[:, 7] - to[:, 7]).max() / wmax
+    ex = np.abs(tg[:, 0:2] - to[:, 0:2]).max()
+    dth = np.abs(to[:, 3] - to[0, 3]).max()
+    eth = np.abs(tg[:, 3] - to[:, 3]).max()
+    print(f"velocity {ev:.2e} of {vmax:.3e}, spin {ew:.2e} of {wmax:.3e}, position {ex:.2e} nodes, "
+          f"angle {eth:.2e} of a {dth:.3e} turn; fell {to[0, 1] - to[-1, 1]:.3f}")
+    assert ev < 1e-4 and ew < 1e-4 and ex < 1e-3 and eth < 1e-4 * dth
+    assert to[0, 1] - to[-1, 1] > 0.1 and dth > 0
+
+
 def test_free_sphere_d3q19_f64():
     """A free sphere sinking in a closed D3Q19 box, FP64, 300 steps."""
     R = 4.2

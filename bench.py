@@ -451,6 +451,31 @@ def run_sedimentation(steps=20000, shape="disc"):
     return res
 
 
+def run_small_graph(name, steps):
+    """A small, launch-bound domain stepped as a one-member batch whose
+    steps are replayed from captured HIP graphs, timed whole (compare with
+    its plain lbm_step line)."""
+    import torch
+    from paper_1407_4524_amd import Batch, Domain
+    w = workload(name)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        dom = Domain.from_spec(w)
+    batch = Batch(stream=stream.cuda_stream)
+    batch.add(dom)
+    batch.config = dict(batch.config, graph=1)
+    batch.step(64)
+    dom.synchronize()
+    t0 = time.perf_counter()
+    batch.step(steps)
+    dom.synchronize()
+    sec = time.perf_counter() - t0
+    batch.close()
+    dom.close()
+    cells = w["nx"] * w["ny"] * w.get("nz", 1)
+    return dict(us_per_step=round(sec / steps * 1e6, 2), mlups=round(cells * steps / sec / 1e6, 1), steps=steps)
+
+
 def secondary_line(r):
     w = r["w"]
     return dict(workload=w["name"], value=round(r["mlups"], 1), unit="MLUPS", storage=w["storage"],
@@ -523,9 +548,16 @@ def main():
         line["copy_ceiling"] = copy_ceiling(main_run["roofline"]["algorithmic_bytes_per_launch"])
     if not args.no_secondary and args.workload == HEADLINE:
         sec = {}
-        for name in ("duct_sphere_f16", "duct_sphere_zouhe_f32", "channel_oscillating_f32", "suspension_f32"):
+        for name in ("duct_sphere_f16", "duct_sphere_zouhe_f32", "channel_oscillating_f32", "suspension_f32",
+                     "channel_cylinder_f64"):
             r = run_gpu(name, args.steps, args.warmup, SCHEDULES[args.schedule])
             sec[r["w"]["name"]] = secondary_line(r)
+            if name == "channel_cylinder_f64":
+                sec[r["w"]["name"]]["note"] = ("5000 nodes: bound by launches and their latency, not by HBM (the "
+                                               "roofline fields only restate the kernel's byte rate); "
+                                               "graph_batch: the same domain as a one-member batch replayed from "
+                                               "captured HIP graphs")
+                sec[r["w"]["name"]]["graph_batch"] = run_small_graph(name, args.steps)
             if name == "suspension_f32":
                 sec[r["w"]["name"]]["note"] = ("lbm_step steps the 32 bodies through batched launches (one for the "
                                                "link rule of the 16 static bodies, one for the advance of the 16 "

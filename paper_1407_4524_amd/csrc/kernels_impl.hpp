@@ -411,6 +411,7 @@ __global__ __launch_bounds__(64) void k_links_part(typename S::T* A, const Link*
                                                    const double* __restrict__ pose, int bc,
                                                    const uint8_t* __restrict__ mask, Geom g, Phys ph,
                                                    double* __restrict__ part) {
+  __shared__ double sm[12 * 64 + 48];
   const int lane = threadIdx.x;
   const int c = (int)blockIdx.x;
   if (c > 0 && c * 64 >= n) return;  // wave-uniform; chunk 0 is written even without links (zero sums)
@@ -418,11 +419,10 @@ __global__ __launch_bounds__(64) void k_links_part(typename S::T* A, const Link*
   double acc[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   const int k = c * 64 + lane;
   if (k < n) link_rule_m<L, S, EQ>(A, links[k], P, bc, mask, g, ph, acc);
-#pragma unroll
-  for (int j = 0; j < 12; ++j) {
-    const double v = wave_sum(acc[j]);
-    if (lane == j) part[c * 12 + j] = v;
-  }
+  // the chunk's 12 sums, the bits of wave_sum (the kernel's time is one
+  // wavefront's instruction chain, of which the DPP sums took a third)
+  const double v = wave_sums_lds<12>(acc, sm);
+  if (lane < 12) part[c * 12 + lane] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -1534,14 +1534,12 @@ __global__ __launch_bounds__(64) void k_links_batch_part(const BatchDomain* __re
   const int64_t t = b.t0 + s;
   const Pose P = *reinterpret_cast<const Pose*>(b.pose + (t - b.pose_base) * POSE_DOUBLES);
   const int lane = threadIdx.x;
+  __shared__ double sm[12 * 64 + 48];
   double acc[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   const int k = c * 64 + lane;
   if (k < b.n_host) link_rule_m<L, S, EQ>((typename S::T*)D.buf[s & 1], b.links[k], P, b.bc, b.mask, D.g, D.ph, acc);
-#pragma unroll
-  for (int j = 0; j < 12; ++j) {
-    const double v = wave_sum(acc[j]);
-    if (lane == j) b.partials[c * 12 + j] = v;
-  }
+  const double v = wave_sums_lds<12>(acc, sm);  // the bits of wave_sum, lane j value j
+  if (lane < 12) b.partials[c * 12 + lane] = v;
 }
 
 template <class L>

@@ -79,6 +79,8 @@ def test_bench_refuses_more_than_one_gpu():
     (dict(faces=("periodic", "wall", "wall", "wall", "periodic", "periodic")), "periodic faces come in pairs"),
     (dict(faces=("outlet", "outlet", "wall", "wall", "periodic", "periodic")), "inlet only on -x"),
     (dict(faces=("wall", "wall", "inlet", "wall", "periodic", "periodic")), "inlet/outlet faces only along x"),
+    (dict(split_schedule=2), "split_schedule is -1, 0 or 1"),
+    (dict(split_schedule=-2), "split_schedule is -1, 0 or 1"),
 ])
 def test_invalid_domain_rejected_on_the_host(kw, msg):
     """The descriptor checks run before any HIP call: each invalid setting
